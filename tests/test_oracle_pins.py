@@ -1,0 +1,418 @@
+"""Pins of the CPU oracle against closed forms, library routines and brute force.
+
+Each test checks the oracle against something other than itself: exact
+rational sample counts, affine-field reproduction, torch grid_sample,
+closed-form transmittance, a hand-derived MLP example (tests/golden/),
+float64 finite differences and sum invariants.  Citations name the
+Oblique-MERF passage the checked behaviour comes from.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.field import feature_terms, interp_features
+from oracle.render import mlp_forward
+from tests._scenes import BOX_HI, BOX_LO, DELTA, micro_scene, vertex_coords
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Placement (Sec. 4.1 Eq. 6-7, Sec. 4.4): exact counts with rational arithmetic
+# ---------------------------------------------------------------------------
+
+def test_vertical_rays_closed_form_counts():
+    """d = (0,0,-1) from z = 1: p_z = 1 - k delta exactly, so the accepted k
+    are the integers in [(1 - zmax')/delta, (1 - zmin')/delta] with the
+    interval clipped to the box."""
+    rng = np.random.default_rng(5)
+    m = 8
+    occ = np.empty((m, m, 2), np.float32)
+    occ[..., 0] = rng.uniform(-0.05, 0.2, (m, m))
+    occ[..., 1] = occ[..., 0] + rng.uniform(-0.02, 0.12, (m, m))
+    n = 300
+    xy = rng.uniform(-1, 1, (n, 2)).astype(np.float32)
+    xy[:4] = [[-1, -1], [1, 1], [0, 0], [-0.75, 0.5]]  # faces and cell borders
+    o = np.concatenate([xy, np.ones((n, 1), np.float32)], axis=1)
+    d = np.tile(_f32([0, 0, -1]), (n, 1))
+    k_list, n_placed, _ = oracle.place_samples(o, d, occ, BOX_LO, BOX_HI, DELTA, 1024)
+    dl = Fraction(DELTA)
+    for r in range(n):
+        x, y = Fraction(float(xy[r, 0])), Fraction(float(xy[r, 1]))
+        i = min(int(math.floor((x + 1) * m / 2)), m - 1)
+        j = min(int(math.floor((y + 1) * m / 2)), m - 1)
+        lo = max(Fraction(float(occ[j, i, 0])), Fraction(0))
+        hi = min(Fraction(float(occ[j, i, 1])), Fraction(1, 4))
+        if lo > hi:
+            want = []
+        else:
+            k0 = math.ceil((1 - hi) / dl)
+            k1 = math.floor((1 - lo) / dl)
+            want = list(range(k0, k1 + 1))
+        assert n_placed[r] == len(want), r
+        assert list(k_list[r, :n_placed[r]]) == want
+
+
+def test_horizontal_ray_closed_form_counts():
+    """d = (1,0,0) from x = -1.5 on the lattice: each occupied cell of width
+    2/M holds 4096/M lattice points (half-open), plus the far face point."""
+    m = 16
+    rng = np.random.default_rng(7)
+    occ = np.empty((m, m, 2), np.float32)
+    occ[..., 0] = 0.1
+    occ[..., 1] = np.where(rng.random((m, m)) < 0.5, 0.2, 0.05)
+    for yv, zv in [(0.3, 0.15), (-0.9, 0.12), (0.0, 0.1)]:
+        o = _f32([[-1.5, yv, zv]])
+        d = _f32([[1, 0, 0]])
+        k_list, n_placed, _ = oracle.place_samples(o, d, occ, BOX_LO, BOX_HI, DELTA, 8192)
+        j = min(int(math.floor((Fraction(float(np.float32(yv))) + 1) * m / 2)), m - 1)
+        z = np.float32(zv)
+        want = []
+        for i in range(m):
+            if occ[j, i, 0] <= z <= occ[j, i, 1]:
+                per = 4096 // m
+                first = 1024 + i * per
+                want.extend(range(first, first + per))
+                if i == m - 1:
+                    want.append(1024 + 4096)
+        assert n_placed[0] == len(want)
+        assert list(k_list[0, :n_placed[0]]) == want
+
+
+def test_empty_and_full_plane():
+    """Empty plane (z_min > z_max): no samples, C = c_bg exactly, T = 1.
+    Full plane: a vertical ray from z = 1 gets every lattice point with
+    0.75 <= k delta <= 1, i.e. 513 samples."""
+    prm = oracle.RenderParams(n_max=4200, c_bg=(0.25, 0.5, 0.75))
+    sc = micro_scene(zmin=0.2, zmax=0.1, seed=3)
+    o, d = _f32([[0.1, 0.2, 1.0], [-2, 0, 0.1]]), _f32([[0, 0, -1], [1, 0, 0]])
+    r = oracle.oracle_render(sc, o, d, prm)
+    assert (r["n_placed"] == 0).all()
+    assert np.array_equal(r["C"], np.tile([0.25, 0.5, 0.75], (2, 1)))
+    assert np.array_equal(r["T"], [1.0, 1.0])
+    sc = micro_scene(zmin=0.0, zmax=0.25, seed=3)
+    r = oracle.oracle_render(sc, o, d, prm)
+    assert r["n_placed"][0] == 513
+    assert r["n_placed"][1] == 4097
+
+
+def _brute_force_count(o, d, occ, n_kmax):
+    """Scalar loop over every k in [0, n_kmax): independent of the oracle's
+    vectorised bisection of the box range."""
+    m = occ.shape[0]
+    cnt = []
+    for k in range(n_kmax):
+        t = np.float32(k * DELTA)
+        p = [np.float32(o[a] + np.float32(t * d[a])) for a in range(3)]
+        if not (-1 <= p[0] <= 1 and -1 <= p[1] <= 1 and 0 <= p[2] <= 0.25):
+            continue
+        i = min(max(int(math.floor(float(p[0]) * (m / 2))) + m // 2, 0), m - 1)
+        j = min(max(int(math.floor(float(p[1]) * (m / 2))) + m // 2, 0), m - 1)
+        if occ[j, i, 0] <= p[2] <= occ[j, i, 1]:
+            cnt.append(k)
+    return cnt
+
+
+def test_placement_brute_force_small():
+    """Random oblique rays near the box vs a plain scalar loop over all k."""
+    rng = np.random.default_rng(11)
+    m = 4
+    occ = np.empty((m, m, 2), np.float32)
+    occ[..., 0] = rng.uniform(0.0, 0.15, (m, m))
+    occ[..., 1] = occ[..., 0] + rng.uniform(0.0, 0.1, (m, m))
+    occ[0, 0] = (0.2, 0.1)  # one empty cell
+    n = 12
+    a = rng.uniform(-1, 1, (n, 2))
+    pitch = rng.uniform(0.2, 1.3, n)
+    yaw = rng.uniform(0, 2 * np.pi, n)
+    d = np.stack([np.cos(pitch) * np.cos(yaw), np.cos(pitch) * np.sin(yaw), -np.sin(pitch)], 1)
+    o = np.concatenate([a, np.full((n, 1), 0.1)], 1) - 0.4 * d
+    o, d = o.astype(np.float32), d.astype(np.float32)
+    k_list, n_placed, _ = oracle.place_samples(o, d, occ, BOX_LO, BOX_HI, DELTA, 8192)
+    for r in range(n):
+        want = _brute_force_count(o[r], d[r], occ, 9000)
+        assert list(k_list[r, :n_placed[r]]) == want
+
+
+def test_nested_intervals_nested_sets():
+    """Widening every occupancy interval can only add samples."""
+    rng = np.random.default_rng(2)
+    m = 8
+    inner = np.empty((m, m, 2), np.float32)
+    inner[..., 0] = rng.uniform(0.05, 0.15, (m, m))
+    inner[..., 1] = inner[..., 0] + rng.uniform(0, 0.05, (m, m))
+    outer = inner.copy()
+    outer[..., 0] -= rng.uniform(0, 0.03, (m, m)).astype(np.float32)
+    outer[..., 1] += rng.uniform(0, 0.03, (m, m)).astype(np.float32)
+    import scenegen
+    o, d = scenegen.oblique_rays(64, seed=4)
+    ki, ni, _ = oracle.place_samples(o, d, inner, BOX_LO, BOX_HI, DELTA, 4096)
+    ko, no, _ = oracle.place_samples(o, d, outer, BOX_LO, BOX_HI, DELTA, 4096)
+    assert (ni <= no).all() and (no > ni).any()
+    for r in range(64):
+        assert set(ki[r, :ni[r]]) <= set(ko[r, :no[r]])
+
+
+def test_n_max_keeps_first_in_k_order():
+    sc = micro_scene(zmin=0.0, zmax=0.25)
+    o, d = _f32([[0.3, 0.3, 1.0]]), _f32([[0, 0, -1]])
+    k_all, n_all, _ = oracle.place_samples(o, d, sc["occ"], BOX_LO, BOX_HI, DELTA, 1024)
+    k5, n5, _ = oracle.place_samples(o, d, sc["occ"], BOX_LO, BOX_HI, DELTA, 5)
+    assert n5[0] == 5 and list(k5[0]) == list(k_all[0, :5])
+    assert list(k_all[0, :3]) == [1536, 1537, 1538]
+
+
+def test_nan_and_inf_rays_place_nothing():
+    sc = micro_scene(zmin=0.0, zmax=0.25)
+    o = _f32([[np.nan, 0, 1], [0, 0, 1], [0, 0, np.inf]])
+    d = _f32([[0, 0, -1], [np.nan, 0, -1], [0, 0, -1]])
+    _, n, _ = oracle.place_samples(o, d, sc["occ"], BOX_LO, BOX_HI, DELTA, 64)
+    assert (n == 0).all()
+
+
+# ---------------------------------------------------------------------------
+# Features (Sec. 3 Eq. 2-3)
+# ---------------------------------------------------------------------------
+
+def _affine_scene(grid, planes, coef):
+    """Each source holds an affine function of its own coordinates."""
+    lx, ly, lz = grid
+    nx, ny, nz = planes
+    sc = micro_scene(grid=grid, planes=planes)
+    gx, gy, gz = (vertex_coords(lx, -1, 1), vertex_coords(ly, -1, 1), vertex_coords(lz, 0, 0.25))
+    Z, Y, X = np.meshgrid(gz, gy, gx, indexing="ij")
+    c = coef["grid"]
+    sc["grid"] = (c[0] + c[1] * X[..., None] + c[2] * Y[..., None] + c[3] * Z[..., None]).astype(np.float64)
+    px, py, pz = vertex_coords(nx, -1, 1), vertex_coords(ny, -1, 1), vertex_coords(nz, 0, 0.25)
+    for name, (u, v) in {"plane_xy": (px, py), "plane_xz": (px, pz), "plane_yz": (py, pz)}.items():
+        V, U = np.meshgrid(v, u, indexing="ij")
+        c = coef[name]
+        sc[name] = c[0] + c[1] * U[..., None] + c[2] * V[..., None]
+    return sc
+
+
+def test_affine_field_reproduced_exactly():
+    rng = np.random.default_rng(9)
+    grid, planes = (5, 7, 4), (9, 6, 8)
+    coef = {"grid": rng.standard_normal((4, 8))}
+    for name in ("plane_xy", "plane_xz", "plane_yz"):
+        coef[name] = rng.standard_normal((3, 8))
+    sc = _affine_scene(grid, planes, coef)
+    p = np.stack([rng.uniform(-1, 1, 500), rng.uniform(-1, 1, 500), rng.uniform(0, 0.25, 500)], 1)
+    p[:3] = [[-1, -1, 0], [1, 1, 0.25], [1, -1, 0.25]]  # faces
+    terms = feature_terms(p, BOX_LO, BOX_HI, grid, planes)
+    t = interp_features(terms, lambda s, c, idx: torch.from_numpy(sc[s].reshape(-1, 8)[idx])).numpy()
+    x, y, z = p[:, 0:1], p[:, 1:2], p[:, 2:3]
+    g, a, b, e = coef["grid"], coef["plane_xy"], coef["plane_xz"], coef["plane_yz"]
+    want = (g[0] + g[1] * x + g[2] * y + g[3] * z + a[0] + a[1] * x + a[2] * y
+            + b[0] + b[1] * x + b[2] * z + e[0] + e[1] * y + e[2] * z)
+    np.testing.assert_allclose(t, want, rtol=0, atol=1e-12)
+
+
+def test_interpolation_matches_grid_sample():
+    """Vertex-aligned interpolation equals grid_sample(align_corners=True)."""
+    import torch.nn.functional as Fn
+    sc = micro_scene(grid=(6, 5, 4), planes=(7, 9, 5), seed=1)
+    rng = np.random.default_rng(3)
+    p = np.stack([rng.uniform(-1, 1, 300), rng.uniform(-1, 1, 300), rng.uniform(0, 0.25, 300)], 1)
+    terms = feature_terms(p, BOX_LO, BOX_HI, (6, 5, 4), (7, 9, 5))
+    src = {k: torch.from_numpy(sc[k].astype(np.float64)) for k in ("grid", "plane_xy", "plane_xz", "plane_yz")}
+    t = interp_features(terms, lambda s, c, idx: src[s].reshape(-1, 8)[torch.from_numpy(idx)]).numpy()
+    nx = torch.from_numpy(p[:, 0])
+    ny = torch.from_numpy(p[:, 1])
+    nz = torch.from_numpy(p[:, 2] / 0.125 - 1)
+    vol = src["grid"].permute(3, 0, 1, 2)[None]
+    g3 = torch.stack([nx, ny, nz], 1)[None, :, None, None, :]
+    ref = Fn.grid_sample(vol, g3, mode="bilinear", align_corners=True)[0, :, :, 0, 0].T
+    for name, (u, v) in {"plane_xy": (nx, ny), "plane_xz": (nx, nz), "plane_yz": (ny, nz)}.items():
+        img = src[name].permute(2, 0, 1)[None]
+        g2 = torch.stack([u, v], 1)[None, :, None, :]
+        ref = ref + Fn.grid_sample(img, g2, mode="bilinear", align_corners=True)[0, :, :, 0].T
+    np.testing.assert_allclose(t, ref.numpy(), rtol=0, atol=1e-12)
+
+
+def test_activations_textbook_values():
+    t = torch.tensor([[math.log(2.0), 0.0, 100.0, -100.0, 0.0, math.log(3.0), 0.0, 0.0]], dtype=torch.float64)
+    tau, cd, f = oracle.field.activations(t)
+    assert tau.item() == pytest.approx(2.0, rel=1e-15)
+    np.testing.assert_allclose(cd.numpy(), [[0.5, 1.0, 0.0]], atol=1e-15)
+    np.testing.assert_allclose(f.numpy(), [[0.5, 0.75, 0.5, 0.5]], atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Compositing (Eq. 1, 4) and the deferred MLP
+# ---------------------------------------------------------------------------
+
+def _sigma32(sigma):
+    """The density actually stored: exp of the binary32 value of ln(sigma)."""
+    return math.exp(float(np.float32(math.log(sigma))))
+
+
+def _constant_density_scene(sigma, colour_pre, mlp_b3):
+    sc = micro_scene(zmin=0.0, zmax=0.25)
+    sc["grid"][..., 0] = np.float32(math.log(sigma))
+    sc["grid"][..., 1:] = np.float32(colour_pre)
+    mlp = np.zeros(499, np.float32)
+    mlp[-3:] = mlp_b3
+    sc["mlp"] = mlp
+    return sc
+
+
+@pytest.mark.parametrize("sigma,n_max", [(50.0, 1024), (800.0, 1024), (30.0, 100)])
+def test_constant_density_closed_form(sigma, n_max):
+    """Constant tau = sigma over n samples: T = exp(-sigma n delta),
+    sum w = 1 - T, Cd = (1 - T) sigmoid(c); zero MLP weights give
+    G = sigmoid(b3)."""
+    c = 0.4
+    b3 = np.array([0.3, -0.7, 1.1], np.float32)
+    sc = _constant_density_scene(sigma, c, b3)
+    sigma = _sigma32(sigma)
+    bg = (0.25, 0.5, 0.75)
+    prm = oracle.RenderParams(n_max=n_max, c_bg=bg)
+    o, d = _f32([[0.2, -0.4, 1.0]]), _f32([[0, 0, -1]])
+    r = oracle.oracle_render(sc, o, d, prm)
+    n = min(513, n_max)
+    assert r["n_placed"][0] == n
+    T = math.exp(-sigma * n * DELTA)
+    s = 1 / (1 + math.exp(-float(np.float32(c))))
+    assert r["T"][0] == pytest.approx(T, rel=1e-12)
+    np.testing.assert_allclose(r["F"][0, :3], (1 - T) * s, rtol=1e-12)
+    np.testing.assert_allclose(r["F"][0, 3:], (1 - T) * s, rtol=1e-12)
+    g = 1 / (1 + np.exp(-b3.astype(np.float64)))
+    np.testing.assert_allclose(r["C"][0], (1 - T) * s + g + T * np.array(bg), rtol=1e-12)
+
+
+def test_single_sample_weight_is_alpha():
+    """A one-point interval (z_min = z_max = 1 - k delta): w_1 = alpha_1."""
+    sigma = 700.0
+    sc = _constant_density_scene(sigma, 0.0, [0, 0, 0])
+    sigma = _sigma32(sigma)
+    z = np.float32(1 - 1700 * DELTA)
+    sc["occ"][..., 0] = z
+    sc["occ"][..., 1] = z
+    r = oracle.oracle_render(sc, _f32([[0.1, 0.1, 1.0]]), _f32([[0, 0, -1]]), oracle.RenderParams(n_max=8))
+    assert r["n_placed"][0] == 1
+    alpha = 1 - math.exp(-sigma * DELTA)
+    np.testing.assert_allclose(r["F"][0, :3], alpha * 0.5, rtol=1e-13)
+    assert r["T"][0] == pytest.approx(1 - alpha, rel=1e-13)
+
+
+def test_opaque_first_sample():
+    """tau delta >> 1 at the first sample: C = c^d_1 + G, T = 0."""
+    sc = _constant_density_scene(math.exp(30.0), 1.5, [0, 0, 0])
+    r = oracle.oracle_render(sc, _f32([[0.1, 0.1, 1.0]]), _f32([[0, 0, -1]]),
+                             oracle.RenderParams(n_max=64, c_bg=(1, 1, 1)))
+    s = 1 / (1 + math.exp(-float(np.float32(1.5))))
+    np.testing.assert_allclose(r["F"][0, :3], s, rtol=1e-14)
+    assert r["T"][0] == 0.0
+    np.testing.assert_allclose(r["C"][0], s + 0.5, rtol=1e-14)
+
+
+def test_mlp_hand_example():
+    g = json.load(open(os.path.join(GOLDEN, "mlp_hand_example.json")))
+    w1 = np.zeros((16, 10))
+    w1[np.arange(10), np.arange(10)] = 1
+    b1 = np.full(16, -0.5)
+    w2 = np.zeros((16, 16))
+    w2[:, :8] = 1
+    b2 = np.zeros(16)
+    w3 = np.full((3, 16), 0.1)
+    b3 = np.array(g["b3"])
+    mlp = torch.from_numpy(np.concatenate([w1.ravel(), b1, w2.ravel(), b2, w3.ravel(), b3]))
+    out = mlp_forward(torch.tensor([g["x"]], dtype=torch.float64), mlp).numpy()[0]
+    np.testing.assert_allclose(out, g["expected_g"], atol=1e-10)
+
+
+def test_ert_stops_after_crossing_sample():
+    """With t_term, the ray stops after the first sample whose T_{i+1}
+    falls below t_term: n_eval = ceil(ln(1/t_term) / (sigma delta))."""
+    sigma = 400.0
+    sc = _constant_density_scene(sigma, 0.0, [0, 0, 0])
+    sigma = _sigma32(sigma)
+    t_term = 1e-3
+    r = oracle.oracle_render(sc, _f32([[0.1, 0.1, 1.0]]), _f32([[0, 0, -1]]),
+                             oracle.RenderParams(n_max=1024, t_term=t_term))
+    want = math.ceil(math.log(1 / t_term) / (sigma * DELTA))
+    assert r["n_placed"][0] == 513 and r["n_eval"][0] == want
+    assert r["T"][0] == pytest.approx(math.exp(-sigma * DELTA * want), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Gradients (O8): float64 FD, sum invariant, closed-form derivative
+# ---------------------------------------------------------------------------
+
+def _grad_problem(seed=0):
+    import scenegen
+    sc = micro_scene(grid=(5, 4, 3), planes=(7, 6, 5), m=4, zmin=0.02, zmax=0.2, seed=seed, std=0.7)
+    sc["grid"][..., 0] += 3.0
+    o, d = scenegen.oblique_rays(24, seed=seed + 10, origin_z=0.6)
+    tgt = np.random.default_rng(seed).uniform(0, 1, (24, 3))
+    return sc, o, d, tgt
+
+
+def test_gradient_matches_fd_float64():
+    sc, o, d, tgt = _grad_problem()
+    prm = oracle.RenderParams(n_max=256, c_bg=(0.2, 0.4, 0.6))
+    loss, _, grads = oracle.oracle_loss_and_grads(sc, o, d, prm, tgt)
+    rng = np.random.default_rng(1)
+    eps = 1e-6
+    checked = 0
+    for src in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp"):
+        flat = sc[src].reshape(-1)
+        if src == "mlp":
+            cand = np.arange(499)
+            gdense = grads["mlp"]
+        else:
+            u, g = grads[src]
+            gdense = np.zeros(flat.size)
+            gdense[(u[:, None] * 8 + np.arange(8)).ravel()] = g.ravel()
+            cand = np.nonzero(gdense)[0]
+        for e in rng.choice(cand, 6, replace=False):
+            sp = {k: (v.astype(np.float64).copy() if k == src else v) for k, v in sc.items()}
+            vals = []
+            for s in (+1, -1):
+                sp[src].reshape(-1)[e] = float(flat[e]) + s * eps
+                r = oracle.oracle_render(sp, o, d, prm)
+                vals.append(np.mean((r["C"] - tgt) ** 2))
+            fd = (vals[0] - vals[1]) / (2 * eps)
+            assert abs(fd - gdense[e]) <= 1e-6 * max(abs(fd), 1e-3), (src, e, fd, gdense[e])
+            checked += 1
+    assert checked == 30
+
+
+def test_gradient_sum_invariant_across_sources():
+    """Each interpolation's weights sum to 1, so per channel the total
+    gradient of every source equals sum_samples dL/dt_c."""
+    sc, o, d, tgt = _grad_problem(seed=4)
+    _, _, grads = oracle.oracle_loss_and_grads(sc, o, d, oracle.RenderParams(n_max=256), tgt)
+    sums = [grads[s][1].sum(axis=0) for s in ("grid", "plane_xy", "plane_xz", "plane_yz")]
+    for s in sums[1:]:
+        np.testing.assert_allclose(s, sums[0], rtol=1e-10, atol=1e-14)
+
+
+def test_gradient_constant_density_closed_form():
+    """Shifting every grid ch0 value by e multiplies sigma by exp(e); with a
+    zero-weight MLP, dL/de = sum_r sum_c 2 (C - C*)/(3R) * sigma n delta
+    exp(-sigma n delta) s, which must equal the sum of the ch0 gradients."""
+    sigma, c = 60.0, 0.3
+    sc = _constant_density_scene(sigma, c, [0.1, 0.2, 0.3])
+    sigma = _sigma32(sigma)
+    o = _f32([[0.1, 0.1, 1.0], [-0.5, 0.6, 1.0], [0.7, -0.2, 1.0]])
+    d = np.tile(_f32([0, 0, -1]), (3, 1))
+    tgt = np.array([[0.2, 0.3, 0.4], [0.9, 0.1, 0.5], [0.5, 0.5, 0.5]])
+    loss, C, grads = oracle.oracle_loss_and_grads(sc, o, d, oracle.RenderParams(n_max=1024), tgt)
+    n = 513
+    s = 1 / (1 + math.exp(-float(np.float32(c))))
+    dcd = sigma * n * DELTA * math.exp(-sigma * n * DELTA) * s
+    want = np.sum(2 * (C - tgt) / 9.0 * dcd)
+    assert grads["grid"][1][:, 0].sum() == pytest.approx(want, rel=1e-10)
