@@ -1,0 +1,210 @@
+"""Throughput of the occupancy-plane ray marcher on one MI355X.
+
+One step = one pass of the whole hot path over one batch: sample placement
+inside the occupancy plane, feature gather, activations, compositing and the
+deferred MLP (om_render), for every ray of the batch.  The default workload
+is the 1920x1080 oblique render of the 1024x1024x128 grid + 4096^2/4096x512
+planes scene with a 256x256 occupancy plane and 200 buildings (float32).
+
+Prints ONE JSON line.  `value` is Mrays/s of the float32 forward render;
+`forms` adds the bfloat16 render and the float32 forward+backward training
+step; `roofline` is for the dominant kernel (the march kernel); the float64
+CPU oracle is timed on a bounded crop of the same image as `cpu_baseline`.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BG = (0.25, 0.5, 0.75)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--t-term", type=float, default=0.0)
+    ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and fwd+bwd forms")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--crop", type=int, default=256, help="side of the centre crop timed on the CPU oracle")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("omerf_device.h", "march.hip"):
+        with open(os.path.join(ROOT, "paper_2404_09531_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, only
+    if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    e = rec.get(kernel, {}).get(workload)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
+def time_stages(step_fns, steps, warmup, torch):
+    """Run `steps` steps; each step calls the stage functions in order with
+    events recorded between them on the current stream.  Returns (total ms,
+    [per-stage mean ms])."""
+    for _ in range(warmup):
+        for f in step_fns:
+            f()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(step_fns) + 1)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for s in range(steps):
+        ev[s][0].record()
+        for i, f in enumerate(step_fns):
+            f()
+            ev[s][i + 1].record()
+    torch.cuda.synchronize()
+    total = ev[0][0].elapsed_time(ev[-1][-1])
+    per = [float(np.mean([ev[s][i].elapsed_time(ev[s][i + 1]) for s in range(steps)])) for i in range(len(step_fns))]
+    return total, per
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_2404_09531_amd as om
+    import scenegen
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    cfg, recipe = scenegen.workload("oblique-1080p")
+    sc = scenegen.make_scene(cfg)
+    o, d = scenegen.make_rays(recipe)
+    n = o.shape[0]
+    n_max = recipe["n_max"]
+    print(f"[bench] scene+rays built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    t = {k: torch.from_numpy(sc[k]).to(dev) for k in ("grid", "plane_xy", "plane_xz", "plane_yz", "occ", "mlp")}
+    scene = om.Scene(t["grid"], t["plane_xy"], t["plane_xz"], t["plane_yz"], t["occ"], t["mlp"])
+    og = torch.from_numpy(o).to(dev)
+    dg = torch.from_numpy(d).to(dev)
+    out = dict(C=torch.empty((n, 3), device=dev), T=torch.empty((n,), device=dev), F=torch.empty((n, 7), device=dev),
+               n_placed=torch.empty((n,), dtype=torch.int32, device=dev),
+               n_eval=torch.empty((n,), dtype=torch.int32, device=dev))
+    kw = dict(n_max=n_max, t_term=a.t_term, c_bg=BG)
+
+    march = lambda: om.render_into(scene, og, dg, out, stage="march", **kw)  # noqa: E731
+    mlp = lambda: om.render_into(scene, og, dg, out, stage="mlp", **kw)  # noqa: E731
+    total_ms, (march_ms, mlp_ms) = time_stages([march, mlp], a.steps, a.warmup, torch)
+    ms_step = total_ms / a.steps
+    samples = int(out["n_eval"].sum().item())
+    mrays = n / (ms_step * 1e-3) / 1e6
+    msamples = samples / (ms_step * 1e-3) / 1e6
+    print(f"[bench] fp32 render {ms_step:.3f} ms/step (march {march_ms:.3f}, mlp {mlp_ms:.3f}), "
+          f"{samples / n:.1f} samples/ray", file=sys.stderr, flush=True)
+
+    # Algorithmic bytes of one march launch: 20 corners x 8 channels x 4 B per
+    # evaluated sample, plus 24 B of ray in and 40 B of F/T/counts out per ray.
+    alg_bytes = samples * 640 + n * 64
+    achieved = alg_bytes / (march_ms * 1e-3) / 1e9
+    traffic = measured_traffic("k_march_fwd<F32Store>", "oblique-1080p")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_march_fwd<F32Store>", "algorithmic_bytes_per_launch": alg_bytes,
+                "kernel_ms": round(march_ms, 4)}
+
+    forms = {}
+    if not a.no_forms:
+        # bfloat16 storage + bfloat16 MFMA MLP, same image.
+        tb = {k: om.to_bf16(t[k]) for k in ("grid", "plane_xy", "plane_xz", "plane_yz")}
+        scene_b = om.Scene(tb["grid"], tb["plane_xy"], tb["plane_xz"], tb["plane_yz"], t["occ"], t["mlp"])
+        outb = {k: torch.empty_like(v) for k, v in out.items()}
+        mb = lambda: om.render_into(scene_b, og, dg, outb, stage="march", **kw)  # noqa: E731
+        lb = lambda: om.render_into(scene_b, og, dg, outb, stage="mlp", **kw)  # noqa: E731
+        tot_b, (mb_ms, lb_ms) = time_stages([mb, lb], a.steps, a.warmup, torch)
+        ms_b = tot_b / a.steps
+        err_b = (outb["C"] - out["C"]).abs().max().item()
+        forms["bf16_render"] = {"Mrays_per_s": round(n / (ms_b * 1e-3) / 1e6, 2), "ms_per_step": round(ms_b, 4),
+                                "march_ms": round(mb_ms, 4), "mlp_ms": round(lb_ms, 4),
+                                "achieved_GBps": round((samples * 320 + n * 64) / (mb_ms * 1e-3) / 1e9, 1),
+                                "max_abs_vs_fp32_render": err_b}
+        del scene_b, tb, outb
+        # float32 forward + backward training step on 2^18 rays from 16 cameras.
+        cfg2, rec2 = scenegen.workload("train-2^18")
+        o2, d2 = scenegen.make_rays(rec2)
+        n2 = o2.shape[0]
+        o2g, d2g = torch.from_numpy(o2).to(dev), torch.from_numpy(d2).to(dev)
+        out2 = {k: torch.empty((n2,) + tuple(v.shape[1:]), dtype=v.dtype, device=dev) for k, v in out.items()}
+        om.render_into(scene, o2g, d2g, out2, **kw)
+        g = torch.Generator(device=dev)
+        g.manual_seed(2)
+        target = (out2["C"] + 0.05 * torch.randn(out2["C"].shape, device=dev, generator=g)).contiguous()
+        grads = {k: torch.zeros(t[k].shape, device=dev) for k in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp")}
+        dC = torch.empty_like(out2["C"])
+        fwd = lambda: om.render_into(scene, o2g, d2g, out2, **kw)  # noqa: E731
+        lossg = lambda: om.l2_loss_grad(out2["C"], target, dL_dC=dC, with_loss=False)  # noqa: E731
+        bwd = lambda: om.render_backward(scene, o2g, d2g, out2, dC, grads, **kw)  # noqa: E731
+        tot2, (f_ms, l_ms, b_ms) = time_stages([fwd, lossg, bwd], max(3, a.steps // 2), a.warmup, torch)
+        ms2 = tot2 / max(3, a.steps // 2)
+        s2 = int(out2["n_eval"].sum().item())
+        forms["fp32_fwd_bwd"] = {"workload": "2^18 rays, 16 cameras 1920x1080, same scene", "rays": n2,
+                                 "Mrays_per_s": round(n2 / (ms2 * 1e-3) / 1e6, 2), "ms_per_step": round(ms2, 4),
+                                 "fwd_ms": round(f_ms, 4), "loss_ms": round(l_ms, 4), "bwd_ms": round(b_ms, 4),
+                                 "samples_per_ray": round(s2 / n2, 1),
+                                 "targets": "forward colours + N(0, 0.05), seeded"}
+        del grads
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        import torch as _t
+
+        import oracle
+        w, h = recipe["width"], recipe["height"]
+        c = a.crop
+        px = np.array([(h // 2 - c // 2 + j) * w + (w // 2 - c // 2 + i) for j in range(c) for i in range(c)])
+        oc, dc = o[px], d[px]
+        t1 = time.time()
+        ref = oracle.oracle_render(sc, oc, dc, oracle.RenderParams(n_max=n_max, c_bg=BG, t_term=a.t_term),
+                                   keep_k=False)
+        dt = time.time() - t1
+        gpu_c = out["C"][torch.from_numpy(px).to(dev)].double().cpu().numpy()
+        cpu = {"value": round(len(px) / dt / 1e6, 6), "unit": "Mrays/s", "cores": _t.get_num_threads(),
+               "kind": "oracle", "sample": f"centre {c}x{c} crop of the 1920x1080 image ({len(px)} rays)",
+               "seconds": round(dt, 2), "Msamples_per_s": round(float(ref["n_eval"].sum()) / dt / 1e6, 4),
+               "max_abs_gpu_vs_oracle_on_crop": float(np.abs(gpu_c - ref["C"]).max())}
+
+    rec = {
+        "metric": "Mrays/s render & fwd+bwd (FP32 vs BF16) at stated error; % HBM/MFMA roofline",
+        "value": round(mrays, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "oblique-1080p", "rays": n, "grid": list(cfg.grid), "planes": list(cfg.planes),
+                   "occupancy": cfg.occ, "buildings": cfg.n_buildings, "n_max": n_max, "t_term": a.t_term,
+                   "camera": "pitch 45 deg, yaw 90 deg, 60 deg hfov"},
+        "Msamples_per_s": round(msamples, 2), "samples_per_ray": round(samples / n, 2),
+        "roofline": roofline, "cpu_baseline": cpu, "forms": forms,
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,227 @@
+/*
+ * omerf.h -- C ABI of the MI355X (gfx950) occupancy-plane ray marcher.
+ *
+ * Implements the real-time hot path of Oblique-MERF (arXiv 2404.09531):
+ * ray marching a MERF-style scene (low-resolution 3D feature grid plus three
+ * high-resolution planes, Sec. 3 Eq. 2) that places samples only inside the
+ * per-column [z_min, z_max] intervals of the occupancy plane (Sec. 4.1,
+ * Eq. 6 with epsilon = 0 and Eq. 7; Sec. 4.4), applies the density and colour
+ * activations (Eq. 3), alpha-composites (Eq. 1) and runs the deferred
+ * view-dependent MLP once per ray (Eq. 4).  A backward pass scatter-adds
+ * gradients of a per-ray colour loss into the grid, the planes and the MLP.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named "device" are HIP device pointers owned by the caller; the
+ *   library never allocates, frees or keeps device memory, and never copies
+ *   to or from the host inside render / backward calls.
+ * - All work is enqueued asynchronously on the caller's stream `stream`
+ *   (a hipStream_t passed as void*; NULL = the default stream).  A kernel
+ *   fault surfaces at the caller's next synchronisation.
+ * - Return value: OM_OK (0) or a negative status (OM_ERR_*).  On error,
+ *   om_last_error() returns a message for the calling thread.  Nothing is
+ *   enqueued when argument validation fails.  The library never aborts.
+ * - Layout: rays are float32 [n][3] (origin o, unit direction d).  Feature
+ *   sources are channels-last with 8 channels: grid [Lz][Ly][Lx][8],
+ *   plane_xy [Ny][Nx][8], plane_xz [Nz][Nx][8], plane_yz [Nz][Ny][8];
+ *   channel 0 = density pre-activation, 1..3 = diffuse colour,
+ *   4..7 = specular features (Eq. 3).  Occupancy plane float32 [My][Mx][2]
+ *   holding (z_min, z_max).  MLP float32[499] packed as
+ *   W1[16][10], b1[16], W2[16][16], b2[16], W3[3][16], b3[3]
+ *   (row-major (out, in)); input order [sum w c^d (3), sum w f (4), d (3)].
+ *
+ * Sample lattice and placement (Sec. 4.1 Eq. 6-7, Sec. 4.4)
+ * ---------------------------------------------------------
+ * Samples sit at t_k = k * delta (k = 0 .. 2^24 - 1) from the ray origin.
+ * The point is p = fl32(o + fl32(t_k * d)) (binary32, no fused multiply-add).
+ * Sample k is accepted iff p lies in the closed box and
+ * z_min[j][i] <= p_z <= z_max[j][i], where (i, j) is the occupancy cell that
+ * contains p's xy (half-open cells, far face in the last cell).  The first
+ * n_max accepted samples in increasing k are used.
+ *
+ * Compositing and output (Eq. 1, Eq. 4)
+ * -------------------------------------
+ * a_i = exp(t0_i) * delta, alpha_i = 1 - exp(-a_i), T_i = exp(-sum_{j<i} a_j),
+ * w_i = T_i alpha_i; F = [sum w c^d, sum w f]; T_n = transmittance after the
+ * last evaluated sample; C = sum w c^d + [n_eval > 0] G(F, d) + T_n c_bg.
+ * With t_term > 0 a ray stops after the first sample whose following
+ * transmittance drops below t_term.
+ */
+#ifndef OMERF_H
+#define OMERF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define OM_OK 0
+#define OM_ERR_INVALID (-1)      /* bad pointer, size or parameter        */
+#define OM_ERR_UNSUPPORTED (-2)  /* shape / dtype the kernels do not take */
+#define OM_ERR_HIP (-3)          /* the HIP runtime reported an error     */
+
+/* Storage types of the feature grid and planes. */
+#define OM_F32 0
+#define OM_BF16 1
+
+#define OM_MLP_NPARAMS 499
+#define OM_CHANNELS 8
+#define OM_MAX_SAMPLES 1024       /* largest n_max the kernels accept   */
+
+typedef struct om_scene om_scene; /* opaque handle, host metadata only */
+
+/*
+ * Scene description.  The device pointers are BORROWED: the handle keeps
+ * them, the caller keeps ownership and must keep the memory alive (and
+ * unchanged while a call using it runs).
+ * Preconditions checked by om_scene_create / om_scene_update:
+ *  - box_hi > box_lo on every axis; each extent (box_hi - box_lo) is a power
+ *    of two, so that interpolation coordinates are exact scalings;
+ *  - grid_dims >= 2 and plane_dims >= 2 per axis; occ_dims >= 1;
+ *  - occ_dims[a] / (box_hi[a] - box_lo[a]) is a power of two and
+ *    box_lo[a] * occ_dims[a] / (box_hi[a] - box_lo[a]) an integer (a = x, y),
+ *    so the containing occupancy cell is an exact floor;
+ *  - every feature source has fewer than 2^31 vertices;
+ *  - dtype is OM_F32 or OM_BF16 (bf16 = the upper 16 bits of a binary32);
+ *  - all pointers non-NULL and 16-byte aligned.
+ */
+typedef struct om_scene_desc {
+    float box_lo[3];
+    float box_hi[3];
+    int32_t grid_dims[3];   /* Lx, Ly, Lz */
+    int32_t plane_dims[3];  /* Nx, Ny, Nz */
+    int32_t occ_dims[2];    /* Mx, My     */
+    int32_t dtype;          /* OM_F32 or OM_BF16 */
+    const void* grid;       /* device, [Lz][Ly][Lx][8] of dtype */
+    const void* plane_xy;   /* device, [Ny][Nx][8] of dtype     */
+    const void* plane_xz;   /* device, [Nz][Nx][8] of dtype     */
+    const void* plane_yz;   /* device, [Nz][Ny][8] of dtype     */
+    const float* occ;       /* device, [My][Mx][2] float32      */
+    const float* mlp;       /* device, float32[499]             */
+} om_scene_desc;
+
+/* Per-call render parameters. */
+typedef struct om_params {
+    float delta;      /* lattice step; must be a positive power of two      */
+    int32_t n_max;    /* samples kept per ray, 1 .. OM_MAX_SAMPLES          */
+    float t_term;     /* early-termination threshold, 0 = never stop        */
+    float c_bg[3];    /* background colour                                  */
+    int32_t mlp_bf16; /* 0: float32 MLP; 1: bfloat16 MLP on MFMA with
+                         float32 accumulation; -1: follow the scene dtype   */
+} om_params;
+
+/* Forward outputs, all device pointers, all REQUIRED (the backward pass
+ * reads F, T and n_eval back).  C [n][3], T [n], F [n][7], n_placed [n],
+ * n_eval [n].  With t_term > 0, n_placed counts the samples placed up to
+ * termination; with t_term = 0 it is the full placed count. */
+typedef struct om_fwd_out {
+    float* C;
+    float* T;
+    float* F;
+    int32_t* n_placed;
+    int32_t* n_eval;
+} om_fwd_out;
+
+/* Gradient buffers (device, float32, caller-zeroed or holding a running
+ * sum: the backward pass ACCUMULATES into them).  Shapes match the scene:
+ * grid [Lz][Ly][Lx][8], planes as the scene, mlp [499]. */
+typedef struct om_grads {
+    float* grid;
+    float* plane_xy;
+    float* plane_xz;
+    float* plane_yz;
+    float* mlp;
+} om_grads;
+
+/* Create a scene handle from `desc` (validated as above).  On success
+ * *out holds a new handle to be released with om_scene_destroy.  Cites:
+ * representation of Sec. 3 (Eq. 2) and the occupancy plane of Sec. 4.1. */
+int om_scene_create(const om_scene_desc* desc, om_scene** out);
+
+/* Re-point an existing handle at new tensors (e.g. after an optimiser step
+ * or a bf16 re-cast); same validation as om_scene_create.  The handle is
+ * unchanged if validation fails.  Must not race with calls using it. */
+int om_scene_update(om_scene* scene, const om_scene_desc* desc);
+
+/* Release a handle (never the tensors).  NULL is accepted. */
+int om_scene_destroy(om_scene* scene);
+
+/*
+ * Sample placement only (Sec. 4.1 Eq. 6-7, Sec. 4.4), for inspection and
+ * parity tests.  o, d: device float32 [n][3].  k_out: device int32
+ * [n][n_max] receiving the accepted lattice indices in increasing order,
+ * padded with -1.  n_placed: device int32 [n].  n = 0 is a no-op.
+ * p->t_term and p->c_bg are ignored.
+ */
+int om_place_samples(const om_scene* scene, const float* o, const float* d, int64_t n,
+                     const om_params* p, int32_t* k_out, int32_t* n_placed, void* stream);
+
+/*
+ * Forward render of n rays (Sec. 3 Eq. 1-4 with the occupancy-plane
+ * sampling of Sec. 4.1 / 4.4).  o, d: device float32 [n][3]; out: see
+ * om_fwd_out.  Deterministic: no atomics, identical results run to run.
+ * Rays with non-finite o or d place no sample and return C = c_bg.
+ */
+int om_render(const om_scene* scene, const float* o, const float* d, int64_t n,
+              const om_params* p, const om_fwd_out* out, void* stream);
+
+/*
+ * The two stages of om_render, callable separately (same arguments and
+ * outputs; om_render == om_march followed by om_deferred_mlp):
+ *  - om_march: placement, feature gather, activations and compositing
+ *    (Sec. 4.1 / 4.4, Eq. 1-3); writes out->F, out->T, out->n_placed,
+ *    out->n_eval (out->C is not touched and may be NULL);
+ *  - om_deferred_mlp: the deferred MLP and final colour (Eq. 4); reads
+ *    out->F, out->T, out->n_eval and d, writes out->C.
+ */
+int om_march(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+             const om_fwd_out* out, void* stream);
+int om_deferred_mlp(const om_scene* scene, const float* d, int64_t n, const om_params* p,
+                    const om_fwd_out* out, void* stream);
+
+/*
+ * Backward of om_render for a per-ray colour loss (derived from Eq. 1-4).
+ * saved: the om_fwd_out written by om_render for the same scene, rays and
+ * parameters (C is not read).  dL_dC: device float32 [n][3].  Gradients are
+ * ADDED with float32 atomics into g (grid, planes, MLP; no ray gradient);
+ * per-sample features are recomputed, not stored.  Summation order of the
+ * atomics is not deterministic.  The MLP part is differentiated in float32
+ * regardless of p->mlp_bf16.
+ */
+int om_render_backward(const om_scene* scene, const float* o, const float* d, int64_t n,
+                       const om_params* p, const om_fwd_out* saved, const float* dL_dC,
+                       const om_grads* g, void* stream);
+
+/*
+ * L2 loss in float64, for finite-difference gradient checks:
+ * *out = sum over n rays and 3 channels of (C - target)^2 / (3 n).
+ * C, target: device float32 [n][3]; out: device double[1] (overwritten).
+ */
+int om_l2_loss_fp64(const float* C, const float* target, int64_t n, double* out, void* stream);
+
+/*
+ * Gradient of the same L2 loss with respect to C, for a training step that
+ * stays inside the library: dL_dC[r][c] = 2 (C[r][c] - target[r][c]) / (3 n).
+ * C, target, dL_dC: device float32 [n][3] (dL_dC may alias neither input).
+ * loss_out: optional device double[1] that receives the float64 loss
+ * (overwritten), or NULL.
+ */
+int om_l2_loss_grad(const float* C, const float* target, int64_t n, float* dL_dC,
+                    double* loss_out, void* stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* om_last_error(void);
+
+/* Static description of a status code. */
+const char* om_status_str(int status);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int om_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OMERF_H */

@@ -1,0 +1,267 @@
+"""MI355X-native (gfx950) occupancy-plane ray marcher of Oblique-MERF (arXiv 2404.09531).
+
+Python surface over the C ABI (include/omerf.h, libomerf.so):
+
+* :class:`Scene` -- a MERF scene (3D grid + XY/XZ/YZ planes, Sec. 3 Eq. 2),
+  its occupancy plane (Sec. 4.1) and the deferred MLP (Eq. 4), as device
+  tensors borrowed by a library handle;
+* :func:`place_samples` -- the samples the marcher places (Sec. 4.1 Eq. 6-7);
+* :func:`render` -- forward render (Eq. 1-4);
+* :func:`render_backward` -- gradients into grid, planes and MLP;
+* :class:`RenderFn` -- ``torch.autograd.Function`` over render/backward;
+* :func:`l2_loss_fp64`, :func:`l2_loss_grad` -- loss kernels.
+
+All computation runs in the library's HIP kernels on the caller's current
+stream; these wrappers only check tensor metadata and marshal pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Dict, Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import OM_BF16, OM_F32, OM_MAX_SAMPLES, OmerfError
+
+DELTA = 0.25 / 512  # lattice step: box height / 512 (2^-11)
+MLP_NPARAMS = 499
+
+__all__ = ["Scene", "place_samples", "render", "render_backward", "RenderFn", "l2_loss_fp64", "l2_loss_grad",
+           "DELTA", "OmerfError", "OM_MAX_SAMPLES", "to_bf16"]
+
+
+def _need(t: torch.Tensor, name: str, dtype, shape=None) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a HIP device, got {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def to_bf16(t: torch.Tensor) -> torch.Tensor:
+    """bfloat16 shadow of a float32 tensor (round to nearest even)."""
+    return t.to(torch.bfloat16).contiguous()
+
+
+class Scene:
+    """Library handle over borrowed device tensors.
+
+    grid [Lz,Ly,Lx,8], plane_xy [Ny,Nx,8], plane_xz [Nz,Nx,8], plane_yz
+    [Nz,Ny,8] (all float32 or all bfloat16), occ float32 [My,Mx,2],
+    mlp float32 [499].  The tensors are referenced (kept alive) by the
+    Scene, never copied."""
+
+    def __init__(self, grid, plane_xy, plane_xz, plane_yz, occ, mlp,
+                 box_lo: Sequence[float] = (-1.0, -1.0, 0.0), box_hi: Sequence[float] = (1.0, 1.0, 0.25)):
+        self._handle = ctypes.c_void_p()
+        self._set(grid, plane_xy, plane_xz, plane_yz, occ, mlp, box_lo, box_hi)
+        _lib.check("om_scene_create", _lib.lib().om_scene_create(ctypes.byref(self._desc), ctypes.byref(self._handle)))
+
+    def _set(self, grid, plane_xy, plane_xz, plane_yz, occ, mlp, box_lo, box_hi):
+        dt = grid.dtype
+        if dt not in (torch.float32, torch.bfloat16):
+            raise TypeError("grid/planes must be float32 or bfloat16")
+        lz, ly, lx, ch = grid.shape
+        if ch != 8:
+            raise ValueError("8 channels expected")
+        ny, nx = plane_xy.shape[:2]
+        nz = plane_xz.shape[0]
+        _need(grid, "grid", dt)
+        _need(plane_xy, "plane_xy", dt, (ny, nx, 8))
+        _need(plane_xz, "plane_xz", dt, (nz, nx, 8))
+        _need(plane_yz, "plane_yz", dt, (nz, ny, 8))
+        my, mx = occ.shape[:2]
+        _need(occ, "occ", torch.float32, (my, mx, 2))
+        _need(mlp, "mlp", torch.float32, (MLP_NPARAMS,))
+        d = _lib.OmSceneDesc()
+        d.box_lo[:] = list(box_lo)
+        d.box_hi[:] = list(box_hi)
+        d.grid_dims[:] = [lx, ly, lz]
+        d.plane_dims[:] = [nx, ny, nz]
+        d.occ_dims[:] = [mx, my]
+        d.dtype = OM_BF16 if dt == torch.bfloat16 else OM_F32
+        d.grid, d.plane_xy, d.plane_xz, d.plane_yz = grid.data_ptr(), plane_xy.data_ptr(), plane_xz.data_ptr(), \
+            plane_yz.data_ptr()
+        d.occ, d.mlp = occ.data_ptr(), mlp.data_ptr()
+        self._desc = d
+        self.tensors = dict(grid=grid, plane_xy=plane_xy, plane_xz=plane_xz, plane_yz=plane_yz, occ=occ, mlp=mlp)
+        self.dtype = dt
+        self.device = grid.device
+
+    def update(self, **tensors) -> None:
+        """Re-point the handle at new tensors (same keys as the constructor)."""
+        t = dict(self.tensors)
+        t.update(tensors)
+        old = (self._desc, self.tensors, self.dtype)
+        self._set(t["grid"], t["plane_xy"], t["plane_xz"], t["plane_yz"], t["occ"], t["mlp"],
+                  tuple(self._desc.box_lo), tuple(self._desc.box_hi))
+        rc = _lib.lib().om_scene_update(self._handle, ctypes.byref(self._desc))
+        if rc != 0:
+            self._desc, self.tensors, self.dtype = old
+            _lib.check("om_scene_update", rc)
+
+    @property
+    def handle(self):
+        return self._handle
+
+    def __del__(self):
+        h = getattr(self, "_handle", None)
+        if h is not None and h.value:
+            try:
+                _lib.lib().om_scene_destroy(h)
+            except Exception:
+                pass
+            self._handle = ctypes.c_void_p()
+
+
+def _params(n_max: int, delta: float, t_term: float, c_bg, mlp_bf16: int) -> _lib.OmParams:
+    p = _lib.OmParams()
+    p.delta = delta
+    p.n_max = int(n_max)
+    p.t_term = float(t_term)
+    p.c_bg[:] = [float(v) for v in c_bg]
+    p.mlp_bf16 = int(mlp_bf16)
+    return p
+
+
+def _rays(scene: Scene, o: torch.Tensor, d: torch.Tensor) -> int:
+    n = o.shape[0]
+    _need(o, "o", torch.float32, (n, 3))
+    _need(d, "d", torch.float32, (n, 3))
+    if o.device != scene.device:
+        raise ValueError("rays and scene must be on the same device")
+    return n
+
+
+def place_samples(scene: Scene, o, d, n_max: int, delta: float = DELTA):
+    """Accepted lattice indices per ray (int32 [n, n_max], -1 padded) and counts."""
+    n = _rays(scene, o, d)
+    k = torch.empty((n, n_max), dtype=torch.int32, device=o.device)
+    cnt = torch.empty((n,), dtype=torch.int32, device=o.device)
+    p = _params(n_max, delta, 0.0, (0, 0, 0), -1)
+    _lib.check("om_place_samples", _lib.lib().om_place_samples(scene.handle, o.data_ptr(), d.data_ptr(), n,
+                                                                 ctypes.byref(p), k.data_ptr(), cnt.data_ptr(),
+                                                                 _lib.stream_of(o)))
+    return k, cnt
+
+
+def render(scene: Scene, o, d, n_max: int, delta: float = DELTA, t_term: float = 0.0,
+           c_bg=(0.0, 0.0, 0.0), mlp_bf16: int = -1) -> Dict[str, torch.Tensor]:
+    """Forward render; returns C [n,3], T [n], F [n,7], n_placed [n], n_eval [n]."""
+    n = _rays(scene, o, d)
+    dev = o.device
+    out = dict(C=torch.empty((n, 3), dtype=torch.float32, device=dev),
+               T=torch.empty((n,), dtype=torch.float32, device=dev),
+               F=torch.empty((n, 7), dtype=torch.float32, device=dev),
+               n_placed=torch.empty((n,), dtype=torch.int32, device=dev),
+               n_eval=torch.empty((n,), dtype=torch.int32, device=dev))
+    render_into(scene, o, d, out, n_max, delta, t_term, c_bg, mlp_bf16)
+    return out
+
+
+def _fwd_out(out):
+    return _lib.OmFwdOut(_lib.ptr(out.get("C")), out["T"].data_ptr(), out["F"].data_ptr(),
+                         _lib.ptr(out.get("n_placed")), out["n_eval"].data_ptr())
+
+
+def render_into(scene: Scene, o, d, out: Dict[str, torch.Tensor], n_max: int, delta: float = DELTA,
+                t_term: float = 0.0, c_bg=(0.0, 0.0, 0.0), mlp_bf16: int = -1, stage: str = "all") -> None:
+    """Forward render into preallocated outputs (same keys as render()).
+
+    stage="all" runs om_render; "march" only om_march (F, T, counts);
+    "mlp" only om_deferred_mlp (C from F, T, n_eval)."""
+    n = o.shape[0]
+    fo = _fwd_out(out)
+    p = _params(n_max, delta, t_term, c_bg, mlp_bf16)
+    L = _lib.lib()
+    st = _lib.stream_of(o)
+    if stage == "all":
+        _lib.check("om_render", L.om_render(scene.handle, o.data_ptr(), d.data_ptr(), n, ctypes.byref(p),
+                                            ctypes.byref(fo), st))
+    elif stage == "march":
+        _lib.check("om_march", L.om_march(scene.handle, o.data_ptr(), d.data_ptr(), n, ctypes.byref(p),
+                                          ctypes.byref(fo), st))
+    elif stage == "mlp":
+        _lib.check("om_deferred_mlp", L.om_deferred_mlp(scene.handle, d.data_ptr(), n, ctypes.byref(p),
+                                                        ctypes.byref(fo), st))
+    else:
+        raise ValueError(stage)
+
+
+def render_backward(scene: Scene, o, d, saved: Dict[str, torch.Tensor], dL_dC, grads: Dict[str, torch.Tensor],
+                    n_max: int, delta: float = DELTA, t_term: float = 0.0, c_bg=(0.0, 0.0, 0.0)) -> None:
+    """Accumulate dL/d(grid, planes, mlp) into float32 `grads` (keys grid,
+    plane_xy, plane_xz, plane_yz, mlp) given dL/dC and the forward's outputs."""
+    n = _rays(scene, o, d)
+    _need(dL_dC, "dL_dC", torch.float32, (n, 3))
+    for key in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp"):
+        _need(grads[key], f"grads[{key}]", torch.float32, scene.tensors[key].shape)
+    fo = _lib.OmFwdOut(saved["C"].data_ptr(), saved["T"].data_ptr(), saved["F"].data_ptr(),
+                       saved["n_placed"].data_ptr(), saved["n_eval"].data_ptr())
+    g = _lib.OmGrads(grads["grid"].data_ptr(), grads["plane_xy"].data_ptr(), grads["plane_xz"].data_ptr(),
+                     grads["plane_yz"].data_ptr(), grads["mlp"].data_ptr())
+    p = _params(n_max, delta, t_term, c_bg, -1)
+    _lib.check("om_render_backward", _lib.lib().om_render_backward(
+        scene.handle, o.data_ptr(), d.data_ptr(), n, ctypes.byref(p), ctypes.byref(fo), dL_dC.data_ptr(),
+        ctypes.byref(g), _lib.stream_of(o)))
+
+
+def l2_loss_fp64(C, target) -> torch.Tensor:
+    """float64 mean over rays x 3 of (C - target)^2, as a 1-element device tensor."""
+    n = C.shape[0]
+    _need(C, "C", torch.float32, (n, 3))
+    _need(target, "target", torch.float32, (n, 3))
+    out = torch.empty((1,), dtype=torch.float64, device=C.device)
+    _lib.check("om_l2_loss_fp64", _lib.lib().om_l2_loss_fp64(C.data_ptr(), target.data_ptr(), n, out.data_ptr(),
+                                                               _lib.stream_of(C)))
+    return out
+
+
+def l2_loss_grad(C, target, dL_dC: Optional[torch.Tensor] = None, with_loss: bool = True):
+    """dL/dC of the mean L2 loss (and the float64 loss if with_loss)."""
+    n = C.shape[0]
+    _need(C, "C", torch.float32, (n, 3))
+    _need(target, "target", torch.float32, (n, 3))
+    if dL_dC is None:
+        dL_dC = torch.empty_like(C)
+    loss = torch.empty((1,), dtype=torch.float64, device=C.device) if with_loss else None
+    _lib.check("om_l2_loss_grad", _lib.lib().om_l2_loss_grad(C.data_ptr(), target.data_ptr(), n, dL_dC.data_ptr(),
+                                                               _lib.ptr(loss), _lib.stream_of(C)))
+    return dL_dC, loss
+
+
+class RenderFn(torch.autograd.Function):
+    """C = render(scene) with gradients into float32 master tensors.
+
+    ``RenderFn.apply(scene, o, d, opts, grid, plane_xy, plane_xz, plane_yz, mlp)``:
+    the render reads the tensors the Scene points at (the float32 masters
+    themselves, or bfloat16 shadows of them); the gradients are float32 and
+    are returned for the master tensors passed as the last five inputs.
+    opts = dict(n_max=..., delta=..., t_term=..., c_bg=..., mlp_bf16=...)."""
+
+    @staticmethod
+    def forward(ctx, scene, o, d, opts, grid, plane_xy, plane_xz, plane_yz, mlp):
+        out = render(scene, o, d, **opts)
+        ctx.scene, ctx.opts = scene, opts
+        ctx.masters = (grid, plane_xy, plane_xz, plane_yz, mlp)
+        ctx.save_for_backward(o, d, out["C"], out["T"], out["F"], out["n_placed"], out["n_eval"])
+        ctx.mark_non_differentiable(out["T"], out["F"], out["n_placed"], out["n_eval"])
+        return out["C"], out["T"], out["F"], out["n_placed"], out["n_eval"]
+
+    @staticmethod
+    def backward(ctx, gC, *_unused):
+        o, d, C, T, F, npl, nev = ctx.saved_tensors
+        saved = dict(C=C, T=T, F=F, n_placed=npl, n_eval=nev)
+        grads = {k: torch.zeros(m.shape, dtype=torch.float32, device=m.device)
+                 for k, m in zip(("grid", "plane_xy", "plane_xz", "plane_yz", "mlp"), ctx.masters)}
+        opts = {k: v for k, v in ctx.opts.items() if k != "mlp_bf16"}
+        render_backward(ctx.scene, o, d, saved, gC.contiguous().float(), grads, **opts)
+        return (None, None, None, None, grads["grid"], grads["plane_xy"], grads["plane_xz"], grads["plane_yz"],
+                grads["mlp"])

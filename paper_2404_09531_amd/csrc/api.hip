@@ -1,0 +1,313 @@
+// api.hip -- C ABI of the ray marcher (declared in include/omerf.h):
+// argument validation, scene handles, launch sequencing and error strings.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/omerf.h"
+#include "omerf_device.h"
+#include "omerf_launch.h"
+
+using namespace omerf;
+
+struct om_scene {
+    om_scene_desc desc;
+    SceneDev dev;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() {
+    g_err.clear();
+    return OM_OK;
+}
+
+bool pow2(double v) {
+    if (!(v > 0.0) || !std::isfinite(v)) return false;
+    int e;
+    return std::frexp(v, &e) == 0.5;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// u = p * (n - 1)/(hi - lo) - lo * (n - 1)/(hi - lo), split as p * s + (ci + cf).
+int make_axis(float lo, float hi, int n, const char* name, AxisMap* m) {
+    const double ext = (double)hi - (double)lo;
+    const double s = (double)(n - 1) / ext;
+    const double c = -(double)lo * s;
+    if ((double)(float)s != s) return fail(OM_ERR_UNSUPPORTED, "%s: scale (n-1)/extent not exact in binary32", name);
+    if ((double)(float)c != c) return fail(OM_ERR_UNSUPPORTED, "%s: offset -lo*(n-1)/extent not exact in binary32", name);
+    if (std::fmax(std::fabs((double)lo), std::fabs((double)hi)) * s >= 4194304.0)
+        return fail(OM_ERR_UNSUPPORTED, "%s: coordinate range too large for exact splitting", name);
+    m->s = (float)s;
+    const double ci = std::floor(c);
+    m->ci = (int)ci;
+    m->cf = (float)(c - ci);
+    m->n = n;
+    return OM_OK;
+}
+
+int validate_desc(const om_scene_desc* d, SceneDev* out) {
+    if (!d) return fail(OM_ERR_INVALID, "scene descriptor is NULL");
+    const float* lo = d->box_lo;
+    const float* hi = d->box_hi;
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(lo[a]) || !std::isfinite(hi[a]) || !(hi[a] > lo[a]))
+            return fail(OM_ERR_INVALID, "box axis %d: need finite lo < hi", a);
+        if (!pow2((double)hi[a] - (double)lo[a]))
+            return fail(OM_ERR_UNSUPPORTED, "box axis %d: extent must be a power of two", a);
+        if (d->grid_dims[a] < 2 || d->plane_dims[a] < 2)
+            return fail(OM_ERR_INVALID, "axis %d: grid and plane dims must be >= 2", a);
+    }
+    const int64_t nv = (int64_t)d->grid_dims[0] * d->grid_dims[1] * d->grid_dims[2];
+    const int64_t nxy = (int64_t)d->plane_dims[0] * d->plane_dims[1];
+    const int64_t nxz = (int64_t)d->plane_dims[0] * d->plane_dims[2];
+    const int64_t nyz = (int64_t)d->plane_dims[1] * d->plane_dims[2];
+    if (nv >= (int64_t)1 << 31 || nxy >= (int64_t)1 << 31 || nxz >= (int64_t)1 << 31 || nyz >= (int64_t)1 << 31)
+        return fail(OM_ERR_UNSUPPORTED, "feature sources must have fewer than 2^31 vertices");
+    for (int a = 0; a < 2; ++a) {
+        const int m = d->occ_dims[a];
+        if (m < 1) return fail(OM_ERR_INVALID, "occupancy dim %d must be >= 1", a);
+        const double s = (double)m / ((double)hi[a] - (double)lo[a]);
+        const double o = (double)lo[a] * s;
+        if (!pow2(s)) return fail(OM_ERR_UNSUPPORTED, "occupancy axis %d: cells per unit length must be a power of two", a);
+        if (o != std::floor(o) || std::fabs(o) >= 16777216.0)
+            return fail(OM_ERR_UNSUPPORTED, "occupancy axis %d: box low corner must be an integer number of cells", a);
+    }
+    if ((int64_t)d->occ_dims[0] * d->occ_dims[1] >= (int64_t)1 << 31)
+        return fail(OM_ERR_UNSUPPORTED, "occupancy plane too large");
+    if (d->dtype != OM_F32 && d->dtype != OM_BF16) return fail(OM_ERR_UNSUPPORTED, "dtype must be OM_F32 or OM_BF16");
+    const void* ptrs[6] = {d->grid, d->plane_xy, d->plane_xz, d->plane_yz, d->occ, d->mlp};
+    const char* names[6] = {"grid", "plane_xy", "plane_xz", "plane_yz", "occ", "mlp"};
+    for (int i = 0; i < 6; ++i) {
+        if (!ptrs[i]) return fail(OM_ERR_INVALID, "%s pointer is NULL", names[i]);
+        if (!aligned16(ptrs[i])) return fail(OM_ERR_INVALID, "%s pointer is not 16-byte aligned", names[i]);
+    }
+    SceneDev s;
+    s.grid = d->grid;
+    s.pxy = d->plane_xy;
+    s.pxz = d->plane_xz;
+    s.pyz = d->plane_yz;
+    s.occ = reinterpret_cast<const float2*>(d->occ);
+    s.mlp = d->mlp;
+    s.Lx = d->grid_dims[0];
+    s.Ly = d->grid_dims[1];
+    s.Lz = d->grid_dims[2];
+    s.Nx = d->plane_dims[0];
+    s.Ny = d->plane_dims[1];
+    s.Nz = d->plane_dims[2];
+    s.Mx = d->occ_dims[0];
+    s.My = d->occ_dims[1];
+    s.lo0 = lo[0];
+    s.lo1 = lo[1];
+    s.lo2 = lo[2];
+    s.hi0 = hi[0];
+    s.hi1 = hi[1];
+    s.hi2 = hi[2];
+    s.occ_sx = (float)((double)s.Mx / ((double)hi[0] - (double)lo[0]));
+    s.occ_sy = (float)((double)s.My / ((double)hi[1] - (double)lo[1]));
+    s.occ_ox = (float)((double)lo[0] * s.occ_sx);
+    s.occ_oy = (float)((double)lo[1] * s.occ_sy);
+    int rc;
+    if ((rc = make_axis(lo[0], hi[0], s.Lx, "grid x", &s.gx)) != OM_OK) return rc;
+    if ((rc = make_axis(lo[1], hi[1], s.Ly, "grid y", &s.gy)) != OM_OK) return rc;
+    if ((rc = make_axis(lo[2], hi[2], s.Lz, "grid z", &s.gz)) != OM_OK) return rc;
+    if ((rc = make_axis(lo[0], hi[0], s.Nx, "plane x", &s.px)) != OM_OK) return rc;
+    if ((rc = make_axis(lo[1], hi[1], s.Ny, "plane y", &s.py)) != OM_OK) return rc;
+    if ((rc = make_axis(lo[2], hi[2], s.Nz, "plane z", &s.pz)) != OM_OK) return rc;
+    *out = s;
+    return OM_OK;
+}
+
+int validate_params(const om_params* p, RayParams* rp) {
+    if (!p) return fail(OM_ERR_INVALID, "params pointer is NULL");
+    if (!pow2((double)p->delta)) return fail(OM_ERR_INVALID, "delta must be a positive power of two");
+    if (!std::isfinite((double)p->delta * 16777216.0)) return fail(OM_ERR_INVALID, "delta too large");
+    if (p->n_max < 1 || p->n_max > OM_MAX_SAMPLES)
+        return fail(OM_ERR_UNSUPPORTED, "n_max must be in [1, %d]", OM_MAX_SAMPLES);
+    if (!std::isfinite(p->t_term) || p->t_term < 0.0f) return fail(OM_ERR_INVALID, "t_term must be finite and >= 0");
+    if (p->mlp_bf16 < -1 || p->mlp_bf16 > 1) return fail(OM_ERR_INVALID, "mlp_bf16 must be -1, 0 or 1");
+    rp->delta = p->delta;
+    rp->n_max = p->n_max;
+    rp->t_term = p->t_term;
+    rp->bg0 = p->c_bg[0];
+    rp->bg1 = p->c_bg[1];
+    rp->bg2 = p->c_bg[2];
+    return OM_OK;
+}
+
+int check_rays(const om_scene* sc, const float* o, const float* d, int64_t n) {
+    if (!sc) return fail(OM_ERR_INVALID, "scene handle is NULL");
+    if (n < 0) return fail(OM_ERR_INVALID, "n must be >= 0");
+    if (n > ((int64_t)1 << 31) - 1) return fail(OM_ERR_UNSUPPORTED, "n must be below 2^31");
+    if (n > 0 && (!o || !d)) return fail(OM_ERR_INVALID, "ray pointers are NULL");
+    return OM_OK;
+}
+
+int hip_status(hipError_t e, const char* what) {
+    if (e != hipSuccess) return fail(OM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int om_scene_create(const om_scene_desc* desc, om_scene** out) {
+    if (!out) return fail(OM_ERR_INVALID, "output handle pointer is NULL");
+    *out = nullptr;
+    SceneDev dev;
+    int rc = validate_desc(desc, &dev);
+    if (rc != OM_OK) return rc;
+    om_scene* s = new (std::nothrow) om_scene;
+    if (!s) return fail(OM_ERR_INVALID, "out of host memory");
+    s->desc = *desc;
+    s->dev = dev;
+    *out = s;
+    return ok();
+}
+
+int om_scene_update(om_scene* scene, const om_scene_desc* desc) {
+    if (!scene) return fail(OM_ERR_INVALID, "scene handle is NULL");
+    SceneDev dev;
+    int rc = validate_desc(desc, &dev);
+    if (rc != OM_OK) return rc;
+    scene->desc = *desc;
+    scene->dev = dev;
+    return ok();
+}
+
+int om_scene_destroy(om_scene* scene) {
+    delete scene;
+    return ok();
+}
+
+int om_place_samples(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                     int32_t* k_out, int32_t* n_placed, void* stream) {
+    int rc = check_rays(scene, o, d, n);
+    if (rc != OM_OK) return rc;
+    RayParams rp;
+    if ((rc = validate_params(p, &rp)) != OM_OK) return rc;
+    if (n == 0) return ok();
+    if (!k_out || !n_placed) return fail(OM_ERR_INVALID, "output pointers are NULL");
+    if ((int64_t)n * rp.n_max >= ((int64_t)1 << 62)) return fail(OM_ERR_INVALID, "k_out too large");
+    return hip_status(launch_place(scene->dev, rp, o, d, n, k_out, n_placed, (hipStream_t)stream), "om_place_samples");
+}
+
+}  // extern "C"
+
+namespace {
+
+int check_fwd(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+              const om_fwd_out* out, bool need_o, bool need_C, RayParams* rp) {
+    int rc = check_rays(scene, need_o ? o : d, d, n);
+    if (rc != OM_OK) return rc;
+    if ((rc = validate_params(p, rp)) != OM_OK) return rc;
+    if (!out) return fail(OM_ERR_INVALID, "output struct is NULL");
+    if (n == 0) return OM_OK;
+    if ((need_C && !out->C) || (need_o && !out->n_placed) || !out->T || !out->F || !out->n_eval)
+        return fail(OM_ERR_INVALID, "required om_fwd_out buffers are NULL");
+    return OM_OK;
+}
+
+bool mlp_in_bf16(const om_scene* scene, const om_params* p) {
+    return p->mlp_bf16 < 0 ? scene->desc.dtype == OM_BF16 : p->mlp_bf16 == 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int om_march(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+             const om_fwd_out* out, void* stream) {
+    RayParams rp;
+    int rc = check_fwd(scene, o, d, n, p, out, true, false, &rp);
+    if (rc != OM_OK || n == 0) return rc == OM_OK ? ok() : rc;
+    const bool bf16 = scene->desc.dtype == OM_BF16;
+    return hip_status(launch_march_fwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_placed, out->n_eval,
+                                       (hipStream_t)stream), "om_march");
+}
+
+int om_deferred_mlp(const om_scene* scene, const float* d, int64_t n, const om_params* p, const om_fwd_out* out,
+                    void* stream) {
+    RayParams rp;
+    int rc = check_fwd(scene, nullptr, d, n, p, out, false, true, &rp);
+    if (rc != OM_OK || n == 0) return rc == OM_OK ? ok() : rc;
+    return hip_status(launch_mlp(scene->dev.mlp, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval,
+                                 out->C, (hipStream_t)stream), "om_deferred_mlp");
+}
+
+int om_render(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+              const om_fwd_out* out, void* stream) {
+    RayParams rp;
+    int rc = check_fwd(scene, o, d, n, p, out, true, true, &rp);
+    if (rc != OM_OK || n == 0) return rc == OM_OK ? ok() : rc;
+    const bool bf16 = scene->desc.dtype == OM_BF16;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_march_fwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_placed, out->n_eval, s);
+    if (e != hipSuccess) return hip_status(e, "om_render (march)");
+    e = launch_mlp(scene->dev.mlp, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval, out->C, s);
+    return hip_status(e, "om_render (mlp)");
+}
+
+int om_render_backward(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                       const om_fwd_out* saved, const float* dL_dC, const om_grads* g, void* stream) {
+    int rc = check_rays(scene, o, d, n);
+    if (rc != OM_OK) return rc;
+    RayParams rp;
+    if ((rc = validate_params(p, &rp)) != OM_OK) return rc;
+    if (!saved || !g) return fail(OM_ERR_INVALID, "saved / grads struct is NULL");
+    if (n == 0) return ok();
+    if (!saved->F || !saved->T || !saved->n_eval) return fail(OM_ERR_INVALID, "saved F, T and n_eval are required");
+    if (!dL_dC) return fail(OM_ERR_INVALID, "dL_dC is NULL");
+    if (!g->grid || !g->plane_xy || !g->plane_xz || !g->plane_yz || !g->mlp)
+        return fail(OM_ERR_INVALID, "all gradient buffers are required");
+    const bool bf16 = scene->desc.dtype == OM_BF16;
+    hipError_t e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, saved->F, saved->T, saved->n_eval, dL_dC, g->grid,
+                                    g->plane_xy, g->plane_xz, g->plane_yz, g->mlp, (hipStream_t)stream);
+    return hip_status(e, "om_render_backward");
+}
+
+int om_l2_loss_fp64(const float* C, const float* target, int64_t n, double* out, void* stream) {
+    if (n <= 0) return fail(OM_ERR_INVALID, "n must be > 0");
+    if (!C || !target || !out) return fail(OM_ERR_INVALID, "NULL pointer");
+    return hip_status(launch_l2(C, target, n, nullptr, out, (hipStream_t)stream), "om_l2_loss_fp64");
+}
+
+int om_l2_loss_grad(const float* C, const float* target, int64_t n, float* dL_dC, double* loss_out, void* stream) {
+    if (n <= 0) return fail(OM_ERR_INVALID, "n must be > 0");
+    if (!C || !target || !dL_dC) return fail(OM_ERR_INVALID, "NULL pointer");
+    if (dL_dC == C || dL_dC == target) return fail(OM_ERR_INVALID, "dL_dC must not alias C or target");
+    return hip_status(launch_l2(C, target, n, dL_dC, loss_out, (hipStream_t)stream), "om_l2_loss_grad");
+}
+
+const char* om_last_error(void) { return g_err.c_str(); }
+
+const char* om_status_str(int status) {
+    switch (status) {
+        case OM_OK: return "ok";
+        case OM_ERR_INVALID: return "invalid argument";
+        case OM_ERR_UNSUPPORTED: return "unsupported shape or dtype";
+        case OM_ERR_HIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+int om_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+// mlp.hip -- deferred view-dependent MLP (Eq. 4) and the L2 loss kernels.
+//
+// C = F[0:3] + [n_eval > 0] G(F, d) + T c_bg,  G = sigmoid(W3 relu(W2 relu(W1 x + b1) + b2) + b3),
+// x = [F (7), d (3)].
+//
+// k_mlp_f32      : one lane per ray, float32 FMA, weights read through the
+//                  scalar path (uniform addresses).
+// k_mlp_bf16     : bfloat16 operands on MFMA (v_mfma_f32_16x16x16_bf16) with
+//                  float32 accumulation, 16 rays per MFMA tile.  Each layer
+//                  is computed transposed, H^T = W X^T, with the weights as
+//                  the A operand: the accumulator layout of one layer (lane l
+//                  holds rows 4(l/16)..+3 of column l%16) is exactly the B
+//                  operand layout of the next, so no data moves between
+//                  layers.  Biases enter as the accumulator's initial value.
+#include "omerf_device.h"
+#include "omerf_launch.h"
+
+namespace omerf {
+
+__global__ __launch_bounds__(kBlock) void k_mlp_f32(const float* __restrict__ W, RayParams rp,
+                                                    const float* __restrict__ d_, int64_t n,
+                                                    const float* __restrict__ F, const float* __restrict__ T,
+                                                    const int32_t* __restrict__ n_eval, float* __restrict__ C) {
+    const int64_t r = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (r >= n) return;
+    float x[10];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) x[c] = F[r * 7 + c];
+    x[7] = d_[r * 3 + 0];
+    x[8] = d_[r * 3 + 1];
+    x[9] = d_[r * 3 + 2];
+    float h1[16], h2[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        float z = W[kB1 + j];
+#pragma unroll
+        for (int c = 0; c < 10; ++c) z += W[kW1 + j * 10 + c] * x[c];
+        h1[j] = fmaxf(z, 0.0f);
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        float z = W[kB2 + j];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) z += W[kW2 + j * 16 + c] * h1[c];
+        h2[j] = fmaxf(z, 0.0f);
+    }
+    const bool gate = n_eval[r] > 0;
+    const float t = T[r];
+    const float bg[3] = {rp.bg0, rp.bg1, rp.bg2};
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        float z = W[kB3 + o];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) z += W[kW3 + o * 16 + c] * h2[c];
+        const float g = gate ? sigmoidf_fast(z) : 0.0f;
+        C[r * 3 + o] = x[o] + g + t * bg[o];
+    }
+}
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float x) {
+    // round to nearest even
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
+    bf16x4 v;
+    v[0] = to_bf16(a);
+    v[1] = to_bf16(b);
+    v[2] = to_bf16(c);
+    v[3] = to_bf16(d);
+    return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mlp_bf16(const float* __restrict__ W, RayParams rp,
+                                                     const float* __restrict__ d_, int64_t n,
+                                                     const float* __restrict__ F, const float* __restrict__ T,
+                                                     const int32_t* __restrict__ n_eval, float* __restrict__ C) {
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15;  // ray within the tile / row of A
+    const int q = lane >> 4;    // k-block (A, B) / row-block (C, D)
+    // A operands: row `col`, k = 4q .. 4q+3 (zero padded).
+    float a1[4], a2[4], a3[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = 4 * q + j;
+        a1[j] = k < 10 ? W[kW1 + col * 10 + k] : 0.0f;
+        a2[j] = W[kW2 + col * 16 + k];
+        a3[j] = col < 3 ? W[kW3 + col * 16 + k] : 0.0f;
+    }
+    const bf16x4 A1 = pack4(a1[0], a1[1], a1[2], a1[3]);
+    const bf16x4 A2 = pack4(a2[0], a2[1], a2[2], a2[3]);
+    const bf16x4 A3 = pack4(a3[0], a3[1], a3[2], a3[3]);
+    // Accumulator initial values: bias of output row 4q + i.
+    f32x4 c1, c2, c3;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = 4 * q + i;
+        c1[i] = W[kB1 + m];
+        c2[i] = W[kB2 + m];
+        c3[i] = m < 3 ? W[kB3 + m] : 0.0f;
+    }
+    const int64_t tiles = (n + 15) / 16;
+    const int64_t wave = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t tile = wave; tile < tiles; tile += nwaves) {
+        const int64_t r = tile * 16 + col;
+        const bool valid = r < n;
+        // B operand of layer 1: x[k] of ray `col`, k = 4q .. 4q+3.
+        float xv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (valid) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 4 * q + j;
+                xv[j] = k < 7 ? F[r * 7 + k] : (k < 10 ? d_[r * 3 + (k - 7)] : 0.0f);
+            }
+        }
+        const bf16x4 B1 = pack4(xv[0], xv[1], xv[2], xv[3]);
+        f32x4 h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A1, B1, c1, 0, 0, 0);
+        const bf16x4 B2 = pack4(fmaxf(h[0], 0.0f), fmaxf(h[1], 0.0f), fmaxf(h[2], 0.0f), fmaxf(h[3], 0.0f));
+        h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A2, B2, c2, 0, 0, 0);
+        const bf16x4 B3 = pack4(fmaxf(h[0], 0.0f), fmaxf(h[1], 0.0f), fmaxf(h[2], 0.0f), fmaxf(h[3], 0.0f));
+        h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A3, B3, c3, 0, 0, 0);
+        // Rows 0..2 of the output live in lanes with q == 0; those lanes
+        // also hold F[0..3] of their ray in xv.
+        if (q == 0 && valid) {
+            const bool gate = n_eval[r] > 0;
+            const float t = T[r];
+            C[r * 3 + 0] = xv[0] + (gate ? sigmoidf_fast(h[0]) : 0.0f) + t * rp.bg0;
+            C[r * 3 + 1] = xv[1] + (gate ? sigmoidf_fast(h[1]) : 0.0f) + t * rp.bg1;
+            C[r * 3 + 2] = xv[2] + (gate ? sigmoidf_fast(h[2]) : 0.0f) + t * rp.bg2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// L2 loss in float64 (finite-difference checks) and its gradient.
+// ---------------------------------------------------------------------------
+__global__ void k_zero_f64(double* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_l2(const float* __restrict__ C, const float* __restrict__ tgt, int64_t n,
+                                               float* __restrict__ dC, double* __restrict__ loss) {
+    __shared__ double part[kBlock / 64];
+    const int64_t m = n * 3;
+    const double scale = 1.0 / (3.0 * (double)n);
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
+        const float e = C[i] - tgt[i];
+        if (dC) dC[i] = (float)(2.0 * scale) * e;
+        s += (double)e * (double)e;
+    }
+    if (!loss) return;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) t += part[w];
+        unsafeAtomicAdd(loss, t * scale);
+    }
+}
+
+hipError_t launch_mlp(const float* W, bool bf16, const RayParams& rp, const float* d, int64_t n, const float* F,
+                      const float* T, const int32_t* n_eval, float* C, hipStream_t s) {
+    if (bf16) {
+        const int64_t tiles = (n + 15) / 16;
+        int64_t blocks = (tiles + 3) / 4;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_mlp_bf16, dim3((unsigned)blocks), dim3(kBlock), 0, s, W, rp, d, n, F, T, n_eval, C);
+    } else {
+        const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_mlp_f32, dim3(blocks), dim3(kBlock), 0, s, W, rp, d, n, F, T, n_eval, C);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_l2(const float* C, const float* tgt, int64_t n, float* dC, double* loss, hipStream_t s) {
+    if (loss) hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, loss);
+    int64_t blocks = (n * 3 + kBlock - 1) / kBlock;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_l2, dim3((unsigned)blocks), dim3(kBlock), 0, s, C, tgt, n, dC, loss);
+    return hipGetLastError();
+}
+
+}  // namespace omerf

@@ -1,0 +1,263 @@
+// omerf_device.h -- device-side building blocks of the gfx950 ray marcher.
+//
+// Work decomposition: one ray per GROUP of 16 lanes (a DPP row of a
+// wave64), four rays per wavefront.  A group tests 16 consecutive lattice
+// candidates at once, compacts the accepted ones through a small per-group
+// LDS queue (ballot + prefix popcount), then shades full batches of 16
+// samples: one sample per lane, a 16-lane inclusive scan of the optical
+// depth gives each lane its transmittance.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace omerf {
+
+constexpr int kGroup = 16;            // lanes per ray
+constexpr int kBlock = 256;           // threads per block (4 waves)
+constexpr int kGroupsPerBlock = kBlock / kGroup;
+constexpr int kQueue = 2 * kGroup;    // per-group LDS queue capacity
+constexpr int kKCap = 1 << 24;        // lattice indices k in [0, 2^24)
+
+// Vertex-aligned coordinate along one axis: u = p * s + (ci + cf) with
+// s = (n - 1) / (hi - lo) a power-of-two scaling of an integer, ci integer,
+// cf in [0, 1).  n = number of vertices / texels on the axis.
+struct AxisMap {
+    float s;
+    float cf;
+    int ci;
+    int n;
+};
+
+struct SceneDev {
+    const void* grid;   // [Lz][Ly][Lx][8]
+    const void* pxy;    // [Ny][Nx][8]
+    const void* pxz;    // [Nz][Nx][8]
+    const void* pyz;    // [Nz][Ny][8]
+    const float2* occ;  // [My][Mx] (z_min, z_max)
+    const float* mlp;   // packed 499
+    int Lx, Ly, Lz, Nx, Ny, Nz, Mx, My;
+    float lo0, lo1, lo2, hi0, hi1, hi2;
+    float occ_sx, occ_sy, occ_ox, occ_oy;  // cell = floor(p * s) - o
+    AxisMap gx, gy, gz, px, py, pz;
+};
+
+struct RayParams {
+    float delta;
+    int n_max;
+    float t_term;
+    float bg0, bg1, bg2;
+};
+
+// MLP parameter offsets in the packed vector.
+constexpr int kW1 = 0, kB1 = 160, kW2 = 176, kB2 = 432, kW3 = 448, kB3 = 496;
+
+// ---------------------------------------------------------------------------
+// Lattice point and placement predicate (Sec. 4.1 Eq. 6-7 at epsilon = 0).
+// p = fl32(o + fl32(t_k * d)) with two roundings: contraction into an FMA is
+// switched off here so the discrete decision matches the binary32 definition.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float3 lattice_point(int k, float3 o, float3 d, float delta) {
+#pragma clang fp contract(off)
+    const float t = (float)k * delta;  // exact: k < 2^24, delta a power of two
+    float3 p;
+    p.x = o.x + t * d.x;
+    p.y = o.y + t * d.y;
+    p.z = o.z + t * d.z;
+    return p;
+}
+
+__device__ __forceinline__ bool accept_point(const SceneDev& sc, float3 p) {
+    const bool inb = p.x >= sc.lo0 && p.x <= sc.hi0 && p.y >= sc.lo1 && p.y <= sc.hi1 &&
+                     p.z >= sc.lo2 && p.z <= sc.hi2;
+    // p * s is exact (s a power of two); fmaxf maps NaN to 0, so the index
+    // is always in range.
+    const float fi = fminf(fmaxf(floorf(p.x * sc.occ_sx) - sc.occ_ox, 0.0f), (float)(sc.Mx - 1));
+    const float fj = fminf(fmaxf(floorf(p.y * sc.occ_sy) - sc.occ_oy, 0.0f), (float)(sc.My - 1));
+    const float2 z = sc.occ[(int)fj * sc.Mx + (int)fi];
+    return inb && p.z >= z.x && p.z <= z.y;
+}
+
+// Conservative candidate range [k_lo, k_hi] for the closed box: every k whose
+// binary32 point lies in the box is inside it (the exact predicate is applied
+// to each candidate afterwards).  Rounding of p is bounded by 2^-22 of the
+// magnitudes involved; the slab bounds are widened by 2^-20 of them and the
+// t range by a relative 2^-20 plus two lattice steps.
+struct KRange {
+    int lo, hi;
+};
+
+__device__ __forceinline__ void slab(float oa, float da, float lo, float hi, float& t0, float& t1, bool& empty) {
+    if (da == 0.0f) {
+        if (oa < lo || oa > hi) empty = true;
+        return;
+    }
+    const float eps = ldexpf(fabsf(oa) + fmaxf(fabsf(lo), fabsf(hi)) + 1.0f, -20);
+    const float inv = 1.0f / da;
+    float a = (lo - eps - oa) * inv;
+    float b = (hi + eps - oa) * inv;
+    if (da < 0.0f) {
+        const float s = a;
+        a = b;
+        b = s;
+    }
+    t0 = fmaxf(t0, a);
+    t1 = fminf(t1, b);
+}
+
+__device__ __forceinline__ KRange candidate_range(const SceneDev& sc, float3 o, float3 d, float delta) {
+    KRange r{0, -1};
+    const bool finite = isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(d.x) &&
+                        isfinite(d.y) && isfinite(d.z);
+    if (!finite) return r;
+    float t0 = 0.0f, t1 = (float)kKCap * delta;
+    bool empty = false;
+    slab(o.x, d.x, sc.lo0, sc.hi0, t0, t1, empty);
+    slab(o.y, d.y, sc.lo1, sc.hi1, t0, t1, empty);
+    slab(o.z, d.z, sc.lo2, sc.hi2, t0, t1, empty);
+    if (empty) return r;
+    t0 = t0 - fabsf(t0) * 0x1p-20f - 2.0f * delta;
+    t1 = t1 + fabsf(t1) * 0x1p-20f + 2.0f * delta;
+    if (!(t0 <= t1)) return r;
+    const float kmax = (float)(kKCap - 1);
+    const float klo = fminf(fmaxf(floorf(t0 / delta), 0.0f), kmax);
+    const float khi = fminf(fmaxf(ceilf(t1 / delta), -1.0f), kmax);
+    r.lo = (int)klo;
+    r.hi = (int)khi;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Interpolation coordinates, with the fractional part kept to ~1e-7 absolute
+// even on 4096-texel axes: the product p * s is split into its rounded value
+// and the exact FMA remainder before the integer part is removed.  Automatic
+// contraction is off here: fusing p * s into (hi - floor(hi)) would count the
+// remainder twice.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void axis_coord(float p, const AxisMap& m, int& i0, float& f) {
+#pragma clang fp contract(off)
+    const float hi = p * m.s;
+    const float lo = __builtin_fmaf(p, m.s, -hi);
+    const float ih = floorf(hi);
+    const float fr = ((hi - ih) + m.cf) + lo;
+    const float fl = floorf(fr);
+    const int i = (int)ih + m.ci + (int)fl;
+    const int ic = min(max(i, 0), m.n - 2);
+    f = (fr - fl) + (float)(i - ic);
+    i0 = ic;
+}
+
+// Storage policies: accumulate w * corner into t[8] / scatter g[8] * w.
+struct F32Store {
+    static __device__ __forceinline__ void acc(const void* base, uint32_t idx, float w, float* t) {
+        const float4* q = reinterpret_cast<const float4*>(base) + (size_t)idx * 2;
+        const float4 a = q[0];
+        const float4 b = q[1];
+        t[0] += w * a.x; t[1] += w * a.y; t[2] += w * a.z; t[3] += w * a.w;
+        t[4] += w * b.x; t[5] += w * b.y; t[6] += w * b.z; t[7] += w * b.w;
+    }
+};
+
+struct BF16Store {
+    static __device__ __forceinline__ float lo16(uint32_t v) { return __uint_as_float(v << 16); }
+    static __device__ __forceinline__ float hi16(uint32_t v) { return __uint_as_float(v & 0xffff0000u); }
+    static __device__ __forceinline__ void acc(const void* base, uint32_t idx, float w, float* t) {
+        const uint4 v = reinterpret_cast<const uint4*>(base)[idx];
+        t[0] += w * lo16(v.x); t[1] += w * hi16(v.x); t[2] += w * lo16(v.y); t[3] += w * hi16(v.y);
+        t[4] += w * lo16(v.z); t[5] += w * hi16(v.z); t[6] += w * lo16(v.w); t[7] += w * hi16(v.w);
+    }
+};
+
+// Corner set of one sample: 8 grid vertices + 3 x 4 plane texels.
+struct Corners {
+    uint32_t g, xy, xz, yz;  // base vertex / texel indices
+    float fx, fy, fz;        // grid fractions
+    float ux, uy, uz;        // plane fractions
+};
+
+__device__ __forceinline__ Corners corners_of(const SceneDev& sc, float3 p) {
+    Corners c;
+    int ix, iy, iz, jx, jy, jz;
+    axis_coord(p.x, sc.gx, ix, c.fx);
+    axis_coord(p.y, sc.gy, iy, c.fy);
+    axis_coord(p.z, sc.gz, iz, c.fz);
+    axis_coord(p.x, sc.px, jx, c.ux);
+    axis_coord(p.y, sc.py, jy, c.uy);
+    axis_coord(p.z, sc.pz, jz, c.uz);
+    c.g = ((uint32_t)iz * (uint32_t)sc.Ly + (uint32_t)iy) * (uint32_t)sc.Lx + (uint32_t)ix;
+    c.xy = (uint32_t)jy * (uint32_t)sc.Nx + (uint32_t)jx;
+    c.xz = (uint32_t)jz * (uint32_t)sc.Nx + (uint32_t)jx;
+    c.yz = (uint32_t)jz * (uint32_t)sc.Ny + (uint32_t)jy;
+    return c;
+}
+
+// Eq. 2: t = trilinear(V) + bilinear(P_xy) + bilinear(P_xz) + bilinear(P_yz).
+template <class S>
+__device__ __forceinline__ void gather_features(const SceneDev& sc, const Corners& c, float* t) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = 0.0f;
+    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
+    const float x0 = 1.0f - c.fx, x1 = c.fx, y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
+    S::acc(sc.grid, c.g, x0 * y0 * z0, t);
+    S::acc(sc.grid, c.g + 1, x1 * y0 * z0, t);
+    S::acc(sc.grid, c.g + sy, x0 * y1 * z0, t);
+    S::acc(sc.grid, c.g + sy + 1, x1 * y1 * z0, t);
+    S::acc(sc.grid, c.g + sz, x0 * y0 * z1, t);
+    S::acc(sc.grid, c.g + sz + 1, x1 * y0 * z1, t);
+    S::acc(sc.grid, c.g + sz + sy, x0 * y1 * z1, t);
+    S::acc(sc.grid, c.g + sz + sy + 1, x1 * y1 * z1, t);
+    const float a0 = 1.0f - c.ux, a1 = c.ux, b0 = 1.0f - c.uy, b1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
+    const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
+    S::acc(sc.pxy, c.xy, a0 * b0, t);
+    S::acc(sc.pxy, c.xy + 1, a1 * b0, t);
+    S::acc(sc.pxy, c.xy + nx, a0 * b1, t);
+    S::acc(sc.pxy, c.xy + nx + 1, a1 * b1, t);
+    S::acc(sc.pxz, c.xz, a0 * e0, t);
+    S::acc(sc.pxz, c.xz + 1, a1 * e0, t);
+    S::acc(sc.pxz, c.xz + nx, a0 * e1, t);
+    S::acc(sc.pxz, c.xz + nx + 1, a1 * e1, t);
+    S::acc(sc.pyz, c.yz, b0 * e0, t);
+    S::acc(sc.pyz, c.yz + 1, b1 * e0, t);
+    S::acc(sc.pyz, c.yz + ny, b0 * e1, t);
+    S::acc(sc.pyz, c.yz + ny + 1, b1 * e1, t);
+}
+
+__device__ __forceinline__ float sigmoidf_fast(float x) {
+    return __builtin_amdgcn_rcpf(1.0f + __expf(-x));
+}
+
+// ---------------------------------------------------------------------------
+// 16-lane group collectives.  All lanes of a group take the same branches,
+// so group members are always active together.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float g_scan_incl(float x, int gl) {
+#pragma unroll
+    for (int s = 1; s < kGroup; s <<= 1) {
+        const float y = __shfl_up(x, s, kGroup);
+        if (gl >= s) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ float g_sum(float x) {
+#pragma unroll
+    for (int m = kGroup / 2; m > 0; m >>= 1) x += __shfl_xor(x, m, kGroup);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t g_ballot(bool pred, int lane) {
+    const unsigned long long m = __ballot(pred);
+    return (uint32_t)(m >> (lane & (64 - kGroup))) & 0xffffu;
+}
+
+__device__ __forceinline__ void wave_order() { __builtin_amdgcn_wave_barrier(); }
+
+// Block index -> virtual block index such that the blocks the hardware
+// places on one XCD (round-robin over 8 XCDs) cover one contiguous range of
+// rays, keeping neighbouring rays in the same L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+    const uint32_t per = nb / 8, rem = nb % 8, x = b % 8, i = b / 8;
+    return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
+}  // namespace omerf

@@ -1,0 +1,130 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+declared in include/omerf.h, and rejects bad arguments with status codes
+before any device work (no pointer is dereferenced on these paths)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+import torch  # noqa: F401  (load torch's HIP runtime first, as the package does)
+
+from paper_2404_09531_amd import _lib
+from paper_2404_09531_amd.build import ensure_built
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x100000  # aligned, non-NULL, never dereferenced on these paths
+
+
+@pytest.fixture(scope="module")
+def L():
+    ensure_built()
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    hdr = open(os.path.join(ROOT, "include", "omerf.h")).read()
+    names = set(re.findall(r"^\s*(?:int|const char\*)\s+(om_\w+)\s*\(", hdr, re.M))
+    assert names == set(_lib.EXPORTS)
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.om_version() == 100
+    assert L.om_status_str(-2) == b"unsupported shape or dtype"
+
+
+def _desc(**kw):
+    d = _lib.OmSceneDesc()
+    d.box_lo[:] = [-1.0, -1.0, 0.0]
+    d.box_hi[:] = [1.0, 1.0, 0.25]
+    d.grid_dims[:] = [64, 64, 16]
+    d.plane_dims[:] = [256, 256, 64]
+    d.occ_dims[:] = [32, 32]
+    d.dtype = _lib.OM_F32
+    for f in ("grid", "plane_xy", "plane_xz", "plane_yz", "occ", "mlp"):
+        setattr(d, f, FAKE)
+    for k, v in kw.items():
+        if isinstance(getattr(d, k), ctypes.Array):
+            getattr(d, k)[:] = v
+        else:
+            setattr(d, k, v)
+    return d
+
+
+def _create(L, d):
+    h = ctypes.c_void_p()
+    rc = L.om_scene_create(ctypes.byref(d), ctypes.byref(h))
+    return rc, h
+
+
+def test_scene_validation(L):
+    rc, h = _create(L, _desc())
+    assert rc == 0 and h.value
+    assert L.om_scene_destroy(h) == 0
+    assert L.om_scene_destroy(None) == 0
+    bad = [
+        (dict(box_hi=[1.0, 1.0, 0.3]), _lib.OM_ERR_UNSUPPORTED),      # extent 0.3 not a power of two
+        (dict(box_hi=[-1.0, 1.0, 0.25]), _lib.OM_ERR_INVALID),        # empty box
+        (dict(grid_dims=[1, 64, 16]), _lib.OM_ERR_INVALID),
+        (dict(occ_dims=[24, 32]), _lib.OM_ERR_UNSUPPORTED),           # 12 cells / unit: not a power of two
+        (dict(occ_dims=[0, 32]), _lib.OM_ERR_INVALID),
+        (dict(dtype=7), _lib.OM_ERR_UNSUPPORTED),
+        (dict(grid=None), _lib.OM_ERR_INVALID),
+        (dict(occ=FAKE + 4), _lib.OM_ERR_INVALID),                    # misaligned
+        (dict(grid_dims=[2048, 2048, 1024]), _lib.OM_ERR_UNSUPPORTED),  # 2^32 vertices
+    ]
+    for kw, code in bad:
+        rc, h = _create(L, _desc(**kw))
+        assert rc == code, (kw, rc)
+        assert not h.value
+        assert len(L.om_last_error()) > 0
+    assert L.om_scene_create(None, ctypes.byref(ctypes.c_void_p())) == _lib.OM_ERR_INVALID
+
+
+def _params(**kw):
+    p = _lib.OmParams()
+    p.delta = 0.25 / 512
+    p.n_max = 64
+    p.t_term = 0.0
+    p.c_bg[:] = [0, 0, 0]
+    p.mlp_bf16 = -1
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_render_argument_errors(L):
+    rc, h = _create(L, _desc())
+    assert rc == 0
+    out = _lib.OmFwdOut(FAKE, FAKE, FAKE, FAKE, FAKE)
+    cases = [
+        (_params(delta=0.001), 4, _lib.OM_ERR_INVALID),
+        (_params(delta=-0.25), 4, _lib.OM_ERR_INVALID),
+        (_params(n_max=0), 4, _lib.OM_ERR_UNSUPPORTED),
+        (_params(n_max=_lib.OM_MAX_SAMPLES + 1), 4, _lib.OM_ERR_UNSUPPORTED),
+        (_params(t_term=float("nan")), 4, _lib.OM_ERR_INVALID),
+        (_params(t_term=-1.0), 4, _lib.OM_ERR_INVALID),
+        (_params(mlp_bf16=3), 4, _lib.OM_ERR_INVALID),
+        (_params(), -1, _lib.OM_ERR_INVALID),
+        (_params(), 1 << 31, _lib.OM_ERR_UNSUPPORTED),
+    ]
+    for p, n, code in cases:
+        assert L.om_render(h, FAKE, FAKE, n, ctypes.byref(p), ctypes.byref(out), None) == code
+    # n = 0 is a no-op that touches nothing
+    assert L.om_render(h, None, None, 0, ctypes.byref(_params()), ctypes.byref(out), None) == 0
+    missing = _lib.OmFwdOut(FAKE, 0, FAKE, FAKE, FAKE)
+    assert L.om_render(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(missing), None) == _lib.OM_ERR_INVALID
+    assert L.om_render(None, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(out), None) == _lib.OM_ERR_INVALID
+    g = _lib.OmGrads(FAKE, FAKE, FAKE, 0, FAKE)
+    assert L.om_render_backward(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(out), FAKE,
+                                ctypes.byref(g), None) == _lib.OM_ERR_INVALID
+    assert L.om_place_samples(h, FAKE, FAKE, 4, ctypes.byref(_params()), 0, FAKE, None) == _lib.OM_ERR_INVALID
+    assert L.om_l2_loss_fp64(FAKE, FAKE, 0, FAKE, None) == _lib.OM_ERR_INVALID
+    assert L.om_l2_loss_grad(FAKE, FAKE, 3, FAKE, None, None) == _lib.OM_ERR_INVALID  # aliasing
+    L.om_scene_destroy(h)
+
+
+def test_scene_update_keeps_handle_on_error(L):
+    rc, h = _create(L, _desc())
+    assert L.om_scene_update(h, ctypes.byref(_desc(occ_dims=[24, 32]))) == _lib.OM_ERR_UNSUPPORTED
+    assert L.om_scene_update(h, ctypes.byref(_desc(grid_dims=[8, 8, 8]))) == 0
+    L.om_scene_destroy(h)

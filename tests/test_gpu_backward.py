@@ -1,0 +1,147 @@
+"""GPU backward: gradients into grid, planes and MLP against the float64
+oracle gradient and against central finite differences of the GPU forward.
+
+Bars: per-entry relative error <= 1e-3 against the oracle gradient on
+entries with |g| >= 1e-3 max|g|; absolute error <= 1e-5 max|g| on the
+smaller entries, whose float32 sums of cancelling per-sample terms carry
+rounding relative to the terms rather than to the result; finite
+differences (eps = 1e-3, float64 loss reduction on the GPU) within
+|g - g_fd| <= 1e-3 max(|g_fd|, 1e-2 RMS of the checked entries).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2404_09531_amd as om
+import scenegen
+from tests.gpu_util import log, rays_to, upload_scene
+
+pytestmark = pytest.mark.gpu
+
+BG = (0.25, 0.5, 0.75)
+SOURCES = ("grid", "plane_xy", "plane_xz", "plane_yz")
+
+
+def _gpu_grads(scene, t, og, dg, target, n_max, t_term=0.0):
+    res = om.render(scene, og, dg, n_max=n_max, c_bg=BG, t_term=t_term)
+    dC, loss = om.l2_loss_grad(res["C"], target)
+    grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp")}
+    om.render_backward(scene, og, dg, res, dC, grads, n_max=n_max, c_bg=BG, t_term=t_term)
+    torch.cuda.synchronize()
+    return res, loss.item(), {k: v.double().cpu().numpy() for k, v in grads.items()}
+
+
+def _check_against_oracle(sc, grads, ref_grads, rel=1e-3):
+    for src in SOURCES:
+        uniq, rows = ref_grads[src]
+        g = grads[src].reshape(-1, 8)
+        got = g[uniq]
+        scale = max(np.abs(rows).max(), 1e-30)
+        big = np.abs(rows) >= 1e-3 * scale
+        err_big = np.abs(got - rows)[big] / np.abs(rows)[big]
+        assert err_big.max() <= rel, (src, err_big.max())
+        assert np.abs(got - rows)[~big].max(initial=0) <= 1e-5 * scale, src
+        mask = np.ones(g.shape[0], bool)
+        mask[uniq] = False
+        assert np.all(g[mask] == 0), f"{src}: gradient outside the touched rows"
+    gm, rm = grads["mlp"], ref_grads["mlp"]
+    big = np.abs(rm) >= 1e-3 * np.abs(rm).max()
+    assert (np.abs(gm - rm)[big] / np.abs(rm)[big]).max() <= rel
+    assert np.abs(gm - rm)[~big].max(initial=0) <= 1e-5 * np.abs(rm).max()
+
+
+@pytest.fixture(scope="module")
+def tiny_train():
+    sc = scenegen.make_scene(scenegen.TINY)
+    pert = scenegen.perturb_scene(sc, 0.05, seed=2)
+    o, d = scenegen.oblique_rays(256, seed=3)
+    prm = oracle.RenderParams(n_max=64, c_bg=BG)
+    target = oracle.oracle_render(pert, o, d, prm, keep_k=False)["C"]
+    scene, t = upload_scene(sc)
+    return sc, scene, t, o, d, target
+
+
+def test_backward_tiny_vs_oracle(tiny_train):
+    sc, scene, t, o, d, target = tiny_train
+    log("test_backward_tiny_vs_oracle: 256 rays")
+    og, dg = rays_to(o, d)
+    tg = torch.from_numpy(target.astype(np.float32)).to(og.device)
+    res, loss, grads = _gpu_grads(scene, t, og, dg, tg, 64)
+    ref_loss, ref_C, ref_grads = oracle.oracle_loss_and_grads(sc, o, d, oracle.RenderParams(n_max=64, c_bg=BG),
+                                                             target.astype(np.float32).astype(np.float64))
+    assert abs(loss - ref_loss) <= 1e-3 * ref_loss
+    _check_against_oracle(sc, grads, ref_grads)
+
+
+def test_backward_sum_invariant(tiny_train):
+    """Per channel the four sources' gradient totals are equal."""
+    sc, scene, t, o, d, target = tiny_train
+    log("test_backward_sum_invariant")
+    og, dg = rays_to(o, d)
+    tg = torch.from_numpy(target.astype(np.float32)).to(og.device)
+    _, _, grads = _gpu_grads(scene, t, og, dg, tg, 64)
+    sums = [grads[s].reshape(-1, 8).sum(0) for s in SOURCES]
+    for s in sums[1:]:
+        np.testing.assert_allclose(s, sums[0], rtol=1e-4, atol=1e-7)
+
+
+def test_backward_ert_matches_oracle(tiny_train):
+    sc, scene, t, o, d, target = tiny_train
+    log("test_backward_ert_matches_oracle: t_term=1e-2")
+    og, dg = rays_to(o, d)
+    tg = torch.from_numpy(target.astype(np.float32)).to(og.device)
+    res, loss, grads = _gpu_grads(scene, t, og, dg, tg, 64, t_term=1e-2)
+    prm = oracle.RenderParams(n_max=64, c_bg=BG, t_term=1e-2)
+    ref = oracle.oracle_render(sc, o, d, prm, keep_k=False)
+    if not np.array_equal(res["n_eval"].cpu().numpy(), ref["n_eval"]):
+        pytest.skip("a ray's transmittance sits at the threshold; gradients are compared with t_term=0")
+    _, _, ref_grads = oracle.oracle_loss_and_grads(sc, o, d, prm, target.astype(np.float32).astype(np.float64))
+    _check_against_oracle(sc, grads, ref_grads)
+
+
+def _pick_params(grads, per_source=12, mlp=16, seed=3):
+    """Entries with the largest |g| per tensor (well-conditioned FD), plus a
+    few random ones with nonzero gradient."""
+    rng = np.random.default_rng(seed)
+    picks = []
+    for src, k in ((s, per_source) for s in (*SOURCES, "mlp")):
+        k = mlp if src == "mlp" else k
+        g = np.abs(grads[src].reshape(-1))
+        top = np.argsort(g)[-(k - 2):]
+        nz = np.nonzero(g)[0]
+        extra = rng.choice(nz, 2, replace=False)
+        picks += [(src, int(i)) for i in np.concatenate([top, extra])]
+    return picks
+
+
+def _fd_check(scene, t, og, dg, tg, n_max, grads, eps=1e-3):
+    picks = _pick_params(grads)
+    fd, an = [], []
+    for src, e in picks:
+        flat = t[src].view(-1)
+        v0 = flat[e].item()
+        vals, steps = [], []
+        for s in (+1.0, -1.0):
+            flat[e] = v0 + s * eps
+            steps.append(flat[e].item())  # the binary32 value actually used
+            res = om.render(scene, og, dg, n_max=n_max, c_bg=BG)
+            vals.append(om.l2_loss_fp64(res["C"], tg).item())
+        flat[e] = v0
+        fd.append((vals[0] - vals[1]) / (steps[0] - steps[1]))
+        an.append(grads[src].reshape(-1)[e])
+    fd, an = np.array(fd), np.array(an)
+    rms = np.sqrt(np.mean(fd ** 2))
+    err = np.abs(an - fd) / np.maximum(np.abs(fd), 1e-2 * rms)
+    return picks, fd, an, err
+
+
+def test_backward_finite_differences_tiny(tiny_train):
+    sc, scene, t, o, d, target = tiny_train
+    log("test_backward_finite_differences_tiny")
+    og, dg = rays_to(o, d)
+    tg = torch.from_numpy(target.astype(np.float32)).to(og.device)
+    _, _, grads = _gpu_grads(scene, t, og, dg, tg, 64)
+    picks, fd, an, err = _fd_check(scene, t, og, dg, tg, 64, grads)
+    log(f"  FD: {len(picks)} params, max rel err {err.max():.2e}, median {np.median(err):.2e}")
+    assert err.max() <= 1e-3, [(p, f, a) for p, f, a, e in zip(picks, fd, an, err) if e > 1e-3]

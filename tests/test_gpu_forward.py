@@ -1,0 +1,206 @@
+"""GPU parity of the forward path (placement, march, MLP) against the CPU oracle.
+
+Bar: sample k-lists and counts bit-exact; float32 colours, F and T within
+1e-5 absolute of the float64 oracle; forward bit-identical run to run.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2404_09531_amd as om
+import scenegen
+from tests._scenes import micro_scene
+from tests.gpu_util import DEV, log, rays_to, upload_scene
+
+pytestmark = pytest.mark.gpu
+
+BG = (0.25, 0.5, 0.75)
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    sc = scenegen.make_scene(scenegen.TINY)
+    o, d = scenegen.oblique_rays(4096, seed=1)
+    scene, t = upload_scene(sc)
+    return sc, scene, t, o, d
+
+
+def _compare(res, ref, rows=None, tol=TOL):
+    rows = slice(None) if rows is None else rows
+    npl = res["n_placed"].cpu().numpy()[rows]
+    nev = res["n_eval"].cpu().numpy()[rows]
+    assert np.array_equal(npl, ref["n_placed"])
+    assert np.array_equal(nev, ref["n_eval"])
+    errs = {}
+    for key in ("C", "T", "F"):
+        got = res[key].double().cpu().numpy()[rows]
+        e = np.abs(got - ref[key]).reshape(got.shape[0], -1).max(axis=1) if got.size else np.zeros(0)
+        errs[key] = e
+        log(f"  max |{key} - oracle| = {e.max(initial=0):.3e}")
+    if errs["C"].size and errs["C"].max() > tol:
+        w = np.argsort(errs["C"])[-5:]
+        for i in w:
+            log(f"  worst ray {i}: C err {errs['C'][i]:.2e} F err {errs['F'][i]:.2e} T err {errs['T'][i]:.2e} "
+                f"n_eval {nev[i]} T {ref['T'][i]:.3e} F {np.round(ref['F'][i], 4)}")
+    for key in ("C", "T", "F"):
+        assert errs[key].max(initial=0) <= tol, (key, errs[key].max())
+
+
+def test_place_tiny_bit_exact(tiny):
+    sc, scene, t, o, d = tiny
+    log("test_place_tiny_bit_exact: 4096 rays, n_max=64")
+    og, dg = rays_to(o, d)
+    k, cnt = om.place_samples(scene, og, dg, n_max=64)
+    torch.cuda.synchronize()
+    kr, nr, _ = oracle.place_samples(o, d, sc["occ"], sc["box_lo"], sc["box_hi"], om.DELTA, 64)
+    assert np.array_equal(cnt.cpu().numpy(), nr)
+    assert np.array_equal(k.cpu().numpy(), kr)
+
+
+@pytest.mark.parametrize("n_max", [64, 1, 17, 300])
+def test_place_tiny_nmax_variants(tiny, n_max):
+    sc, scene, t, o, d = tiny
+    log(f"test_place_tiny_nmax_variants: n_max={n_max}")
+    og, dg = rays_to(o[:1000], d[:1000])
+    k, cnt = om.place_samples(scene, og, dg, n_max=n_max)
+    kr, nr, _ = oracle.place_samples(o[:1000], d[:1000], sc["occ"], sc["box_lo"], sc["box_hi"], om.DELTA, n_max)
+    assert np.array_equal(cnt.cpu().numpy(), nr)
+    assert np.array_equal(k.cpu().numpy(), kr)
+
+
+def test_render_tiny_parity(tiny):
+    sc, scene, t, o, d = tiny
+    log("test_render_tiny_parity: 4096 rays fp32")
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG)
+    torch.cuda.synchronize()
+    ref = oracle.oracle_render(sc, o, d, oracle.RenderParams(n_max=64, c_bg=BG), keep_k=False)
+    _compare(res, ref)
+
+
+def test_render_ragged_and_deterministic(tiny):
+    sc, scene, t, o, d = tiny
+    n = 4096 - 5  # not a multiple of the 16 rays per block
+    log(f"test_render_ragged_and_deterministic: {n} rays, n_max=200")
+    og, dg = rays_to(o[:n], d[:n])
+    a = om.render(scene, og, dg, n_max=200, c_bg=BG)
+    b = om.render(scene, og, dg, n_max=200, c_bg=BG)
+    torch.cuda.synchronize()
+    for key in a:
+        assert torch.equal(a[key], b[key]), key
+    ref = oracle.oracle_render(sc, o[:n], d[:n], oracle.RenderParams(n_max=200, c_bg=BG), keep_k=False)
+    _compare(a, ref)
+
+
+def test_render_empty_and_single():
+    log("test_render_empty_and_single")
+    sc = micro_scene(zmin=0.2, zmax=0.1, seed=1)
+    scene, t = upload_scene(sc)
+    o = np.array([[0.1, 0.2, 1.0], [-2, 0, 0.1], [np.nan, 0, 1], [0, 0, 1]], np.float32)
+    d = np.array([[0, 0, -1], [1, 0, 0], [0, 0, -1], [np.inf, 0, -1]], np.float32)
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG)
+    assert (res["n_placed"].cpu() == 0).all()
+    assert torch.equal(res["C"].cpu(), torch.tensor([BG] * 4, dtype=torch.float32))
+    assert (res["T"].cpu() == 1.0).all()
+    # zero rays is a no-op
+    z = torch.empty((0, 3), dtype=torch.float32, device=DEV)
+    out = om.render(scene, z, z, n_max=8)
+    assert out["C"].shape == (0, 3)
+
+
+def test_render_full_plane_closed_form():
+    """Vertical ray, full plane: 513 samples; constant density closed form."""
+    log("test_render_full_plane_closed_form")
+    sc = micro_scene(zmin=0.0, zmax=0.25)
+    sigma = 40.0
+    sc["grid"][..., 0] = np.float32(np.log(sigma))
+    scene, t = upload_scene(sc)
+    o = np.array([[0.3, -0.2, 1.0]], np.float32)
+    d = np.array([[0, 0, -1]], np.float32)
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=1024, c_bg=BG)
+    assert res["n_placed"].item() == 513
+    ref = oracle.oracle_render(sc, o, d, oracle.RenderParams(n_max=1024, c_bg=BG), keep_k=False)
+    _compare(res, ref)
+
+
+def test_render_ert_rule(tiny):
+    """With t_term > 0 the counts may differ from the oracle only where the
+    oracle's transmittance at the crossing is within 1e-5 of t_term."""
+    sc, scene, t, o, d = tiny
+    t_term = 1e-2
+    log("test_render_ert_rule: t_term=1e-2")
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG, t_term=t_term)
+    ref = oracle.oracle_render(sc, o, d, oracle.RenderParams(n_max=64, c_bg=BG, t_term=t_term), keep_k=False)
+    nev = res["n_eval"].cpu().numpy()
+    same = nev == ref["n_eval"]
+    assert same.mean() > 0.99
+    if (~same).any():
+        assert np.all(np.abs(nev[~same] - ref["n_eval"][~same]) == 1)
+        tg = res["T"].double().cpu().numpy()[~same]
+        near = np.minimum(np.abs(tg - t_term), np.abs(ref["T"][~same] - t_term)) / t_term
+        assert np.all(near <= 1e-4), near
+    C = res["C"].double().cpu().numpy()
+    assert np.abs(C[same] - ref["C"][same]).max() <= TOL
+    assert (nev < 64).any()  # termination happened
+
+
+def test_mlp_bf16_mfma_close_to_oracle(tiny):
+    """BF16 MFMA MLP on the FP32 march: error bounded by bf16 rounding."""
+    sc, scene, t, o, d = tiny
+    log("test_mlp_bf16_mfma_close_to_oracle")
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG, mlp_bf16=1)
+    ref = oracle.oracle_render(sc, o, d, oracle.RenderParams(n_max=64, c_bg=BG), keep_k=False)
+    err = np.abs(res["C"].double().cpu().numpy() - ref["C"])
+    assert err.max() < 2e-2 and err.mean() < 3e-3, (err.max(), err.mean())
+    # the march outputs are unaffected by the MLP precision
+    np.testing.assert_allclose(res["F"].double().cpu().numpy(), ref["F"], atol=TOL, rtol=0)
+
+
+@pytest.fixture(scope="module")
+def oblique():
+    log("building oblique 1024x1024x128 scene")
+    sc = scenegen.make_scene(scenegen.OBLIQUE)
+    scene, t = upload_scene(sc)
+    o, d = scenegen.camera_rays(1920, 1080, 45.0, 90.0)
+    return sc, scene, t, o, d
+
+
+def _sample_rows(n, k, seed):
+    rng = np.random.default_rng(seed)
+    rows = np.concatenate([rng.choice(n, k, replace=False), np.arange(16), np.arange(n - 21, n)])
+    return np.unique(rows)
+
+
+def test_oblique_1080p_sampled_parity(oblique):
+    """Full 1920x1080 render in the benchmark's launch configuration; the
+    oracle checks a sample of rays (random + first/last blocks)."""
+    sc, scene, t, o, d = oblique
+    log("test_oblique_1080p_sampled_parity: 2073600 rays, n_max=256")
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=256, c_bg=BG)
+    torch.cuda.synchronize()
+    rows = _sample_rows(o.shape[0], 1500, 7)
+    ref = oracle.oracle_render(sc, o[rows], d[rows], oracle.RenderParams(n_max=256, c_bg=BG), keep_k=False)
+    _compare(res, ref, rows)
+    # properties over every ray
+    nev = res["n_eval"].cpu()
+    assert torch.equal(nev, res["n_placed"].cpu())
+    assert torch.isfinite(res["C"]).all()
+    log(f"  mean samples/ray {nev.double().mean().item():.1f}")
+
+
+def test_oblique_placement_sampled(oblique):
+    sc, scene, t, o, d = oblique
+    log("test_oblique_placement_sampled")
+    rows = _sample_rows(o.shape[0], 400, 8)
+    og, dg = rays_to(o[rows], d[rows])
+    k, cnt = om.place_samples(scene, og, dg, n_max=256)
+    kr, nr, _ = oracle.place_samples(o[rows], d[rows], sc["occ"], sc["box_lo"], sc["box_hi"], om.DELTA, 256)
+    assert np.array_equal(cnt.cpu().numpy(), nr)
+    assert np.array_equal(k.cpu().numpy(), kr)
