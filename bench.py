@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and fwd+bwd forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--crop", type=int, default=256, help="side of the centre crop timed on the CPU oracle")
+    ap.add_argument("--order", default=None, help="ray issue order of the image (row | tile4)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one 1 GiB device copy (HBM byte-counter calibration under rocprofv3)")
     return ap.parse_args()
 
 
@@ -95,8 +98,16 @@ def main():
     import scenegen
 
     dev = torch.device("cuda:0")
+    if a.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.time()
     cfg, recipe = scenegen.workload("oblique-1080p")
+    if a.order:
+        recipe = dict(recipe, order=a.order)
     sc = scenegen.make_scene(cfg)
     o, d = scenegen.make_rays(recipe)
     n = o.shape[0]
@@ -180,7 +191,10 @@ def main():
         import oracle
         w, h = recipe["width"], recipe["height"]
         c = a.crop
-        px = np.array([(h // 2 - c // 2 + j) * w + (w // 2 - c // 2 + i) for j in range(c) for i in range(c)])
+        pix = np.array([(h // 2 - c // 2 + j) * w + (w // 2 - c // 2 + i) for j in range(c) for i in range(c)])
+        inv = np.empty(w * h, dtype=np.int64)
+        inv[scenegen.pixel_order(w, h, recipe.get("order", "row"))] = np.arange(w * h)
+        px = inv[pix]  # ray indices of the crop's pixels
         oc, dc = o[px], d[px]
         t1 = time.time()
         ref = oracle.oracle_render(sc, oc, dc, oracle.RenderParams(n_max=n_max, c_bg=BG, t_term=a.t_term),
@@ -199,7 +213,7 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "oblique-1080p", "rays": n, "grid": list(cfg.grid), "planes": list(cfg.planes),
                    "occupancy": cfg.occ, "buildings": cfg.n_buildings, "n_max": n_max, "t_term": a.t_term,
-                   "camera": "pitch 45 deg, yaw 90 deg, 60 deg hfov"},
+                   "camera": "pitch 45 deg, yaw 90 deg, 60 deg hfov", "ray_order": recipe.get("order", "row")},
         "Msamples_per_s": round(msamples, 2), "samples_per_ray": round(samples / n, 2),
         "roofline": roofline, "cpu_baseline": cpu, "forms": forms,
     }

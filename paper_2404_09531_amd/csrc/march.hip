@@ -39,6 +39,19 @@ __device__ __forceinline__ int march_candidates(const SceneDev& sc, const RayPar
             k += kGroup;
             more = (k <= kr.hi) && (n_acc < rp.n_max);
             wave_order();
+            // An empty window: jump over the segments whose columns cannot
+            // hold a sample, 16 segments of 16 candidates per step.
+            while (more && m == 0u) {
+                const bool maybe = column_maybe(sc, o, d, rp.delta, k + gl * kGroup, kGroup);
+                const uint32_t mm = g_ballot(maybe, lane);
+                if (mm) {
+                    k += kGroup * (__ffs(mm) - 1);
+                    more = k <= kr.hi;
+                    break;
+                }
+                k += kGroup * kGroup;
+                more = k <= kr.hi;
+            }
         }
         if (qn >= kGroup || (!more && qn > 0)) {
             const int nb = min(qn, kGroup);
@@ -155,22 +168,145 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
 // ---------------------------------------------------------------------------
 // Backward.  Per ray: the deferred MLP backward runs across the 16 lanes of
 // the group (lane h owns hidden unit h of both hidden layers), giving
-// g7 = dL/dF (+ dL/dC on the diffuse part); then the samples are replayed in
-// the forward's order and each lane scatters the gradient of its sample's
-// 8 feature channels into the 8 grid and 12 plane corners.
+// g7 = dL/dF (+ dL/dC on the diffuse part).  The samples are then replayed
+// twice in the forward's order with recomputed features:
 //
-// dL/da_i = T_{i+1} (g7 . v_i) - (g7 . F - S_i) - T_n (dL/dC . c_bg),
-// S_i = sum_{k<=i} w_k (g7 . v_k), derived from Eq. 1 with
-// w_k = T_k - T_{k+1}; then dL/dt0 = dL/da * delta * tau and
-// dL/dt_c = w g7_c v_c (1 - v_c) through the sigmoids of Eq. 3.
+//   pass 1 records, per 16-sample batch, B_b = sum_{i in b} w_i (g7 . v_i);
+//   pass 2 forms for each sample the suffix S_i = sum_{k > i} w_k (g7 . v_k)
+//   from an in-batch reverse scan plus the totals of the later batches, and
+//
+//   dL/da_i = T_{i+1} (g7 . v_i) - S_i - T_n (dL/dC . c_bg),
+//
+// derived from Eq. 1 with w_k = T_k - T_{k+1}; then dL/dt0 = dL/da delta tau
+// and dL/dt_c = w g7_c v_c (1 - v_c) through the sigmoids of Eq. 3.  The
+// suffix is summed from its own terms (never as a total minus a prefix), so
+// samples behind opaque surfaces keep their relative accuracy.
+//
+// Scatter: per batch and per feature source, the contributions of the
+// group's 16 samples are first summed in an LDS tile covering the batch's
+// bounding box of corners (consecutive samples of a ray share most
+// corners), then each touched corner is added to global memory once with a
+// float32 atomic.  Boxes larger than the tile fall back to direct atomics.
 // ---------------------------------------------------------------------------
-struct F32Scatter {
-    static __device__ __forceinline__ void add(float* base, uint32_t idx, float w, const float* g) {
-        float* q = base + (size_t)idx * 8;
+constexpr int kTile = 64;                       // corners per group tile
+constexpr int kBatchSlots = 1024 / kGroup / kGroup;  // registers holding batch totals (n_max <= 1024)
+
+__device__ __forceinline__ void atomic_row(float* base, uint32_t idx, float w, const float* g) {
+    float* q = base + (size_t)idx * 8;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) unsafeAtomicAdd(q + c, w * g[c]);
+    for (int c = 0; c < 8; ++c) unsafeAtomicAdd(q + c, w * g[c]);
+}
+
+__device__ __forceinline__ void tile_zero(float* tile, int entries, int gl) {
+    float4* t4 = reinterpret_cast<float4*>(tile);
+    for (int i = gl; i < entries * 2; i += kGroup) t4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__device__ __forceinline__ void tile_add(float* tile, int e, float w, const float* g) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) atomicAdd(tile + e * 8 + c, w * g[c]);
+}
+
+__device__ __forceinline__ void tile_flush_row(float* dst, const float* tile, int e, uint32_t idx) {
+    const float4 a = reinterpret_cast<const float4*>(tile)[e * 2];
+    const float4 b = reinterpret_cast<const float4*>(tile)[e * 2 + 1];
+    float* q = dst + (size_t)idx * 8;
+    if (a.x != 0.f) unsafeAtomicAdd(q + 0, a.x);
+    if (a.y != 0.f) unsafeAtomicAdd(q + 1, a.y);
+    if (a.z != 0.f) unsafeAtomicAdd(q + 2, a.z);
+    if (a.w != 0.f) unsafeAtomicAdd(q + 3, a.w);
+    if (b.x != 0.f) unsafeAtomicAdd(q + 4, b.x);
+    if (b.y != 0.f) unsafeAtomicAdd(q + 5, b.y);
+    if (b.z != 0.f) unsafeAtomicAdd(q + 6, b.z);
+    if (b.w != 0.f) unsafeAtomicAdd(q + 7, b.w);
+}
+
+// Trilinear scatter of gt[8] into the grid gradient.
+__device__ __forceinline__ void scatter_grid(const SceneDev& sc, float* gV, float* tile, bool act, const Corners& cn,
+                                             const float* gt, int gl) {
+    constexpr int BIG = 1 << 30;
+    const int x0 = g_min(act ? cn.ix : BIG), x1 = g_max(act ? cn.ix : -BIG);
+    const int y0 = g_min(act ? cn.iy : BIG), y1 = g_max(act ? cn.iy : -BIG);
+    const int z0 = g_min(act ? cn.iz : BIG), z1 = g_max(act ? cn.iz : -BIG);
+    const float x0w = 1.0f - cn.fx, x1w = cn.fx, y0w = 1.0f - cn.fy, y1w = cn.fy;
+    const float z0w = 1.0f - cn.fz, z1w = cn.fz;
+    const float w[8] = {x0w * y0w * z0w, x1w * y0w * z0w, x0w * y1w * z0w, x1w * y1w * z0w,
+                        x0w * y0w * z1w, x1w * y0w * z1w, x0w * y1w * z1w, x1w * y1w * z1w};
+    const int bx = x1 - x0 + 2, by = y1 - y0 + 2, bz = z1 - z0 + 2;
+    if (bx <= kTile && by <= kTile && bz <= kTile && bx * by * bz <= kTile) {
+        const int ent = bx * by * bz;
+        tile_zero(tile, ent, gl);
+        wave_order();
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int e = ((cn.iz + (j >> 2) - z0) * by + (cn.iy + ((j >> 1) & 1) - y0)) * bx + (cn.ix + (j & 1) - x0);
+                tile_add(tile, e, w[j], gt);
+            }
+        }
+        wave_order();
+        for (int e = gl; e < ent; e += kGroup) {
+            const int ex = e % bx, r = e / bx, ey = r % by, ez = r / by;
+            const uint32_t v = ((uint32_t)(z0 + ez) * (uint32_t)sc.Ly + (uint32_t)(y0 + ey)) * (uint32_t)sc.Lx +
+                               (uint32_t)(x0 + ex);
+            tile_flush_row(gV, tile, e, v);
+        }
+        wave_order();
+    } else if (act) {
+        const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            atomic_row(gV, cn.g + ((j >> 2) ? sz : 0u) + (((j >> 1) & 1) ? sy : 0u) + (j & 1), w[j], gt);
     }
-};
+}
+
+// Bilinear scatter into a plane gradient [nb][na][8] at base texel (ia, ib).
+__device__ __forceinline__ void scatter_plane(float* gP, int na, float* tile, bool act, int ia, int ib, float fa,
+                                              float fb, const float* gt, int gl) {
+    constexpr int BIG = 1 << 30;
+    const int a0 = g_min(act ? ia : BIG), a1 = g_max(act ? ia : -BIG);
+    const int b0 = g_min(act ? ib : BIG), b1 = g_max(act ? ib : -BIG);
+    const float w[4] = {(1.0f - fa) * (1.0f - fb), fa * (1.0f - fb), (1.0f - fa) * fb, fa * fb};
+    const int ba = a1 - a0 + 2, bb = b1 - b0 + 2;
+    if (ba <= kTile && bb <= kTile && ba * bb <= kTile) {
+        const int ent = ba * bb;
+        tile_zero(tile, ent, gl);
+        wave_order();
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tile_add(tile, (ib + (j >> 1) - b0) * ba + (ia + (j & 1) - a0), w[j], gt);
+        }
+        wave_order();
+        for (int e = gl; e < ent; e += kGroup) {
+            const int ea = e % ba, eb = e / ba;
+            tile_flush_row(gP, tile, e, (uint32_t)(b0 + eb) * (uint32_t)na + (uint32_t)(a0 + ea));
+        }
+        wave_order();
+    } else if (act) {
+        const uint32_t base = (uint32_t)ib * (uint32_t)na + (uint32_t)ia;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) atomic_row(gP, base + ((j >> 1) ? (uint32_t)na : 0u) + (j & 1), w[j], gt);
+    }
+}
+
+// One replayed sample: optical depth, density, activated colours/features.
+template <class S>
+__device__ __forceinline__ void replay_sample(const SceneDev& sc, const RayParams& rp, float3 o, float3 d, int kq,
+                                              bool act, float& a, float& tau, float* v, Corners& cn) {
+    a = 0.0f;
+    tau = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[c] = 0.0f;
+    if (act) {
+        cn = corners_of(sc, lattice_point(kq, o, d, rp.delta));
+        float t[8];
+        gather_features<S>(sc, cn, t);
+        tau = __expf(t[0]);
+        a = tau * rp.delta;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] = sigmoidf_fast(t[c + 1]);
+    }
+}
 
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
@@ -182,12 +318,14 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
                                                       float* __restrict__ gyz, float* __restrict__ gmlp) {
     __shared__ int qs[kGroupsPerBlock][kQueue];
     __shared__ float sW[512];
+    __shared__ __attribute__((aligned(16))) float tiles[kGroupsPerBlock][kTile * 8];
     for (int i = threadIdx.x; i < 512; i += kBlock) sW[i] = 0.0f;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kGroup - 1);
     const int gid = threadIdx.x / kGroup;
     const int h = gl;
+    float* tile = tiles[gid];
     const float* W = sc.mlp;
     const int64_t start = (int64_t)xcd_block(blockIdx.x, gridDim.x) * chunk;
     const int64_t stop_r = min(n, start + chunk);
@@ -207,8 +345,9 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
         g7[1] = dc1;
         g7[2] = dc2;
         g7[3] = g7[4] = g7[5] = g7[6] = 0.0f;
-        if (ne > 0) {
-            // Forward of G for hidden unit h (Eq. 4).
+        if (ne <= 0) continue;  // no sample: C = c_bg, no parameter gradient
+        {
+            // Deferred MLP G (Eq. 4) for hidden unit h, forward then backward.
             float z1 = W[kB1 + h];
 #pragma unroll
             for (int c = 0; c < 10; ++c) z1 += W[kW1 + h * 10 + c] * x[c];
@@ -229,8 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
             float dh1 = 0.0f;
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
-                const float dz2j = __shfl(dz2, j, kGroup);
-                dh1 += W[kW2 + j * 16 + h] * dz2j;
+                dh1 += W[kW2 + j * 16 + h] * __shfl(dz2, j, kGroup);
                 atomicAdd(&sW[kW2 + h * 16 + j], dz2 * __shfl(h1, j, kGroup));
             }
             const float dz1 = z1 > 0.0f ? dh1 : 0.0f;
@@ -245,78 +383,90 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
             if (h < 3) atomicAdd(&sW[kB3 + h], h == 0 ? dz3[0] : h == 1 ? dz3[1] : dz3[2]);
         }
         const float gT = dc0 * rp.bg0 + dc1 * rp.bg1 + dc2 * rp.bg2;
-        float gF = 0.0f;
+
+        // Pass 1: per-batch totals of w (g7 . v); batch b lives in lane b % 16
+        // of register slot b / 16.
+        float btot[kBatchSlots];
 #pragma unroll
-        for (int c = 0; c < 7; ++c) gF += g7[c] * x[c];
-        float carry = 0.0f, carryS = 0.0f;
-        int done = 0;
-        if (ne > 0) {
+        for (int s = 0; s < kBatchSlots; ++s) btot[s] = 0.0f;
+        {
+            float carry = 0.0f;
+            int done = 0, b = 0;
             march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
                 const int nb_eff = min(nb, ne - done);
                 const bool act = gl < nb_eff;
-                float a = 0.0f, tau = 0.0f, v[7];
-#pragma unroll
-                for (int c = 0; c < 7; ++c) v[c] = 0.0f;
+                float a, tau, v[7];
                 Corners cn;
-                if (act) {
-                    const float3 p = lattice_point(kq, o, d, rp.delta);
-                    cn = corners_of(sc, p);
-                    float t[8];
-                    gather_features<S>(sc, cn, t);
-                    tau = __expf(t[0]);
-                    a = tau * rp.delta;
-#pragma unroll
-                    for (int c = 0; c < 7; ++c) v[c] = sigmoidf_fast(t[c + 1]);
-                }
+                replay_sample<S>(sc, rp, o, d, kq, act, a, tau, v, cn);
                 const float incl = g_scan_incl(a, gl);
                 float excl = __shfl_up(incl, 1, kGroup);
                 if (gl == 0) excl = 0.0f;
-                const float Ti = __expf(-(carry + excl));
-                const float Tnext = __expf(-(carry + incl));
-                const float w = act ? Ti * (-expm1f(-a)) : 0.0f;
+                const float w = act ? __expf(-(carry + excl)) * (-expm1f(-a)) : 0.0f;
                 float gv = 0.0f;
 #pragma unroll
                 for (int c = 0; c < 7; ++c) gv += g7[c] * v[c];
-                const float sincl = carryS + g_scan_incl(w * gv, gl);
-                if (act) {
-                    const float dLda = Tnext * gv - (gF - sincl) - Tn * gT;
-                    float gt[8];
-                    gt[0] = dLda * rp.delta * tau;
+                const float tot = g_sum(w * gv);
 #pragma unroll
-                    for (int c = 0; c < 7; ++c) gt[c + 1] = w * g7[c] * v[c] * (1.0f - v[c]);
-                    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
-                    const float x0 = 1.0f - cn.fx, x1 = cn.fx, y0 = 1.0f - cn.fy, y1 = cn.fy;
-                    const float z0 = 1.0f - cn.fz, z1 = cn.fz;
-                    F32Scatter::add(gV, cn.g, x0 * y0 * z0, gt);
-                    F32Scatter::add(gV, cn.g + 1, x1 * y0 * z0, gt);
-                    F32Scatter::add(gV, cn.g + sy, x0 * y1 * z0, gt);
-                    F32Scatter::add(gV, cn.g + sy + 1, x1 * y1 * z0, gt);
-                    F32Scatter::add(gV, cn.g + sz, x0 * y0 * z1, gt);
-                    F32Scatter::add(gV, cn.g + sz + 1, x1 * y0 * z1, gt);
-                    F32Scatter::add(gV, cn.g + sz + sy, x0 * y1 * z1, gt);
-                    F32Scatter::add(gV, cn.g + sz + sy + 1, x1 * y1 * z1, gt);
-                    const float a0 = 1.0f - cn.ux, a1 = cn.ux, b0 = 1.0f - cn.uy, b1 = cn.uy;
-                    const float e0 = 1.0f - cn.uz, e1 = cn.uz;
-                    const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
-                    F32Scatter::add(gxy, cn.xy, a0 * b0, gt);
-                    F32Scatter::add(gxy, cn.xy + 1, a1 * b0, gt);
-                    F32Scatter::add(gxy, cn.xy + nx, a0 * b1, gt);
-                    F32Scatter::add(gxy, cn.xy + nx + 1, a1 * b1, gt);
-                    F32Scatter::add(gxz, cn.xz, a0 * e0, gt);
-                    F32Scatter::add(gxz, cn.xz + 1, a1 * e0, gt);
-                    F32Scatter::add(gxz, cn.xz + nx, a0 * e1, gt);
-                    F32Scatter::add(gxz, cn.xz + nx + 1, a1 * e1, gt);
-                    F32Scatter::add(gyz, cn.yz, b0 * e0, gt);
-                    F32Scatter::add(gyz, cn.yz + 1, b1 * e0, gt);
-                    F32Scatter::add(gyz, cn.yz + ny, b0 * e1, gt);
-                    F32Scatter::add(gyz, cn.yz + ny + 1, b1 * e1, gt);
-                }
+                for (int s = 0; s < kBatchSlots; ++s)
+                    if ((b >> 4) == s && gl == (b & 15)) btot[s] = tot;
                 carry += __shfl(incl, kGroup - 1, kGroup);
-                carryS = __shfl(sincl, kGroup - 1, kGroup);
                 done += nb_eff;
+                ++b;
                 return done >= ne;
             });
         }
+        // R[s] at lane l = sum of the totals of batches >= 16 s + l.
+        float R[kBatchSlots];
+        {
+            float above = 0.0f;
+#pragma unroll
+            for (int s = kBatchSlots - 1; s >= 0; --s) {
+                const float r = g_rscan_incl(btot[s], gl);
+                R[s] = r + above;
+                above += __shfl(r, 0, kGroup);
+            }
+        }
+
+        // Pass 2: gradients and scatter.
+        float carry = 0.0f;
+        int done = 0, b = 0;
+        march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
+            const int nb_eff = min(nb, ne - done);
+            const bool act = gl < nb_eff;
+            float a, tau, v[7];
+            Corners cn;
+            replay_sample<S>(sc, rp, o, d, kq, act, a, tau, v, cn);
+            const float incl = g_scan_incl(a, gl);
+            float excl = __shfl_up(incl, 1, kGroup);
+            if (gl == 0) excl = 0.0f;
+            const float Ti = __expf(-(carry + excl));
+            const float Tnext = __expf(-(carry + incl));
+            const float w = act ? Ti * (-expm1f(-a)) : 0.0f;
+            float gv = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) gv += g7[c] * v[c];
+            const float cterm = w * gv;
+            float rin = __shfl_down(g_rscan_incl(cterm, gl), 1, kGroup);  // terms of later lanes
+            if (gl == kGroup - 1) rin = 0.0f;
+            const int nxt = b + 1;
+            float after = 0.0f;
+#pragma unroll
+            for (int s = 0; s < kBatchSlots; ++s)
+                if ((nxt >> 4) == s) after = __shfl(R[s], nxt & 15, kGroup);
+            const float suffix = rin + after;
+            float gt[8];
+            gt[0] = (Tnext * gv - suffix - Tn * gT) * rp.delta * tau;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) gt[c + 1] = w * g7[c] * v[c] * (1.0f - v[c]);
+            scatter_grid(sc, gV, tile, act, cn, gt, gl);
+            scatter_plane(gxy, sc.Nx, tile, act, cn.jx, cn.jy, cn.ux, cn.uy, gt, gl);
+            scatter_plane(gxz, sc.Nx, tile, act, cn.jx, cn.jz, cn.ux, cn.uz, gt, gl);
+            scatter_plane(gyz, sc.Ny, tile, act, cn.jy, cn.jz, cn.uy, cn.uz, gt, gl);
+            carry += __shfl(incl, kGroup - 1, kGroup);
+            done += nb_eff;
+            ++b;
+            return done >= ne;
+        });
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 499; i += kBlock) {

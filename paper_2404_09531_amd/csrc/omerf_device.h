@@ -78,6 +78,43 @@ __device__ __forceinline__ bool accept_point(const SceneDev& sc, float3 p) {
     return inb && p.z >= z.x && p.z <= z.y;
 }
 
+// Empty-space skipping over occupancy columns (the bounding-box jump of
+// Sec. 4.4): may any lattice sample k in [ka, ka + len - 1] be accepted?
+// The binary32 points of those samples lie within the segment between the
+// two end points padded by eps (rounding is bounded by 2^-22 of the
+// coordinate magnitudes; eps is 2^-20 of them), so the segment may hold an
+// accepted sample only if its padded box meets the scene box and some
+// column it overlaps has an interval [z_min, z_max] meeting its padded z
+// range.  The containing-cell map is monotone, so the overlapped columns are
+// the cells of the padded x and y bounds.  More than 3 x 3 columns: answer
+// "maybe".
+__device__ __forceinline__ bool column_maybe(const SceneDev& sc, float3 o, float3 d, float delta, int ka, int len) {
+    const float ta = (float)ka * delta, tb = (float)(ka + len - 1) * delta;
+    const float xa = o.x + ta * d.x, xb = o.x + tb * d.x;
+    const float ya = o.y + ta * d.y, yb = o.y + tb * d.y;
+    const float za = o.z + ta * d.z, zb = o.z + tb * d.z;
+    const float ex = ldexpf(1.0f + fabsf(o.x) + fabsf(tb * d.x), -20);
+    const float ey = ldexpf(1.0f + fabsf(o.y) + fabsf(tb * d.y), -20);
+    const float ez = ldexpf(1.0f + fabsf(o.z) + fabsf(tb * d.z), -20);
+    const float x0 = fminf(xa, xb) - ex, x1 = fmaxf(xa, xb) + ex;
+    const float y0 = fminf(ya, yb) - ey, y1 = fmaxf(ya, yb) + ey;
+    const float z0 = fminf(za, zb) - ez, z1 = fmaxf(za, zb) + ez;
+    if (x1 < sc.lo0 || x0 > sc.hi0 || y1 < sc.lo1 || y0 > sc.hi1 || z1 < sc.lo2 || z0 > sc.hi2) return false;
+    const float mx = (float)(sc.Mx - 1), my = (float)(sc.My - 1);
+    const int i0 = (int)fminf(fmaxf(floorf(x0 * sc.occ_sx) - sc.occ_ox, 0.0f), mx);
+    const int i1 = (int)fminf(fmaxf(floorf(x1 * sc.occ_sx) - sc.occ_ox, 0.0f), mx);
+    const int j0 = (int)fminf(fmaxf(floorf(y0 * sc.occ_sy) - sc.occ_oy, 0.0f), my);
+    const int j1 = (int)fminf(fmaxf(floorf(y1 * sc.occ_sy) - sc.occ_oy, 0.0f), my);
+    if (i1 - i0 > 2 || j1 - j0 > 2) return true;
+    bool maybe = false;
+    for (int j = j0; j <= j1; ++j)
+        for (int i = i0; i <= i1; ++i) {
+            const float2 z = sc.occ[j * sc.Mx + i];
+            maybe |= (z.x <= z1) && (z.y >= z0) && (z.x <= z.y);
+        }
+    return maybe;
+}
+
 // Conservative candidate range [k_lo, k_hi] for the closed box: every k whose
 // binary32 point lies in the box is inside it (the exact predicate is applied
 // to each candidate afterwards).  Rounding of p is bounded by 2^-22 of the
@@ -171,23 +208,24 @@ struct BF16Store {
 // Corner set of one sample: 8 grid vertices + 3 x 4 plane texels.
 struct Corners {
     uint32_t g, xy, xz, yz;  // base vertex / texel indices
+    int ix, iy, iz;          // grid base vertex
+    int jx, jy, jz;          // plane base texel per axis
     float fx, fy, fz;        // grid fractions
     float ux, uy, uz;        // plane fractions
 };
 
 __device__ __forceinline__ Corners corners_of(const SceneDev& sc, float3 p) {
     Corners c;
-    int ix, iy, iz, jx, jy, jz;
-    axis_coord(p.x, sc.gx, ix, c.fx);
-    axis_coord(p.y, sc.gy, iy, c.fy);
-    axis_coord(p.z, sc.gz, iz, c.fz);
-    axis_coord(p.x, sc.px, jx, c.ux);
-    axis_coord(p.y, sc.py, jy, c.uy);
-    axis_coord(p.z, sc.pz, jz, c.uz);
-    c.g = ((uint32_t)iz * (uint32_t)sc.Ly + (uint32_t)iy) * (uint32_t)sc.Lx + (uint32_t)ix;
-    c.xy = (uint32_t)jy * (uint32_t)sc.Nx + (uint32_t)jx;
-    c.xz = (uint32_t)jz * (uint32_t)sc.Nx + (uint32_t)jx;
-    c.yz = (uint32_t)jz * (uint32_t)sc.Ny + (uint32_t)jy;
+    axis_coord(p.x, sc.gx, c.ix, c.fx);
+    axis_coord(p.y, sc.gy, c.iy, c.fy);
+    axis_coord(p.z, sc.gz, c.iz, c.fz);
+    axis_coord(p.x, sc.px, c.jx, c.ux);
+    axis_coord(p.y, sc.py, c.jy, c.uy);
+    axis_coord(p.z, sc.pz, c.jz, c.uz);
+    c.g = ((uint32_t)c.iz * (uint32_t)sc.Ly + (uint32_t)c.iy) * (uint32_t)sc.Lx + (uint32_t)c.ix;
+    c.xy = (uint32_t)c.jy * (uint32_t)sc.Nx + (uint32_t)c.jx;
+    c.xz = (uint32_t)c.jz * (uint32_t)sc.Nx + (uint32_t)c.jx;
+    c.yz = (uint32_t)c.jz * (uint32_t)sc.Ny + (uint32_t)c.jy;
     return c;
 }
 
@@ -239,6 +277,28 @@ __device__ __forceinline__ float g_scan_incl(float x, int gl) {
     return x;
 }
 
+// Inclusive scan towards lower lanes: lane i gets x_i + ... + x_15.
+__device__ __forceinline__ float g_rscan_incl(float x, int gl) {
+#pragma unroll
+    for (int s = 1; s < kGroup; s <<= 1) {
+        const float y = __shfl_down(x, s, kGroup);
+        if (gl + s < kGroup) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int g_min(int x) {
+#pragma unroll
+    for (int m = kGroup / 2; m > 0; m >>= 1) x = min(x, __shfl_xor(x, m, kGroup));
+    return x;
+}
+
+__device__ __forceinline__ int g_max(int x) {
+#pragma unroll
+    for (int m = kGroup / 2; m > 0; m >>= 1) x = max(x, __shfl_xor(x, m, kGroup));
+    return x;
+}
+
 __device__ __forceinline__ float g_sum(float x) {
 #pragma unroll
     for (int m = kGroup / 2; m > 0; m >>= 1) x += __shfl_xor(x, m, kGroup);
@@ -250,7 +310,12 @@ __device__ __forceinline__ uint32_t g_ballot(bool pred, int lane) {
     return (uint32_t)(m >> (lane & (64 - kGroup))) & 0xffffu;
 }
 
-__device__ __forceinline__ void wave_order() { __builtin_amdgcn_wave_barrier(); }
+// Keeps the compiler from moving LDS accesses across this point; the
+// hardware executes one wave's LDS instructions in order.
+__device__ __forceinline__ void wave_order() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 
 // Block index -> virtual block index such that the blocks the hardware
 // places on one XCD (round-robin over 8 XCDs) cover one contiguous range of

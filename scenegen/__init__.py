@@ -312,6 +312,26 @@ def camera_rays(width: int, height: int, pitch_deg: float, yaw_deg: float,
     return np.ascontiguousarray(o, dtype=np.float32), d.astype(np.float32)
 
 
+def pixel_order(width: int, height: int, order: str = "row") -> np.ndarray:
+    """Flat pixel indices in the order rays are issued.
+
+    "row": row-major.  "tile4": 4x4 pixel tiles in row-major tile order;
+    inside a tile the four 2x2 quads in row-major order, each quad
+    row-major (16 consecutive rays = one 4x4 tile, 4 rays = one quad).
+    Image sides must be multiples of 4 for "tile4"."""
+    if order == "row":
+        return np.arange(width * height, dtype=np.int64)
+    if order != "tile4":
+        raise KeyError(order)
+    if width % 4 or height % 4:
+        raise ValueError("tile4 order needs sides that are multiples of 4")
+    ty, tx, qy, qx, py, px = np.meshgrid(np.arange(height // 4), np.arange(width // 4), np.arange(2),
+                                         np.arange(2), np.arange(2), np.arange(2), indexing="ij")
+    y = ty * 4 + qy * 2 + py
+    x = tx * 4 + qx * 2 + px
+    return (y * width + x).reshape(-1).astype(np.int64)
+
+
 def random_cameras(count: int, seed: int, pitch_deg=(30.0, 60.0), aim_range: float = 0.8):
     """List of (pitch_deg, yaw_deg, aim) for `count` seeded oblique cameras."""
     g = np.random.Generator(np.random.PCG64(seed))
@@ -360,7 +380,8 @@ def make_rays(recipe: dict):
     if kind == "oblique":
         return oblique_rays(recipe["n"], recipe.get("seed", 1))
     if kind == "camera":
-        return camera_rays(recipe["width"], recipe["height"], recipe["pitch"], recipe["yaw"])
+        px = pixel_order(recipe["width"], recipe["height"], recipe.get("order", "row"))
+        return camera_rays(recipe["width"], recipe["height"], recipe["pitch"], recipe["yaw"], pixels=px)
     if kind == "multi":
         cams = random_cameras(recipe["cameras"], recipe.get("seed", 1))
         return multi_camera_rays(recipe["n"], cams, recipe["width"], recipe["height"], recipe.get("seed", 1) + 100)

@@ -1,0 +1,92 @@
+"""BF16 form: bfloat16 grid/plane storage with float32 arithmetic, and the
+bfloat16 MFMA deferred MLP.
+
+* The march computes in float32 on bfloat16-stored features, so its outputs
+  (F, T, counts) must match the float64 oracle run on the bfloat16-rounded
+  scene to the float32 bar (1e-5).
+* Fidelity of the full BF16 form against the float64 oracle of the float32
+  scene is reported (max-abs, PSNR) and bounded.
+* Quality gate: PSNR of the BF16 render minus PSNR of the FP32 render, both
+  against the float64 oracle render of the perturbed scene (a ground-truth
+  stand-in), must not fall by more than 0.1 dB.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2404_09531_amd as om
+import scenegen
+from tests.gpu_util import bf16_round, log, rays_to, upload_scene
+
+pytestmark = pytest.mark.gpu
+
+BG = (0.25, 0.5, 0.75)
+
+
+def psnr(a, b):
+    mse = np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2)
+    return 10.0 * np.log10(1.0 / mse)
+
+
+def _rounded(sc):
+    r = dict(sc)
+    for k in ("grid", "plane_xy", "plane_xz", "plane_yz"):
+        r[k] = bf16_round(sc[k])
+    return r
+
+
+def test_bf16_march_matches_oracle_on_rounded_scene():
+    sc = scenegen.make_scene(scenegen.TINY)
+    o, d = scenegen.oblique_rays(4096, seed=1)
+    log("test_bf16_march_matches_oracle_on_rounded_scene")
+    scene, t = upload_scene(sc, dtype=torch.bfloat16)
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG, mlp_bf16=0)
+    ref = oracle.oracle_render(_rounded(sc), o, d, oracle.RenderParams(n_max=64, c_bg=BG), keep_k=False)
+    assert np.array_equal(res["n_eval"].cpu().numpy(), ref["n_eval"])
+    for key in ("F", "T", "C"):
+        err = np.abs(res[key].double().cpu().numpy() - ref[key]).max()
+        log(f"  bf16 storage, fp32 MLP: max |{key} - oracle(rounded)| = {err:.2e}")
+        assert err <= 1e-5, key
+    # full BF16 form (MFMA MLP): bounded by bfloat16 rounding of the MLP
+    res2 = om.render(scene, og, dg, n_max=64, c_bg=BG)
+    err2 = np.abs(res2["C"].double().cpu().numpy() - ref["C"]).max()
+    log(f"  bf16 storage + bf16 MFMA MLP: max |C - oracle(rounded)| = {err2:.2e}")
+    assert err2 < 2e-2
+
+
+@pytest.fixture(scope="module")
+def oblique_crop():
+    log("building oblique scene and its perturbed copy")
+    sc = scenegen.make_scene(scenegen.OBLIQUE)
+    pert = scenegen.perturb_scene(sc, 0.05, seed=2)
+    w, h, c = 1920, 1080, 256
+    pix = np.array([(h // 2 - c // 2 + j) * w + (w // 2 - c // 2 + i) for j in range(c) for i in range(c)])
+    o, d = scenegen.camera_rays(w, h, 45.0, 90.0, pixels=pix)
+    prm = oracle.RenderParams(n_max=256, c_bg=BG)
+    log("oracle renders of the 256x256 crop (scene, perturbed scene)")
+    ref = oracle.oracle_render(sc, o, d, prm, keep_k=False)["C"]
+    gt = oracle.oracle_render(pert, o, d, prm, keep_k=False)["C"]
+    return sc, o, d, ref, gt
+
+
+def test_bf16_psnr_gate_and_fidelity(oblique_crop):
+    sc, o, d, ref, gt = oblique_crop
+    log("test_bf16_psnr_gate_and_fidelity: 256x256 crop of the oblique 1080p image")
+    og, dg = rays_to(o, d)
+    s32, _ = upload_scene(sc)
+    c32 = om.render(s32, og, dg, n_max=256, c_bg=BG)["C"].double().cpu().numpy()
+    del s32
+    torch.cuda.empty_cache()
+    s16, _ = upload_scene(sc, dtype=torch.bfloat16)
+    c16 = om.render(s16, og, dg, n_max=256, c_bg=BG)["C"].double().cpu().numpy()
+    e32, e16 = np.abs(c32 - ref).max(), np.abs(c16 - ref).max()
+    p32, p16 = psnr(c32, ref), psnr(c16, ref)
+    g32, g16 = psnr(c32, gt), psnr(c16, gt)
+    log(f"  fidelity vs FP64 oracle: FP32 max-abs {e32:.2e} PSNR {p32:.1f} dB; "
+        f"BF16 max-abs {e16:.2e} PSNR {p16:.1f} dB")
+    log(f"  vs perturbed-scene target: FP32 {g32:.3f} dB, BF16 {g16:.3f} dB, loss {g32 - g16:.4f} dB")
+    assert e32 <= 1e-5
+    assert e16 < 5e-2 and p16 > 40.0
+    assert g32 - g16 <= 0.1

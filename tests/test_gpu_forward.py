@@ -165,9 +165,10 @@ def test_mlp_bf16_mfma_close_to_oracle(tiny):
 @pytest.fixture(scope="module")
 def oblique():
     log("building oblique 1024x1024x128 scene")
-    sc = scenegen.make_scene(scenegen.OBLIQUE)
+    cfg, recipe = scenegen.workload("oblique-1080p")  # the benchmark's workload and ray order
+    sc = scenegen.make_scene(cfg)
     scene, t = upload_scene(sc)
-    o, d = scenegen.camera_rays(1920, 1080, 45.0, 90.0)
+    o, d = scenegen.make_rays(recipe)
     return sc, scene, t, o, d
 
 
