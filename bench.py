@@ -87,6 +87,122 @@ def time_stages(step_fns, steps, warmup, torch):
     return total, per
 
 
+def _outputs(torch, n, dev):
+    return dict(C=torch.empty((n, 3), device=dev), T=torch.empty((n,), device=dev),
+                F=torch.empty((n, 7), device=dev), n_placed=torch.empty((n,), dtype=torch.int32, device=dev),
+                n_eval=torch.empty((n,), dtype=torch.int32, device=dev))
+
+
+def _bf16_scene(om, t):
+    tb = {k: om.to_bf16(t[k]) for k in ("grid", "plane_xy", "plane_xz", "plane_yz")}
+    return om.Scene(tb["grid"], tb["plane_xy"], tb["plane_xz"], tb["plane_yz"], t["occ"], t["mlp"]), tb
+
+
+def form_bf16_render(om, torch, t, og, dg, out, kw, samples, n, a):
+    """bfloat16 grid/planes + bfloat16 MFMA MLP on the same 1080p image."""
+    scene_b, tb = _bf16_scene(om, t)
+    outb = {k: torch.empty_like(v) for k, v in out.items()}
+    mb = lambda: om.render_into(scene_b, og, dg, outb, stage="march", **kw)  # noqa: E731
+    lb = lambda: om.render_into(scene_b, og, dg, outb, stage="mlp", **kw)  # noqa: E731
+    tot, (mb_ms, lb_ms) = time_stages([mb, lb], a.steps, a.warmup, torch)
+    ms = tot / a.steps
+    sb = int(outb["n_eval"].sum().item())
+    return {"Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
+            "march_ms": round(mb_ms, 4), "mlp_ms": round(lb_ms, 4),
+            "roofline_frac_algorithmic": round((sb * 320 + n * 64) / (mb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "max_abs_vs_fp32_render": float((outb["C"] - out["C"]).abs().max().item())}
+
+
+def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a):
+    """float32 forward + L2 loss gradient + backward on 2^18 rays of 16 cameras."""
+    dev = out["C"].device
+    cfg2, rec2 = scenegen.workload("train-2^18")
+    o2, d2 = scenegen.make_rays(rec2)
+    n2 = o2.shape[0]
+    o2g, d2g = torch.from_numpy(o2).to(dev), torch.from_numpy(d2).to(dev)
+    out2 = _outputs(torch, n2, dev)
+    om.render_into(scene, o2g, d2g, out2, **kw)
+    g = torch.Generator(device=dev)
+    g.manual_seed(2)
+    target = (out2["C"] + 0.05 * torch.randn(out2["C"].shape, device=dev, generator=g)).contiguous()
+    grads = {k: torch.zeros(t[k].shape, device=dev) for k in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp")}
+    dC = torch.empty_like(out2["C"])
+    fwd = lambda: om.render_into(scene, o2g, d2g, out2, **kw)  # noqa: E731
+    lossg = lambda: om.l2_loss_grad(out2["C"], target, dL_dC=dC, with_loss=False)  # noqa: E731
+    bwd = lambda: om.render_backward(scene, o2g, d2g, out2, dC, grads, **kw)  # noqa: E731
+    steps = max(3, a.steps // 2)
+    tot, (f_ms, l_ms, b_ms) = time_stages([fwd, lossg, bwd], steps, a.warmup, torch)
+    ms = tot / steps
+    s2 = int(out2["n_eval"].sum().item())
+    return {"workload": "2^18 rays, 16 cameras 1920x1080, oblique scene", "rays": n2,
+            "Mrays_per_s": round(n2 / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4),
+            "fwd_ms": round(f_ms, 4), "loss_ms": round(l_ms, 4), "bwd_ms": round(b_ms, 4),
+            "samples_per_ray": round(s2 / n2, 1), "targets": "forward colours + N(0, 0.05), seeded"}
+
+
+def form_bf16_4k(om, scenegen, torch, t, kw, a):
+    """bfloat16 render of eight 3840x2160 images from seeded oblique cameras."""
+    dev = t["grid"].device
+    cams = scenegen.random_cameras(8, seed=3)
+    W, H = 3840, 2160
+    n = 8 * W * H
+    og = torch.empty((n, 3), device=dev)
+    dg = torch.empty((n, 3), device=dev)
+    px = scenegen.pixel_order(W, H, "tile4")
+    for i, (p, y, aim) in enumerate(cams):
+        o, d = scenegen.camera_rays(W, H, p, y, aim, pixels=px)
+        og[i * W * H:(i + 1) * W * H] = torch.from_numpy(o).to(dev)
+        dg[i * W * H:(i + 1) * W * H] = torch.from_numpy(d).to(dev)
+    scene_b, tb = _bf16_scene(om, t)
+    outb = _outputs(torch, n, dev)
+    mb = lambda: om.render_into(scene_b, og, dg, outb, stage="march", **kw)  # noqa: E731
+    lb = lambda: om.render_into(scene_b, og, dg, outb, stage="mlp", **kw)  # noqa: E731
+    steps = max(2, a.steps // 5)
+    tot, (mb_ms, lb_ms) = time_stages([mb, lb], steps, 1, torch)
+    ms = tot / steps
+    sb = int(outb["n_eval"].sum().item())
+    return {"workload": "8 x 3840x2160, pitch U[30,60] deg, tile4 order", "rays": n,
+            "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 3),
+            "march_ms": round(mb_ms, 3), "mlp_ms": round(lb_ms, 3), "samples_per_ray": round(sb / n, 1),
+            "Msamples_per_s": round(sb / (ms * 1e-3) / 1e6, 1),
+            "roofline_frac_algorithmic": round((sb * 320 + n * 64) / (mb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def form_towers(om, scenegen, torch, a):
+    """Uneven rays: 512^2 occupancy with 10% towers, 2^20 rays of 64 cameras,
+    n_max 512; bfloat16 storage, float32 master gradients."""
+    dev = torch.device("cuda:0")
+    cfg, rec = scenegen.workload("towers-2^20")
+    sc = scenegen.make_scene(cfg)
+    o, d = scenegen.make_rays(rec)
+    n = o.shape[0]
+    t = {k: torch.from_numpy(sc[k]).to(dev) for k in ("grid", "plane_xy", "plane_xz", "plane_yz", "occ", "mlp")}
+    del sc
+    scene_b, tb = _bf16_scene(om, t)
+    og, dg = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
+    kw = dict(n_max=rec["n_max"], c_bg=BG)
+    out = _outputs(torch, n, dev)
+    om.render_into(scene_b, og, dg, out, **kw)
+    g = torch.Generator(device=dev)
+    g.manual_seed(2)
+    target = (out["C"] + 0.05 * torch.randn(out["C"].shape, device=dev, generator=g)).contiguous()
+    grads = {k: torch.zeros(t[k].shape, device=dev) for k in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp")}
+    dC = torch.empty_like(out["C"])
+    fwd = lambda: om.render_into(scene_b, og, dg, out, **kw)  # noqa: E731
+    lossg = lambda: om.l2_loss_grad(out["C"], target, dL_dC=dC, with_loss=False)  # noqa: E731
+    bwd = lambda: om.render_backward(scene_b, og, dg, out, dC, grads, **kw)  # noqa: E731
+    steps = max(3, a.steps // 4)
+    tot, (f_ms, l_ms, b_ms) = time_stages([fwd, lossg, bwd], steps, 1, torch)
+    ms = tot / steps
+    npl = out["n_placed"].cpu().numpy()
+    hist = np.histogram(npl, bins=np.arange(0, 513 + 32, 32))[0]
+    return {"workload": "towers: occupancy 512^2, 10% towers, 2^20 rays of 64 cameras, n_max 512", "rays": n,
+            "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 3),
+            "fwd_ms": round(f_ms, 3), "bwd_ms": round(b_ms, 3),
+            "samples_per_ray": round(float(npl.mean()), 1), "max_samples": int(npl.max()),
+            "n_placed_hist_bins32": hist.tolist()}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -143,64 +259,33 @@ def main():
                 "kernel": "k_march_fwd<F32Store>", "algorithmic_bytes_per_launch": alg_bytes,
                 "kernel_ms": round(march_ms, 4)}
 
+    w, h = recipe["width"], recipe["height"]
+    c = a.crop
+    pix = np.array([(h // 2 - c // 2 + j) * w + (w // 2 - c // 2 + i) for j in range(c) for i in range(c)])
+    inv = np.empty(w * h, dtype=np.int64)
+    inv[scenegen.pixel_order(w, h, recipe.get("order", "row"))] = np.arange(w * h)
+    px = inv[pix]  # ray indices of the crop's pixels
+    gpu_c = out["C"][torch.from_numpy(px).to(dev)].double().cpu().numpy()
+
     forms = {}
     if not a.no_forms:
-        # bfloat16 storage + bfloat16 MFMA MLP, same image.
-        tb = {k: om.to_bf16(t[k]) for k in ("grid", "plane_xy", "plane_xz", "plane_yz")}
-        scene_b = om.Scene(tb["grid"], tb["plane_xy"], tb["plane_xz"], tb["plane_yz"], t["occ"], t["mlp"])
-        outb = {k: torch.empty_like(v) for k, v in out.items()}
-        mb = lambda: om.render_into(scene_b, og, dg, outb, stage="march", **kw)  # noqa: E731
-        lb = lambda: om.render_into(scene_b, og, dg, outb, stage="mlp", **kw)  # noqa: E731
-        tot_b, (mb_ms, lb_ms) = time_stages([mb, lb], a.steps, a.warmup, torch)
-        ms_b = tot_b / a.steps
-        err_b = (outb["C"] - out["C"]).abs().max().item()
-        forms["bf16_render"] = {"Mrays_per_s": round(n / (ms_b * 1e-3) / 1e6, 2), "ms_per_step": round(ms_b, 4),
-                                "march_ms": round(mb_ms, 4), "mlp_ms": round(lb_ms, 4),
-                                "achieved_GBps": round((samples * 320 + n * 64) / (mb_ms * 1e-3) / 1e9, 1),
-                                "max_abs_vs_fp32_render": err_b}
-        del scene_b, tb, outb
-        # float32 forward + backward training step on 2^18 rays from 16 cameras.
-        cfg2, rec2 = scenegen.workload("train-2^18")
-        o2, d2 = scenegen.make_rays(rec2)
-        n2 = o2.shape[0]
-        o2g, d2g = torch.from_numpy(o2).to(dev), torch.from_numpy(d2).to(dev)
-        out2 = {k: torch.empty((n2,) + tuple(v.shape[1:]), dtype=v.dtype, device=dev) for k, v in out.items()}
-        om.render_into(scene, o2g, d2g, out2, **kw)
-        g = torch.Generator(device=dev)
-        g.manual_seed(2)
-        target = (out2["C"] + 0.05 * torch.randn(out2["C"].shape, device=dev, generator=g)).contiguous()
-        grads = {k: torch.zeros(t[k].shape, device=dev) for k in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp")}
-        dC = torch.empty_like(out2["C"])
-        fwd = lambda: om.render_into(scene, o2g, d2g, out2, **kw)  # noqa: E731
-        lossg = lambda: om.l2_loss_grad(out2["C"], target, dL_dC=dC, with_loss=False)  # noqa: E731
-        bwd = lambda: om.render_backward(scene, o2g, d2g, out2, dC, grads, **kw)  # noqa: E731
-        tot2, (f_ms, l_ms, b_ms) = time_stages([fwd, lossg, bwd], max(3, a.steps // 2), a.warmup, torch)
-        ms2 = tot2 / max(3, a.steps // 2)
-        s2 = int(out2["n_eval"].sum().item())
-        forms["fp32_fwd_bwd"] = {"workload": "2^18 rays, 16 cameras 1920x1080, same scene", "rays": n2,
-                                 "Mrays_per_s": round(n2 / (ms2 * 1e-3) / 1e6, 2), "ms_per_step": round(ms2, 4),
-                                 "fwd_ms": round(f_ms, 4), "loss_ms": round(l_ms, 4), "bwd_ms": round(b_ms, 4),
-                                 "samples_per_ray": round(s2 / n2, 1),
-                                 "targets": "forward colours + N(0, 0.05), seeded"}
-        del grads
+        forms["bf16_render"] = form_bf16_render(om, torch, t, og, dg, out, kw, samples, n, a)
+        forms["fp32_fwd_bwd"] = form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a)
+        forms["bf16_render_4k_x8"] = form_bf16_4k(om, scenegen, torch, t, kw, a)
+        del t, scene, out, og, dg
+        torch.cuda.empty_cache()
+        forms["towers_bf16_fwd_bwd"] = form_towers(om, scenegen, torch, a)
 
     cpu = None
     if not a.no_cpu_baseline:
         import torch as _t
 
         import oracle
-        w, h = recipe["width"], recipe["height"]
-        c = a.crop
-        pix = np.array([(h // 2 - c // 2 + j) * w + (w // 2 - c // 2 + i) for j in range(c) for i in range(c)])
-        inv = np.empty(w * h, dtype=np.int64)
-        inv[scenegen.pixel_order(w, h, recipe.get("order", "row"))] = np.arange(w * h)
-        px = inv[pix]  # ray indices of the crop's pixels
         oc, dc = o[px], d[px]
         t1 = time.time()
         ref = oracle.oracle_render(sc, oc, dc, oracle.RenderParams(n_max=n_max, c_bg=BG, t_term=a.t_term),
                                    keep_k=False)
         dt = time.time() - t1
-        gpu_c = out["C"][torch.from_numpy(px).to(dev)].double().cpu().numpy()
         cpu = {"value": round(len(px) / dt / 1e6, 6), "unit": "Mrays/s", "cores": _t.get_num_threads(),
                "kind": "oracle", "sample": f"centre {c}x{c} crop of the 1920x1080 image ({len(px)} rays)",
                "seconds": round(dt, 2), "Msamples_per_s": round(float(ref["n_eval"].sum()) / dt / 1e6, 4),

@@ -132,8 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
             for (int c = 0; c < 7; ++c) v[c] = sigmoidf_fast(t[c + 1]);
         }
         const float incl = g_scan_incl(a, gl);
-        float excl = __shfl_up(incl, 1, kGroup);
-        if (gl == 0) excl = 0.0f;
+        const float excl = g_shift_up1(incl);
         const float Ti = __expf(-(carry + excl));
         float w = Ti * (-expm1f(-a));
         int nb_eff = nb;
@@ -399,8 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
                 Corners cn;
                 replay_sample<S>(sc, rp, o, d, kq, act, a, tau, v, cn);
                 const float incl = g_scan_incl(a, gl);
-                float excl = __shfl_up(incl, 1, kGroup);
-                if (gl == 0) excl = 0.0f;
+                const float excl = g_shift_up1(incl);
                 const float w = act ? __expf(-(carry + excl)) * (-expm1f(-a)) : 0.0f;
                 float gv = 0.0f;
 #pragma unroll
@@ -437,8 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
             Corners cn;
             replay_sample<S>(sc, rp, o, d, kq, act, a, tau, v, cn);
             const float incl = g_scan_incl(a, gl);
-            float excl = __shfl_up(incl, 1, kGroup);
-            if (gl == 0) excl = 0.0f;
+            const float excl = g_shift_up1(incl);
             const float Ti = __expf(-(carry + excl));
             const float Tnext = __expf(-(carry + incl));
             const float w = act ? Ti * (-expm1f(-a)) : 0.0f;
@@ -446,8 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
 #pragma unroll
             for (int c = 0; c < 7; ++c) gv += g7[c] * v[c];
             const float cterm = w * gv;
-            float rin = __shfl_down(g_rscan_incl(cterm, gl), 1, kGroup);  // terms of later lanes
-            if (gl == kGroup - 1) rin = 0.0f;
+            const float rin = g_shift_down1(g_rscan_incl(cterm, gl));  // terms of later lanes
             const int nxt = b + 1;
             float after = 0.0f;
 #pragma unroll

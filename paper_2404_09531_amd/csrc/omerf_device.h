@@ -268,22 +268,34 @@ __device__ __forceinline__ float sigmoidf_fast(float x) {
 // 16-lane group collectives.  All lanes of a group take the same branches,
 // so group members are always active together.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float g_scan_incl(float x, int gl) {
-#pragma unroll
-    for (int s = 1; s < kGroup; s <<= 1) {
-        const float y = __shfl_up(x, s, kGroup);
-        if (gl >= s) x += y;
-    }
+// DPP move within a 16-lane row (= one group); out-of-row sources read 0.
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+constexpr int kRowShr = 0x110, kRowShl = 0x100;
+
+// Inclusive scan over the group: lane i gets x_0 + ... + x_i (row_shr DPP).
+__device__ __forceinline__ float g_scan_incl(float x, int /*gl*/) {
+    x += dpp_row<kRowShr | 1>(x);
+    x += dpp_row<kRowShr | 2>(x);
+    x += dpp_row<kRowShr | 4>(x);
+    x += dpp_row<kRowShr | 8>(x);
     return x;
 }
 
+// Value of the next lower lane (0 for lane 0).
+__device__ __forceinline__ float g_shift_up1(float x) { return dpp_row<kRowShr | 1>(x); }
+
+// Value of the next higher lane (0 for lane 15).
+__device__ __forceinline__ float g_shift_down1(float x) { return dpp_row<kRowShl | 1>(x); }
+
 // Inclusive scan towards lower lanes: lane i gets x_i + ... + x_15.
-__device__ __forceinline__ float g_rscan_incl(float x, int gl) {
-#pragma unroll
-    for (int s = 1; s < kGroup; s <<= 1) {
-        const float y = __shfl_down(x, s, kGroup);
-        if (gl + s < kGroup) x += y;
-    }
+__device__ __forceinline__ float g_rscan_incl(float x, int /*gl*/) {
+    x += dpp_row<kRowShl | 1>(x);
+    x += dpp_row<kRowShl | 2>(x);
+    x += dpp_row<kRowShl | 4>(x);
+    x += dpp_row<kRowShl | 8>(x);
     return x;
 }
 
@@ -299,11 +311,8 @@ __device__ __forceinline__ int g_max(int x) {
     return x;
 }
 
-__device__ __forceinline__ float g_sum(float x) {
-#pragma unroll
-    for (int m = kGroup / 2; m > 0; m >>= 1) x += __shfl_xor(x, m, kGroup);
-    return x;
-}
+// Group sum, returned in every lane: scan, then broadcast lane 15.
+__device__ __forceinline__ float g_sum(float x) { return __shfl(g_scan_incl(x, 0), kGroup - 1, kGroup); }
 
 __device__ __forceinline__ uint32_t g_ballot(bool pred, int lane) {
     const unsigned long long m = __ballot(pred);

@@ -318,9 +318,18 @@ def pixel_order(width: int, height: int, order: str = "row") -> np.ndarray:
     "row": row-major.  "tile4": 4x4 pixel tiles in row-major tile order;
     inside a tile the four 2x2 quads in row-major order, each quad
     row-major (16 consecutive rays = one 4x4 tile, 4 rays = one quad).
-    Image sides must be multiples of 4 for "tile4"."""
+    Image sides must be multiples of 4 for "tile4".  "morton": Z-order of
+    (x, y), so every aligned run of 4^k rays is a 2^k x 2^k square (where it
+    lies inside the image)."""
     if order == "row":
         return np.arange(width * height, dtype=np.int64)
+    if order == "morton":
+        y, x = np.divmod(np.arange(width * height, dtype=np.int64), width)
+        key = np.zeros_like(x)
+        for b in range(16):
+            key |= ((x >> b) & 1) << (2 * b)
+            key |= ((y >> b) & 1) << (2 * b + 1)
+        return np.argsort(key, kind="stable").astype(np.int64)
     if order != "tile4":
         raise KeyError(order)
     if width % 4 or height % 4:

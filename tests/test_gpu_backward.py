@@ -145,3 +145,120 @@ def test_backward_finite_differences_tiny(tiny_train):
     picks, fd, an, err = _fd_check(scene, t, og, dg, tg, 64, grads)
     log(f"  FD: {len(picks)} params, max rel err {err.max():.2e}, median {np.median(err):.2e}")
     assert err.max() <= 1e-3, [(p, f, a) for p, f, a, e in zip(picks, fd, an, err) if e > 1e-3]
+
+
+@pytest.fixture(scope="module")
+def towers():
+    log("building towers scene (512^2 occupancy, 10% towers) and its perturbed copy")
+    cfg, rec = scenegen.workload("towers-2^20")
+    sc = scenegen.make_scene(cfg)
+    pert = scenegen.perturb_scene(sc, 0.05, seed=2)
+    o, d = scenegen.make_rays(rec)
+    o, d = o[:256].copy(), d[:256].copy()
+    prm = oracle.RenderParams(n_max=rec["n_max"], c_bg=BG)
+    target = oracle.oracle_render(pert, o, d, prm, keep_k=False)["C"].astype(np.float32)
+    del pert
+    return sc, o, d, target, rec["n_max"]
+
+
+def _rounded_scene(sc):
+    from tests.gpu_util import bf16_round
+    r = dict(sc)
+    for k in SOURCES:
+        r[k] = bf16_round(sc[k])
+    return r
+
+
+def test_towers_bf16_storage_gradient_vs_oracle(towers):
+    """bfloat16 storage, float32 arithmetic and float32 master gradients:
+    must match the float64 oracle on the bfloat16-rounded scene."""
+    sc, o, d, target, n_max = towers
+    log("test_towers_bf16_storage_gradient_vs_oracle: 256 rays, n_max 512")
+    scene, t = upload_scene(sc, dtype=torch.bfloat16)
+    og, dg = rays_to(o, d)
+    tg = torch.from_numpy(target).to(og.device)
+    res = om.render(scene, og, dg, n_max=n_max, c_bg=BG, mlp_bf16=0)
+    dC, loss = om.l2_loss_grad(res["C"], tg)
+    grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp")}
+    om.render_backward(scene, og, dg, res, dC, grads, n_max=n_max, c_bg=BG)
+    g = {k: v.double().cpu().numpy() for k, v in grads.items()}
+    npl = res["n_placed"].cpu().numpy()
+    log(f"  samples/ray: min {npl.min()} mean {npl.mean():.1f} max {npl.max()}; "
+        f"hist(32-wide bins) {np.histogram(npl, bins=np.arange(0, 545, 32))[0].tolist()}")
+    rsc = _rounded_scene(sc)
+    _, _, ref = oracle.oracle_loss_and_grads(rsc, o, d, oracle.RenderParams(n_max=n_max, c_bg=BG),
+                                             target.astype(np.float64))
+    _check_against_oracle(rsc, g, ref)
+
+
+def test_towers_full_bf16_gradient_error(towers):
+    """Full BF16 form (bf16 storage + bf16 MFMA MLP forward) against the
+    float64 oracle gradient of the float32 scene: reported, and the
+    gradient direction must agree (cosine > 0.999)."""
+    sc, o, d, target, n_max = towers
+    log("test_towers_full_bf16_gradient_error")
+    scene, t = upload_scene(sc, dtype=torch.bfloat16)
+    og, dg = rays_to(o, d)
+    tg = torch.from_numpy(target).to(og.device)
+    res = om.render(scene, og, dg, n_max=n_max, c_bg=BG)
+    dC, _ = om.l2_loss_grad(res["C"], tg)
+    grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp")}
+    om.render_backward(scene, og, dg, res, dC, grads, n_max=n_max, c_bg=BG)
+    _, _, ref = oracle.oracle_loss_and_grads(sc, o, d, oracle.RenderParams(n_max=n_max, c_bg=BG),
+                                             target.astype(np.float64))
+    a, b = [], []
+    for src in SOURCES:
+        uniq, rows = ref[src]
+        a.append(grads[src].double().cpu().numpy().reshape(-1, 8)[uniq].ravel())
+        b.append(rows.ravel())
+    a.append(grads["mlp"].double().cpu().numpy())
+    b.append(ref["mlp"])
+    a, b = np.concatenate(a), np.concatenate(b)
+    cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+    big = np.abs(b) >= 1e-2 * np.abs(b).max()
+    rel = np.abs(a - b)[big] / np.abs(b)[big]
+    log(f"  BF16 form vs FP64 oracle gradient: cosine {cos:.6f}, max rel err (|g| >= 1e-2 max) {rel.max():.3e}, "
+        f"median {np.median(rel):.3e}")
+    assert cos > 0.999
+
+
+@pytest.fixture(scope="module")
+def oblique_train():
+    log("building oblique scene, perturbed copy and 2^18 training rays")
+    cfg, rec = scenegen.workload("train-2^18")
+    sc = scenegen.make_scene(cfg)
+    pert = scenegen.perturb_scene(sc, 0.05, seed=2)
+    o, d = scenegen.make_rays(rec)
+    prm = oracle.RenderParams(n_max=rec["n_max"], c_bg=BG)
+    o256, d256 = o[:256].copy(), d[:256].copy()
+    t256 = oracle.oracle_render(pert, o256, d256, prm, keep_k=False)["C"].astype(np.float32)
+    del pert
+    scene, t = upload_scene(sc)
+    return sc, scene, t, o, d, o256, d256, t256, rec["n_max"]
+
+
+def test_oblique_backward_vs_oracle_256(oblique_train):
+    sc, scene, t, o, d, o256, d256, t256, n_max = oblique_train
+    log("test_oblique_backward_vs_oracle_256: oblique scene, 256 rays, perturbed-scene targets")
+    og, dg = rays_to(o256, d256)
+    tg = torch.from_numpy(t256).to(og.device)
+    _, loss, grads = _gpu_grads(scene, t, og, dg, tg, n_max)
+    ref_loss, _, ref = oracle.oracle_loss_and_grads(sc, o256, d256, oracle.RenderParams(n_max=n_max, c_bg=BG),
+                                                   t256.astype(np.float64))
+    assert abs(loss - ref_loss) <= 1e-3 * ref_loss
+    _check_against_oracle(sc, grads, ref)
+
+
+def test_oblique_finite_differences_2e18(oblique_train):
+    """Central FD (eps = 1e-3) of the float64 GPU loss over all 2^18 rays."""
+    sc, scene, t, o, d, o256, d256, t256, n_max = oblique_train
+    log("test_oblique_finite_differences_2e18: 64 params, 2^18 rays")
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=n_max, c_bg=BG)
+    g = torch.Generator(device=og.device)
+    g.manual_seed(5)
+    tg = (res["C"] + 0.05 * torch.randn(res["C"].shape, device=og.device, generator=g)).contiguous()
+    _, _, grads = _gpu_grads(scene, t, og, dg, tg, n_max)
+    picks, fd, an, err = _fd_check(scene, t, og, dg, tg, n_max, grads)
+    log(f"  FD: {len(picks)} params, max rel err {err.max():.2e}, median {np.median(err):.2e}")
+    assert err.max() <= 1e-3, [(p, f, a) for p, f, a, e in zip(picks, fd, an, err) if e > 1e-3]
