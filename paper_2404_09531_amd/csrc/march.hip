@@ -299,7 +299,7 @@ __device__ __forceinline__ void replay_sample(const SceneDev& sc, const RayParam
     if (act) {
         cn = corners_of(sc, lattice_point(kq, o, d, rp.delta));
         float t[8];
-        gather_features<S>(sc, cn, t);
+        gather_features_split<S>(sc, cn, t);
         tau = __expf(t[0]);
         a = tau * rp.delta;
 #pragma unroll

@@ -184,22 +184,31 @@ __device__ __forceinline__ void axis_coord(float p, const AxisMap& m, int& i0, f
     i0 = ic;
 }
 
-// Storage policies: accumulate w * corner into t[8] / scatter g[8] * w.
+// Storage policies.  A corner is 8 channels: two 16-byte loads (float32) or
+// one (bfloat16).  load() only issues the loads; acc() consumes them, so a
+// whole source's corners can be in flight before the first is used.
 struct F32Store {
-    static __device__ __forceinline__ void acc(const void* base, uint32_t idx, float w, float* t) {
+    struct Row {
+        float4 a, b;
+    };
+    static __device__ __forceinline__ Row load(const void* base, uint32_t idx) {
         const float4* q = reinterpret_cast<const float4*>(base) + (size_t)idx * 2;
-        const float4 a = q[0];
-        const float4 b = q[1];
-        t[0] += w * a.x; t[1] += w * a.y; t[2] += w * a.z; t[3] += w * a.w;
-        t[4] += w * b.x; t[5] += w * b.y; t[6] += w * b.z; t[7] += w * b.w;
+        return Row{q[0], q[1]};
+    }
+    static __device__ __forceinline__ void acc(const Row& r, float w, float* t) {
+        t[0] += w * r.a.x; t[1] += w * r.a.y; t[2] += w * r.a.z; t[3] += w * r.a.w;
+        t[4] += w * r.b.x; t[5] += w * r.b.y; t[6] += w * r.b.z; t[7] += w * r.b.w;
     }
 };
 
 struct BF16Store {
+    typedef uint4 Row;
     static __device__ __forceinline__ float lo16(uint32_t v) { return __uint_as_float(v << 16); }
     static __device__ __forceinline__ float hi16(uint32_t v) { return __uint_as_float(v & 0xffff0000u); }
-    static __device__ __forceinline__ void acc(const void* base, uint32_t idx, float w, float* t) {
-        const uint4 v = reinterpret_cast<const uint4*>(base)[idx];
+    static __device__ __forceinline__ Row load(const void* base, uint32_t idx) {
+        return reinterpret_cast<const uint4*>(base)[idx];
+    }
+    static __device__ __forceinline__ void acc(const Row& v, float w, float* t) {
         t[0] += w * lo16(v.x); t[1] += w * hi16(v.x); t[2] += w * lo16(v.y); t[3] += w * hi16(v.y);
         t[4] += w * lo16(v.z); t[5] += w * hi16(v.z); t[6] += w * lo16(v.w); t[7] += w * hi16(v.w);
     }
@@ -230,34 +239,106 @@ __device__ __forceinline__ Corners corners_of(const SceneDev& sc, float3 p) {
 }
 
 // Eq. 2: t = trilinear(V) + bilinear(P_xy) + bilinear(P_xz) + bilinear(P_yz).
+// All 20 corner loads are issued before the first one is consumed.
 template <class S>
 __device__ __forceinline__ void gather_features(const SceneDev& sc, const Corners& c, float* t) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) t[i] = 0.0f;
     const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
-    const float x0 = 1.0f - c.fx, x1 = c.fx, y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
-    S::acc(sc.grid, c.g, x0 * y0 * z0, t);
-    S::acc(sc.grid, c.g + 1, x1 * y0 * z0, t);
-    S::acc(sc.grid, c.g + sy, x0 * y1 * z0, t);
-    S::acc(sc.grid, c.g + sy + 1, x1 * y1 * z0, t);
-    S::acc(sc.grid, c.g + sz, x0 * y0 * z1, t);
-    S::acc(sc.grid, c.g + sz + 1, x1 * y0 * z1, t);
-    S::acc(sc.grid, c.g + sz + sy, x0 * y1 * z1, t);
-    S::acc(sc.grid, c.g + sz + sy + 1, x1 * y1 * z1, t);
-    const float a0 = 1.0f - c.ux, a1 = c.ux, b0 = 1.0f - c.uy, b1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
     const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
-    S::acc(sc.pxy, c.xy, a0 * b0, t);
-    S::acc(sc.pxy, c.xy + 1, a1 * b0, t);
-    S::acc(sc.pxy, c.xy + nx, a0 * b1, t);
-    S::acc(sc.pxy, c.xy + nx + 1, a1 * b1, t);
-    S::acc(sc.pxz, c.xz, a0 * e0, t);
-    S::acc(sc.pxz, c.xz + 1, a1 * e0, t);
-    S::acc(sc.pxz, c.xz + nx, a0 * e1, t);
-    S::acc(sc.pxz, c.xz + nx + 1, a1 * e1, t);
-    S::acc(sc.pyz, c.yz, b0 * e0, t);
-    S::acc(sc.pyz, c.yz + 1, b1 * e0, t);
-    S::acc(sc.pyz, c.yz + ny, b0 * e1, t);
-    S::acc(sc.pyz, c.yz + ny + 1, b1 * e1, t);
+    typename S::Row r[20];
+    r[0] = S::load(sc.grid, c.g);
+    r[1] = S::load(sc.grid, c.g + 1);
+    r[2] = S::load(sc.grid, c.g + sy);
+    r[3] = S::load(sc.grid, c.g + sy + 1);
+    r[4] = S::load(sc.grid, c.g + sz);
+    r[5] = S::load(sc.grid, c.g + sz + 1);
+    r[6] = S::load(sc.grid, c.g + sz + sy);
+    r[7] = S::load(sc.grid, c.g + sz + sy + 1);
+    r[8] = S::load(sc.pxy, c.xy);
+    r[9] = S::load(sc.pxy, c.xy + 1);
+    r[10] = S::load(sc.pxy, c.xy + nx);
+    r[11] = S::load(sc.pxy, c.xy + nx + 1);
+    r[12] = S::load(sc.pxz, c.xz);
+    r[13] = S::load(sc.pxz, c.xz + 1);
+    r[14] = S::load(sc.pxz, c.xz + nx);
+    r[15] = S::load(sc.pxz, c.xz + nx + 1);
+    r[16] = S::load(sc.pyz, c.yz);
+    r[17] = S::load(sc.pyz, c.yz + 1);
+    r[18] = S::load(sc.pyz, c.yz + ny);
+    r[19] = S::load(sc.pyz, c.yz + ny + 1);
+    const float x0 = 1.0f - c.fx, x1 = c.fx, y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
+    const float a0 = 1.0f - c.ux, a1 = c.ux, b0 = 1.0f - c.uy, b1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
+    S::acc(r[0], x0 * y0 * z0, t);
+    S::acc(r[1], x1 * y0 * z0, t);
+    S::acc(r[2], x0 * y1 * z0, t);
+    S::acc(r[3], x1 * y1 * z0, t);
+    S::acc(r[4], x0 * y0 * z1, t);
+    S::acc(r[5], x1 * y0 * z1, t);
+    S::acc(r[6], x0 * y1 * z1, t);
+    S::acc(r[7], x1 * y1 * z1, t);
+    S::acc(r[8], a0 * b0, t);
+    S::acc(r[9], a1 * b0, t);
+    S::acc(r[10], a0 * b1, t);
+    S::acc(r[11], a1 * b1, t);
+    S::acc(r[12], a0 * e0, t);
+    S::acc(r[13], a1 * e0, t);
+    S::acc(r[14], a0 * e1, t);
+    S::acc(r[15], a1 * e1, t);
+    S::acc(r[16], b0 * e0, t);
+    S::acc(r[17], b1 * e0, t);
+    S::acc(r[18], b0 * e1, t);
+    S::acc(r[19], b1 * e1, t);
+}
+
+// Same sum with at most 12 corners in flight (grid first, then planes), for
+// kernels that carry more live state than the forward march.
+template <class S>
+__device__ __forceinline__ void gather_features_split(const SceneDev& sc, const Corners& c, float* t) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = 0.0f;
+    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
+    const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
+    {
+        typename S::Row r[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] = S::load(sc.grid, c.g + ((j >> 2) ? sz : 0u) + (((j >> 1) & 1) ? sy : 0u) + (j & 1));
+        const float x0 = 1.0f - c.fx, x1 = c.fx, y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
+        S::acc(r[0], x0 * y0 * z0, t);
+        S::acc(r[1], x1 * y0 * z0, t);
+        S::acc(r[2], x0 * y1 * z0, t);
+        S::acc(r[3], x1 * y1 * z0, t);
+        S::acc(r[4], x0 * y0 * z1, t);
+        S::acc(r[5], x1 * y0 * z1, t);
+        S::acc(r[6], x0 * y1 * z1, t);
+        S::acc(r[7], x1 * y1 * z1, t);
+    }
+    typename S::Row r[12];
+    r[0] = S::load(sc.pxy, c.xy);
+    r[1] = S::load(sc.pxy, c.xy + 1);
+    r[2] = S::load(sc.pxy, c.xy + nx);
+    r[3] = S::load(sc.pxy, c.xy + nx + 1);
+    r[4] = S::load(sc.pxz, c.xz);
+    r[5] = S::load(sc.pxz, c.xz + 1);
+    r[6] = S::load(sc.pxz, c.xz + nx);
+    r[7] = S::load(sc.pxz, c.xz + nx + 1);
+    r[8] = S::load(sc.pyz, c.yz);
+    r[9] = S::load(sc.pyz, c.yz + 1);
+    r[10] = S::load(sc.pyz, c.yz + ny);
+    r[11] = S::load(sc.pyz, c.yz + ny + 1);
+    const float a0 = 1.0f - c.ux, a1 = c.ux, b0 = 1.0f - c.uy, b1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
+    S::acc(r[0], a0 * b0, t);
+    S::acc(r[1], a1 * b0, t);
+    S::acc(r[2], a0 * b1, t);
+    S::acc(r[3], a1 * b1, t);
+    S::acc(r[4], a0 * e0, t);
+    S::acc(r[5], a1 * e0, t);
+    S::acc(r[6], a0 * e1, t);
+    S::acc(r[7], a1 * e1, t);
+    S::acc(r[8], b0 * e0, t);
+    S::acc(r[9], b1 * e0, t);
+    S::acc(r[10], b0 * e1, t);
+    S::acc(r[11], b1 * e1, t);
 }
 
 __device__ __forceinline__ float sigmoidf_fast(float x) {

@@ -115,8 +115,8 @@ def _pick_params(grads, per_source=12, mlp=16, seed=3):
     return picks
 
 
-def _fd_check(scene, t, og, dg, tg, n_max, grads, eps=1e-3):
-    picks = _pick_params(grads)
+def _fd_check(scene, t, og, dg, tg, n_max, grads, eps=1e-3, picks=None):
+    picks = _pick_params(grads) if picks is None else picks
     fd, an = [], []
     for src, e in picks:
         flat = t[src].view(-1)
@@ -224,22 +224,22 @@ def test_towers_full_bf16_gradient_error(towers):
 
 @pytest.fixture(scope="module")
 def oblique_train():
-    log("building oblique scene, perturbed copy and 2^18 training rays")
+    log("building oblique scene, perturbed copy, 2^18 training rays and their oracle targets")
     cfg, rec = scenegen.workload("train-2^18")
     sc = scenegen.make_scene(cfg)
     pert = scenegen.perturb_scene(sc, 0.05, seed=2)
     o, d = scenegen.make_rays(rec)
     prm = oracle.RenderParams(n_max=rec["n_max"], c_bg=BG)
-    o256, d256 = o[:256].copy(), d[:256].copy()
-    t256 = oracle.oracle_render(pert, o256, d256, prm, keep_k=False)["C"].astype(np.float32)
+    target = oracle.oracle_render(pert, o, d, prm, keep_k=False, chunk=4096)["C"].astype(np.float32)
     del pert
     scene, t = upload_scene(sc)
-    return sc, scene, t, o, d, o256, d256, t256, rec["n_max"]
+    return sc, scene, t, o, d, target, rec["n_max"]
 
 
 def test_oblique_backward_vs_oracle_256(oblique_train):
-    sc, scene, t, o, d, o256, d256, t256, n_max = oblique_train
+    sc, scene, t, o, d, target, n_max = oblique_train
     log("test_oblique_backward_vs_oracle_256: oblique scene, 256 rays, perturbed-scene targets")
+    o256, d256, t256 = o[:256].copy(), d[:256].copy(), target[:256].copy()
     og, dg = rays_to(o256, d256)
     tg = torch.from_numpy(t256).to(og.device)
     _, loss, grads = _gpu_grads(scene, t, og, dg, tg, n_max)
@@ -250,15 +250,18 @@ def test_oblique_backward_vs_oracle_256(oblique_train):
 
 
 def test_oblique_finite_differences_2e18(oblique_train):
-    """Central FD (eps = 1e-3) of the float64 GPU loss over all 2^18 rays."""
-    sc, scene, t, o, d, o256, d256, t256, n_max = oblique_train
+    """Central FD (eps = 1e-3) of the float64 GPU loss over all 2^18 rays,
+    L2 against oracle renders of the perturbed scene."""
+    sc, scene, t, o, d, target, n_max = oblique_train
     log("test_oblique_finite_differences_2e18: 64 params, 2^18 rays")
     og, dg = rays_to(o, d)
-    res = om.render(scene, og, dg, n_max=n_max, c_bg=BG)
-    g = torch.Generator(device=og.device)
-    g.manual_seed(5)
-    tg = (res["C"] + 0.05 * torch.randn(res["C"].shape, device=og.device, generator=g)).contiguous()
+    tg = torch.from_numpy(target).to(og.device)
     _, _, grads = _gpu_grads(scene, t, og, dg, tg, n_max)
     picks, fd, an, err = _fd_check(scene, t, og, dg, tg, n_max, grads)
-    log(f"  FD: {len(picks)} params, max rel err {err.max():.2e}, median {np.median(err):.2e}")
+    for src in (*SOURCES, "mlp"):
+        sel = [i for i, (s_, _) in enumerate(picks) if s_ == src]
+        log(f"  FD eps=1e-3 {src:9s}: max rel err {err[sel].max():.2e}, median {np.median(err[sel]):.2e}")
+    mlp_sel = [(s_, e) for s_, e in picks if s_ == "mlp"]
+    _, fd4, an4, err4 = _fd_check(scene, t, og, dg, tg, n_max, grads, eps=1e-4, picks=mlp_sel)
+    log(f"  FD eps=1e-4 mlp      : max rel err {err4.max():.2e}, median {np.median(err4):.2e}")
     assert err.max() <= 1e-3, [(p, f, a) for p, f, a, e in zip(picks, fd, an, err) if e > 1e-3]

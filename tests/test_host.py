@@ -1,0 +1,47 @@
+"""Host-side checks that need no GPU: the benchmark's one-GPU contract and
+the determinism of the seeded input generators."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import scenegen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_scene_independent_of_thread_count(monkeypatch):
+    a = scenegen.make_scene(scenegen.TINY)
+    monkeypatch.setattr(scenegen, "_threads", lambda: 1)
+    b = scenegen.make_scene(scenegen.TINY)
+    for k in ("grid", "plane_xy", "plane_xz", "plane_yz", "occ", "mlp"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_ray_orders_are_permutations():
+    for order in ("row", "tile4", "morton"):
+        p = scenegen.pixel_order(64, 48, order)
+        assert np.array_equal(np.sort(p), np.arange(64 * 48)), order
+    # a 4x4 tile / Morton block of 16 consecutive rays is a 4x4 pixel square
+    for order in ("tile4", "morton"):
+        p = scenegen.pixel_order(64, 48, order)[:16]
+        ys, xs = np.divmod(p, 64)
+        assert ys.max() - ys.min() == 3 and xs.max() - xs.min() == 3
+
+
+def test_towers_scene_has_uneven_intervals():
+    cfg = scenegen.SceneConfig(grid=(8, 8, 8), planes=(8, 8, 8), occ=64, band=0.01, tower_fraction=0.1)
+    sc = scenegen.make_scene(cfg)
+    thick = sc["occ"][..., 1] - sc["occ"][..., 0]
+    assert (thick > 0.019).mean() >= 0.1
+    assert thick.max() <= 0.25 + 1e-6
