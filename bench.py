@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--t-term", type=float, default=0.0)
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and fwd+bwd forms")
+    ap.add_argument("--forms", default="bf16_render,fp32_fwd_bwd,bf16_render_4k_x8,towers_bf16_fwd_bwd",
+                    help="comma-separated subset of forms to run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--crop", type=int, default=256, help="side of the centre crop timed on the CPU oracle")
     ap.add_argument("--order", default=None, help="ray issue order of the image (row | tile4)")
@@ -268,10 +270,14 @@ def main():
     gpu_c = out["C"][torch.from_numpy(px).to(dev)].double().cpu().numpy()
 
     forms = {}
-    if not a.no_forms:
+    want = set() if a.no_forms else set(a.forms.split(","))
+    if "bf16_render" in want:
         forms["bf16_render"] = form_bf16_render(om, torch, t, og, dg, out, kw, samples, n, a)
+    if "fp32_fwd_bwd" in want:
         forms["fp32_fwd_bwd"] = form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a)
+    if "bf16_render_4k_x8" in want:
         forms["bf16_render_4k_x8"] = form_bf16_4k(om, scenegen, torch, t, kw, a)
+    if "towers_bf16_fwd_bwd" in want:
         del t, scene, out, og, dg
         torch.cuda.empty_cache()
         forms["towers_bf16_fwd_bwd"] = form_towers(om, scenegen, torch, a)

@@ -36,15 +36,17 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(asm_dir: str | None = None, verbose: bool = False) -> str:
-    """Compile every source to an object, then link the shared library."""
-    obj_dir = os.path.join(ROOT, "_build")
+def build(asm_dir: str | None = None, verbose: bool = False, out: str | None = None,
+          defines: tuple = ()) -> str:
+    """Compile every source to an object, then link the shared library
+    (to `out`, default the in-tree libomerf.so) with extra -D `defines`."""
+    obj_dir = os.path.join(ROOT, "_build", "_".join(defines) or "default")
     os.makedirs(obj_dir, exist_ok=True)
     cc = hipcc()
 
     def compile_one(src: str) -> str:
         obj = os.path.join(obj_dir, src.replace(".hip", ".o"))
-        cmd = [cc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *FLAGS, *[f"-D{x}" for x in defines], "-c", os.path.join(CSRC, src), "-o", obj]
         if asm_dir:
             os.makedirs(asm_dir, exist_ok=True)
             cmd += ["-save-temps=obj"]
@@ -59,13 +61,15 @@ def build(asm_dir: str | None = None, verbose: bool = False) -> str:
 
     with ThreadPoolExecutor(len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
+    lib = out or LIB
+    os.makedirs(os.path.dirname(lib), exist_ok=True)
+    tmp = lib + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

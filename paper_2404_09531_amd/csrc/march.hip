@@ -106,6 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
                                                       float* __restrict__ F, float* __restrict__ T,
                                                       int32_t* __restrict__ n_placed, int32_t* __restrict__ n_eval) {
     __shared__ int qs[kGroupsPerBlock][kQueue];
+    __shared__ typename S::Row stage[kGroupsPerBlock][kStage];
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kGroup - 1);
     const int gid = threadIdx.x / kGroup;
@@ -118,15 +119,16 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
     float carry = 0.0f;  // optical depth of all samples before the batch
     int evals = 0;
     const int placed = march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
+        const bool act = gl < nb;
+        Corners cn;
+        if (act) cn = corners_of(sc, lattice_point(kq, o, d, rp.delta));
+        float t[8];
+        gather_march<S>(sc, cn, act, gl, stage[gid], t);
         float a = 0.0f;
         float v[7];
 #pragma unroll
         for (int c = 0; c < 7; ++c) v[c] = 0.0f;
-        if (gl < nb) {
-            const float3 p = lattice_point(kq, o, d, rp.delta);
-            const Corners cn = corners_of(sc, p);
-            float t[8];
-            gather_features<S>(sc, cn, t);
+        if (act) {
             a = __expf(t[0]) * rp.delta;
 #pragma unroll
             for (int c = 0; c < 7; ++c) v[c] = sigmoidf_fast(t[c + 1]);
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
         bool stop = false;
         if (rp.t_term > 0.0f) {
             const float Tnext = __expf(-(carry + incl));
-            const uint32_t m = g_ballot(gl < nb && Tnext < rp.t_term, lane);
+            const uint32_t m = g_ballot(act && Tnext < rp.t_term, lane);
             if (m) {
                 nb_eff = __ffs(m);  // index of first terminating lane + 1
                 stop = true;

@@ -1,0 +1,154 @@
+"""Mutation check of the oracle pins: plant a plausible mistake in the oracle
+(on the CPU) and require that at least one pin of test_oracle_pins fails.
+
+Each mutant is a small, realistic slip -- a dropped feature source, a
+transposed plane, a cell-centred instead of vertex-aligned grid, a missing
+transmittance factor, a wrong decay, a lost background term, a missing ReLU,
+a rounded instead of floored cell index, an open instead of closed interval,
+an off-by-one lattice step.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle.field as field
+import oracle.placement as placement
+import oracle.render as render
+from tests import test_oracle_pins as pins
+
+PIN_TESTS = [
+    pins.test_vertical_rays_closed_form_counts,
+    pins.test_horizontal_ray_closed_form_counts,
+    pins.test_empty_and_full_plane,
+    pins.test_placement_brute_force_small,
+    pins.test_affine_field_reproduced_exactly,
+    pins.test_interpolation_matches_grid_sample,
+    lambda: pins.test_constant_density_closed_form(50.0, 1024),
+    pins.test_single_sample_weight_is_alpha,
+    pins.test_opaque_first_sample,
+    pins.test_mlp_hand_example,
+    pins.test_ert_stops_after_crossing_sample,
+]
+
+
+def _any_pin_fails():
+    for t in PIN_TESTS:
+        try:
+            t()
+        except (AssertionError, ValueError, IndexError, RuntimeError):
+            return True
+    return False
+
+
+def _drop_plane_yz(orig):
+    def f(*a, **k):
+        terms = orig(*a, **k)
+        idx, w = terms["plane_yz"]
+        terms["plane_yz"] = (idx, np.zeros_like(w))
+        return terms
+    return f
+
+
+def _transpose_xz(orig):
+    def f(p, box_lo, box_hi, grid_dims, plane_dims):
+        terms = orig(p, box_lo, box_hi, grid_dims, plane_dims)
+        nx, ny, nz = plane_dims
+        # index the XZ plane as [x][z] instead of [z][x]
+        terms["plane_xz"] = field.bilinear_corners(p[:, 2], p[:, 0], box_lo[2], box_hi[2], box_lo[0], box_hi[0],
+                                                   nz, nx)
+        return terms
+    return f
+
+
+def _cell_centred(c, lo, hi, n):
+    u = (np.asarray(c, dtype=np.float64) - lo) / (hi - lo) * n - 0.5
+    i0 = np.clip(np.floor(u), 0, n - 2).astype(np.int64)
+    return i0, u - i0
+
+
+def _composite_no_T(tau, cd, f, n_placed, delta, t_term=0.0):
+    r, s_max = tau.shape
+    cd_acc = torch.zeros(r, 3, dtype=torch.float64)
+    f_acc = torch.zeros(r, 4, dtype=torch.float64)
+    T = torch.ones(r, dtype=torch.float64)
+    npl = torch.as_tensor(n_placed, dtype=torch.int64)
+    for s in range(s_max):
+        m = npl > s
+        a = tau[:, s] * delta
+        w = torch.where(m, -torch.expm1(-a), torch.zeros_like(a))  # T dropped
+        cd_acc = cd_acc + w[:, None] * cd[:, s]
+        f_acc = f_acc + w[:, None] * f[:, s]
+        T = torch.where(m, T * torch.exp(-a), T)
+    return cd_acc, f_acc, T, npl
+
+
+def _wrap_composite_decay(orig):
+    def f(tau, cd, fe, n_placed, delta, t_term=0.0):
+        return orig(tau, cd, fe, n_placed, 2.0 * delta, t_term)
+    return f
+
+
+def _mlp_no_relu(x, mlp):
+    w1, b1, w2, b2, w3, b3 = render.unpack_mlp(mlp)
+    return torch.sigmoid(((x @ w1.T + b1) @ w2.T + b2) @ w3.T + b3)
+
+
+def _round_cell(p_a, lo, hi, m):
+    scale = m / (hi - lo)
+    v = np.round(np.asarray(p_a, dtype=np.float64) * scale) - lo * scale
+    v = np.where(np.isfinite(v), v, 0.0)
+    return np.clip(v, 0, m - 1).astype(np.int64)
+
+
+def _open_zmax(orig):
+    def f(p, occ, box_lo, box_hi):
+        i = placement.cell_index(p[..., 0], box_lo[0], box_hi[0], occ.shape[1])
+        j = placement.cell_index(p[..., 1], box_lo[1], box_hi[1], occ.shape[0])
+        return orig(p, occ, box_lo, box_hi) & (p[..., 2] < occ[j, i, 1])
+    return f
+
+
+def _off_by_one(orig):
+    def f(o, d, k, delta):
+        return orig(o, d, np.asarray(k) + 1, delta)
+    return f
+
+
+def _no_background(orig):
+    def f(scene, o, d, prm, grad, mlp_leaf=None):
+        res = orig(scene, o, d, prm, grad, mlp_leaf)
+        bg = torch.tensor(list(prm.c_bg), dtype=torch.float64)
+        res["C"] = res["C"] - res["T"][:, None] * bg[None, :]
+        return res
+    return f
+
+
+def _both(mp, name, new):
+    """Patch a field-module function in every module that bound it."""
+    mp.setattr(field, name, new)
+    if hasattr(render, name):
+        mp.setattr(render, name, new)
+
+
+MUTANTS = {
+    "drop plane_yz": lambda mp: _both(mp, "feature_terms", _drop_plane_yz(field.feature_terms)),
+    "transposed XZ plane": lambda mp: _both(mp, "feature_terms", _transpose_xz(field.feature_terms)),
+    "cell-centred grid": lambda mp: mp.setattr(field, "corner_weights_1d", _cell_centred),
+    "weight without T": lambda mp: mp.setattr(render, "composite", _composite_no_T),
+    "double decay": lambda mp: mp.setattr(render, "composite", _wrap_composite_decay(render.composite)),
+    "no ReLU": lambda mp: mp.setattr(render, "mlp_forward", _mlp_no_relu),
+    "rounded cell index": lambda mp: mp.setattr(placement, "cell_index", _round_cell),
+    "open z_max": lambda mp: mp.setattr(placement, "accept_mask", _open_zmax(placement.accept_mask)),
+    "no background term": lambda mp: mp.setattr(render, "_render_chunk", _no_background(render._render_chunk)),
+    "lattice off by one": lambda mp: mp.setattr(placement, "lattice_points", _off_by_one(placement.lattice_points)),
+}
+
+
+def test_unmutated_pins_pass():
+    assert not _any_pin_fails()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, monkeypatch):
+    MUTANTS[name](monkeypatch)
+    assert _any_pin_fails(), f"no pin catches the mutant '{name}'"

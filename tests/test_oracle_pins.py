@@ -16,8 +16,8 @@ import pytest
 import torch
 
 import oracle
-from oracle.field import feature_terms, interp_features
-from oracle.render import mlp_forward
+import oracle.field
+import oracle.render
 from tests._scenes import BOX_HI, BOX_LO, DELTA, micro_scene, vertex_coords
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -210,8 +210,8 @@ def test_affine_field_reproduced_exactly():
     sc = _affine_scene(grid, planes, coef)
     p = np.stack([rng.uniform(-1, 1, 500), rng.uniform(-1, 1, 500), rng.uniform(0, 0.25, 500)], 1)
     p[:3] = [[-1, -1, 0], [1, 1, 0.25], [1, -1, 0.25]]  # faces
-    terms = feature_terms(p, BOX_LO, BOX_HI, grid, planes)
-    t = interp_features(terms, lambda s, c, idx: torch.from_numpy(sc[s].reshape(-1, 8)[idx])).numpy()
+    terms = oracle.field.feature_terms(p, BOX_LO, BOX_HI, grid, planes)
+    t = oracle.field.interp_features(terms, lambda s, c, idx: torch.from_numpy(sc[s].reshape(-1, 8)[idx])).numpy()
     x, y, z = p[:, 0:1], p[:, 1:2], p[:, 2:3]
     g, a, b, e = coef["grid"], coef["plane_xy"], coef["plane_xz"], coef["plane_yz"]
     want = (g[0] + g[1] * x + g[2] * y + g[3] * z + a[0] + a[1] * x + a[2] * y
@@ -225,9 +225,9 @@ def test_interpolation_matches_grid_sample():
     sc = micro_scene(grid=(6, 5, 4), planes=(7, 9, 5), seed=1)
     rng = np.random.default_rng(3)
     p = np.stack([rng.uniform(-1, 1, 300), rng.uniform(-1, 1, 300), rng.uniform(0, 0.25, 300)], 1)
-    terms = feature_terms(p, BOX_LO, BOX_HI, (6, 5, 4), (7, 9, 5))
+    terms = oracle.field.feature_terms(p, BOX_LO, BOX_HI, (6, 5, 4), (7, 9, 5))
     src = {k: torch.from_numpy(sc[k].astype(np.float64)) for k in ("grid", "plane_xy", "plane_xz", "plane_yz")}
-    t = interp_features(terms, lambda s, c, idx: src[s].reshape(-1, 8)[torch.from_numpy(idx)]).numpy()
+    t = oracle.field.interp_features(terms, lambda s, c, idx: src[s].reshape(-1, 8)[torch.from_numpy(idx)]).numpy()
     nx = torch.from_numpy(p[:, 0])
     ny = torch.from_numpy(p[:, 1])
     nz = torch.from_numpy(p[:, 2] / 0.125 - 1)
@@ -329,7 +329,7 @@ def test_mlp_hand_example():
     w3 = np.full((3, 16), 0.1)
     b3 = np.array(g["b3"])
     mlp = torch.from_numpy(np.concatenate([w1.ravel(), b1, w2.ravel(), b2, w3.ravel(), b3]))
-    out = mlp_forward(torch.tensor([g["x"]], dtype=torch.float64), mlp).numpy()[0]
+    out = oracle.render.mlp_forward(torch.tensor([g["x"]], dtype=torch.float64), mlp).numpy()[0]
     np.testing.assert_allclose(out, g["expected_g"], atol=1e-10)
 
 
