@@ -167,6 +167,97 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
 }
 
 // ---------------------------------------------------------------------------
+// Forward march, lane-pair shading: each queued batch of up to 16 samples is
+// shaded as two halves of 8 samples; sample s of a half is owned by lanes
+// 2s and 2s+1, which fetch the x-offset-0 and x-offset-1 corners (the two
+// 32-byte halves of one contiguous 64-byte pair) and add their partial sums
+// with a lane swap.  Each gather instruction then covers 32 samples with two
+// adjacent corners per sample.  Transmittance comes from a 16-lane scan with
+// the optical depth on the even lanes only.
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(kBlock) void k_march_fwd_pair(SceneDev sc, RayParams rp, const float* __restrict__ o_,
+                                                           const float* __restrict__ d_, int64_t n,
+                                                           float* __restrict__ F, float* __restrict__ T,
+                                                           int32_t* __restrict__ n_placed,
+                                                           int32_t* __restrict__ n_eval) {
+    __shared__ int qs[kGroupsPerBlock][kQueue];
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (kGroup - 1);
+    const int gid = threadIdx.x / kGroup;
+    const int half = gl & 1;
+    const int64_t ray = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kGroupsPerBlock + gid;
+    if (ray >= n) return;
+    const float3 o = load3(o_, ray), d = load3(d_, ray);
+    float acc[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) acc[c] = 0.0f;
+    float carry = 0.0f;
+    int evals = 0;
+    const int placed = march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
+        bool stop = false;
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+            const int nsub = min(max(nb - sub * 8, 0), 8);  // samples in this half (group-uniform)
+            if (nsub > 0 && !stop) {
+                const int s = gl >> 1;
+                const bool act = s < nsub;
+                const int ks = __shfl(kq, sub * 8 + s, kGroup);
+                float t[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) t[c] = 0.0f;
+                if (act) {
+                    const Corners cn = corners_of(sc, lattice_point(ks, o, d, rp.delta));
+                    gather_half<S>(sc, cn, half, t);
+                }
+#pragma unroll
+                for (int c = 0; c < 8; ++c) t[c] += pair_swap(t[c]);
+                float a = 0.0f;
+                float v[7];
+#pragma unroll
+                for (int c = 0; c < 7; ++c) v[c] = 0.0f;
+                if (act) {
+                    a = __expf(t[0]) * rp.delta;
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) v[c] = sigmoidf_fast(t[c + 1]);
+                }
+                const float ae = half ? 0.0f : a;             // depth on the even lane of each pair
+                const float incl = g_scan_incl(ae, gl);         // lane 2s: sum_{j<=s} a_j
+                const float excl_e = g_shift_up1(incl);         // even lanes: sum_{j<s} a_j (from lane 2s-1)
+                const float excl = half ? pair_swap(excl_e) : excl_e;
+                const float Ti = __expf(-(carry + excl));
+                float w = Ti * (-expm1f(-a));
+                int nb_eff = nsub;
+                if (rp.t_term > 0.0f) {
+                    const float Tnext = __expf(-(carry + incl));
+                    const uint32_t m = g_ballot(act && !half && Tnext < rp.t_term, lane);
+                    if (m) {
+                        nb_eff = ((__ffs(m) - 1) >> 1) + 1;
+                        stop = true;
+                    }
+                }
+                if (s >= nb_eff || half) w = 0.0f;  // accumulate once per sample (even lane)
+#pragma unroll
+                for (int c = 0; c < 7; ++c) acc[c] += w * v[c];
+                carry += __shfl(incl, 2 * (nb_eff - 1), kGroup);
+                evals += nb_eff;
+            }
+        }
+        return stop;
+    });
+    float f[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) f[c] = g_sum(acc[c]);
+    if (gl == 0) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) F[ray * 7 + c] = f[c];
+        T[ray] = __expf(-carry);
+        n_placed[ray] = placed;
+        n_eval[ray] = evals;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Backward.  Per ray: the deferred MLP backward runs across the 16 lanes of
 // the group (lane h owns hidden unit h of both hidden layers), giving
 // g7 = dL/dF (+ dL/dC on the diffuse part).  The samples are then replayed
@@ -484,8 +575,21 @@ hipError_t launch_place(const SceneDev& sc, const RayParams& rp, const float* o,
     return hipGetLastError();
 }
 
+#ifndef OMERF_PAIR
+#define OMERF_PAIR 0
+#endif
+
 hipError_t launch_march_fwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
                             int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, hipStream_t s) {
+    if (OMERF_PAIR) {
+        if (bf16)
+            hipLaunchKernelGGL(k_march_fwd_pair<BF16Store>, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n,
+                               F, T, n_placed, n_eval);
+        else
+            hipLaunchKernelGGL(k_march_fwd_pair<F32Store>, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n,
+                               F, T, n_placed, n_eval);
+        return hipGetLastError();
+    }
     if (bf16)
         hipLaunchKernelGGL(k_march_fwd<BF16Store>, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n, F, T,
                            n_placed, n_eval);

@@ -365,6 +365,11 @@ __device__ __forceinline__ float g_scan_incl(float x, int /*gl*/) {
     return x;
 }
 
+// Value of the neighbouring lane of the pair (lane ^ 1), via DPP quad_perm.
+__device__ __forceinline__ float pair_swap(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xf, 0xf, false));  // [1,0,3,2]
+}
+
 // Value of the next lower lane (0 for lane 0).
 __device__ __forceinline__ float g_shift_up1(float x) { return dpp_row<kRowShr | 1>(x); }
 
@@ -505,6 +510,45 @@ __device__ __forceinline__ void stage_plane(const void* P, int na, int ia, int i
 #pragma unroll
         for (int j = 0; j < 4; ++j) S::acc(r[j], w[j], t);
     }
+}
+
+// Half of Eq. 2 for lane-pair shading: the lane with x-offset h (0 or 1)
+// sums the corners whose first interpolation axis index is i0 + h (grid: x;
+// XY and XZ planes: x; YZ plane: y).  The two lanes' partial sums add up to
+// the full feature vector.
+template <class S>
+__device__ __forceinline__ void gather_half(const SceneDev& sc, const Corners& c, int h, float* t) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = 0.0f;
+    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
+    const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
+    const uint32_t hh = (uint32_t)h;
+    typename S::Row r[10];
+    r[0] = S::load(sc.grid, c.g + hh);
+    r[1] = S::load(sc.grid, c.g + sy + hh);
+    r[2] = S::load(sc.grid, c.g + sz + hh);
+    r[3] = S::load(sc.grid, c.g + sz + sy + hh);
+    r[4] = S::load(sc.pxy, c.xy + hh);
+    r[5] = S::load(sc.pxy, c.xy + nx + hh);
+    r[6] = S::load(sc.pxz, c.xz + hh);
+    r[7] = S::load(sc.pxz, c.xz + nx + hh);
+    r[8] = S::load(sc.pyz, c.yz + hh);
+    r[9] = S::load(sc.pyz, c.yz + ny + hh);
+    const float wx = h ? c.fx : 1.0f - c.fx;
+    const float y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
+    const float wa = h ? c.ux : 1.0f - c.ux;  // x for XY / XZ
+    const float wb = h ? c.uy : 1.0f - c.uy;  // y for YZ
+    const float b0 = 1.0f - c.uy, b1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
+    S::acc(r[0], wx * y0 * z0, t);
+    S::acc(r[1], wx * y1 * z0, t);
+    S::acc(r[2], wx * y0 * z1, t);
+    S::acc(r[3], wx * y1 * z1, t);
+    S::acc(r[4], wa * b0, t);
+    S::acc(r[5], wa * b1, t);
+    S::acc(r[6], wa * e0, t);
+    S::acc(r[7], wa * e1, t);
+    S::acc(r[8], wb * e0, t);
+    S::acc(r[9], wb * e1, t);
 }
 
 #ifndef OMERF_GATHER
