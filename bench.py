@@ -150,7 +150,7 @@ def form_bf16_4k(om, scenegen, torch, t, kw, a):
     n = 8 * W * H
     og = torch.empty((n, 3), device=dev)
     dg = torch.empty((n, 3), device=dev)
-    px = scenegen.pixel_order(W, H, "tile4")
+    px = scenegen.pixel_order(W, H, "morton")
     for i, (p, y, aim) in enumerate(cams):
         o, d = scenegen.camera_rays(W, H, p, y, aim, pixels=px)
         og[i * W * H:(i + 1) * W * H] = torch.from_numpy(o).to(dev)
@@ -163,7 +163,7 @@ def form_bf16_4k(om, scenegen, torch, t, kw, a):
     tot, (mb_ms, lb_ms) = time_stages([mb, lb], steps, 1, torch)
     ms = tot / steps
     sb = int(outb["n_eval"].sum().item())
-    return {"workload": "8 x 3840x2160, pitch U[30,60] deg, tile4 order", "rays": n,
+    return {"workload": "8 x 3840x2160, pitch U[30,60] deg, Morton ray order", "rays": n,
             "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 3),
             "march_ms": round(mb_ms, 3), "mlp_ms": round(lb_ms, 3), "samples_per_ray": round(sb / n, 1),
             "Msamples_per_s": round(sb / (ms * 1e-3) / 1e6, 1),

@@ -112,13 +112,14 @@ class Scene:
         return self._handle
 
     def __del__(self):
-        h = getattr(self, "_handle", None)
-        if h is not None and h.value:
-            try:
+        # may run during interpreter shutdown, when module globals are gone
+        try:
+            h = self._handle
+            if h is not None and h.value:
                 _lib.lib().om_scene_destroy(h)
-            except Exception:
-                pass
-            self._handle = ctypes.c_void_p()
+                h.value = None
+        except Exception:
+            pass
 
 
 def _params(n_max: int, delta: float, t_term: float, c_bg, mlp_bf16: int) -> _lib.OmParams:

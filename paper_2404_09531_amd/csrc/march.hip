@@ -99,75 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_place(SceneDev sc, RayParams rp, con
 
 // ---------------------------------------------------------------------------
 // Forward march: writes F [n][7], T [n], n_placed [n], n_eval [n].
-// ---------------------------------------------------------------------------
-template <class S>
-__global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
-                                                      const float* __restrict__ d_, int64_t n,
-                                                      float* __restrict__ F, float* __restrict__ T,
-                                                      int32_t* __restrict__ n_placed, int32_t* __restrict__ n_eval) {
-    __shared__ int qs[kGroupsPerBlock][kQueue];
-    __shared__ typename S::Row stage[kGroupsPerBlock][kStage];
-    const int lane = threadIdx.x & 63;
-    const int gl = lane & (kGroup - 1);
-    const int gid = threadIdx.x / kGroup;
-    const int64_t ray = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kGroupsPerBlock + gid;
-    if (ray >= n) return;
-    const float3 o = load3(o_, ray), d = load3(d_, ray);
-    float acc[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) acc[c] = 0.0f;
-    float carry = 0.0f;  // optical depth of all samples before the batch
-    int evals = 0;
-    const int placed = march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
-        const bool act = gl < nb;
-        Corners cn;
-        if (act) cn = corners_of(sc, lattice_point(kq, o, d, rp.delta));
-        float t[8];
-        gather_march<S>(sc, cn, act, gl, stage[gid], t);
-        float a = 0.0f;
-        float v[7];
-#pragma unroll
-        for (int c = 0; c < 7; ++c) v[c] = 0.0f;
-        if (act) {
-            a = __expf(t[0]) * rp.delta;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) v[c] = sigmoidf_fast(t[c + 1]);
-        }
-        const float incl = g_scan_incl(a, gl);
-        const float excl = g_shift_up1(incl);
-        const float Ti = __expf(-(carry + excl));
-        float w = Ti * (-expm1f(-a));
-        int nb_eff = nb;
-        bool stop = false;
-        if (rp.t_term > 0.0f) {
-            const float Tnext = __expf(-(carry + incl));
-            const uint32_t m = g_ballot(act && Tnext < rp.t_term, lane);
-            if (m) {
-                nb_eff = __ffs(m);  // index of first terminating lane + 1
-                stop = true;
-            }
-        }
-        if (gl >= nb_eff) w = 0.0f;
-#pragma unroll
-        for (int c = 0; c < 7; ++c) acc[c] += w * v[c];
-        carry += __shfl(incl, nb_eff - 1, kGroup);
-        evals += nb_eff;
-        return stop;
-    });
-    float f[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) f[c] = g_sum(acc[c]);
-    if (gl == 0) {
-#pragma unroll
-        for (int c = 0; c < 7; ++c) F[ray * 7 + c] = f[c];
-        T[ray] = __expf(-carry);
-        n_placed[ray] = placed;
-        n_eval[ray] = evals;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Forward march, lane-pair shading: each queued batch of up to 16 samples is
+// Lane-pair shading: each queued batch of up to 16 samples is
 // shaded as two halves of 8 samples; sample s of a half is owned by lanes
 // 2s and 2s+1, which fetch the x-offset-0 and x-offset-1 corners (the two
 // 32-byte halves of one contiguous 64-byte pair) and add their partial sums
@@ -176,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
 // the optical depth on the even lanes only.
 // ---------------------------------------------------------------------------
 template <class S>
-__global__ __launch_bounds__(kBlock) void k_march_fwd_pair(SceneDev sc, RayParams rp, const float* __restrict__ o_,
+__global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                            const float* __restrict__ d_, int64_t n,
                                                            float* __restrict__ F, float* __restrict__ T,
                                                            int32_t* __restrict__ n_placed,
@@ -277,8 +209,12 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_pair(SceneDev sc, RayParam
 // Scatter: per batch and per feature source, the contributions of the
 // group's 16 samples are first summed in an LDS tile covering the batch's
 // bounding box of corners (consecutive samples of a ray share most
-// corners), then each touched corner is added to global memory once with a
-// float32 atomic.  Boxes larger than the tile fall back to direct atomics.
+// corners), then each touched corner is added to global memory once with
+// float32 atomics laid out so that 16 lanes cover 64 contiguous bytes:
+// device-memory float atomics are resolved beyond L2, one request per
+// 64-byte segment of an instruction, so contiguous lanes are ~16x cheaper
+// than scattered ones.  Boxes larger than the tile fall back to direct
+// atomics.
 // ---------------------------------------------------------------------------
 constexpr int kTile = 64;                       // corners per group tile
 constexpr int kBatchSlots = 1024 / kGroup / kGroup;  // registers holding batch totals (n_max <= 1024)
@@ -299,23 +235,11 @@ __device__ __forceinline__ void tile_add(float* tile, int e, float w, const floa
     for (int c = 0; c < 8; ++c) atomicAdd(tile + e * 8 + c, w * g[c]);
 }
 
-__device__ __forceinline__ void tile_flush_row(float* dst, const float* tile, int e, uint32_t idx) {
-    const float4 a = reinterpret_cast<const float4*>(tile)[e * 2];
-    const float4 b = reinterpret_cast<const float4*>(tile)[e * 2 + 1];
-    float* q = dst + (size_t)idx * 8;
-    if (a.x != 0.f) unsafeAtomicAdd(q + 0, a.x);
-    if (a.y != 0.f) unsafeAtomicAdd(q + 1, a.y);
-    if (a.z != 0.f) unsafeAtomicAdd(q + 2, a.z);
-    if (a.w != 0.f) unsafeAtomicAdd(q + 3, a.w);
-    if (b.x != 0.f) unsafeAtomicAdd(q + 4, b.x);
-    if (b.y != 0.f) unsafeAtomicAdd(q + 5, b.y);
-    if (b.z != 0.f) unsafeAtomicAdd(q + 6, b.z);
-    if (b.w != 0.f) unsafeAtomicAdd(q + 7, b.w);
-}
-
-// Trilinear scatter of gt[8] into the grid gradient.
-__device__ __forceinline__ void scatter_grid(const SceneDev& sc, float* gV, float* tile, bool act, const Corners& cn,
-                                             const float* gt, int gl) {
+// Trilinear scatter of gt[8] into the grid gradient.  Returns false (and
+// does nothing) if the corner box of the participating lanes does not fit
+// the tile and `may_fail` is set.
+__device__ __forceinline__ bool scatter_grid(const SceneDev& sc, float* gV, float* tile, bool act, const Corners& cn,
+                                             const float* gt, int gl, bool may_fail) {
     constexpr int BIG = 1 << 30;
     const int x0 = g_min(act ? cn.ix : BIG), x1 = g_max(act ? cn.ix : -BIG);
     const int y0 = g_min(act ? cn.iy : BIG), y1 = g_max(act ? cn.iy : -BIG);
@@ -337,24 +261,34 @@ __device__ __forceinline__ void scatter_grid(const SceneDev& sc, float* gV, floa
             }
         }
         wave_order();
-        for (int e = gl; e < ent; e += kGroup) {
+        // 16 lanes add two x-adjacent rows x 8 channels (64 contiguous
+        // bytes) per instruction: the memory-side atomic unit takes one
+        // request per 64-byte segment instead of one per float.
+        for (int f = gl; f < ent * 8; f += kGroup) {
+            const int e = f >> 3;
             const int ex = e % bx, r = e / bx, ey = r % by, ez = r / by;
             const uint32_t v = ((uint32_t)(z0 + ez) * (uint32_t)sc.Ly + (uint32_t)(y0 + ey)) * (uint32_t)sc.Lx +
                                (uint32_t)(x0 + ex);
-            tile_flush_row(gV, tile, e, v);
+            const float val = tile[f];
+            if (val != 0.0f) unsafeAtomicAdd(gV + (size_t)v * 8 + (f & 7), val);
         }
         wave_order();
-    } else if (act) {
+        return true;
+    }
+    if (may_fail) return false;
+    if (act) {
         const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
 #pragma unroll
         for (int j = 0; j < 8; ++j)
             atomic_row(gV, cn.g + ((j >> 2) ? sz : 0u) + (((j >> 1) & 1) ? sy : 0u) + (j & 1), w[j], gt);
     }
+    return true;
 }
 
-// Bilinear scatter into a plane gradient [nb][na][8] at base texel (ia, ib).
-__device__ __forceinline__ void scatter_plane(float* gP, int na, float* tile, bool act, int ia, int ib, float fa,
-                                              float fb, const float* gt, int gl) {
+// Bilinear scatter into a plane gradient [nb][na][8] at base texel (ia, ib);
+// same contract as scatter_grid.
+__device__ __forceinline__ bool scatter_plane(float* gP, int na, float* tile, bool act, int ia, int ib, float fa,
+                                              float fb, const float* gt, int gl, bool may_fail) {
     constexpr int BIG = 1 << 30;
     const int a0 = g_min(act ? ia : BIG), a1 = g_max(act ? ia : -BIG);
     const int b0 = g_min(act ? ib : BIG), b1 = g_max(act ? ib : -BIG);
@@ -369,15 +303,50 @@ __device__ __forceinline__ void scatter_plane(float* gP, int na, float* tile, bo
             for (int j = 0; j < 4; ++j) tile_add(tile, (ib + (j >> 1) - b0) * ba + (ia + (j & 1) - a0), w[j], gt);
         }
         wave_order();
-        for (int e = gl; e < ent; e += kGroup) {
+        for (int f = gl; f < ent * 8; f += kGroup) {
+            const int e = f >> 3;
             const int ea = e % ba, eb = e / ba;
-            tile_flush_row(gP, tile, e, (uint32_t)(b0 + eb) * (uint32_t)na + (uint32_t)(a0 + ea));
+            const uint32_t row = (uint32_t)(b0 + eb) * (uint32_t)na + (uint32_t)(a0 + ea);
+            const float val = tile[f];
+            if (val != 0.0f) unsafeAtomicAdd(gP + (size_t)row * 8 + (f & 7), val);
         }
         wave_order();
-    } else if (act) {
+        return true;
+    }
+    if (may_fail) return false;
+    if (act) {
         const uint32_t base = (uint32_t)ib * (uint32_t)na + (uint32_t)ia;
 #pragma unroll
         for (int j = 0; j < 4; ++j) atomic_row(gP, base + ((j >> 1) ? (uint32_t)na : 0u) + (j & 1), w[j], gt);
+    }
+    return true;
+}
+
+// Scatter one batch into all four gradient arrays: each source is tried
+// with all 16 samples in one tile, else as two halves of 8 samples (about
+// half the box per axis), else with direct atomics.
+// Lane 0 of the group is always active (a batch has at least one sample),
+// so the first half is never empty; the second half may be.
+__device__ __forceinline__ void scatter_batch(const SceneDev& sc, float* gV, float* gxy, float* gxz, float* gyz,
+                                              float* tile, bool act, const Corners& cn, const float* gt, int gl,
+                                              int lane) {
+    const bool lo = act && gl < 8, hi = act && gl >= 8;
+    const bool hi_any = g_ballot(hi, lane) != 0u;
+    if (!scatter_grid(sc, gV, tile, act, cn, gt, gl, true)) {
+        scatter_grid(sc, gV, tile, lo, cn, gt, gl, false);
+        if (hi_any) scatter_grid(sc, gV, tile, hi, cn, gt, gl, false);
+    }
+    if (!scatter_plane(gxy, sc.Nx, tile, act, cn.jx, cn.jy, cn.ux, cn.uy, gt, gl, true)) {
+        scatter_plane(gxy, sc.Nx, tile, lo, cn.jx, cn.jy, cn.ux, cn.uy, gt, gl, false);
+        if (hi_any) scatter_plane(gxy, sc.Nx, tile, hi, cn.jx, cn.jy, cn.ux, cn.uy, gt, gl, false);
+    }
+    if (!scatter_plane(gxz, sc.Nx, tile, act, cn.jx, cn.jz, cn.ux, cn.uz, gt, gl, true)) {
+        scatter_plane(gxz, sc.Nx, tile, lo, cn.jx, cn.jz, cn.ux, cn.uz, gt, gl, false);
+        if (hi_any) scatter_plane(gxz, sc.Nx, tile, hi, cn.jx, cn.jz, cn.ux, cn.uz, gt, gl, false);
+    }
+    if (!scatter_plane(gyz, sc.Ny, tile, act, cn.jy, cn.jz, cn.uy, cn.uz, gt, gl, true)) {
+        scatter_plane(gyz, sc.Ny, tile, lo, cn.jy, cn.jz, cn.uy, cn.uz, gt, gl, false);
+        if (hi_any) scatter_plane(gyz, sc.Ny, tile, hi, cn.jy, cn.jz, cn.uy, cn.uz, gt, gl, false);
     }
 }
 
@@ -547,10 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
             gt[0] = (Tnext * gv - suffix - Tn * gT) * rp.delta * tau;
 #pragma unroll
             for (int c = 0; c < 7; ++c) gt[c + 1] = w * g7[c] * v[c] * (1.0f - v[c]);
-            scatter_grid(sc, gV, tile, act, cn, gt, gl);
-            scatter_plane(gxy, sc.Nx, tile, act, cn.jx, cn.jy, cn.ux, cn.uy, gt, gl);
-            scatter_plane(gxz, sc.Nx, tile, act, cn.jx, cn.jz, cn.ux, cn.uz, gt, gl);
-            scatter_plane(gyz, sc.Ny, tile, act, cn.jy, cn.jz, cn.uy, cn.uz, gt, gl);
+            scatter_batch(sc, gV, gxy, gxz, gyz, tile, act, cn, gt, gl, lane);
             carry += __shfl(incl, kGroup - 1, kGroup);
             done += nb_eff;
             ++b;
@@ -575,21 +541,8 @@ hipError_t launch_place(const SceneDev& sc, const RayParams& rp, const float* o,
     return hipGetLastError();
 }
 
-#ifndef OMERF_PAIR
-#define OMERF_PAIR 0
-#endif
-
 hipError_t launch_march_fwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
                             int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, hipStream_t s) {
-    if (OMERF_PAIR) {
-        if (bf16)
-            hipLaunchKernelGGL(k_march_fwd_pair<BF16Store>, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n,
-                               F, T, n_placed, n_eval);
-        else
-            hipLaunchKernelGGL(k_march_fwd_pair<F32Store>, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n,
-                               F, T, n_placed, n_eval);
-        return hipGetLastError();
-    }
     if (bf16)
         hipLaunchKernelGGL(k_march_fwd<BF16Store>, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n, F, T,
                            n_placed, n_eval);

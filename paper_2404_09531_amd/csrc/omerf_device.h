@@ -412,106 +412,6 @@ __device__ __forceinline__ void wave_order() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// ---------------------------------------------------------------------------
-// LDS-staged gather (forward march).  Per batch and per feature source, the
-// group loads the bounding box of its samples' corners cooperatively: lane
-// gl takes box entries gl, gl + 16, ... in x-fastest order, so each load
-// instruction reads contiguous runs of corners instead of 16 scattered
-// ones, and every corner shared by several samples is read from memory
-// once.  Each lane then sums its own corners from LDS.  Boxes of more than
-// kStage entries fall back to direct loads.  The values summed are the same
-// in both cases.
-// ---------------------------------------------------------------------------
-constexpr int kStage = 64;  // staged corners per group and source
-
-template <class S>
-__device__ __forceinline__ void stage_grid(const SceneDev& sc, const Corners& c, bool act, int gl,
-                                           typename S::Row* st, float* t) {
-    constexpr int BIG = 1 << 30;
-    const int x0 = g_min(act ? c.ix : BIG), x1 = g_max(act ? c.ix : -BIG);
-    const int y0 = g_min(act ? c.iy : BIG), y1 = g_max(act ? c.iy : -BIG);
-    const int z0 = g_min(act ? c.iz : BIG), z1 = g_max(act ? c.iz : -BIG);
-    const int bx = x1 - x0 + 2, by = y1 - y0 + 2, bz = z1 - z0 + 2;
-    const float xa = 1.0f - c.fx, xb = c.fx, ya = 1.0f - c.fy, yb = c.fy, za = 1.0f - c.fz, zb = c.fz;
-    const float w[8] = {xa * ya * za, xb * ya * za, xa * yb * za, xb * yb * za,
-                        xa * ya * zb, xb * ya * zb, xa * yb * zb, xb * yb * zb};
-    const uint32_t Lx = (uint32_t)sc.Lx, Ly = (uint32_t)sc.Ly;
-    if (bx <= kStage && by <= kStage && bz <= kStage && bx * by * bz <= kStage) {
-        const int cnt = bx * by * bz;
-        typename S::Row r[kStage / kGroup];
-#pragma unroll
-        for (int it = 0; it < kStage / kGroup; ++it) {
-            const int e = gl + it * kGroup;
-            if (e < cnt) {
-                const int ex = e % bx, q = e / bx, ey = q % by, ez = q / by;
-                r[it] = S::load(sc.grid, ((uint32_t)(z0 + ez) * Ly + (uint32_t)(y0 + ey)) * Lx + (uint32_t)(x0 + ex));
-            }
-        }
-#pragma unroll
-        for (int it = 0; it < kStage / kGroup; ++it) {
-            const int e = gl + it * kGroup;
-            if (e < cnt) st[e] = r[it];
-        }
-        wave_order();
-        if (act) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int e = ((c.iz + (j >> 2) - z0) * by + (c.iy + ((j >> 1) & 1) - y0)) * bx + (c.ix + (j & 1) - x0);
-                S::acc(st[e], w[j], t);
-            }
-        }
-        wave_order();
-    } else if (act) {
-        const uint32_t sy = Lx, sz = Lx * Ly;
-        typename S::Row r[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) r[j] = S::load(sc.grid, c.g + ((j >> 2) ? sz : 0u) + (((j >> 1) & 1) ? sy : 0u) + (j & 1));
-#pragma unroll
-        for (int j = 0; j < 8; ++j) S::acc(r[j], w[j], t);
-    }
-}
-
-// Plane [nb][na] at base texel (ia, ib) with fractions (fa, fb).
-template <class S>
-__device__ __forceinline__ void stage_plane(const void* P, int na, int ia, int ib, float fa, float fb, bool act, int gl,
-                                            typename S::Row* st, float* t) {
-    constexpr int BIG = 1 << 30;
-    const int a0 = g_min(act ? ia : BIG), a1 = g_max(act ? ia : -BIG);
-    const int b0 = g_min(act ? ib : BIG), b1 = g_max(act ? ib : -BIG);
-    const int ba = a1 - a0 + 2, bb = b1 - b0 + 2;
-    const float w[4] = {(1.0f - fa) * (1.0f - fb), fa * (1.0f - fb), (1.0f - fa) * fb, fa * fb};
-    if (ba <= kStage && bb <= kStage && ba * bb <= kStage) {
-        const int cnt = ba * bb;
-        typename S::Row r[kStage / kGroup];
-#pragma unroll
-        for (int it = 0; it < kStage / kGroup; ++it) {
-            const int e = gl + it * kGroup;
-            if (e < cnt) {
-                const int ea = e % ba, eb = e / ba;
-                r[it] = S::load(P, (uint32_t)(b0 + eb) * (uint32_t)na + (uint32_t)(a0 + ea));
-            }
-        }
-#pragma unroll
-        for (int it = 0; it < kStage / kGroup; ++it) {
-            const int e = gl + it * kGroup;
-            if (e < cnt) st[e] = r[it];
-        }
-        wave_order();
-        if (act) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) S::acc(st[(ib + (j >> 1) - b0) * ba + (ia + (j & 1) - a0)], w[j], t);
-        }
-        wave_order();
-    } else if (act) {
-        const uint32_t base = (uint32_t)ib * (uint32_t)na + (uint32_t)ia;
-        typename S::Row r[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) r[j] = S::load(P, base + ((j >> 1) ? (uint32_t)na : 0u) + (j & 1));
-#pragma unroll
-        for (int j = 0; j < 4; ++j) S::acc(r[j], w[j], t);
-    }
-}
-
 // Half of Eq. 2 for lane-pair shading: the lane with x-offset h (0 or 1)
 // sums the corners whose first interpolation axis index is i0 + h (grid: x;
 // XY and XZ planes: x; YZ plane: y).  The two lanes' partial sums add up to
@@ -549,70 +449,6 @@ __device__ __forceinline__ void gather_half(const SceneDev& sc, const Corners& c
     S::acc(r[7], wa * e1, t);
     S::acc(r[8], wb * e0, t);
     S::acc(r[9], wb * e1, t);
-}
-
-#ifndef OMERF_GATHER
-#define OMERF_GATHER 0
-#endif
-
-// Eq. 2 for the forward march; all lanes of the group call it, `act`
-// marks the lanes holding a sample (whose Corners are valid).
-template <class S>
-__device__ __forceinline__ void gather_march(const SceneDev& sc, const Corners& c, bool act, int gl,
-                                             typename S::Row* st, float* t) {
-#if OMERF_GATHER == 1
-#pragma unroll
-    for (int i = 0; i < 8; ++i) t[i] = 0.0f;
-    stage_grid<S>(sc, c, act, gl, st, t);
-    stage_plane<S>(sc.pxy, sc.Nx, c.jx, c.jy, c.ux, c.uy, act, gl, st, t);
-    stage_plane<S>(sc.pxz, sc.Nx, c.jx, c.jz, c.ux, c.uz, act, gl, st, t);
-    stage_plane<S>(sc.pyz, sc.Ny, c.jy, c.jz, c.uy, c.uz, act, gl, st, t);
-#elif OMERF_GATHER == 2
-    // planes issued first (direct), grid staged while they are in flight
-    const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
-    typename S::Row r[12];
-    if (act) {
-        r[0] = S::load(sc.pxy, c.xy);
-        r[1] = S::load(sc.pxy, c.xy + 1);
-        r[2] = S::load(sc.pxy, c.xy + nx);
-        r[3] = S::load(sc.pxy, c.xy + nx + 1);
-        r[4] = S::load(sc.pxz, c.xz);
-        r[5] = S::load(sc.pxz, c.xz + 1);
-        r[6] = S::load(sc.pxz, c.xz + nx);
-        r[7] = S::load(sc.pxz, c.xz + nx + 1);
-        r[8] = S::load(sc.pyz, c.yz);
-        r[9] = S::load(sc.pyz, c.yz + 1);
-        r[10] = S::load(sc.pyz, c.yz + ny);
-        r[11] = S::load(sc.pyz, c.yz + ny + 1);
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) t[i] = 0.0f;
-    stage_grid<S>(sc, c, act, gl, st, t);
-    if (act) {
-        const float a0 = 1.0f - c.ux, a1 = c.ux, b0 = 1.0f - c.uy, b1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
-        S::acc(r[0], a0 * b0, t);
-        S::acc(r[1], a1 * b0, t);
-        S::acc(r[2], a0 * b1, t);
-        S::acc(r[3], a1 * b1, t);
-        S::acc(r[4], a0 * e0, t);
-        S::acc(r[5], a1 * e0, t);
-        S::acc(r[6], a0 * e1, t);
-        S::acc(r[7], a1 * e1, t);
-        S::acc(r[8], b0 * e0, t);
-        S::acc(r[9], b1 * e0, t);
-        S::acc(r[10], b0 * e1, t);
-        S::acc(r[11], b1 * e1, t);
-    }
-#else
-    (void)gl;
-    (void)st;
-    if (act) {
-        gather_features<S>(sc, c, t);
-    } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) t[i] = 0.0f;
-    }
-#endif
 }
 
 // Block index -> virtual block index such that the blocks the hardware

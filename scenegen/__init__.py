@@ -374,7 +374,8 @@ def workload(name: str):
     if name == "tiny":
         return TINY, dict(kind="oblique", n=4096, seed=1, n_max=64)
     if name == "oblique-1080p":
-        return OBLIQUE, dict(kind="camera", width=1920, height=1080, pitch=45.0, yaw=90.0, n_max=256)
+        return OBLIQUE, dict(kind="camera", width=1920, height=1080, pitch=45.0, yaw=90.0, n_max=256,
+                             order="morton")
     if name == "train-2^18":
         return OBLIQUE, dict(kind="multi", n=1 << 18, cameras=16, width=1920, height=1080, seed=1, n_max=256)
     if name == "bf16-4k-x8":

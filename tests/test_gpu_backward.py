@@ -1,10 +1,10 @@
 """GPU backward: gradients into grid, planes and MLP against the float64
 oracle gradient and against central finite differences of the GPU forward.
 
-Bars: per-entry relative error <= 1e-3 against the oracle gradient on
-entries with |g| >= 1e-3 max|g|; absolute error <= 1e-5 max|g| on the
-smaller entries, whose float32 sums of cancelling per-sample terms carry
-rounding relative to the terms rather than to the result; finite
+Bars: per entry |g - g_oracle| <= 1e-3 |g_oracle| + 2e-6 max|g_oracle|:
+relative 1e-3, plus an absolute floor for float32 sums of cancelling
+per-sample terms, whose rounding is relative to the terms rather than to
+their sum; finite
 differences (eps = 1e-3, float64 loss reduction on the GPU) within
 |g - g_fd| <= 1e-3 max(|g_fd|, 1e-2 RMS of the checked entries).
 """
@@ -32,23 +32,19 @@ def _gpu_grads(scene, t, og, dg, target, n_max, t_term=0.0):
     return res, loss.item(), {k: v.double().cpu().numpy() for k, v in grads.items()}
 
 
-def _check_against_oracle(sc, grads, ref_grads, rel=1e-3):
+def _check_against_oracle(sc, grads, ref_grads, rel=1e-3, floor=2e-6):
+    scale = max(max(np.abs(ref_grads[s][1]).max() for s in SOURCES), 1e-30)
     for src in SOURCES:
         uniq, rows = ref_grads[src]
         g = grads[src].reshape(-1, 8)
-        got = g[uniq]
-        scale = max(np.abs(rows).max(), 1e-30)
-        big = np.abs(rows) >= 1e-3 * scale
-        err_big = np.abs(got - rows)[big] / np.abs(rows)[big]
-        assert err_big.max() <= rel, (src, err_big.max())
-        assert np.abs(got - rows)[~big].max(initial=0) <= 1e-5 * scale, src
+        excess = np.abs(g[uniq] - rows) - (rel * np.abs(rows) + floor * scale)
+        assert excess.max() <= 0, (src, float(excess.max() / scale))
         mask = np.ones(g.shape[0], bool)
         mask[uniq] = False
         assert np.all(g[mask] == 0), f"{src}: gradient outside the touched rows"
     gm, rm = grads["mlp"], ref_grads["mlp"]
-    big = np.abs(rm) >= 1e-3 * np.abs(rm).max()
-    assert (np.abs(gm - rm)[big] / np.abs(rm)[big]).max() <= rel
-    assert np.abs(gm - rm)[~big].max(initial=0) <= 1e-5 * np.abs(rm).max()
+    excess = np.abs(gm - rm) - (rel * np.abs(rm) + floor * np.abs(rm).max())
+    assert excess.max() <= 0, ("mlp", float(excess.max()))
 
 
 @pytest.fixture(scope="module")
@@ -101,29 +97,35 @@ def test_backward_ert_matches_oracle(tiny_train):
 
 
 def _pick_params(grads, per_source=12, mlp=16, seed=3):
-    """Entries with the largest |g| per tensor (well-conditioned FD), plus a
-    few random ones with nonzero gradient."""
+    """Entries with the largest |g| per tensor, plus two random ones with
+    |g| >= 1e-2 max|g|. A central difference of float32 renders carries an
+    absolute noise of a few ulp of C per ray divided by eps, so only such
+    well-conditioned entries can be held to a relative bar; the small ones
+    are covered by the exact comparison with the float64 oracle gradient."""
     rng = np.random.default_rng(seed)
     picks = []
     for src, k in ((s, per_source) for s in (*SOURCES, "mlp")):
         k = mlp if src == "mlp" else k
         g = np.abs(grads[src].reshape(-1))
         top = np.argsort(g)[-(k - 2):]
-        nz = np.nonzero(g)[0]
-        extra = rng.choice(nz, 2, replace=False)
+        pool = np.setdiff1d(np.nonzero(g >= 1e-2 * g.max())[0], top)
+        extra = rng.choice(pool, min(2, pool.size), replace=False)
         picks += [(src, int(i)) for i in np.concatenate([top, extra])]
     return picks
 
 
-def _fd_check(scene, t, og, dg, tg, n_max, grads, eps=1e-3, picks=None):
+def _fd_check(scene, t, og, dg, tg, n_max, grads, eps=1e-3, picks=None, feature_eps=None):
+    """Central differences of the float64 loss of float32 renders; `eps` for
+    the MLP weights, `feature_eps` (default `eps`) for grid and plane entries."""
     picks = _pick_params(grads) if picks is None else picks
     fd, an = [], []
     for src, e in picks:
         flat = t[src].view(-1)
         v0 = flat[e].item()
+        h = eps if src == "mlp" or feature_eps is None else feature_eps
         vals, steps = [], []
         for s in (+1.0, -1.0):
-            flat[e] = v0 + s * eps
+            flat[e] = v0 + s * h
             steps.append(flat[e].item())  # the binary32 value actually used
             res = om.render(scene, og, dg, n_max=n_max, c_bg=BG)
             vals.append(om.l2_loss_fp64(res["C"], tg).item())
@@ -141,8 +143,12 @@ def test_backward_finite_differences_tiny(tiny_train):
     log("test_backward_finite_differences_tiny")
     og, dg = rays_to(o, d)
     tg = torch.from_numpy(target.astype(np.float32)).to(og.device)
+    # 256 rays: one entry moves the loss by ~1e-5 of itself at eps=1e-3, the
+    # size of the float32 rounding of C, so feature entries take eps=1e-2
+    # (the loss is smooth in them; truncation stays ~1e-4 relative) and the
+    # MLP weights eps=1e-3 (larger steps cross ReLU kinks of some rays).
     _, _, grads = _gpu_grads(scene, t, og, dg, tg, 64)
-    picks, fd, an, err = _fd_check(scene, t, og, dg, tg, 64, grads)
+    picks, fd, an, err = _fd_check(scene, t, og, dg, tg, 64, grads, feature_eps=1e-2)
     log(f"  FD: {len(picks)} params, max rel err {err.max():.2e}, median {np.median(err):.2e}")
     assert err.max() <= 1e-3, [(p, f, a) for p, f, a, e in zip(picks, fd, an, err) if e > 1e-3]
 
@@ -256,7 +262,7 @@ def test_oblique_finite_differences_2e18(oblique_train):
     log("test_oblique_finite_differences_2e18: 64 params, 2^18 rays")
     og, dg = rays_to(o, d)
     tg = torch.from_numpy(target).to(og.device)
-    _, _, grads = _gpu_grads(scene, t, og, dg, tg, n_max)
+    res, _, grads = _gpu_grads(scene, t, og, dg, tg, n_max)
     picks, fd, an, err = _fd_check(scene, t, og, dg, tg, n_max, grads)
     for src in (*SOURCES, "mlp"):
         sel = [i for i, (s_, _) in enumerate(picks) if s_ == src]
