@@ -190,6 +190,152 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
 }
 
 // ---------------------------------------------------------------------------
+// Forward march for float32 features, lane-quad shading.  A queued batch of
+// up to 16 samples is shaded in four quarters; in quarter j, lanes
+// 4s..4s+3 of the group shade sample 4j + s, lane 4s+q taking x-offset
+// (q & 1) and channel half (q >> 1).  A float32 corner pair is 64
+// contiguous bytes, so each gather instruction reads one 64-byte span for
+// each of 4 consecutive samples of the ray; consecutive samples often share
+// a grid cell or plane texel, and lanes of one instruction that hit the same
+// cache line cost one lookup.  After the x-offset sum, lanes with c = 0 hold
+// channels 0..3 (density, diffuse colour) and lanes with c = 1 channels
+// 4..7, so the activations split evenly over the quad.  The four quarters
+// are gathered before the batch is composited, so their loads overlap.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void quad_gather(const SceneDev& sc, const Corners& c, int h, int ch, float* t) {
+    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
+    const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
+    const uint32_t hh = (uint32_t)h;
+    const float4* G = reinterpret_cast<const float4*>(sc.grid) + ch;
+    const float4* XY = reinterpret_cast<const float4*>(sc.pxy) + ch;
+    const float4* XZ = reinterpret_cast<const float4*>(sc.pxz) + ch;
+    const float4* YZ = reinterpret_cast<const float4*>(sc.pyz) + ch;
+    float4 r[10];
+    r[0] = G[(size_t)(c.g + hh) * 2];
+    r[1] = G[(size_t)(c.g + sy + hh) * 2];
+    r[2] = G[(size_t)(c.g + sz + hh) * 2];
+    r[3] = G[(size_t)(c.g + sz + sy + hh) * 2];
+    r[4] = XY[(size_t)(c.xy + hh) * 2];
+    r[5] = XY[(size_t)(c.xy + nx + hh) * 2];
+    r[6] = XZ[(size_t)(c.xz + hh) * 2];
+    r[7] = XZ[(size_t)(c.xz + nx + hh) * 2];
+    r[8] = YZ[(size_t)(c.yz + hh) * 2];
+    r[9] = YZ[(size_t)(c.yz + ny + hh) * 2];
+    const float wx = h ? c.fx : 1.0f - c.fx;
+    const float y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
+    const float wa = h ? c.ux : 1.0f - c.ux;  // x for XY / XZ
+    const float wb = h ? c.uy : 1.0f - c.uy;  // y for YZ
+    const float b0 = 1.0f - c.uy, b1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
+    const float w[10] = {wx * y0 * z0, wx * y1 * z0, wx * y0 * z1, wx * y1 * z1, wa * b0,
+                         wa * b1,      wa * e0,      wa * e1,      wb * e0,      wb * e1};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[i] = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+        t[0] += w[j] * r[j].x;
+        t[1] += w[j] * r[j].y;
+        t[2] += w[j] * r[j].z;
+        t[3] += w[j] * r[j].w;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParams rp, const float* __restrict__ o_,
+                                                           const float* __restrict__ d_, int64_t n,
+                                                           float* __restrict__ F, float* __restrict__ T,
+                                                           int32_t* __restrict__ n_placed,
+                                                           int32_t* __restrict__ n_eval) {
+    __shared__ int qs[kGroupsPerBlock][kQueue];
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (kGroup - 1);
+    const int gid = threadIdx.x / kGroup;
+    const int h = gl & 1, ch = (gl >> 1) & 1;
+    const int s = gl >> 2;            // sample of the quad within a quarter
+    const bool lead = (gl & 3) == 0;  // lane 4s: the quad's depth owner
+    const int64_t ray = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kGroupsPerBlock + gid;
+    if (ray >= n) return;
+    const float3 o = load3(o_, ray), d = load3(d_, ray);
+    float acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = 0.0f;
+    float carry = 0.0f;
+    int evals = 0;
+    const int placed = march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
+        float a[4], v[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = 4 * j + s;
+            const int ks = __shfl(kq, i, kGroup);
+            float t[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (i < nb) quad_gather(sc, corners_of(sc, lattice_point(ks, o, d, rp.delta)), h, ch, t);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) t[c] += pair_swap(t[c]);
+            a[j] = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[j][c] = 0.0f;
+            if (i < nb) {
+                if (ch == 0) {
+                    a[j] = __expf(t[0]) * rp.delta;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) v[j][c] = sigmoidf_fast(t[c + 1]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) v[j][c] = sigmoidf_fast(t[c]);
+                }
+            }
+            a[j] = quad_bcast0(a[j]);
+        }
+        // Optical depth in front of sample 4j + s: carry + all samples of
+        // quarters < j + samples of quads < s in quarter j.
+        float incl[4], pre[4];
+        float run = carry;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            incl[j] = g_scan_incl(lead ? a[j] : 0.0f, gl);
+            pre[j] = run + quad_bcast0(g_shift_up1(incl[j]));
+            run += __shfl(incl[j], kGroup - 1, kGroup);
+        }
+        int nb_eff = nb;
+        bool stop = false;
+        if (rp.t_term > 0.0f) {
+            int first = kGroup;
+#pragma unroll
+            for (int j = 3; j >= 0; --j)
+                if (4 * j + s < nb && __expf(-(pre[j] + a[j])) < rp.t_term) first = 4 * j + s;
+            first = g_min(first);
+            if (first < nb) {
+                nb_eff = first + 1;
+                stop = true;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float w = __expf(-pre[j]) * (-expm1f(-a[j]));
+            if (4 * j + s >= nb_eff || h) w = 0.0f;  // once per sample and channel half
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] += w * v[j][c];
+        }
+        // depth through the last evaluated sample, from the quad that owns it
+        const int jl = (nb_eff - 1) >> 2;
+        const float mine = (jl == 0 ? pre[0] + a[0] : jl == 1 ? pre[1] + a[1] : jl == 2 ? pre[2] + a[2] : pre[3] + a[3]);
+        carry = __shfl(mine, 4 * ((nb_eff - 1) & 3), kGroup);
+        evals += nb_eff;
+        return stop;
+    });
+    float f[7];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) f[c] = g_sum(ch == 0 ? acc[c] : 0.0f);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) f[3 + c] = g_sum(ch == 1 ? acc[c] : 0.0f);
+    if (gl == 0) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) F[ray * 7 + c] = f[c];
+        T[ray] = __expf(-carry);
+        n_placed[ray] = placed;
+        n_eval[ray] = evals;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Backward.  Per ray: the deferred MLP backward runs across the 16 lanes of
 // the group (lane h owns hidden unit h of both hidden layers), giving
 // g7 = dL/dF (+ dL/dC on the diffuse part).  The samples are then replayed
@@ -547,7 +693,7 @@ hipError_t launch_march_fwd(const SceneDev& sc, bool bf16, const RayParams& rp, 
         hipLaunchKernelGGL(k_march_fwd<BF16Store>, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n, F, T,
                            n_placed, n_eval);
     else
-        hipLaunchKernelGGL(k_march_fwd<F32Store>, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n, F, T,
+        hipLaunchKernelGGL(k_march_fwd_f32q, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n, F, T,
                            n_placed, n_eval);
     return hipGetLastError();
 }

@@ -370,6 +370,11 @@ __device__ __forceinline__ float pair_swap(float x) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xf, 0xf, false));  // [1,0,3,2]
 }
 
+// Value of lane 0 of the lane's quad (DPP quad_perm [0,0,0,0]).
+__device__ __forceinline__ float quad_bcast0(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x00, 0xf, 0xf, false));
+}
+
 // Value of the next lower lane (0 for lane 0).
 __device__ __forceinline__ float g_shift_up1(float x) { return dpp_row<kRowShr | 1>(x); }
 
