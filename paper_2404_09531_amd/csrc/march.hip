@@ -381,89 +381,138 @@ __device__ __forceinline__ void tile_add(float* tile, int e, float w, const floa
     for (int c = 0; c < 8; ++c) atomicAdd(tile + e * 8 + c, w * g[c]);
 }
 
-// Trilinear scatter of gt[8] into the grid gradient.  Returns false (and
-// does nothing) if the corner box of the participating lanes does not fit
-// the tile and `may_fail` is set.
+// Plain read-add-write of one tile entry, for updates whose lanes address
+// distinct entries within the instruction; one wave's LDS accesses execute
+// in order, so successive updates of an entry compose.
+__device__ __forceinline__ void tile_rmw(float* tile, int e, const float* g) {
+    float4* q = reinterpret_cast<float4*>(tile + e * 8);
+    float4 a = q[0], b = q[1];
+    a.x += g[0]; a.y += g[1]; a.z += g[2]; a.w += g[3];
+    b.x += g[4]; b.y += g[5]; b.z += g[6]; b.w += g[7];
+    q[0] = a;
+    q[1] = b;
+}
+
+// a / b for 0 <= a < 2^12, 1 <= b <= 2^12, with rb = 1 / b: the quotient
+// (a + 1/2) / b sits at least 1 / (2b) from an integer, far beyond the
+// float32 error of the product, so truncation gives the exact floor.
+__device__ __forceinline__ int small_div(int a, float rb) { return (int)(((float)a + 0.5f) * rb); }
+
+// Trilinear scatter of gt[8] into the grid gradient.  Consecutive samples of
+// a ray share cells, so each corner's contributions are first summed over
+// the run of lanes with the same cell (g_runs / g_seg_sum); only run tails
+// add into the LDS tile covering the batch's corner box, at distinct
+// addresses within each instruction.  Returns false (and does nothing) if the
+// box does not fit the tile and `may_fail` is set; without `may_fail` an
+// oversized box takes direct global atomics from the run tails.
 __device__ __forceinline__ bool scatter_grid(const SceneDev& sc, float* gV, float* tile, bool act, const Corners& cn,
                                              const float* gt, int gl, bool may_fail) {
     constexpr int BIG = 1 << 30;
     const int x0 = g_min(act ? cn.ix : BIG), x1 = g_max(act ? cn.ix : -BIG);
     const int y0 = g_min(act ? cn.iy : BIG), y1 = g_max(act ? cn.iy : -BIG);
     const int z0 = g_min(act ? cn.iz : BIG), z1 = g_max(act ? cn.iz : -BIG);
+    const int bx = x1 - x0 + 2, by = y1 - y0 + 2, bz = z1 - z0 + 2;
+    const bool fits = bx <= kTile && by <= kTile && bz <= kTile && bx * by * bz <= kTile;
+    if (!fits && may_fail) return false;
     const float x0w = 1.0f - cn.fx, x1w = cn.fx, y0w = 1.0f - cn.fy, y1w = cn.fy;
     const float z0w = 1.0f - cn.fz, z1w = cn.fz;
     const float w[8] = {x0w * y0w * z0w, x1w * y0w * z0w, x0w * y1w * z0w, x1w * y1w * z0w,
                         x0w * y0w * z1w, x1w * y0w * z1w, x0w * y1w * z1w, x1w * y1w * z1w};
-    const int bx = x1 - x0 + 2, by = y1 - y0 + 2, bz = z1 - z0 + 2;
-    if (bx <= kTile && by <= kTile && bz <= kTile && bx * by * bz <= kTile) {
-        const int ent = bx * by * bz;
+    const Runs rn = g_runs(cn.g, act, gl);
+    // Along a ray each axis index is monotone, so distinct runs are distinct
+    // cells and the run tails of one corner slot address distinct entries.
+    const int lane = __lane_id();
+    const bool mono = g_monotone(cn.ix, act, lane) && g_monotone(cn.iy, act, lane) && g_monotone(cn.iz, act, lane);
+    const int ent = fits ? bx * by * bz : 0;
+    if (fits) {
         tile_zero(tile, ent, gl);
         wave_order();
-        if (act) {
+    }
+    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < 8; ++j) {
+        float v[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[c] = g_seg_sum(w[j] * gt[c], rn.len);
+        if (rn.tail) {
+            if (fits) {
                 const int e = ((cn.iz + (j >> 2) - z0) * by + (cn.iy + ((j >> 1) & 1) - y0)) * bx + (cn.ix + (j & 1) - x0);
-                tile_add(tile, e, w[j], gt);
+                if (mono)
+                    tile_rmw(tile, e, v);
+                else
+                    tile_add(tile, e, 1.0f, v);
+            } else {
+                atomic_row(gV, cn.g + ((j >> 2) ? sz : 0u) + (((j >> 1) & 1) ? sy : 0u) + (j & 1), 1.0f, v);
             }
         }
+    }
+    if (fits) {
         wave_order();
         // 16 lanes add two x-adjacent rows x 8 channels (64 contiguous
         // bytes) per instruction: the memory-side atomic unit takes one
         // request per 64-byte segment instead of one per float.
+        const float rbx = 1.0f / (float)bx, rby = 1.0f / (float)by;
         for (int f = gl; f < ent * 8; f += kGroup) {
             const int e = f >> 3;
-            const int ex = e % bx, r = e / bx, ey = r % by, ez = r / by;
-            const uint32_t v = ((uint32_t)(z0 + ez) * (uint32_t)sc.Ly + (uint32_t)(y0 + ey)) * (uint32_t)sc.Lx +
-                               (uint32_t)(x0 + ex);
+            const int r = small_div(e, rbx), ex = e - r * bx;
+            const int ez = small_div(r, rby), ey = r - ez * by;
+            const uint32_t vtx = ((uint32_t)(z0 + ez) * (uint32_t)sc.Ly + (uint32_t)(y0 + ey)) * (uint32_t)sc.Lx +
+                                 (uint32_t)(x0 + ex);
             const float val = tile[f];
-            if (val != 0.0f) unsafeAtomicAdd(gV + (size_t)v * 8 + (f & 7), val);
+            if (val != 0.0f) unsafeAtomicAdd(gV + (size_t)vtx * 8 + (f & 7), val);
         }
         wave_order();
-        return true;
-    }
-    if (may_fail) return false;
-    if (act) {
-        const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-            atomic_row(gV, cn.g + ((j >> 2) ? sz : 0u) + (((j >> 1) & 1) ? sy : 0u) + (j & 1), w[j], gt);
     }
     return true;
 }
 
 // Bilinear scatter into a plane gradient [nb][na][8] at base texel (ia, ib);
-// same contract as scatter_grid.
+// same scheme and contract as scatter_grid.
 __device__ __forceinline__ bool scatter_plane(float* gP, int na, float* tile, bool act, int ia, int ib, float fa,
                                               float fb, const float* gt, int gl, bool may_fail) {
     constexpr int BIG = 1 << 30;
     const int a0 = g_min(act ? ia : BIG), a1 = g_max(act ? ia : -BIG);
     const int b0 = g_min(act ? ib : BIG), b1 = g_max(act ? ib : -BIG);
-    const float w[4] = {(1.0f - fa) * (1.0f - fb), fa * (1.0f - fb), (1.0f - fa) * fb, fa * fb};
     const int ba = a1 - a0 + 2, bb = b1 - b0 + 2;
-    if (ba <= kTile && bb <= kTile && ba * bb <= kTile) {
-        const int ent = ba * bb;
+    const bool fits = ba <= kTile && bb <= kTile && ba * bb <= kTile;
+    if (!fits && may_fail) return false;
+    const float w[4] = {(1.0f - fa) * (1.0f - fb), fa * (1.0f - fb), (1.0f - fa) * fb, fa * fb};
+    const uint32_t base = (uint32_t)ib * (uint32_t)na + (uint32_t)ia;
+    const Runs rn = g_runs(base, act, gl);
+    const int lane = __lane_id();
+    const bool mono = g_monotone(ia, act, lane) && g_monotone(ib, act, lane);
+    const int ent = fits ? ba * bb : 0;
+    if (fits) {
         tile_zero(tile, ent, gl);
         wave_order();
-        if (act) {
+    }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) tile_add(tile, (ib + (j >> 1) - b0) * ba + (ia + (j & 1) - a0), w[j], gt);
+    for (int j = 0; j < 4; ++j) {
+        float v[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[c] = g_seg_sum(w[j] * gt[c], rn.len);
+        if (rn.tail) {
+            if (fits) {
+                const int e = (ib + (j >> 1) - b0) * ba + (ia + (j & 1) - a0);
+                if (mono)
+                    tile_rmw(tile, e, v);
+                else
+                    tile_add(tile, e, 1.0f, v);
+            } else
+                atomic_row(gP, base + ((j >> 1) ? (uint32_t)na : 0u) + (j & 1), 1.0f, v);
         }
+    }
+    if (fits) {
         wave_order();
+        const float rba = 1.0f / (float)ba;
         for (int f = gl; f < ent * 8; f += kGroup) {
             const int e = f >> 3;
-            const int ea = e % ba, eb = e / ba;
+            const int eb = small_div(e, rba), ea = e - eb * ba;
             const uint32_t row = (uint32_t)(b0 + eb) * (uint32_t)na + (uint32_t)(a0 + ea);
             const float val = tile[f];
             if (val != 0.0f) unsafeAtomicAdd(gP + (size_t)row * 8 + (f & 7), val);
         }
         wave_order();
-        return true;
-    }
-    if (may_fail) return false;
-    if (act) {
-        const uint32_t base = (uint32_t)ib * (uint32_t)na + (uint32_t)ia;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) atomic_row(gP, base + ((j >> 1) ? (uint32_t)na : 0u) + (j & 1), w[j], gt);
     }
     return true;
 }
@@ -502,6 +551,7 @@ __device__ __forceinline__ void replay_sample(const SceneDev& sc, const RayParam
                                               bool act, float& a, float& tau, float* v, Corners& cn) {
     a = 0.0f;
     tau = 0.0f;
+    cn = Corners{};  // defined keys and weights on inactive lanes, which the group scans read
 #pragma unroll
     for (int c = 0; c < 7; ++c) v[c] = 0.0f;
     if (act) {

@@ -370,6 +370,45 @@ __device__ __forceinline__ float pair_swap(float x) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xf, 0xf, false));  // [1,0,3,2]
 }
 
+template <int CTRL>
+__device__ __forceinline__ int dpp_row_i(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, true);
+}
+
+// Runs of equal keys among the active lanes of a group, in lane order:
+// `len` = lanes of the run before this one (this lane is the run's head when
+// 0), `tail` = last active lane of its run.  Inactive lanes end runs.
+struct Runs {
+    int len;
+    bool tail;
+};
+__device__ __forceinline__ Runs g_runs(uint32_t key, bool act, int gl) {
+    const int a = act ? 1 : 0;
+    const int prev_act = dpp_row_i<kRowShr | 1>(a), next_act = dpp_row_i<kRowShl | 1>(a);
+    const uint32_t prev_key = (uint32_t)dpp_row_i<kRowShr | 1>((int)key);
+    const uint32_t next_key = (uint32_t)dpp_row_i<kRowShl | 1>((int)key);
+    int st = (!prev_act || prev_key != key) ? gl : 0;
+    st = max(st, dpp_row_i<kRowShr | 1>(st));
+    st = max(st, dpp_row_i<kRowShr | 2>(st));
+    st = max(st, dpp_row_i<kRowShr | 4>(st));
+    st = max(st, dpp_row_i<kRowShr | 8>(st));
+    return Runs{gl - st, act && (!next_act || next_key != key)};
+}
+
+// Inclusive sum over the lane's run (see g_runs): the run's tail lane gets
+// the run total.
+__device__ __forceinline__ float g_seg_sum(float x, int len) {
+    float y = dpp_row<kRowShr | 1>(x);
+    x = len >= 1 ? x + y : x;
+    y = dpp_row<kRowShr | 2>(x);
+    x = len >= 2 ? x + y : x;
+    y = dpp_row<kRowShr | 4>(x);
+    x = len >= 4 ? x + y : x;
+    y = dpp_row<kRowShr | 8>(x);
+    x = len >= 8 ? x + y : x;
+    return x;
+}
+
 // Value of lane 0 of the lane's quad (DPP quad_perm [0,0,0,0]).
 __device__ __forceinline__ float quad_bcast0(float x) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x00, 0xf, 0xf, false));
@@ -390,16 +429,21 @@ __device__ __forceinline__ float g_rscan_incl(float x, int /*gl*/) {
     return x;
 }
 
-__device__ __forceinline__ int g_min(int x) {
-#pragma unroll
-    for (int m = kGroup / 2; m > 0; m >>= 1) x = min(x, __shfl_xor(x, m, kGroup));
+// Group min / max in every lane: DPP butterflies over the quad, then
+// rotations of the 16-lane row by 4 and 8 (no LDS crossbar).
+template <class Op>
+__device__ __forceinline__ int g_reduce(int x, Op op) {
+    x = op(x, __builtin_amdgcn_mov_dpp(x, 0xB1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
+    x = op(x, __builtin_amdgcn_mov_dpp(x, 0x4E, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
+    x = op(x, __builtin_amdgcn_mov_dpp(x, 0x124, 0xf, 0xf, false));  // row_ror:4
+    x = op(x, __builtin_amdgcn_mov_dpp(x, 0x128, 0xf, 0xf, false));  // row_ror:8
     return x;
 }
-
+__device__ __forceinline__ int g_min(int x) {
+    return g_reduce(x, [](int a, int b) { return min(a, b); });
+}
 __device__ __forceinline__ int g_max(int x) {
-#pragma unroll
-    for (int m = kGroup / 2; m > 0; m >>= 1) x = max(x, __shfl_xor(x, m, kGroup));
-    return x;
+    return g_reduce(x, [](int a, int b) { return max(a, b); });
 }
 
 // Group sum, returned in every lane: scan, then broadcast lane 15.
@@ -408,6 +452,16 @@ __device__ __forceinline__ float g_sum(float x) { return __shfl(g_scan_incl(x, 0
 __device__ __forceinline__ uint32_t g_ballot(bool pred, int lane) {
     const unsigned long long m = __ballot(pred);
     return (uint32_t)(m >> (lane & (64 - kGroup))) & 0xffffu;
+}
+
+// True unless the active lanes' x goes both up and down in lane order.
+__device__ __forceinline__ bool g_monotone(int x, bool act, int lane) {
+    const int gl = lane & (kGroup - 1);
+    const int a = act ? 1 : 0;
+    const bool both = act && dpp_row_i<kRowShr | 1>(a) != 0 && gl > 0;
+    const int px = dpp_row_i<kRowShr | 1>(x);
+    const uint32_t up = g_ballot(both && x > px, lane), down = g_ballot(both && x < px, lane);
+    return up == 0u || down == 0u;
 }
 
 // Keeps the compiler from moving LDS accesses across this point; the
