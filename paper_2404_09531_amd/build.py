@@ -29,6 +29,21 @@ FLAGS = [
 ]
 
 
+def check_no_scratch(src: str, remarks: str) -> None:
+    """Refuse kernels that spill to scratch memory.  The shipped kernels keep
+    every live value in registers; a build whose register allocation spills
+    (e.g. after a change that raises register pressure) is rejected rather
+    than shipped, so its cross-lane code always runs on unspilled registers."""
+    name = None
+    for line in remarks.splitlines():
+        if "Function Name:" in line:
+            name = line.split("Function Name:")[1].split("[")[0].strip()
+        elif "ScratchSize [bytes/lane]:" in line:
+            size = int(line.split("ScratchSize [bytes/lane]:")[1].split("[")[0])
+            if size != 0:
+                raise RuntimeError(f"{src}: kernel {name} uses {size} bytes/lane of scratch (register spills)")
+
+
 def hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
         if c and (os.path.sep not in c or os.path.exists(c)):
@@ -46,7 +61,8 @@ def build(asm_dir: str | None = None, verbose: bool = False, out: str | None = N
 
     def compile_one(src: str) -> str:
         obj = os.path.join(obj_dir, src.replace(".hip", ".o"))
-        cmd = [cc, *FLAGS, *[f"-D{x}" for x in defines], "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *FLAGS, *[f"-D{x}" for x in defines], "-Rpass-analysis=kernel-resource-usage", "-c",
+               os.path.join(CSRC, src), "-o", obj]
         if asm_dir:
             os.makedirs(asm_dir, exist_ok=True)
             cmd += ["-save-temps=obj"]
@@ -55,6 +71,7 @@ def build(asm_dir: str | None = None, verbose: bool = False, out: str | None = N
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{res.stderr}")
+        check_no_scratch(src, res.stderr)
         if verbose and res.stderr.strip():
             print(res.stderr, file=sys.stderr)
         return obj
