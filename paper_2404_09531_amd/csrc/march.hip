@@ -416,8 +416,6 @@ __device__ __forceinline__ bool scatter_grid(const SceneDev& sc, float* gV, floa
     if (!fits && may_fail) return false;
     const float x0w = 1.0f - cn.fx, x1w = cn.fx, y0w = 1.0f - cn.fy, y1w = cn.fy;
     const float z0w = 1.0f - cn.fz, z1w = cn.fz;
-    const float w[8] = {x0w * y0w * z0w, x1w * y0w * z0w, x0w * y1w * z0w, x1w * y1w * z0w,
-                        x0w * y0w * z1w, x1w * y0w * z1w, x0w * y1w * z1w, x1w * y1w * z1w};
     const Runs rn = g_runs(cn.g, act, gl);
     // Along a ray each axis index is monotone, so distinct runs are distinct
     // cells and the run tails of one corner slot address distinct entries.
@@ -429,11 +427,12 @@ __device__ __forceinline__ bool scatter_grid(const SceneDev& sc, float* gV, floa
         wave_order();
     }
     const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
-#pragma unroll
+#pragma unroll 1  // one corner slot at a time keeps the kernel at 3 waves/SIMD
     for (int j = 0; j < 8; ++j) {
+        const float wj = ((j & 1) ? x1w : x0w) * (((j >> 1) & 1) ? y1w : y0w) * ((j >> 2) ? z1w : z0w);
         float v[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) v[c] = g_seg_sum(w[j] * gt[c], rn.len);
+        for (int c = 0; c < 8; ++c) v[c] = g_seg_sum(wj * gt[c], rn.len);
         if (rn.tail) {
             if (fits) {
                 const int e = ((cn.iz + (j >> 2) - z0) * by + (cn.iy + ((j >> 1) & 1) - y0)) * bx + (cn.ix + (j & 1) - x0);
@@ -476,7 +475,6 @@ __device__ __forceinline__ bool scatter_plane(float* gP, int na, float* tile, bo
     const int ba = a1 - a0 + 2, bb = b1 - b0 + 2;
     const bool fits = ba <= kTile && bb <= kTile && ba * bb <= kTile;
     if (!fits && may_fail) return false;
-    const float w[4] = {(1.0f - fa) * (1.0f - fb), fa * (1.0f - fb), (1.0f - fa) * fb, fa * fb};
     const uint32_t base = (uint32_t)ib * (uint32_t)na + (uint32_t)ia;
     const Runs rn = g_runs(base, act, gl);
     const int lane = __lane_id();
@@ -486,11 +484,12 @@ __device__ __forceinline__ bool scatter_plane(float* gP, int na, float* tile, bo
         tile_zero(tile, ent, gl);
         wave_order();
     }
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j < 4; ++j) {
+        const float wj = ((j & 1) ? fa : 1.0f - fa) * ((j >> 1) ? fb : 1.0f - fb);
         float v[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) v[c] = g_seg_sum(w[j] * gt[c], rn.len);
+        for (int c = 0; c < 8; ++c) v[c] = g_seg_sum(wj * gt[c], rn.len);
         if (rn.tail) {
             if (fits) {
                 const int e = (ib + (j >> 1) - b0) * ba + (ia + (j & 1) - a0);

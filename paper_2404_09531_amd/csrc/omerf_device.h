@@ -299,46 +299,37 @@ __device__ __forceinline__ void gather_features_split(const SceneDev& sc, const 
     for (int i = 0; i < 8; ++i) t[i] = 0.0f;
     const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
     const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
-    {
-        typename S::Row r[8];
+    const float x0 = 1.0f - c.fx, x1 = c.fx, y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) r[j] = S::load(sc.grid, c.g + ((j >> 2) ? sz : 0u) + (((j >> 1) & 1) ? sy : 0u) + (j & 1));
-        const float x0 = 1.0f - c.fx, x1 = c.fx, y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
-        S::acc(r[0], x0 * y0 * z0, t);
-        S::acc(r[1], x1 * y0 * z0, t);
-        S::acc(r[2], x0 * y1 * z0, t);
-        S::acc(r[3], x1 * y1 * z0, t);
-        S::acc(r[4], x0 * y0 * z1, t);
-        S::acc(r[5], x1 * y0 * z1, t);
-        S::acc(r[6], x0 * y1 * z1, t);
-        S::acc(r[7], x1 * y1 * z1, t);
+    for (int zz = 0; zz < 2; ++zz) {
+        const uint32_t base = c.g + (zz ? sz : 0u);
+        typename S::Row r[4];
+        r[0] = S::load(sc.grid, base);
+        r[1] = S::load(sc.grid, base + 1);
+        r[2] = S::load(sc.grid, base + sy);
+        r[3] = S::load(sc.grid, base + sy + 1);
+        const float wz = zz ? z1 : z0;
+        S::acc(r[0], x0 * y0 * wz, t);
+        S::acc(r[1], x1 * y0 * wz, t);
+        S::acc(r[2], x0 * y1 * wz, t);
+        S::acc(r[3], x1 * y1 * wz, t);
     }
-    typename S::Row r[12];
-    r[0] = S::load(sc.pxy, c.xy);
-    r[1] = S::load(sc.pxy, c.xy + 1);
-    r[2] = S::load(sc.pxy, c.xy + nx);
-    r[3] = S::load(sc.pxy, c.xy + nx + 1);
-    r[4] = S::load(sc.pxz, c.xz);
-    r[5] = S::load(sc.pxz, c.xz + 1);
-    r[6] = S::load(sc.pxz, c.xz + nx);
-    r[7] = S::load(sc.pxz, c.xz + nx + 1);
-    r[8] = S::load(sc.pyz, c.yz);
-    r[9] = S::load(sc.pyz, c.yz + 1);
-    r[10] = S::load(sc.pyz, c.yz + ny);
-    r[11] = S::load(sc.pyz, c.yz + ny + 1);
     const float a0 = 1.0f - c.ux, a1 = c.ux, b0 = 1.0f - c.uy, b1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
-    S::acc(r[0], a0 * b0, t);
-    S::acc(r[1], a1 * b0, t);
-    S::acc(r[2], a0 * b1, t);
-    S::acc(r[3], a1 * b1, t);
-    S::acc(r[4], a0 * e0, t);
-    S::acc(r[5], a1 * e0, t);
-    S::acc(r[6], a0 * e1, t);
-    S::acc(r[7], a1 * e1, t);
-    S::acc(r[8], b0 * e0, t);
-    S::acc(r[9], b1 * e0, t);
-    S::acc(r[10], b0 * e1, t);
-    S::acc(r[11], b1 * e1, t);
+    const void* P[3] = {sc.pxy, sc.pxz, sc.pyz};
+    const uint32_t B[3] = {c.xy, c.xz, c.yz}, S2[3] = {nx, nx, ny};
+    const float U0[3] = {a0, a0, b0}, U1[3] = {a1, a1, b1}, V0[3] = {b0, e0, e0}, V1[3] = {b1, e1, e1};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        typename S::Row r[4];
+        r[0] = S::load(P[q], B[q]);
+        r[1] = S::load(P[q], B[q] + 1);
+        r[2] = S::load(P[q], B[q] + S2[q]);
+        r[3] = S::load(P[q], B[q] + S2[q] + 1);
+        S::acc(r[0], U0[q] * V0[q], t);
+        S::acc(r[1], U1[q] * V0[q], t);
+        S::acc(r[2], U0[q] * V1[q], t);
+        S::acc(r[3], U1[q] * V1[q], t);
+    }
 }
 
 __device__ __forceinline__ float sigmoidf_fast(float x) {
