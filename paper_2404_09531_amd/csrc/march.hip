@@ -400,7 +400,7 @@ __device__ __forceinline__ int small_div(int a, float rb) { return (int)(((float
 
 // Trilinear scatter of gt[8] into the grid gradient.  Consecutive samples of
 // a ray share cells, so each corner's contributions are first summed over
-// the run of lanes with the same cell (g_runs / g_seg_sum); only run tails
+// the run of lanes with the same cell (g_runs / g_seg_sum8); only run tails
 // add into the LDS tile covering the batch's corner box, at distinct
 // addresses within each instruction.  Returns false (and does nothing) if the
 // box does not fit the tile and `may_fail` is set; without `may_fail` an
@@ -417,6 +417,7 @@ __device__ __forceinline__ bool scatter_grid(const SceneDev& sc, float* gV, floa
     const float x0w = 1.0f - cn.fx, x1w = cn.fx, y0w = 1.0f - cn.fy, y1w = cn.fy;
     const float z0w = 1.0f - cn.fz, z1w = cn.fz;
     const Runs rn = g_runs(cn.g, act, gl);
+    const int lmax = g_max(act ? rn.len : 0);
     // Along a ray each axis index is monotone, so distinct runs are distinct
     // cells and the run tails of one corner slot address distinct entries.
     const int lane = __lane_id();
@@ -432,7 +433,8 @@ __device__ __forceinline__ bool scatter_grid(const SceneDev& sc, float* gV, floa
         const float wj = ((j & 1) ? x1w : x0w) * (((j >> 1) & 1) ? y1w : y0w) * ((j >> 2) ? z1w : z0w);
         float v[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) v[c] = g_seg_sum(wj * gt[c], rn.len);
+        for (int c = 0; c < 8; ++c) v[c] = wj * gt[c];
+        g_seg_sum8(v, rn.len, lmax);
         if (rn.tail) {
             if (fits) {
                 const int e = ((cn.iz + (j >> 2) - z0) * by + (cn.iy + ((j >> 1) & 1) - y0)) * bx + (cn.ix + (j & 1) - x0);
@@ -477,6 +479,7 @@ __device__ __forceinline__ bool scatter_plane(float* gP, int na, float* tile, bo
     if (!fits && may_fail) return false;
     const uint32_t base = (uint32_t)ib * (uint32_t)na + (uint32_t)ia;
     const Runs rn = g_runs(base, act, gl);
+    const int lmax = g_max(act ? rn.len : 0);
     const int lane = __lane_id();
     const bool mono = g_monotone(ia, act, lane) && g_monotone(ib, act, lane);
     const int ent = fits ? ba * bb : 0;
@@ -489,7 +492,8 @@ __device__ __forceinline__ bool scatter_plane(float* gP, int na, float* tile, bo
         const float wj = ((j & 1) ? fa : 1.0f - fa) * ((j >> 1) ? fb : 1.0f - fb);
         float v[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) v[c] = g_seg_sum(wj * gt[c], rn.len);
+        for (int c = 0; c < 8; ++c) v[c] = wj * gt[c];
+        g_seg_sum8(v, rn.len, lmax);
         if (rn.tail) {
             if (fits) {
                 const int e = (ib + (j >> 1) - b0) * ba + (ia + (j & 1) - a0);

@@ -386,18 +386,38 @@ __device__ __forceinline__ Runs g_runs(uint32_t key, bool act, int gl) {
     return Runs{gl - st, act && (!next_act || next_key != key)};
 }
 
-// Inclusive sum over the lane's run (see g_runs): the run's tail lane gets
-// the run total.
-__device__ __forceinline__ float g_seg_sum(float x, int len) {
-    float y = dpp_row<kRowShr | 1>(x);
-    x = len >= 1 ? x + y : x;
-    y = dpp_row<kRowShr | 2>(x);
-    x = len >= 2 ? x + y : x;
-    y = dpp_row<kRowShr | 4>(x);
-    x = len >= 4 ? x + y : x;
-    y = dpp_row<kRowShr | 8>(x);
-    x = len >= 8 ? x + y : x;
-    return x;
+// Inclusive sums over the lane's run (see g_runs) of 8 values: the run's
+// tail lane gets the run totals.  `lmax` is the group's largest `len`; only
+// the scan steps that some run needs are executed.
+__device__ __forceinline__ void g_seg_sum8(float* x, int len, int lmax) {
+    if (lmax >= 1) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float y = dpp_row<kRowShr | 1>(x[c]);
+            x[c] = len >= 1 ? x[c] + y : x[c];
+        }
+    }
+    if (lmax >= 2) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float y = dpp_row<kRowShr | 2>(x[c]);
+            x[c] = len >= 2 ? x[c] + y : x[c];
+        }
+    }
+    if (lmax >= 4) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float y = dpp_row<kRowShr | 4>(x[c]);
+            x[c] = len >= 4 ? x[c] + y : x[c];
+        }
+    }
+    if (lmax >= 8) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float y = dpp_row<kRowShr | 8>(x[c]);
+            x[c] = len >= 8 ? x[c] + y : x[c];
+        }
+    }
 }
 
 // Value of lane 0 of the lane's quad (DPP quad_perm [0,0,0,0]).
