@@ -352,200 +352,96 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParam
 // suffix is summed from its own terms (never as a total minus a prefix), so
 // samples behind opaque surfaces keep their relative accuracy.
 //
-// Scatter: per batch and per feature source, the contributions of the
-// group's 16 samples are first summed in an LDS tile covering the batch's
-// bounding box of corners (consecutive samples of a ray share most
-// corners), then each touched corner is added to global memory once with
-// float32 atomics laid out so that 16 lanes cover 64 contiguous bytes:
-// device-memory float atomics are resolved beyond L2, one request per
-// 64-byte segment of an instruction, so contiguous lanes are ~16x cheaper
-// than scattered ones.  Boxes larger than the tile fall back to direct
-// atomics.
+// Scatter: per batch and per feature source, consecutive samples of a ray
+// that share a cell (or texel) are summed onto the last lane of their run
+// with DPP, so each corner gets one contribution per run; the run tails
+// stage two row-adjacent corners (64 contiguous bytes) in LDS, and the group
+// adds each staged pair to global memory with one atomic instruction whose
+// 16 lanes cover those 64 bytes.  Device-memory float atomics are performed
+// beyond L2, one request per 64-byte segment of an instruction, so
+// contiguous lanes are ~16x cheaper than scattered ones.
 // ---------------------------------------------------------------------------
-constexpr int kTile = 64;                       // corners per group tile
 constexpr int kBatchSlots = 1024 / kGroup / kGroup;  // registers holding batch totals (n_max <= 1024)
 
-__device__ __forceinline__ void atomic_row(float* base, uint32_t idx, float w, const float* g) {
-    float* q = base + (size_t)idx * 8;
+// Row-list scatter.  Per source, the samples sharing a cell form runs (see
+// g_runs); for every pair of corners adjacent along the row axis (two
+// contiguous 32-byte rows) each run's totals are summed onto its tail lane,
+// the tails stage their 16 floats in LDS at their rank, and the group flushes
+// one staged pair per instruction: 16 lanes x 4 B = 64 contiguous bytes.
+struct Stage {
+    float v[kGroup][16];
+    int row[kGroup];
+};
+
+__device__ __forceinline__ void flush_pair(float* G, Stage& st, const Runs& rn, int rank, int nt, uint32_t row0,
+                                           float w0, float w1, const float* gt, int lmax, int gl) {
+    float4* q = reinterpret_cast<float4*>(st.v[rank]);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) unsafeAtomicAdd(q + c, w * g[c]);
-}
-
-__device__ __forceinline__ void tile_zero(float* tile, int entries, int gl) {
-    float4* t4 = reinterpret_cast<float4*>(tile);
-    for (int i = gl; i < entries * 2; i += kGroup) t4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-}
-
-__device__ __forceinline__ void tile_add(float* tile, int e, float w, const float* g) {
-#pragma unroll
-    for (int c = 0; c < 8; ++c) atomicAdd(tile + e * 8 + c, w * g[c]);
-}
-
-// Plain read-add-write of one tile entry, for updates whose lanes address
-// distinct entries within the instruction; one wave's LDS accesses execute
-// in order, so successive updates of an entry compose.
-__device__ __forceinline__ void tile_rmw(float* tile, int e, const float* g) {
-    float4* q = reinterpret_cast<float4*>(tile + e * 8);
-    float4 a = q[0], b = q[1];
-    a.x += g[0]; a.y += g[1]; a.z += g[2]; a.w += g[3];
-    b.x += g[4]; b.y += g[5]; b.z += g[6]; b.w += g[7];
-    q[0] = a;
-    q[1] = b;
-}
-
-// a / b for 0 <= a < 2^12, 1 <= b <= 2^12, with rb = 1 / b: the quotient
-// (a + 1/2) / b sits at least 1 / (2b) from an integer, far beyond the
-// float32 error of the product, so truncation gives the exact floor.
-__device__ __forceinline__ int small_div(int a, float rb) { return (int)(((float)a + 0.5f) * rb); }
-
-// Trilinear scatter of gt[8] into the grid gradient.  Consecutive samples of
-// a ray share cells, so each corner's contributions are first summed over
-// the run of lanes with the same cell (g_runs / g_seg_sum8); only run tails
-// add into the LDS tile covering the batch's corner box, at distinct
-// addresses within each instruction.  Returns false (and does nothing) if the
-// box does not fit the tile and `may_fail` is set; without `may_fail` an
-// oversized box takes direct global atomics from the run tails.
-__device__ __forceinline__ bool scatter_grid(const SceneDev& sc, float* gV, float* tile, bool act, const Corners& cn,
-                                             const float* gt, int gl, bool may_fail) {
-    constexpr int BIG = 1 << 30;
-    const int x0 = g_min(act ? cn.ix : BIG), x1 = g_max(act ? cn.ix : -BIG);
-    const int y0 = g_min(act ? cn.iy : BIG), y1 = g_max(act ? cn.iy : -BIG);
-    const int z0 = g_min(act ? cn.iz : BIG), z1 = g_max(act ? cn.iz : -BIG);
-    const int bx = x1 - x0 + 2, by = y1 - y0 + 2, bz = z1 - z0 + 2;
-    const bool fits = bx <= kTile && by <= kTile && bz <= kTile && bx * by * bz <= kTile;
-    if (!fits && may_fail) return false;
-    const float x0w = 1.0f - cn.fx, x1w = cn.fx, y0w = 1.0f - cn.fy, y1w = cn.fy;
-    const float z0w = 1.0f - cn.fz, z1w = cn.fz;
-    const Runs rn = g_runs(cn.g, act, gl);
-    const int lmax = g_max(act ? rn.len : 0);
-    // Along a ray each axis index is monotone, so distinct runs are distinct
-    // cells and the run tails of one corner slot address distinct entries.
-    const int lane = __lane_id();
-    const bool mono = g_monotone(cn.ix, act, lane) && g_monotone(cn.iy, act, lane) && g_monotone(cn.iz, act, lane);
-    const int ent = fits ? bx * by * bz : 0;
-    if (fits) {
-        tile_zero(tile, ent, gl);
-        wave_order();
-    }
-    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
-#pragma unroll 1  // one corner slot at a time keeps the kernel at 3 waves/SIMD
-    for (int j = 0; j < 8; ++j) {
-        const float wj = ((j & 1) ? x1w : x0w) * (((j >> 1) & 1) ? y1w : y0w) * ((j >> 2) ? z1w : z0w);
+    for (int h = 0; h < 2; ++h) {  // the two rows one after the other: fewer live registers
+        const float w = h ? w1 : w0;
         float v[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) v[c] = wj * gt[c];
+        for (int c = 0; c < 8; ++c) v[c] = w * gt[c];
         g_seg_sum8(v, rn.len, lmax);
         if (rn.tail) {
-            if (fits) {
-                const int e = ((cn.iz + (j >> 2) - z0) * by + (cn.iy + ((j >> 1) & 1) - y0)) * bx + (cn.ix + (j & 1) - x0);
-                if (mono)
-                    tile_rmw(tile, e, v);
-                else
-                    tile_add(tile, e, 1.0f, v);
-            } else {
-                atomic_row(gV, cn.g + ((j >> 2) ? sz : 0u) + (((j >> 1) & 1) ? sy : 0u) + (j & 1), 1.0f, v);
-            }
+            q[2 * h] = make_float4(v[0], v[1], v[2], v[3]);
+            q[2 * h + 1] = make_float4(v[4], v[5], v[6], v[7]);
         }
     }
-    if (fits) {
-        wave_order();
-        // 16 lanes add two x-adjacent rows x 8 channels (64 contiguous
-        // bytes) per instruction: the memory-side atomic unit takes one
-        // request per 64-byte segment instead of one per float.
-        const float rbx = 1.0f / (float)bx, rby = 1.0f / (float)by;
-        for (int f = gl; f < ent * 8; f += kGroup) {
-            const int e = f >> 3;
-            const int r = small_div(e, rbx), ex = e - r * bx;
-            const int ez = small_div(r, rby), ey = r - ez * by;
-            const uint32_t vtx = ((uint32_t)(z0 + ez) * (uint32_t)sc.Ly + (uint32_t)(y0 + ey)) * (uint32_t)sc.Lx +
-                                 (uint32_t)(x0 + ex);
-            const float val = tile[f];
-            if (val != 0.0f) unsafeAtomicAdd(gV + (size_t)vtx * 8 + (f & 7), val);
-        }
-        wave_order();
+    if (rn.tail) st.row[rank] = (int)row0;
+    wave_order();
+    for (int e = 0; e < nt; ++e) {
+        const float val = st.v[e][gl];
+        const uint32_t r = (uint32_t)st.row[e];
+        if (val != 0.0f) unsafeAtomicAdd(G + (size_t)r * 8 + gl, val);
     }
-    return true;
+    wave_order();
 }
 
-// Bilinear scatter into a plane gradient [nb][na][8] at base texel (ia, ib);
-// same scheme and contract as scatter_grid.
-__device__ __forceinline__ bool scatter_plane(float* gP, int na, float* tile, bool act, int ia, int ib, float fa,
-                                              float fb, const float* gt, int gl, bool may_fail) {
-    constexpr int BIG = 1 << 30;
-    const int a0 = g_min(act ? ia : BIG), a1 = g_max(act ? ia : -BIG);
-    const int b0 = g_min(act ? ib : BIG), b1 = g_max(act ? ib : -BIG);
-    const int ba = a1 - a0 + 2, bb = b1 - b0 + 2;
-    const bool fits = ba <= kTile && bb <= kTile && ba * bb <= kTile;
-    if (!fits && may_fail) return false;
-    const uint32_t base = (uint32_t)ib * (uint32_t)na + (uint32_t)ia;
-    const Runs rn = g_runs(base, act, gl);
-    const int lmax = g_max(act ? rn.len : 0);
-    const int lane = __lane_id();
-    const bool mono = g_monotone(ia, act, lane) && g_monotone(ib, act, lane);
-    const int ent = fits ? ba * bb : 0;
-    if (fits) {
-        tile_zero(tile, ent, gl);
-        wave_order();
-    }
+struct RunSet {
+    Runs rn;
+    int lmax, rank, nt;
+};
+
+__device__ __forceinline__ RunSet run_set(uint32_t key, bool act, int gl, int lane) {
+    RunSet r;
+    r.rn = g_runs(key, act, gl);
+    r.lmax = g_max(act ? r.rn.len : 0);
+    const uint32_t tm = g_ballot(r.rn.tail, lane);
+    r.nt = __popc(tm);
+    r.rank = __popc(tm & ((1u << gl) - 1u));
+    return r;
+}
+
+__device__ __forceinline__ void scatter_plane_runs(float* gP, int na, Stage& st, bool act, uint32_t key, float fa,
+                                                   float fb, const float* gt, int gl, int lane) {
+    const RunSet rs = run_set(key, act, gl, lane);
+    const float a0 = 1.0f - fa, a1 = fa;
 #pragma unroll 1
-    for (int j = 0; j < 4; ++j) {
-        const float wj = ((j & 1) ? fa : 1.0f - fa) * ((j >> 1) ? fb : 1.0f - fb);
-        float v[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) v[c] = wj * gt[c];
-        g_seg_sum8(v, rn.len, lmax);
-        if (rn.tail) {
-            if (fits) {
-                const int e = (ib + (j >> 1) - b0) * ba + (ia + (j & 1) - a0);
-                if (mono)
-                    tile_rmw(tile, e, v);
-                else
-                    tile_add(tile, e, 1.0f, v);
-            } else
-                atomic_row(gP, base + ((j >> 1) ? (uint32_t)na : 0u) + (j & 1), 1.0f, v);
-        }
+    for (int p = 0; p < 2; ++p) {
+        const float wb = p ? fb : 1.0f - fb;
+        flush_pair(gP, st, rs.rn, rs.rank, rs.nt, key + (p ? (uint32_t)na : 0u), a0 * wb, a1 * wb, gt, rs.lmax, gl);
     }
-    if (fits) {
-        wave_order();
-        const float rba = 1.0f / (float)ba;
-        for (int f = gl; f < ent * 8; f += kGroup) {
-            const int e = f >> 3;
-            const int eb = small_div(e, rba), ea = e - eb * ba;
-            const uint32_t row = (uint32_t)(b0 + eb) * (uint32_t)na + (uint32_t)(a0 + ea);
-            const float val = tile[f];
-            if (val != 0.0f) unsafeAtomicAdd(gP + (size_t)row * 8 + (f & 7), val);
-        }
-        wave_order();
-    }
-    return true;
 }
 
-// Scatter one batch into all four gradient arrays: each source is tried
-// with all 16 samples in one tile, else as two halves of 8 samples (about
-// half the box per axis), else with direct atomics.
-// Lane 0 of the group is always active (a batch has at least one sample),
-// so the first half is never empty; the second half may be.
-__device__ __forceinline__ void scatter_batch(const SceneDev& sc, float* gV, float* gxy, float* gxz, float* gyz,
-                                              float* tile, bool act, const Corners& cn, const float* gt, int gl,
-                                              int lane) {
-    const bool lo = act && gl < 8, hi = act && gl >= 8;
-    const bool hi_any = g_ballot(hi, lane) != 0u;
-    if (!scatter_grid(sc, gV, tile, act, cn, gt, gl, true)) {
-        scatter_grid(sc, gV, tile, lo, cn, gt, gl, false);
-        if (hi_any) scatter_grid(sc, gV, tile, hi, cn, gt, gl, false);
+__device__ __forceinline__ void scatter_batch_runs(const SceneDev& sc, float* gV, float* gxy, float* gxz, float* gyz,
+                                                   Stage& st, bool act, const Corners& cn, const float* gt, int gl,
+                                                   int lane) {
+    {
+        const RunSet rs = run_set(cn.g, act, gl, lane);
+        const float x0w = 1.0f - cn.fx, x1w = cn.fx, y0w = 1.0f - cn.fy, y1w = cn.fy;
+        const float z0w = 1.0f - cn.fz, z1w = cn.fz;
+        const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
+#pragma unroll 1
+        for (int p = 0; p < 4; ++p) {
+            const float yw = (p & 1) ? y1w : y0w, zw = (p >> 1) ? z1w : z0w;
+            flush_pair(gV, st, rs.rn, rs.rank, rs.nt, cn.g + ((p & 1) ? sy : 0u) + ((p >> 1) ? sz : 0u),
+                       x0w * yw * zw, x1w * yw * zw, gt, rs.lmax, gl);
+        }
     }
-    if (!scatter_plane(gxy, sc.Nx, tile, act, cn.jx, cn.jy, cn.ux, cn.uy, gt, gl, true)) {
-        scatter_plane(gxy, sc.Nx, tile, lo, cn.jx, cn.jy, cn.ux, cn.uy, gt, gl, false);
-        if (hi_any) scatter_plane(gxy, sc.Nx, tile, hi, cn.jx, cn.jy, cn.ux, cn.uy, gt, gl, false);
-    }
-    if (!scatter_plane(gxz, sc.Nx, tile, act, cn.jx, cn.jz, cn.ux, cn.uz, gt, gl, true)) {
-        scatter_plane(gxz, sc.Nx, tile, lo, cn.jx, cn.jz, cn.ux, cn.uz, gt, gl, false);
-        if (hi_any) scatter_plane(gxz, sc.Nx, tile, hi, cn.jx, cn.jz, cn.ux, cn.uz, gt, gl, false);
-    }
-    if (!scatter_plane(gyz, sc.Ny, tile, act, cn.jy, cn.jz, cn.uy, cn.uz, gt, gl, true)) {
-        scatter_plane(gyz, sc.Ny, tile, lo, cn.jy, cn.jz, cn.uy, cn.uz, gt, gl, false);
-        if (hi_any) scatter_plane(gyz, sc.Ny, tile, hi, cn.jy, cn.jz, cn.uy, cn.uz, gt, gl, false);
-    }
+    scatter_plane_runs(gxy, sc.Nx, st, act, cn.xy, cn.ux, cn.uy, gt, gl, lane);
+    scatter_plane_runs(gxz, sc.Nx, st, act, cn.xz, cn.ux, cn.uz, gt, gl, lane);
+    scatter_plane_runs(gyz, sc.Ny, st, act, cn.yz, cn.uy, cn.uz, gt, gl, lane);
 }
 
 // One replayed sample: optical depth, density, activated colours/features.
@@ -578,14 +474,14 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
                                                       float* __restrict__ gyz, float* __restrict__ gmlp) {
     __shared__ int qs[kGroupsPerBlock][kQueue];
     __shared__ float sW[512];
-    __shared__ __attribute__((aligned(16))) float tiles[kGroupsPerBlock][kTile * 8];
+    __shared__ __attribute__((aligned(16))) Stage stages[kGroupsPerBlock];
     for (int i = threadIdx.x; i < 512; i += kBlock) sW[i] = 0.0f;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kGroup - 1);
     const int gid = threadIdx.x / kGroup;
     const int h = gl;
-    float* tile = tiles[gid];
+    Stage& stage = stages[gid];
     const float* W = sc.mlp;
     const int64_t start = (int64_t)xcd_block(blockIdx.x, gridDim.x) * chunk;
     const int64_t stop_r = min(n, start + chunk);
@@ -715,7 +611,7 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
             gt[0] = (Tnext * gv - suffix - Tn * gT) * rp.delta * tau;
 #pragma unroll
             for (int c = 0; c < 7; ++c) gt[c + 1] = w * g7[c] * v[c] * (1.0f - v[c]);
-            scatter_batch(sc, gV, gxy, gxz, gyz, tile, act, cn, gt, gl, lane);
+            scatter_batch_runs(sc, gV, gxy, gxz, gyz, stage, act, cn, gt, gl, lane);
             carry += __shfl(incl, kGroup - 1, kGroup);
             done += nb_eff;
             ++b;

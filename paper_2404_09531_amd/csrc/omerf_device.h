@@ -465,16 +465,6 @@ __device__ __forceinline__ uint32_t g_ballot(bool pred, int lane) {
     return (uint32_t)(m >> (lane & (64 - kGroup))) & 0xffffu;
 }
 
-// True unless the active lanes' x goes both up and down in lane order.
-__device__ __forceinline__ bool g_monotone(int x, bool act, int lane) {
-    const int gl = lane & (kGroup - 1);
-    const int a = act ? 1 : 0;
-    const bool both = act && dpp_row_i<kRowShr | 1>(a) != 0 && gl > 0;
-    const int px = dpp_row_i<kRowShr | 1>(x);
-    const uint32_t up = g_ballot(both && x > px, lane), down = g_ballot(both && x < px, lane);
-    return up == 0u || down == 0u;
-}
-
 // Keeps the compiler from moving LDS accesses across this point; the
 // hardware executes one wave's LDS instructions in order.
 __device__ __forceinline__ void wave_order() {
