@@ -89,10 +89,15 @@ def time_stages(step_fns, steps, warmup, torch):
     return total, per
 
 
-def _outputs(torch, n, dev):
-    return dict(C=torch.empty((n, 3), device=dev), T=torch.empty((n,), device=dev),
-                F=torch.empty((n, 7), device=dev), n_placed=torch.empty((n,), dtype=torch.int32, device=dev),
-                n_eval=torch.empty((n,), dtype=torch.int32, device=dev))
+def _outputs(torch, n, dev, batch_slots=0):
+    """Forward outputs; batch_slots > 0 adds the per-batch w v sums that a
+    training forward saves for the backward."""
+    out = dict(C=torch.empty((n, 3), device=dev), T=torch.empty((n,), device=dev),
+               F=torch.empty((n, 7), device=dev), n_placed=torch.empty((n,), dtype=torch.int32, device=dev),
+               n_eval=torch.empty((n,), dtype=torch.int32, device=dev))
+    if batch_slots:
+        out["batch_wv"] = torch.empty((n, batch_slots, 7), device=dev)
+    return out
 
 
 def _bf16_scene(om, t):
@@ -122,7 +127,7 @@ def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a):
     o2, d2 = scenegen.make_rays(rec2)
     n2 = o2.shape[0]
     o2g, d2g = torch.from_numpy(o2).to(dev), torch.from_numpy(d2).to(dev)
-    out2 = _outputs(torch, n2, dev)
+    out2 = _outputs(torch, n2, dev, om.batch_slots(kw["n_max"]))
     om.render_into(scene, o2g, d2g, out2, **kw)
     g = torch.Generator(device=dev)
     g.manual_seed(2)
@@ -183,7 +188,7 @@ def form_towers(om, scenegen, torch, a):
     scene_b, tb = _bf16_scene(om, t)
     og, dg = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
     kw = dict(n_max=rec["n_max"], c_bg=BG)
-    out = _outputs(torch, n, dev)
+    out = _outputs(torch, n, dev, om.batch_slots(kw["n_max"]))
     om.render_into(scene_b, og, dg, out, **kw)
     g = torch.Generator(device=dev)
     g.manual_seed(2)

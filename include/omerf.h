@@ -122,7 +122,21 @@ typedef struct om_fwd_out {
     float* F;
     int32_t* n_placed;
     int32_t* n_eval;
+    /* Optional (NULL to skip), for the backward: float32
+     * [n][OM_BATCH_SLOTS(n_max)][7].  Slot b of a ray holds, for its b-th
+     * group of OM_BATCH consecutive evaluated samples (the last group may be
+     * shorter), the sum over the group of w_i * v_i: the compositing weight
+     * of Eq. 1 times the activated diffuse colour and feature channels of
+     * Eq. 3 (the same 7 channels as F, which is the sum over all groups).
+     * Slots from ceil(n_eval / OM_BATCH) on are not written.  The march
+     * writes it when non-NULL; om_render_backward reads it when non-NULL
+     * and otherwise recomputes these sums with an extra replay of the
+     * samples. */
+    float* batch_wv;
 } om_fwd_out;
+
+#define OM_BATCH 16
+#define OM_BATCH_SLOTS(n_max) (((n_max) + OM_BATCH - 1) / OM_BATCH)
 
 /* Gradient buffers (device, float32, caller-zeroed or holding a running
  * sum: the backward pass ACCUMULATES into them).  Shapes match the scene:
@@ -184,7 +198,7 @@ int om_deferred_mlp(const om_scene* scene, const float* d, int64_t n, const om_p
 /*
  * Backward of om_render for a per-ray colour loss (derived from Eq. 1-4).
  * saved: the om_fwd_out written by om_render for the same scene, rays and
- * parameters (C is not read).  dL_dC: device float32 [n][3].  Gradients are
+ * parameters (C is not read; batch_wv is used when non-NULL).  dL_dC: device float32 [n][3].  Gradients are
  * ADDED with float32 atomics into g (grid, planes, MLP; no ray gradient);
  * per-sample features are recomputed, not stored.  Summation order of the
  * atomics is not deterministic.  The MLP part is differentiated in float32

@@ -153,9 +153,19 @@ def place_samples(scene: Scene, o, d, n_max: int, delta: float = DELTA):
     return k, cnt
 
 
+BATCH = 16  # samples per batch of the per-batch w v sums (OM_BATCH)
+
+
+def batch_slots(n_max: int) -> int:
+    """Per-ray slots of the optional `batch_wv` output (OM_BATCH_SLOTS)."""
+    return (n_max + BATCH - 1) // BATCH
+
+
 def render(scene: Scene, o, d, n_max: int, delta: float = DELTA, t_term: float = 0.0,
-           c_bg=(0.0, 0.0, 0.0), mlp_bf16: int = -1) -> Dict[str, torch.Tensor]:
-    """Forward render; returns C [n,3], T [n], F [n,7], n_placed [n], n_eval [n]."""
+           c_bg=(0.0, 0.0, 0.0), mlp_bf16: int = -1, batch_wv: bool = False) -> Dict[str, torch.Tensor]:
+    """Forward render; returns C [n,3], T [n], F [n,7], n_placed [n], n_eval [n]
+    and, with batch_wv=True, the per-batch sums of w v [n, batch_slots(n_max), 7]
+    that let the backward skip one replay of the samples."""
     n = _rays(scene, o, d)
     dev = o.device
     out = dict(C=torch.empty((n, 3), dtype=torch.float32, device=dev),
@@ -163,23 +173,34 @@ def render(scene: Scene, o, d, n_max: int, delta: float = DELTA, t_term: float =
                F=torch.empty((n, 7), dtype=torch.float32, device=dev),
                n_placed=torch.empty((n,), dtype=torch.int32, device=dev),
                n_eval=torch.empty((n,), dtype=torch.int32, device=dev))
+    if batch_wv:
+        out["batch_wv"] = torch.empty((n, batch_slots(n_max), 7), dtype=torch.float32, device=dev)
     render_into(scene, o, d, out, n_max, delta, t_term, c_bg, mlp_bf16)
     return out
 
 
-def _fwd_out(out):
+def _batch_wv(out, n: int, n_max: int) -> int:
+    bw = out.get("batch_wv")
+    if bw is None:
+        return 0
+    _need(bw, "batch_wv", torch.float32, (n, batch_slots(n_max), 7))
+    return bw.data_ptr()
+
+
+def _fwd_out(out, n: int, n_max: int):
     return _lib.OmFwdOut(_lib.ptr(out.get("C")), out["T"].data_ptr(), out["F"].data_ptr(),
-                         _lib.ptr(out.get("n_placed")), out["n_eval"].data_ptr())
+                         _lib.ptr(out.get("n_placed")), out["n_eval"].data_ptr(), _batch_wv(out, n, n_max))
 
 
 def render_into(scene: Scene, o, d, out: Dict[str, torch.Tensor], n_max: int, delta: float = DELTA,
                 t_term: float = 0.0, c_bg=(0.0, 0.0, 0.0), mlp_bf16: int = -1, stage: str = "all") -> None:
-    """Forward render into preallocated outputs (same keys as render()).
+    """Forward render into preallocated outputs (same keys as render(); an
+    optional "batch_wv" entry receives the per-batch w v sums).
 
     stage="all" runs om_render; "march" only om_march (F, T, counts);
     "mlp" only om_deferred_mlp (C from F, T, n_eval)."""
     n = o.shape[0]
-    fo = _fwd_out(out)
+    fo = _fwd_out(out, n, n_max)
     p = _params(n_max, delta, t_term, c_bg, mlp_bf16)
     L = _lib.lib()
     st = _lib.stream_of(o)
@@ -199,13 +220,14 @@ def render_into(scene: Scene, o, d, out: Dict[str, torch.Tensor], n_max: int, de
 def render_backward(scene: Scene, o, d, saved: Dict[str, torch.Tensor], dL_dC, grads: Dict[str, torch.Tensor],
                     n_max: int, delta: float = DELTA, t_term: float = 0.0, c_bg=(0.0, 0.0, 0.0)) -> None:
     """Accumulate dL/d(grid, planes, mlp) into float32 `grads` (keys grid,
-    plane_xy, plane_xz, plane_yz, mlp) given dL/dC and the forward's outputs."""
+    plane_xy, plane_xz, plane_yz, mlp) given dL/dC and the forward's outputs
+    (with "batch_wv" among them when the forward wrote it)."""
     n = _rays(scene, o, d)
     _need(dL_dC, "dL_dC", torch.float32, (n, 3))
     for key in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp"):
         _need(grads[key], f"grads[{key}]", torch.float32, scene.tensors[key].shape)
     fo = _lib.OmFwdOut(saved["C"].data_ptr(), saved["T"].data_ptr(), saved["F"].data_ptr(),
-                       saved["n_placed"].data_ptr(), saved["n_eval"].data_ptr())
+                       saved["n_placed"].data_ptr(), saved["n_eval"].data_ptr(), _batch_wv(saved, n, n_max))
     g = _lib.OmGrads(grads["grid"].data_ptr(), grads["plane_xy"].data_ptr(), grads["plane_xz"].data_ptr(),
                      grads["plane_yz"].data_ptr(), grads["mlp"].data_ptr())
     p = _params(n_max, delta, t_term, c_bg, -1)
@@ -249,17 +271,17 @@ class RenderFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, scene, o, d, opts, grid, plane_xy, plane_xz, plane_yz, mlp):
-        out = render(scene, o, d, **opts)
+        out = render(scene, o, d, batch_wv=True, **opts)
         ctx.scene, ctx.opts = scene, opts
         ctx.masters = (grid, plane_xy, plane_xz, plane_yz, mlp)
-        ctx.save_for_backward(o, d, out["C"], out["T"], out["F"], out["n_placed"], out["n_eval"])
+        ctx.save_for_backward(o, d, out["C"], out["T"], out["F"], out["n_placed"], out["n_eval"], out["batch_wv"])
         ctx.mark_non_differentiable(out["T"], out["F"], out["n_placed"], out["n_eval"])
         return out["C"], out["T"], out["F"], out["n_placed"], out["n_eval"]
 
     @staticmethod
     def backward(ctx, gC, *_unused):
-        o, d, C, T, F, npl, nev = ctx.saved_tensors
-        saved = dict(C=C, T=T, F=F, n_placed=npl, n_eval=nev)
+        o, d, C, T, F, npl, nev, bwv = ctx.saved_tensors
+        saved = dict(C=C, T=T, F=F, n_placed=npl, n_eval=nev, batch_wv=bwv)
         grads = {k: torch.zeros(m.shape, dtype=torch.float32, device=m.device)
                  for k, m in zip(("grid", "plane_xy", "plane_xz", "plane_yz", "mlp"), ctx.masters)}
         opts = {k: v for k, v in ctx.opts.items() if k != "mlp_bf16"}

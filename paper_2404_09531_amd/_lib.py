@@ -37,7 +37,8 @@ class OmParams(ctypes.Structure):
 
 
 class OmFwdOut(ctypes.Structure):
-    _fields_ = [("C", c_void_p), ("T", c_void_p), ("F", c_void_p), ("n_placed", c_void_p), ("n_eval", c_void_p)]
+    _fields_ = [("C", c_void_p), ("T", c_void_p), ("F", c_void_p), ("n_placed", c_void_p), ("n_eval", c_void_p),
+                ("batch_wv", c_void_p)]
 
 
 class OmGrads(ctypes.Structure):

@@ -222,6 +222,8 @@ int check_fwd(const om_scene* scene, const float* o, const float* d, int64_t n, 
     if (n == 0) return OM_OK;
     if ((need_C && !out->C) || (need_o && !out->n_placed) || !out->T || !out->F || !out->n_eval)
         return fail(OM_ERR_INVALID, "required om_fwd_out buffers are NULL");
+    if (out->batch_wv && ((uintptr_t)out->batch_wv & 3u))
+        return fail(OM_ERR_INVALID, "batch_wv must be 4-byte aligned");
     return OM_OK;
 }
 
@@ -240,7 +242,7 @@ int om_march(const om_scene* scene, const float* o, const float* d, int64_t n, c
     if (rc != OM_OK || n == 0) return rc == OM_OK ? ok() : rc;
     const bool bf16 = scene->desc.dtype == OM_BF16;
     return hip_status(launch_march_fwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_placed, out->n_eval,
-                                       (hipStream_t)stream), "om_march");
+                                       out->batch_wv, (hipStream_t)stream), "om_march");
 }
 
 int om_deferred_mlp(const om_scene* scene, const float* d, int64_t n, const om_params* p, const om_fwd_out* out,
@@ -259,7 +261,8 @@ int om_render(const om_scene* scene, const float* o, const float* d, int64_t n, 
     if (rc != OM_OK || n == 0) return rc == OM_OK ? ok() : rc;
     const bool bf16 = scene->desc.dtype == OM_BF16;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_march_fwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_placed, out->n_eval, s);
+    hipError_t e = launch_march_fwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_placed, out->n_eval,
+                                    out->batch_wv, s);
     if (e != hipSuccess) return hip_status(e, "om_render (march)");
     e = launch_mlp(scene->dev.mlp, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval, out->C, s);
     return hip_status(e, "om_render (mlp)");
@@ -274,12 +277,15 @@ int om_render_backward(const om_scene* scene, const float* o, const float* d, in
     if (!saved || !g) return fail(OM_ERR_INVALID, "saved / grads struct is NULL");
     if (n == 0) return ok();
     if (!saved->F || !saved->T || !saved->n_eval) return fail(OM_ERR_INVALID, "saved F, T and n_eval are required");
+    if (saved->batch_wv && ((uintptr_t)saved->batch_wv & 3u))
+        return fail(OM_ERR_INVALID, "batch_wv must be 4-byte aligned");
     if (!dL_dC) return fail(OM_ERR_INVALID, "dL_dC is NULL");
     if (!g->grid || !g->plane_xy || !g->plane_xz || !g->plane_yz || !g->mlp)
         return fail(OM_ERR_INVALID, "all gradient buffers are required");
     const bool bf16 = scene->desc.dtype == OM_BF16;
-    hipError_t e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, saved->F, saved->T, saved->n_eval, dL_dC, g->grid,
-                                    g->plane_xy, g->plane_xz, g->plane_yz, g->mlp, (hipStream_t)stream);
+    hipError_t e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, saved->F, saved->T, saved->n_eval, saved->batch_wv,
+                                    dL_dC, g->grid, g->plane_xy, g->plane_xz, g->plane_yz, g->mlp,
+                                    (hipStream_t)stream);
     return hip_status(e, "om_render_backward");
 }
 
@@ -308,6 +314,6 @@ const char* om_status_str(int status) {
     }
 }
 
-int om_version(void) { return 100; }
+int om_version(void) { return 101; }
 
 }  // extern "C"

@@ -107,12 +107,20 @@ __global__ __launch_bounds__(kBlock) void k_place(SceneDev sc, RayParams rp, con
 // adjacent corners per sample.  Transmittance comes from a 16-lane scan with
 // the optical depth on the even lanes only.
 // ---------------------------------------------------------------------------
+// Group total of x (inclusive DPP scan; the row's last lane holds it) stored
+// by that lane at dst, for the optional per-batch sums of w v.
+__device__ __forceinline__ void store_group_total(float x, int gl, float* dst) {
+    x = g_scan_incl(x, gl);
+    if (gl == kGroup - 1) *dst = x;
+}
+
 template <class S>
 __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                            const float* __restrict__ d_, int64_t n,
                                                            float* __restrict__ F, float* __restrict__ T,
                                                            int32_t* __restrict__ n_placed,
-                                                           int32_t* __restrict__ n_eval) {
+                                                           int32_t* __restrict__ n_eval,
+                                                           float* __restrict__ BW) {
     __shared__ int qs[kGroupsPerBlock][kQueue];
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kGroup - 1);
@@ -125,9 +133,13 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
 #pragma unroll
     for (int c = 0; c < 7; ++c) acc[c] = 0.0f;
     float carry = 0.0f;
-    int evals = 0;
+    int evals = 0, batch = 0;
+    const int slots = (rp.n_max + kGroup - 1) / kGroup;
     const int placed = march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
         bool stop = false;
+        float bacc[7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) bacc[c] = 0.0f;
 #pragma unroll
         for (int sub = 0; sub < 2; ++sub) {
             const int nsub = min(max(nb - sub * 8, 0), 8);  // samples in this half (group-uniform)
@@ -170,11 +182,19 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
                 }
                 if (s >= nb_eff || half) w = 0.0f;  // accumulate once per sample (even lane)
 #pragma unroll
-                for (int c = 0; c < 7; ++c) acc[c] += w * v[c];
+                for (int c = 0; c < 7; ++c) bacc[c] += w * v[c];
                 carry += __shfl(incl, 2 * (nb_eff - 1), kGroup);
                 evals += nb_eff;
             }
         }
+#pragma unroll
+        for (int c = 0; c < 7; ++c) acc[c] += bacc[c];
+        if (BW) {
+            float* dst = BW + ((size_t)ray * slots + batch) * 7;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) store_group_total(bacc[c], gl, dst + c);
+        }
+        ++batch;
         return stop;
     });
     float f[7];
@@ -243,7 +263,8 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParam
                                                            const float* __restrict__ d_, int64_t n,
                                                            float* __restrict__ F, float* __restrict__ T,
                                                            int32_t* __restrict__ n_placed,
-                                                           int32_t* __restrict__ n_eval) {
+                                                           int32_t* __restrict__ n_eval,
+                                                           float* __restrict__ BW) {
     __shared__ int qs[kGroupsPerBlock][kQueue];
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kGroup - 1);
@@ -258,7 +279,8 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParam
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = 0.0f;
     float carry = 0.0f;
-    int evals = 0;
+    int evals = 0, batch = 0;
+    const int slots = (rp.n_max + kGroup - 1) / kGroup;
     const int placed = march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
         float a[4], v[4][4];
 #pragma unroll
@@ -307,13 +329,24 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParam
                 stop = true;
             }
         }
+        float bacc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             float w = __expf(-pre[j]) * (-expm1f(-a[j]));
             if (4 * j + s >= nb_eff || h) w = 0.0f;  // once per sample and channel half
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[c] += w * v[j][c];
+            for (int c = 0; c < 4; ++c) bacc[c] += w * v[j][c];
         }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += bacc[c];
+        if (BW) {
+            float* dst = BW + ((size_t)ray * slots + batch) * 7;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) store_group_total(ch == 0 ? bacc[c] : 0.0f, gl, dst + c);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) store_group_total(ch == 1 ? bacc[c] : 0.0f, gl, dst + 3 + c);
+        }
+        ++batch;
         // depth through the last evaluated sample, from the quad that owns it
         const int jl = (nb_eff - 1) >> 2;
         const float mine = (jl == 0 ? pre[0] + a[0] : jl == 1 ? pre[1] + a[1] : jl == 2 ? pre[2] + a[2] : pre[3] + a[3]);
@@ -469,6 +502,7 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
                                                       const float* __restrict__ d_, int64_t n, int64_t chunk,
                                                       const float* __restrict__ Fs, const float* __restrict__ Ts,
                                                       const int32_t* __restrict__ n_eval,
+                                                      const float* __restrict__ BW,
                                                       const float* __restrict__ dC, float* __restrict__ gV,
                                                       float* __restrict__ gxy, float* __restrict__ gxz,
                                                       float* __restrict__ gyz, float* __restrict__ gmlp) {
@@ -545,7 +579,23 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
         float btot[kBatchSlots];
 #pragma unroll
         for (int s = 0; s < kBatchSlots; ++s) btot[s] = 0.0f;
-        {
+        if (BW) {
+            // The forward's per-batch sums of w v: B_b = g7 . sum_{i in b} w_i v_i.
+            const int slots = (rp.n_max + kGroup - 1) / kGroup, nbat = (ne + kGroup - 1) / kGroup;
+#pragma unroll 1
+            for (int s = 0; s < (nbat + kGroup - 1) / kGroup; ++s) {
+                const int b = s * kGroup + gl;
+                float t = 0.0f;
+                if (b < nbat) {
+                    const float* src = BW + ((size_t)ray * slots + b) * 7;
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) t += g7[c] * src[c];
+                }
+#pragma unroll
+                for (int k = 0; k < kBatchSlots; ++k)
+                    if (s == k) btot[k] = t;
+            }
+        } else {
             float carry = 0.0f;
             int done = 0, b = 0;
             march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
@@ -637,18 +687,20 @@ hipError_t launch_place(const SceneDev& sc, const RayParams& rp, const float* o,
 }
 
 hipError_t launch_march_fwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
-                            int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, hipStream_t s) {
+                            int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, float* batch_wv,
+                            hipStream_t s) {
     if (bf16)
         hipLaunchKernelGGL(k_march_fwd<BF16Store>, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n, F, T,
-                           n_placed, n_eval);
+                           n_placed, n_eval, batch_wv);
     else
         hipLaunchKernelGGL(k_march_fwd_f32q, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n, F, T,
-                           n_placed, n_eval);
+                           n_placed, n_eval, batch_wv);
     return hipGetLastError();
 }
 
 hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
-                            int64_t n, const float* F, const float* T, const int32_t* n_eval, const float* dC,
+                            int64_t n, const float* F, const float* T, const int32_t* n_eval, const float* batch_wv,
+                            const float* dC,
                             float* gV, float* gxy, float* gxz, float* gyz, float* gmlp, hipStream_t s) {
     // Persistent blocks, each owning a contiguous chunk of rays, so the MLP
     // weight gradients are reduced in LDS over many rays before one set of
@@ -661,10 +713,10 @@ hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, 
     nb = (n + chunk - 1) / chunk;
     if (bf16)
         hipLaunchKernelGGL(k_march_bwd<BF16Store>, dim3((unsigned)nb), dim3(kBlock), 0, s, sc, rp, o, d, n, chunk, F, T,
-                           n_eval, dC, gV, gxy, gxz, gyz, gmlp);
+                           n_eval, batch_wv, dC, gV, gxy, gxz, gyz, gmlp);
     else
         hipLaunchKernelGGL(k_march_bwd<F32Store>, dim3((unsigned)nb), dim3(kBlock), 0, s, sc, rp, o, d, n, chunk, F, T,
-                           n_eval, dC, gV, gxy, gxz, gyz, gmlp);
+                           n_eval, batch_wv, dC, gV, gxy, gxz, gyz, gmlp);
     return hipGetLastError();
 }
 

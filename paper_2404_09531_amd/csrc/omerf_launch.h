@@ -11,9 +11,11 @@ namespace omerf {
 hipError_t launch_place(const SceneDev& sc, const RayParams& rp, const float* o, const float* d, int64_t n,
                         int32_t* k_out, int32_t* n_placed, hipStream_t s);
 hipError_t launch_march_fwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
-                            int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, hipStream_t s);
+                            int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, float* batch_wv,
+                            hipStream_t s);
 hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
-                            int64_t n, const float* F, const float* T, const int32_t* n_eval, const float* dC,
+                            int64_t n, const float* F, const float* T, const int32_t* n_eval, const float* batch_wv,
+                            const float* dC,
                             float* gV, float* gxy, float* gxz, float* gyz, float* gmlp, hipStream_t s);
 hipError_t launch_mlp(const float* W, bool bf16, const RayParams& rp, const float* d, int64_t n, const float* F,
                       const float* T, const int32_t* n_eval, float* C, hipStream_t s);

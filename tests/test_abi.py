@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol(L):
     assert names == set(_lib.EXPORTS)
     for n in names:
         assert hasattr(L, n), n
-    assert L.om_version() == 100
+    assert L.om_version() == 101
     assert L.om_status_str(-2) == b"unsupported shape or dtype"
 
 
@@ -117,10 +117,27 @@ def test_render_argument_errors(L):
     g = _lib.OmGrads(FAKE, FAKE, FAKE, 0, FAKE)
     assert L.om_render_backward(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(out), FAKE,
                                 ctypes.byref(g), None) == _lib.OM_ERR_INVALID
+    # the optional per-batch sums must be float-aligned when given
+    bad_bw = _lib.OmFwdOut(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE + 2)
+    assert L.om_render(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(bad_bw), None) == _lib.OM_ERR_INVALID
+    assert L.om_march(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(bad_bw), None) == _lib.OM_ERR_INVALID
+    g_ok = _lib.OmGrads(FAKE, FAKE, FAKE, FAKE, FAKE)
+    assert L.om_render_backward(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(bad_bw), FAKE,
+                                ctypes.byref(g_ok), None) == _lib.OM_ERR_INVALID
     assert L.om_place_samples(h, FAKE, FAKE, 4, ctypes.byref(_params()), 0, FAKE, None) == _lib.OM_ERR_INVALID
     assert L.om_l2_loss_fp64(FAKE, FAKE, 0, FAKE, None) == _lib.OM_ERR_INVALID
     assert L.om_l2_loss_grad(FAKE, FAKE, 3, FAKE, None, None) == _lib.OM_ERR_INVALID  # aliasing
     L.om_scene_destroy(h)
+
+
+def test_fwd_out_layout_matches_header():
+    """om_fwd_out is six pointers in header order, batch_wv last."""
+    hdr = open(os.path.join(ROOT, "include", "omerf.h")).read()
+    body = re.search(r"typedef struct om_fwd_out \{(.*?)\} om_fwd_out;", hdr, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\*\s*(\w+);", body)
+    assert fields == [f for f, _ in _lib.OmFwdOut._fields_]
+    assert ctypes.sizeof(_lib.OmFwdOut) == 6 * ctypes.sizeof(ctypes.c_void_p)
 
 
 def test_scene_update_keeps_handle_on_error(L):

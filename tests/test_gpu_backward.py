@@ -23,8 +23,8 @@ BG = (0.25, 0.5, 0.75)
 SOURCES = ("grid", "plane_xy", "plane_xz", "plane_yz")
 
 
-def _gpu_grads(scene, t, og, dg, target, n_max, t_term=0.0):
-    res = om.render(scene, og, dg, n_max=n_max, c_bg=BG, t_term=t_term)
+def _gpu_grads(scene, t, og, dg, target, n_max, t_term=0.0, batch_wv=False):
+    res = om.render(scene, og, dg, n_max=n_max, c_bg=BG, t_term=t_term, batch_wv=batch_wv)
     dC, loss = om.l2_loss_grad(res["C"], target)
     grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp")}
     om.render_backward(scene, og, dg, res, dC, grads, n_max=n_max, c_bg=BG, t_term=t_term)
@@ -63,11 +63,37 @@ def test_backward_tiny_vs_oracle(tiny_train):
     log("test_backward_tiny_vs_oracle: 256 rays")
     og, dg = rays_to(o, d)
     tg = torch.from_numpy(target.astype(np.float32)).to(og.device)
-    res, loss, grads = _gpu_grads(scene, t, og, dg, tg, 64)
     ref_loss, ref_C, ref_grads = oracle.oracle_loss_and_grads(sc, o, d, oracle.RenderParams(n_max=64, c_bg=BG),
                                                              target.astype(np.float32).astype(np.float64))
-    assert abs(loss - ref_loss) <= 1e-3 * ref_loss
-    _check_against_oracle(sc, grads, ref_grads)
+    for bw in (False, True):  # batch totals from a replay / from the forward's per-batch sums
+        res, loss, grads = _gpu_grads(scene, t, og, dg, tg, 64, batch_wv=bw)
+        assert abs(loss - ref_loss) <= 1e-3 * ref_loss
+        _check_against_oracle(sc, grads, ref_grads)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_batch_wv_prefixes_match_truncated_oracle_renders(tiny_train, dtype):
+    """The forward's per-batch sums of w v, accumulated over the first b + 1
+    batches of 16 samples, equal F of the oracle render truncated to
+    n_max = 16 (b + 1): truncation keeps exactly the first samples."""
+    sc, _, _, o, d, _ = tiny_train
+    log(f"test_batch_wv_prefixes_match_truncated_oracle_renders: {dtype}")
+    scene, _ = upload_scene(sc, dtype=dtype)
+    ref_sc = sc if dtype == torch.float32 else _rounded_scene(sc)
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG, mlp_bf16=0, batch_wv=True)
+    bw = res["batch_wv"].double().cpu().numpy()
+    ne = res["n_eval"].cpu().numpy()
+    cum = np.cumsum(bw, axis=1)
+    for b in range(om.batch_slots(64)):
+        ref = oracle.oracle_render(ref_sc, o, d, oracle.RenderParams(n_max=16 * (b + 1), c_bg=BG), keep_k=False)
+        live = ne > 16 * b  # rays whose slot b was written
+        assert live.any()
+        err = np.abs(cum[live, b] - ref["F"][live]).max()
+        log(f"  batches 0..{b}: {live.sum()} rays, max |sum - F_oracle(n_max={16 * (b + 1)})| = {err:.2e}")
+        assert err <= 1e-5
+    assert np.abs(cum[np.arange(len(ne)), np.maximum((ne + 15) // 16 - 1, 0)][ne > 0]
+                  - res["F"].double().cpu().numpy()[ne > 0]).max() <= 1e-5
 
 
 def test_backward_sum_invariant(tiny_train):
@@ -93,6 +119,8 @@ def test_backward_ert_matches_oracle(tiny_train):
     if not np.array_equal(res["n_eval"].cpu().numpy(), ref["n_eval"]):
         pytest.skip("a ray's transmittance sits at the threshold; gradients are compared with t_term=0")
     _, _, ref_grads = oracle.oracle_loss_and_grads(sc, o, d, prm, target.astype(np.float32).astype(np.float64))
+    _check_against_oracle(sc, grads, ref_grads)
+    _, _, grads = _gpu_grads(scene, t, og, dg, tg, 64, t_term=1e-2, batch_wv=True)
     _check_against_oracle(sc, grads, ref_grads)
 
 
@@ -183,18 +211,19 @@ def test_towers_bf16_storage_gradient_vs_oracle(towers):
     scene, t = upload_scene(sc, dtype=torch.bfloat16)
     og, dg = rays_to(o, d)
     tg = torch.from_numpy(target).to(og.device)
-    res = om.render(scene, og, dg, n_max=n_max, c_bg=BG, mlp_bf16=0)
-    dC, loss = om.l2_loss_grad(res["C"], tg)
-    grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp")}
-    om.render_backward(scene, og, dg, res, dC, grads, n_max=n_max, c_bg=BG)
-    g = {k: v.double().cpu().numpy() for k, v in grads.items()}
-    npl = res["n_placed"].cpu().numpy()
-    log(f"  samples/ray: min {npl.min()} mean {npl.mean():.1f} max {npl.max()}; "
-        f"hist(32-wide bins) {np.histogram(npl, bins=np.arange(0, 545, 32))[0].tolist()}")
     rsc = _rounded_scene(sc)
     _, _, ref = oracle.oracle_loss_and_grads(rsc, o, d, oracle.RenderParams(n_max=n_max, c_bg=BG),
                                              target.astype(np.float64))
-    _check_against_oracle(rsc, g, ref)
+    for bw in (False, True):
+        res = om.render(scene, og, dg, n_max=n_max, c_bg=BG, mlp_bf16=0, batch_wv=bw)
+        dC, loss = om.l2_loss_grad(res["C"], tg)
+        grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp")}
+        om.render_backward(scene, og, dg, res, dC, grads, n_max=n_max, c_bg=BG)
+        g = {k: v.double().cpu().numpy() for k, v in grads.items()}
+        npl = res["n_placed"].cpu().numpy()
+        log(f"  samples/ray: min {npl.min()} mean {npl.mean():.1f} max {npl.max()}; "
+            f"hist(32-wide bins) {np.histogram(npl, bins=np.arange(0, 545, 32))[0].tolist()}")
+        _check_against_oracle(rsc, g, ref)
 
 
 def test_towers_full_bf16_gradient_error(towers):
@@ -248,11 +277,12 @@ def test_oblique_backward_vs_oracle_256(oblique_train):
     o256, d256, t256 = o[:256].copy(), d[:256].copy(), target[:256].copy()
     og, dg = rays_to(o256, d256)
     tg = torch.from_numpy(t256).to(og.device)
-    _, loss, grads = _gpu_grads(scene, t, og, dg, tg, n_max)
     ref_loss, _, ref = oracle.oracle_loss_and_grads(sc, o256, d256, oracle.RenderParams(n_max=n_max, c_bg=BG),
                                                    t256.astype(np.float64))
-    assert abs(loss - ref_loss) <= 1e-3 * ref_loss
-    _check_against_oracle(sc, grads, ref)
+    for bw in (False, True):
+        _, loss, grads = _gpu_grads(scene, t, og, dg, tg, n_max, batch_wv=bw)
+        assert abs(loss - ref_loss) <= 1e-3 * ref_loss
+        _check_against_oracle(sc, grads, ref)
 
 
 def test_oblique_finite_differences_2e18(oblique_train):
@@ -262,7 +292,7 @@ def test_oblique_finite_differences_2e18(oblique_train):
     log("test_oblique_finite_differences_2e18: 64 params, 2^18 rays")
     og, dg = rays_to(o, d)
     tg = torch.from_numpy(target).to(og.device)
-    res, _, grads = _gpu_grads(scene, t, og, dg, tg, n_max)
+    res, _, grads = _gpu_grads(scene, t, og, dg, tg, n_max, batch_wv=True)  # the training path
     picks, fd, an, err = _fd_check(scene, t, og, dg, tg, n_max, grads)
     for src in (*SOURCES, "mlp"):
         sel = [i for i, (s_, _) in enumerate(picks) if s_ == src]
