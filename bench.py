@@ -260,10 +260,10 @@ def main():
     # evaluated sample, plus 24 B of ray in and 40 B of F/T/counts out per ray.
     alg_bytes = samples * 640 + n * 64
     achieved = alg_bytes / (march_ms * 1e-3) / 1e9
-    traffic = measured_traffic("k_march_fwd<F32Store>", "oblique-1080p")
+    traffic = measured_traffic("k_march_fwd_f32q<false>", "oblique-1080p")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_march_fwd<F32Store>", "algorithmic_bytes_per_launch": alg_bytes,
+                "kernel": "k_march_fwd_f32q<false>", "algorithmic_bytes_per_launch": alg_bytes,
                 "kernel_ms": round(march_ms, 4)}
 
     w, h = recipe["width"], recipe["height"]

@@ -114,7 +114,7 @@ __device__ __forceinline__ void store_group_total(float x, int gl, float* dst) {
     if (gl == kGroup - 1) *dst = x;
 }
 
-template <class S>
+template <class S, bool kBW>
 __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                            const float* __restrict__ d_, int64_t n,
                                                            float* __restrict__ F, float* __restrict__ T,
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
         }
 #pragma unroll
         for (int c = 0; c < 7; ++c) acc[c] += bacc[c];
-        if (BW) {
+        if (kBW) {
             float* dst = BW + ((size_t)ray * slots + batch) * 7;
 #pragma unroll
             for (int c = 0; c < 7; ++c) store_group_total(bacc[c], gl, dst + c);
@@ -259,6 +259,7 @@ __device__ __forceinline__ void quad_gather(const SceneDev& sc, const Corners& c
     }
 }
 
+template <bool kBW>
 __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                            const float* __restrict__ d_, int64_t n,
                                                            float* __restrict__ F, float* __restrict__ T,
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParam
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] += bacc[c];
-        if (BW) {
+        if (kBW) {
             float* dst = BW + ((size_t)ray * slots + batch) * 7;
 #pragma unroll
             for (int c = 0; c < 3; ++c) store_group_total(ch == 0 ? bacc[c] : 0.0f, gl, dst + c);
@@ -689,12 +690,24 @@ hipError_t launch_place(const SceneDev& sc, const RayParams& rp, const float* o,
 hipError_t launch_march_fwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
                             int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, float* batch_wv,
                             hipStream_t s) {
-    if (bf16)
-        hipLaunchKernelGGL(k_march_fwd<BF16Store>, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n, F, T,
-                           n_placed, n_eval, batch_wv);
-    else
-        hipLaunchKernelGGL(k_march_fwd_f32q, dim3(blocks_for(n)), dim3(kBlock), 0, s, sc, rp, o, d, n, F, T,
-                           n_placed, n_eval, batch_wv);
+    // The per-batch sums are a separate specialisation, so the render path
+    // carries none of their code.
+    const dim3 grid(blocks_for(n)), block(kBlock);
+    if (bf16) {
+        if (batch_wv)
+            hipLaunchKernelGGL((k_march_fwd<BF16Store, true>), grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed,
+                               n_eval, batch_wv);
+        else
+            hipLaunchKernelGGL((k_march_fwd<BF16Store, false>), grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed,
+                               n_eval, batch_wv);
+    } else {
+        if (batch_wv)
+            hipLaunchKernelGGL(k_march_fwd_f32q<true>, grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed, n_eval,
+                               batch_wv);
+        else
+            hipLaunchKernelGGL(k_march_fwd_f32q<false>, grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed, n_eval,
+                               batch_wv);
+    }
     return hipGetLastError();
 }
 
