@@ -203,6 +203,23 @@ def _rounded_scene(sc):
     return r
 
 
+def test_towers_fp32_forward_parity(towers):
+    """float32 render of the uneven towers rays (up to 512 samples per ray)."""
+    sc, o, d, target, n_max = towers
+    log("test_towers_fp32_forward_parity: 256 rays, n_max 512")
+    scene, t = upload_scene(sc)
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=n_max, c_bg=BG)
+    ref = oracle.oracle_render(sc, o, d, oracle.RenderParams(n_max=n_max, c_bg=BG), keep_k=False)
+    assert np.array_equal(res["n_placed"].cpu().numpy(), ref["n_placed"])
+    assert np.array_equal(res["n_eval"].cpu().numpy(), ref["n_eval"])
+    for key in ("C", "T", "F"):
+        assert np.abs(res[key].double().cpu().numpy() - ref[key]).max() <= 1e-5, key
+    log(f"  n_placed max {int(ref['n_placed'].max())}, mean {ref['n_placed'].mean():.1f}")
+    del scene, t
+    torch.cuda.empty_cache()
+
+
 def test_towers_bf16_storage_gradient_vs_oracle(towers):
     """bfloat16 storage, float32 arithmetic and float32 master gradients:
     must match the float64 oracle on the bfloat16-rounded scene."""

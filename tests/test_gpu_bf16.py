@@ -56,6 +56,31 @@ def test_bf16_march_matches_oracle_on_rounded_scene():
     assert err2 < 2e-2
 
 
+def test_bf16_ert_rule():
+    """Early termination in the bfloat16 kernel: counts agree with the oracle
+    on the rounded scene except, by one, where the transmittance at the
+    crossing is within 1e-4 (relative) of t_term; equal counts give colours
+    within the float32 bar."""
+    sc = scenegen.make_scene(scenegen.TINY)
+    o, d = scenegen.oblique_rays(4096, seed=1)
+    t_term = 1e-2
+    log("test_bf16_ert_rule: t_term=1e-2")
+    scene, t = upload_scene(sc, dtype=torch.bfloat16)
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG, t_term=t_term, mlp_bf16=0)
+    ref = oracle.oracle_render(_rounded(sc), o, d, oracle.RenderParams(n_max=64, c_bg=BG, t_term=t_term),
+                               keep_k=False)
+    nev = res["n_eval"].cpu().numpy()
+    same = nev == ref["n_eval"]
+    assert same.mean() > 0.99
+    if (~same).any():
+        assert np.all(np.abs(nev[~same] - ref["n_eval"][~same]) == 1)
+        near = np.abs(ref["T"][~same] - t_term) / t_term
+        assert np.all(near <= 1e-4), near
+    assert np.abs(res["C"].double().cpu().numpy()[same] - ref["C"][same]).max() <= 1e-5
+    assert (nev < 64).any()
+
+
 @pytest.fixture(scope="module")
 def oblique_crop():
     log("building oblique scene and its perturbed copy")

@@ -70,13 +70,15 @@ def test_place_tiny_nmax_variants(tiny, n_max):
     assert np.array_equal(k.cpu().numpy(), kr)
 
 
-def test_render_tiny_parity(tiny):
+@pytest.mark.parametrize("n_max", [64, 1, 17])
+def test_render_tiny_parity(tiny, n_max):
+    """n_max 1: one sample per ray; 17: a full batch of 16 plus one."""
     sc, scene, t, o, d = tiny
-    log("test_render_tiny_parity: 4096 rays fp32")
+    log(f"test_render_tiny_parity: 4096 rays fp32, n_max={n_max}")
     og, dg = rays_to(o, d)
-    res = om.render(scene, og, dg, n_max=64, c_bg=BG)
+    res = om.render(scene, og, dg, n_max=n_max, c_bg=BG)
     torch.cuda.synchronize()
-    ref = oracle.oracle_render(sc, o, d, oracle.RenderParams(n_max=64, c_bg=BG), keep_k=False)
+    ref = oracle.oracle_render(sc, o, d, oracle.RenderParams(n_max=n_max, c_bg=BG), keep_k=False)
     _compare(res, ref)
 
 
