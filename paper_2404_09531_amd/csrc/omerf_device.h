@@ -299,36 +299,50 @@ __device__ __forceinline__ void gather_features_split(const SceneDev& sc, const 
     for (int i = 0; i < 8; ++i) t[i] = 0.0f;
     const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
     const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
+    // two rows (one pair adjacent along the row axis) in flight for 32-byte
+    // rows, four for 16-byte rows
+    constexpr int kPerGroup = sizeof(typename S::Row) > 16 ? 1 : 2;
     const float x0 = 1.0f - c.fx, x1 = c.fx, y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
 #pragma unroll
-    for (int zz = 0; zz < 2; ++zz) {
-        const uint32_t base = c.g + (zz ? sz : 0u);
-        typename S::Row r[4];
-        r[0] = S::load(sc.grid, base);
-        r[1] = S::load(sc.grid, base + 1);
-        r[2] = S::load(sc.grid, base + sy);
-        r[3] = S::load(sc.grid, base + sy + 1);
-        const float wz = zz ? z1 : z0;
-        S::acc(r[0], x0 * y0 * wz, t);
-        S::acc(r[1], x1 * y0 * wz, t);
-        S::acc(r[2], x0 * y1 * wz, t);
-        S::acc(r[3], x1 * y1 * wz, t);
+    for (int p0 = 0; p0 < 4; p0 += kPerGroup) {
+        typename S::Row r[2 * kPerGroup];
+#pragma unroll
+        for (int k = 0; k < kPerGroup; ++k) {
+            const int p = p0 + k;  // (dy, dz) = (p & 1, p >> 1)
+            const uint32_t base = c.g + ((p & 1) ? sy : 0u) + ((p >> 1) ? sz : 0u);
+            r[2 * k] = S::load(sc.grid, base);
+            r[2 * k + 1] = S::load(sc.grid, base + 1);
+        }
+#pragma unroll
+        for (int k = 0; k < kPerGroup; ++k) {
+            const int p = p0 + k;
+            const float wyz = ((p & 1) ? y1 : y0) * ((p >> 1) ? z1 : z0);
+            S::acc(r[2 * k], x0 * wyz, t);
+            S::acc(r[2 * k + 1], x1 * wyz, t);
+        }
     }
     const float a0 = 1.0f - c.ux, a1 = c.ux, b0 = 1.0f - c.uy, b1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
-    const void* P[3] = {sc.pxy, sc.pxz, sc.pyz};
-    const uint32_t B[3] = {c.xy, c.xz, c.yz}, S2[3] = {nx, nx, ny};
-    const float U0[3] = {a0, a0, b0}, U1[3] = {a1, a1, b1}, V0[3] = {b0, e0, e0}, V1[3] = {b1, e1, e1};
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        typename S::Row r[4];
-        r[0] = S::load(P[q], B[q]);
-        r[1] = S::load(P[q], B[q] + 1);
-        r[2] = S::load(P[q], B[q] + S2[q]);
-        r[3] = S::load(P[q], B[q] + S2[q] + 1);
-        S::acc(r[0], U0[q] * V0[q], t);
-        S::acc(r[1], U1[q] * V0[q], t);
-        S::acc(r[2], U0[q] * V1[q], t);
-        S::acc(r[3], U1[q] * V1[q], t);
+    for (int p0 = 0; p0 < 6; p0 += kPerGroup) {
+        typename S::Row r[2 * kPerGroup];
+#pragma unroll
+        for (int k = 0; k < kPerGroup; ++k) {
+            const int p = p0 + k;  // plane p >> 1, second-axis offset p & 1
+            const int q = p >> 1;
+            const void* P = q == 0 ? sc.pxy : q == 1 ? sc.pxz : sc.pyz;
+            const uint32_t base = (q == 0 ? c.xy : q == 1 ? c.xz : c.yz) + ((p & 1) ? (q == 2 ? ny : nx) : 0u);
+            r[2 * k] = S::load(P, base);
+            r[2 * k + 1] = S::load(P, base + 1);
+        }
+#pragma unroll
+        for (int k = 0; k < kPerGroup; ++k) {
+            const int p = p0 + k;
+            const int q = p >> 1;
+            const float u0 = q == 2 ? b0 : a0, u1 = q == 2 ? b1 : a1;
+            const float v = (p & 1) ? (q == 0 ? b1 : e1) : (q == 0 ? b0 : e0);
+            S::acc(r[2 * k], u0 * v, t);
+            S::acc(r[2 * k + 1], u1 * v, t);
+        }
     }
 }
 
