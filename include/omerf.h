@@ -225,6 +225,29 @@ int om_l2_loss_fp64(const float* C, const float* target, int64_t n, double* out,
 int om_l2_loss_grad(const float* C, const float* target, int64_t n, float* dL_dC,
                     double* loss_out, void* stream);
 
+/*
+ * Fused training step for an L2 photometric loss, everything on `stream`:
+ * the forward of om_render (writing out->C, T, F, n_placed, n_eval), the
+ * gradient dL/dC = 2 (C - target) / (3 n) of the loss of om_l2_loss_fp64,
+ * and om_render_backward, which ADDS the parameter gradients into g.  The
+ * forward also records the per-batch sums of w v (see om_fwd_out.batch_wv)
+ * so that the backward replays the samples once.  target: device float32
+ * [n][3].  workspace: caller-owned device memory of at least
+ * om_render_fwd_bwd_l2_workspace_size(n, p) bytes, 256-byte aligned; it
+ * holds dL/dC and the per-batch sums (out->batch_wv is ignored).
+ * loss_fp64: optional device double[1] receiving the float64 loss
+ * (overwritten), or NULL.  Equivalent to om_render + om_l2_loss_grad +
+ * om_render_backward.  Cites: Eq. 1-4 (forward) and their derivative.
+ */
+int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, int64_t n,
+                         const om_params* p, const float* target, const om_fwd_out* out,
+                         void* workspace, int64_t workspace_bytes, double* loss_fp64,
+                         const om_grads* g, void* stream);
+
+/* Workspace bytes om_render_fwd_bwd_l2 needs for n rays and p->n_max, or
+ * -1 (with om_last_error set) if n < 0 or p is invalid. */
+int64_t om_render_fwd_bwd_l2_workspace_size(int64_t n, const om_params* p);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* om_last_error(void);
 

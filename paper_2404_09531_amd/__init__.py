@@ -236,6 +236,45 @@ def render_backward(scene: Scene, o, d, saved: Dict[str, torch.Tensor], dL_dC, g
         ctypes.byref(g), _lib.stream_of(o)))
 
 
+def fwd_bwd_l2_workspace_size(n: int, n_max: int, delta: float = DELTA) -> int:
+    """Bytes of workspace render_fwd_bwd_l2 needs (om_render_fwd_bwd_l2_workspace_size)."""
+    p = _params(n_max, delta, 0.0, (0.0, 0.0, 0.0), -1)
+    nb = _lib.lib().om_render_fwd_bwd_l2_workspace_size(n, ctypes.byref(p))
+    if nb < 0:
+        raise _lib.OmerfError("om_render_fwd_bwd_l2_workspace_size", _lib.OM_ERR_INVALID,
+                              _lib.lib().om_last_error().decode())
+    return nb
+
+
+def render_fwd_bwd_l2(scene: Scene, o, d, target, out: Dict[str, torch.Tensor], grads: Dict[str, torch.Tensor],
+                      n_max: int, delta: float = DELTA, t_term: float = 0.0, c_bg=(0.0, 0.0, 0.0),
+                      mlp_bf16: int = -1, workspace: Optional[torch.Tensor] = None,
+                      loss: Optional[torch.Tensor] = None) -> Optional[torch.Tensor]:
+    """One fused L2 training step (om_render_fwd_bwd_l2): forward into `out`
+    (keys as render()), dL/dC, float64 loss into `loss` (a device float64 [1]
+    tensor, or None to skip), and the backward ADDED into float32 `grads`.
+    `workspace` is a device uint8 tensor of fwd_bwd_l2_workspace_size bytes
+    (allocated here if None)."""
+    n = _rays(scene, o, d)
+    _need(target, "target", torch.float32, (n, 3))
+    for key in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp"):
+        _need(grads[key], f"grads[{key}]", torch.float32, scene.tensors[key].shape)
+    nbytes = fwd_bwd_l2_workspace_size(n, n_max, delta)
+    if workspace is None:
+        workspace = torch.empty((max(nbytes, 1),), dtype=torch.uint8, device=o.device)
+    if loss is not None:
+        _need(loss, "loss", torch.float64, (1,))
+    fo = _lib.OmFwdOut(out["C"].data_ptr(), out["T"].data_ptr(), out["F"].data_ptr(), out["n_placed"].data_ptr(),
+                       out["n_eval"].data_ptr(), 0)
+    g = _lib.OmGrads(grads["grid"].data_ptr(), grads["plane_xy"].data_ptr(), grads["plane_xz"].data_ptr(),
+                     grads["plane_yz"].data_ptr(), grads["mlp"].data_ptr())
+    p = _params(n_max, delta, t_term, c_bg, mlp_bf16)
+    _lib.check("om_render_fwd_bwd_l2", _lib.lib().om_render_fwd_bwd_l2(
+        scene.handle, o.data_ptr(), d.data_ptr(), n, ctypes.byref(p), target.data_ptr(), ctypes.byref(fo),
+        workspace.data_ptr(), workspace.numel(), _lib.ptr(loss), ctypes.byref(g), _lib.stream_of(o)))
+    return loss
+
+
 def l2_loss_fp64(C, target) -> torch.Tensor:
     """float64 mean over rays x 3 of (C - target)^2, as a 1-element device tensor."""
     n = C.shape[0]

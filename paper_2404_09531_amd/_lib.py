@@ -20,8 +20,8 @@ OM_F32, OM_BF16 = 0, 1
 OM_MAX_SAMPLES = 1024
 EXPORTS = ("om_scene_create", "om_scene_update", "om_scene_destroy", "om_place_samples", "om_march",
            "om_deferred_mlp", "om_render",
-           "om_render_backward", "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str",
-           "om_version")
+           "om_render_backward", "om_render_fwd_bwd_l2", "om_render_fwd_bwd_l2_workspace_size",
+           "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str", "om_version")
 
 
 class OmSceneDesc(ctypes.Structure):
@@ -74,12 +74,17 @@ def lib() -> ctypes.CDLL:
                                          POINTER(OmFwdOut), c_void_p, POINTER(OmGrads), c_void_p]
         L.om_l2_loss_fp64.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
         L.om_l2_loss_grad.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
+        L.om_render_fwd_bwd_l2.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(OmParams), c_void_p,
+                                           POINTER(OmFwdOut), c_void_p, c_int64, c_void_p, POINTER(OmGrads),
+                                           c_void_p]
+        L.om_render_fwd_bwd_l2_workspace_size.argtypes = [c_int64, POINTER(OmParams)]
         L.om_last_error.restype = c_char_p
         L.om_status_str.restype = c_char_p
         L.om_status_str.argtypes = [c_int]
         for name in EXPORTS:
-            if name not in ("om_last_error", "om_status_str"):
+            if name not in ("om_last_error", "om_status_str", "om_render_fwd_bwd_l2_workspace_size"):
                 getattr(L, name).restype = c_int
+        L.om_render_fwd_bwd_l2_workspace_size.restype = c_int64
         _lib = L
     return _lib
 

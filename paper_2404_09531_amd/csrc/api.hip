@@ -289,6 +289,48 @@ int om_render_backward(const om_scene* scene, const float* o, const float* d, in
     return hip_status(e, "om_render_backward");
 }
 
+int64_t om_render_fwd_bwd_l2_workspace_size(int64_t n, const om_params* p) {
+    RayParams rp;
+    if (n < 0) {
+        fail(OM_ERR_INVALID, "n must be >= 0");
+        return -1;
+    }
+    if (validate_params(p, &rp) != OM_OK) return -1;
+    const int64_t slots = (p->n_max + kGroup - 1) / kGroup;
+    const int64_t dc = (n * 3 * (int64_t)sizeof(float) + 255) / 256 * 256;
+    return dc + n * slots * 7 * (int64_t)sizeof(float);
+}
+
+int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                         const float* target, const om_fwd_out* out, void* workspace, int64_t workspace_bytes,
+                         double* loss_fp64, const om_grads* g, void* stream) {
+    RayParams rp;
+    int rc = check_fwd(scene, o, d, n, p, out, true, true, &rp);
+    if (rc != OM_OK) return rc;
+    if (n == 0) return ok();
+    if (!target || !g) return fail(OM_ERR_INVALID, "target / grads is NULL");
+    if (!g->grid || !g->plane_xy || !g->plane_xz || !g->plane_yz || !g->mlp)
+        return fail(OM_ERR_INVALID, "all gradient buffers are required");
+    const int64_t need = om_render_fwd_bwd_l2_workspace_size(n, p);
+    if (!workspace || ((uintptr_t)workspace & 255u)) return fail(OM_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (workspace_bytes < need)
+        return fail(OM_ERR_INVALID, "workspace holds %lld bytes, %lld needed", (long long)workspace_bytes,
+                    (long long)need);
+    float* dC = static_cast<float*>(workspace);
+    float* bw = reinterpret_cast<float*>(static_cast<char*>(workspace) + (n * 3 * (int64_t)sizeof(float) + 255) / 256 * 256);
+    const bool bf16 = scene->desc.dtype == OM_BF16;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_march_fwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_placed, out->n_eval, bw, s);
+    if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2 (march)");
+    e = launch_mlp(scene->dev.mlp, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval, out->C, s);
+    if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2 (mlp)");
+    e = launch_l2(out->C, target, n, dC, loss_fp64, s);
+    if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2 (loss)");
+    e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_eval, bw, dC, g->grid, g->plane_xy,
+                         g->plane_xz, g->plane_yz, g->mlp, s);
+    return hip_status(e, "om_render_fwd_bwd_l2 (backward)");
+}
+
 int om_l2_loss_fp64(const float* C, const float* target, int64_t n, double* out, void* stream) {
     if (n <= 0) return fail(OM_ERR_INVALID, "n must be > 0");
     if (!C || !target || !out) return fail(OM_ERR_INVALID, "NULL pointer");
@@ -314,6 +356,6 @@ const char* om_status_str(int status) {
     }
 }
 
-int om_version(void) { return 101; }
+int om_version(void) { return 102; }
 
 }  // extern "C"

@@ -24,11 +24,11 @@ def L():
 
 def test_exports_every_declared_symbol(L):
     hdr = open(os.path.join(ROOT, "include", "omerf.h")).read()
-    names = set(re.findall(r"^\s*(?:int|const char\*)\s+(om_\w+)\s*\(", hdr, re.M))
+    names = set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(om_\w+)\s*\(", hdr, re.M))
     assert names == set(_lib.EXPORTS)
     for n in names:
         assert hasattr(L, n), n
-    assert L.om_version() == 101
+    assert L.om_version() == 102
     assert L.om_status_str(-2) == b"unsupported shape or dtype"
 
 
@@ -127,6 +127,27 @@ def test_render_argument_errors(L):
     assert L.om_place_samples(h, FAKE, FAKE, 4, ctypes.byref(_params()), 0, FAKE, None) == _lib.OM_ERR_INVALID
     assert L.om_l2_loss_fp64(FAKE, FAKE, 0, FAKE, None) == _lib.OM_ERR_INVALID
     assert L.om_l2_loss_grad(FAKE, FAKE, 3, FAKE, None, None) == _lib.OM_ERR_INVALID  # aliasing
+    L.om_scene_destroy(h)
+
+
+def test_fused_training_step_validation(L):
+    """Workspace query and the fused step's argument checks (no device work)."""
+    p = _params()
+    n = 1000
+    ws = L.om_render_fwd_bwd_l2_workspace_size(n, ctypes.byref(p))
+    assert ws == (n * 12 + 255) // 256 * 256 + n * 4 * 7 * 4  # dL/dC, then 4 batch slots x 7 floats per ray
+    assert L.om_render_fwd_bwd_l2_workspace_size(-1, ctypes.byref(p)) == -1
+    assert L.om_render_fwd_bwd_l2_workspace_size(n, ctypes.byref(_params(n_max=0))) == -1
+    rc, h = _create(L, _desc())
+    out = _lib.OmFwdOut(FAKE, FAKE, FAKE, FAKE, FAKE, 0)
+    g = _lib.OmGrads(FAKE, FAKE, FAKE, FAKE, FAKE)
+    step = lambda *a: L.om_render_fwd_bwd_l2(h, FAKE, FAKE, n, ctypes.byref(p), *a)  # noqa: E731
+    assert step(FAKE, ctypes.byref(out), FAKE, ws - 1, None, ctypes.byref(g), None) == _lib.OM_ERR_INVALID
+    assert step(FAKE, ctypes.byref(out), FAKE + 16, ws, None, ctypes.byref(g), None) == _lib.OM_ERR_INVALID
+    assert step(None, ctypes.byref(out), FAKE, ws, None, ctypes.byref(g), None) == _lib.OM_ERR_INVALID
+    bad_g = _lib.OmGrads(FAKE, 0, FAKE, FAKE, FAKE)
+    assert step(FAKE, ctypes.byref(out), FAKE, ws, None, ctypes.byref(bad_g), None) == _lib.OM_ERR_INVALID
+    assert "workspace" in L.om_last_error().decode() or "gradient" in L.om_last_error().decode()
     L.om_scene_destroy(h)
 
 

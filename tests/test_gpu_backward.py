@@ -96,6 +96,34 @@ def test_batch_wv_prefixes_match_truncated_oracle_renders(tiny_train, dtype):
                   - res["F"].double().cpu().numpy()[ne > 0]).max() <= 1e-5
 
 
+def test_fused_training_step_matches_separate_calls(tiny_train):
+    """om_render_fwd_bwd_l2 == om_render + om_l2_loss_grad + om_render_backward,
+    and both match the oracle."""
+    sc, scene, t, o, d, target = tiny_train
+    log("test_fused_training_step_matches_separate_calls")
+    og, dg = rays_to(o, d)
+    tg = torch.from_numpy(target.astype(np.float32)).to(og.device)
+    res, loss_sep, g_sep = _gpu_grads(scene, t, og, dg, tg, 64, batch_wv=True)
+    n = og.shape[0]
+    out = dict(C=torch.empty((n, 3), device=og.device), T=torch.empty((n,), device=og.device),
+               F=torch.empty((n, 7), device=og.device), n_placed=torch.empty((n,), dtype=torch.int32, device=og.device),
+               n_eval=torch.empty((n,), dtype=torch.int32, device=og.device))
+    grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp")}
+    loss = torch.empty((1,), dtype=torch.float64, device=og.device)
+    om.render_fwd_bwd_l2(scene, og, dg, tg, out, grads, n_max=64, c_bg=BG, loss=loss)
+    torch.cuda.synchronize()
+    for key in ("C", "T", "F", "n_placed", "n_eval"):
+        assert torch.equal(out[key], res[key]), key
+    assert abs(loss.item() - loss_sep) <= 1e-12 * loss_sep
+    g = {k: v.double().cpu().numpy() for k, v in grads.items()}
+    for k in g:
+        scale = np.abs(g_sep[k]).max()
+        assert np.abs(g[k] - g_sep[k]).max() <= 1e-5 * scale, k  # float32 atomics in another order
+    _, _, ref_grads = oracle.oracle_loss_and_grads(sc, o, d, oracle.RenderParams(n_max=64, c_bg=BG),
+                                                   target.astype(np.float32).astype(np.float64))
+    _check_against_oracle(sc, g, ref_grads)
+
+
 def test_backward_sum_invariant(tiny_train):
     """Per channel the four sources' gradient totals are equal."""
     sc, scene, t, o, d, target = tiny_train
