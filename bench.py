@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--t-term", type=float, default=0.0)
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and fwd+bwd forms")
-    ap.add_argument("--forms", default="bf16_render,fp32_fwd_bwd,bf16_render_4k_x8,towers_bf16_fwd_bwd",
+    ap.add_argument("--forms", default="bf16_render,fp32_fwd_bwd,bf16_render_4k_x8,high_altitude_mips,"
+                                       "towers_bf16_fwd_bwd",
                     help="comma-separated subset of forms to run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--crop", type=int, default=256, help="side of the centre crop timed on the CPU oracle")
@@ -210,6 +211,28 @@ def form_towers(om, scenegen, torch, a):
             "n_placed_hist_bins32": hist.tolist()}
 
 
+def form_high_altitude(om, scenegen, torch, t, a):
+    """The oblique scene's tensors over a box four times taller than the
+    terrain (z in [0, 1]: the upper three quarters of every column empty),
+    one 1920x1080 camera at pitch 45 deg from z = 1.5, Morton order: render
+    time without and with the 4-level occupancy pyramid."""
+    dev = torch.device("cuda:0")
+    scene = om.Scene(t["grid"], t["plane_xy"], t["plane_xz"], t["plane_yz"], t["occ"], t["mlp"],
+                     box_lo=(-1.0, -1.0, 0.0), box_hi=(1.0, 1.0, 1.0))
+    o, d = scenegen.camera_rays(1920, 1080, 45.0, 90.0, origin_z=1.5, pixels=scenegen.pixel_order(1920, 1080, "morton"))
+    og, dg = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
+    n = o.shape[0]
+    out = _outputs(torch, n, dev)
+    res = {"workload": "oblique scene in a [0,1] z box, 1920x1080, pitch 45 deg from z=1.5", "rays": n}
+    for levels in (0, 4):
+        scene.build_occupancy_mips(levels)
+        ms, _ = time_stages([lambda: om.render_into(scene, og, dg, out, n_max=256, c_bg=BG)], a.steps, a.warmup, torch)
+        ms /= a.steps
+        res[f"levels{levels}"] = {"ms_per_step": round(ms, 4), "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 2)}
+    res["samples_per_ray"] = round(float(out["n_eval"].double().mean().item()), 1)
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -282,6 +305,8 @@ def main():
         forms["fp32_fwd_bwd"] = form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a)
     if "bf16_render_4k_x8" in want:
         forms["bf16_render_4k_x8"] = form_bf16_4k(om, scenegen, torch, t, kw, a)
+    if "high_altitude_mips" in want:
+        forms["high_altitude_mips"] = form_high_altitude(om, scenegen, torch, t, a)
     if "towers_bf16_fwd_bwd" in want:
         del t, scene, out, og, dg
         torch.cuda.empty_cache()

@@ -159,6 +159,30 @@ int om_scene_create(const om_scene_desc* desc, om_scene** out);
  * unchanged if validation fails.  Must not race with calls using it. */
 int om_scene_update(om_scene* scene, const om_scene_desc* desc);
 
+/*
+ * Occupancy pyramid for hierarchical empty-space skipping (the jump through
+ * blank columns of Sec. 4.4, extended from single columns to blocks of
+ * 2^l x 2^l columns).  Level l = 1..levels holds (My >> l) x (Mx >> l)
+ * float2 entries, row-major, levels stored one after the other from l = 1:
+ * for each block, (min z_min, max z_max) over its cells with
+ * z_min <= z_max, or (+inf, -inf) if it has none.
+ *
+ * om_occupancy_mips_size: bytes needed for `levels` levels, or -1 (with
+ * om_last_error set) unless 0 <= levels <= 8 and both occupancy dims are
+ * divisible by 2^levels.
+ *
+ * om_build_occupancy_mips: computes the pyramid of the scene's occupancy
+ * plane into the caller-owned device buffer `mips` (8-byte aligned, at
+ * least om_occupancy_mips_size bytes; it must outlive its use) on `stream`
+ * and attaches it to the handle: every later placement, render and backward
+ * call skips empty space level by level.  Sample placement is unchanged
+ * (the pyramid only skips candidates that cannot be accepted).  levels = 0
+ * detaches it; so does om_scene_update, after which it must be built again
+ * for the new occupancy.  Must not race with calls using the handle.
+ */
+int64_t om_occupancy_mips_size(const om_scene* scene, int levels);
+int om_build_occupancy_mips(om_scene* scene, void* mips, int64_t mips_bytes, int levels, void* stream);
+
 /* Release a handle (never the tensors).  NULL is accepted. */
 int om_scene_destroy(om_scene* scene);
 

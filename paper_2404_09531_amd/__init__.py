@@ -61,6 +61,7 @@ class Scene:
     def __init__(self, grid, plane_xy, plane_xz, plane_yz, occ, mlp,
                  box_lo: Sequence[float] = (-1.0, -1.0, 0.0), box_hi: Sequence[float] = (1.0, 1.0, 0.25)):
         self._handle = ctypes.c_void_p()
+        self.mips, self.mip_levels = None, 0
         self._set(grid, plane_xy, plane_xz, plane_yz, occ, mlp, box_lo, box_hi)
         _lib.check("om_scene_create", _lib.lib().om_scene_create(ctypes.byref(self._desc), ctypes.byref(self._handle)))
 
@@ -106,6 +107,36 @@ class Scene:
         if rc != 0:
             self._desc, self.tensors, self.dtype = old
             _lib.check("om_scene_update", rc)
+        self.mips = None  # the library detached the pyramid; build it again if wanted
+        self.mip_levels = 0
+
+    def build_occupancy_mips(self, levels: int) -> None:
+        """Compute the occupancy pyramid (levels 1..levels of pooled
+        (min z_min, max z_max) blocks) into a device buffer held by this
+        Scene and attach it, so placement skips empty space hierarchically;
+        levels=0 detaches it."""
+        L = _lib.lib()
+        nbytes = L.om_occupancy_mips_size(self._handle, levels)
+        if nbytes < 0:
+            raise _lib.OmerfError("om_occupancy_mips_size", _lib.OM_ERR_UNSUPPORTED, L.om_last_error().decode())
+        buf = torch.empty((max(nbytes, 8),), dtype=torch.uint8, device=self.device) if levels > 0 else None
+        _lib.check("om_build_occupancy_mips", L.om_build_occupancy_mips(
+            self._handle, _lib.ptr(buf), nbytes, levels, _lib.stream_of(self.tensors["occ"])))
+        self.mips, self.mip_levels = buf, levels
+
+    def occupancy_mips(self):
+        """The attached pyramid as a list of float32 [My >> l, Mx >> l, 2]
+        views, level 1 first (empty list if none)."""
+        out, off = [], 0
+        my, mx = self.tensors["occ"].shape[:2]
+        if self.mips is None:
+            return out
+        flat = self.mips.view(torch.float32)
+        for lvl in range(1, self.mip_levels + 1):
+            h, w = my >> lvl, mx >> lvl
+            out.append(flat[off:off + h * w * 2].view(h, w, 2))
+            off += h * w * 2
+        return out
 
     @property
     def handle(self):

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libomerf.so
 OM_OK, OM_ERR_INVALID, OM_ERR_UNSUPPORTED, OM_ERR_HIP = 0, -1, -2, -3
 OM_F32, OM_BF16 = 0, 1
 OM_MAX_SAMPLES = 1024
-EXPORTS = ("om_scene_create", "om_scene_update", "om_scene_destroy", "om_place_samples", "om_march",
+EXPORTS = ("om_scene_create", "om_scene_update", "om_scene_destroy", "om_occupancy_mips_size",
+           "om_build_occupancy_mips", "om_place_samples", "om_march",
            "om_deferred_mlp", "om_render",
            "om_render_backward", "om_render_fwd_bwd_l2", "om_render_fwd_bwd_l2_workspace_size",
            "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str", "om_version")
@@ -78,13 +79,17 @@ def lib() -> ctypes.CDLL:
                                            POINTER(OmFwdOut), c_void_p, c_int64, c_void_p, POINTER(OmGrads),
                                            c_void_p]
         L.om_render_fwd_bwd_l2_workspace_size.argtypes = [c_int64, POINTER(OmParams)]
+        L.om_occupancy_mips_size.argtypes = [c_void_p, c_int]
+        L.om_build_occupancy_mips.argtypes = [c_void_p, c_void_p, c_int64, c_int, c_void_p]
         L.om_last_error.restype = c_char_p
         L.om_status_str.restype = c_char_p
         L.om_status_str.argtypes = [c_int]
         for name in EXPORTS:
-            if name not in ("om_last_error", "om_status_str", "om_render_fwd_bwd_l2_workspace_size"):
+            if name not in ("om_last_error", "om_status_str", "om_render_fwd_bwd_l2_workspace_size",
+                            "om_occupancy_mips_size"):
                 getattr(L, name).restype = c_int
         L.om_render_fwd_bwd_l2_workspace_size.restype = c_int64
+        L.om_occupancy_mips_size.restype = c_int64
         _lib = L
     return _lib
 

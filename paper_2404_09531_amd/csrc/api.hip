@@ -99,6 +99,9 @@ int validate_desc(const om_scene_desc* d, SceneDev* out) {
         if (!aligned16(ptrs[i])) return fail(OM_ERR_INVALID, "%s pointer is not 16-byte aligned", names[i]);
     }
     SceneDev s;
+    s.mips = nullptr;  // no pyramid until om_build_occupancy_mips attaches one
+    s.mip_levels = 0;
+    for (int l = 0; l <= kMaxMipLevels; ++l) s.mip_off[l] = 0;
     s.grid = d->grid;
     s.pxy = d->plane_xy;
     s.pxz = d->plane_xz;
@@ -194,6 +197,44 @@ int om_scene_update(om_scene* scene, const om_scene_desc* desc) {
 
 int om_scene_destroy(om_scene* scene) {
     delete scene;
+    return ok();
+}
+
+int64_t om_occupancy_mips_size(const om_scene* scene, int levels) {
+    if (!scene) {
+        fail(OM_ERR_INVALID, "scene handle is NULL");
+        return -1;
+    }
+    const int Mx = scene->dev.Mx, My = scene->dev.My;
+    if (levels < 0 || levels > kMaxMipLevels || (Mx % (1 << levels)) || (My % (1 << levels))) {
+        fail(OM_ERR_UNSUPPORTED, "levels must be in [0, %d] with both occupancy dims divisible by 2^levels",
+             kMaxMipLevels);
+        return -1;
+    }
+    int64_t cells = 0;
+    for (int l = 1; l <= levels; ++l) cells += (int64_t)(Mx >> l) * (My >> l);
+    return cells * (int64_t)sizeof(float2);
+}
+
+int om_build_occupancy_mips(om_scene* scene, void* mips, int64_t mips_bytes, int levels, void* stream) {
+    const int64_t need = om_occupancy_mips_size(scene, levels);
+    if (need < 0) return OM_ERR_INVALID;
+    SceneDev& dev = scene->dev;
+    dev.mips = nullptr;
+    dev.mip_levels = 0;
+    if (levels == 0) return ok();
+    if (!mips || ((uintptr_t)mips & 7u)) return fail(OM_ERR_INVALID, "mips must be non-NULL and 8-byte aligned");
+    if (mips_bytes < need)
+        return fail(OM_ERR_INVALID, "mips holds %lld bytes, %lld needed", (long long)mips_bytes, (long long)need);
+    hipError_t e = launch_occ_pyramid(dev.occ, dev.Mx, dev.My, static_cast<float2*>(mips), levels, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_status(e, "om_build_occupancy_mips");
+    int off = 0;
+    for (int l = 1; l <= levels; ++l) {
+        dev.mip_off[l] = off;
+        off += (dev.Mx >> l) * (dev.My >> l);
+    }
+    dev.mips = static_cast<const float2*>(mips);
+    dev.mip_levels = levels;
     return ok();
 }
 
@@ -356,6 +397,6 @@ const char* om_status_str(int status) {
     }
 }
 
-int om_version(void) { return 102; }
+int om_version(void) { return 103; }
 
 }  // extern "C"

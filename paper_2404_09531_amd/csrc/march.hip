@@ -40,17 +40,30 @@ __device__ __forceinline__ int march_candidates(const SceneDev& sc, const RayPar
             more = (k <= kr.hi) && (n_acc < rp.n_max);
             wave_order();
             // An empty window: jump over the segments whose columns cannot
-            // hold a sample, 16 segments of 16 candidates per step.
+            // hold a sample.  16 lanes test 16 consecutive segments of
+            // 16 << lv candidates against pyramid level lv; after two sweeps
+            // in a row with no possible sample the level coarsens (when a
+            // pyramid is attached), the first possible segment is refined
+            // one level at a time, and candidate testing resumes at level 0.
+            int lv = 0, empty_sweeps = 0;
             while (more && m == 0u) {
-                const bool maybe = column_maybe(sc, o, d, rp.delta, k + gl * kGroup, kGroup);
+                const int seg = kGroup << lv;
+                const bool maybe = column_maybe(sc, o, d, rp.delta, k + gl * seg, seg, lv);
                 const uint32_t mm = g_ballot(maybe, lane);
                 if (mm) {
-                    k += kGroup * (__ffs(mm) - 1);
+                    k += seg * (__ffs(mm) - 1);
                     more = k <= kr.hi;
-                    break;
+                    if (lv == 0) break;
+                    --lv;
+                    empty_sweeps = 0;
+                } else {
+                    k += kGroup * seg;
+                    more = k <= kr.hi;
+                    if (++empty_sweeps >= 2 && lv < sc.mip_levels) {
+                        ++lv;
+                        empty_sweeps = 0;
+                    }
                 }
-                k += kGroup * kGroup;
-                more = k <= kr.hi;
             }
         }
         if (qn >= kGroup || (!more && qn > 0)) {

@@ -189,4 +189,42 @@ hipError_t launch_l2(const float* C, const float* tgt, int64_t n, float* dC, dou
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Occupancy pyramid: one level from the one below.  Each output block holds
+// (min z_min, max z_max) over the non-empty entries of its 2 x 2 children
+// (an entry is empty when not z_min <= z_max, NaN included); a block with
+// no non-empty child gets (+inf, -inf), which no segment meets.
+// ---------------------------------------------------------------------------
+__global__ void k_occ_pool(const float2* __restrict__ src, int sw, float2* __restrict__ dst, int dw, int dh) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)dw * dh) return;
+    const int i = (int)(idx % dw), j = (int)(idx / dw);
+    float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float2 z = src[(2 * j + (c >> 1)) * sw + 2 * i + (c & 1)];
+        if (z.x <= z.y) {
+            lo = fminf(lo, z.x);
+            hi = fmaxf(hi, z.y);
+        }
+    }
+    dst[idx] = make_float2(lo, hi);
+}
+
+hipError_t launch_occ_pyramid(const float2* occ, int Mx, int My, float2* mips, int levels, hipStream_t s) {
+    const float2* src = occ;
+    int sw = Mx, sh = My;
+    float2* dst = mips;
+    for (int l = 1; l <= levels; ++l) {
+        const int dw = sw / 2, dh = sh / 2;
+        const int64_t cells = (int64_t)dw * dh;
+        hipLaunchKernelGGL(k_occ_pool, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, src, sw, dst, dw, dh);
+        src = dst;
+        dst += cells;
+        sw = dw;
+        sh = dh;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace omerf

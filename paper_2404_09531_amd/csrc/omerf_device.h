@@ -18,6 +18,7 @@ constexpr int kBlock = 256;           // threads per block (4 waves)
 constexpr int kGroupsPerBlock = kBlock / kGroup;
 constexpr int kQueue = 2 * kGroup;    // per-group LDS queue capacity
 constexpr int kKCap = 1 << 24;        // lattice indices k in [0, 2^24)
+constexpr int kMaxMipLevels = 8;      // occupancy pyramid levels above the plane
 
 // Vertex-aligned coordinate along one axis: u = p * s + (ci + cf) with
 // s = (n - 1) / (hi - lo) a power-of-two scaling of an integer, ci integer,
@@ -40,6 +41,12 @@ struct SceneDev {
     float lo0, lo1, lo2, hi0, hi1, hi2;
     float occ_sx, occ_sy, occ_ox, occ_oy;  // cell = floor(p * s) - o
     AxisMap gx, gy, gz, px, py, pz;
+    // Optional occupancy pyramid: level l (1..mip_levels) at mips + mip_off[l],
+    // (My >> l) x (Mx >> l) blocks of 2^l x 2^l cells, each holding
+    // (min z_min, max z_max) over its non-empty cells.
+    const float2* mips;
+    int mip_levels;
+    int mip_off[kMaxMipLevels + 1];
 };
 
 struct RayParams {
@@ -79,16 +86,18 @@ __device__ __forceinline__ bool accept_point(const SceneDev& sc, float3 p) {
 }
 
 // Empty-space skipping over occupancy columns (the bounding-box jump of
-// Sec. 4.4): may any lattice sample k in [ka, ka + len - 1] be accepted?
-// The binary32 points of those samples lie within the segment between the
-// two end points padded by eps (rounding is bounded by 2^-22 of the
-// coordinate magnitudes; eps is 2^-20 of them), so the segment may hold an
-// accepted sample only if its padded box meets the scene box and some
-// column it overlaps has an interval [z_min, z_max] meeting its padded z
-// range.  The containing-cell map is monotone, so the overlapped columns are
-// the cells of the padded x and y bounds.  More than 3 x 3 columns: answer
-// "maybe".
-__device__ __forceinline__ bool column_maybe(const SceneDev& sc, float3 o, float3 d, float delta, int ka, int len) {
+// Sec. 4.4), at pyramid level lv (0 = the occupancy plane itself): may any
+// lattice sample k in [ka, ka + len - 1] be accepted?  The binary32 points
+// of those samples lie within the segment between the two end points padded
+// by eps (rounding is bounded by 2^-22 of the coordinate magnitudes; eps is
+// 2^-20 of them), so the segment may hold an accepted sample only if its
+// padded box meets the scene box and some level-lv block it overlaps has an
+// interval [z_min, z_max] meeting its padded z range.  A block's interval
+// contains those of all its cells, and the containing-cell map is monotone,
+// so the overlapped blocks are those of the padded x and y bounds.  More
+// than 3 x 3 blocks: answer "maybe".
+__device__ __forceinline__ bool column_maybe(const SceneDev& sc, float3 o, float3 d, float delta, int ka, int len,
+                                             int lv) {
     const float ta = (float)ka * delta, tb = (float)(ka + len - 1) * delta;
     const float xa = o.x + ta * d.x, xb = o.x + tb * d.x;
     const float ya = o.y + ta * d.y, yb = o.y + tb * d.y;
@@ -101,15 +110,17 @@ __device__ __forceinline__ bool column_maybe(const SceneDev& sc, float3 o, float
     const float z0 = fminf(za, zb) - ez, z1 = fmaxf(za, zb) + ez;
     if (x1 < sc.lo0 || x0 > sc.hi0 || y1 < sc.lo1 || y0 > sc.hi1 || z1 < sc.lo2 || z0 > sc.hi2) return false;
     const float mx = (float)(sc.Mx - 1), my = (float)(sc.My - 1);
-    const int i0 = (int)fminf(fmaxf(floorf(x0 * sc.occ_sx) - sc.occ_ox, 0.0f), mx);
-    const int i1 = (int)fminf(fmaxf(floorf(x1 * sc.occ_sx) - sc.occ_ox, 0.0f), mx);
-    const int j0 = (int)fminf(fmaxf(floorf(y0 * sc.occ_sy) - sc.occ_oy, 0.0f), my);
-    const int j1 = (int)fminf(fmaxf(floorf(y1 * sc.occ_sy) - sc.occ_oy, 0.0f), my);
+    const int i0 = (int)fminf(fmaxf(floorf(x0 * sc.occ_sx) - sc.occ_ox, 0.0f), mx) >> lv;
+    const int i1 = (int)fminf(fmaxf(floorf(x1 * sc.occ_sx) - sc.occ_ox, 0.0f), mx) >> lv;
+    const int j0 = (int)fminf(fmaxf(floorf(y0 * sc.occ_sy) - sc.occ_oy, 0.0f), my) >> lv;
+    const int j1 = (int)fminf(fmaxf(floorf(y1 * sc.occ_sy) - sc.occ_oy, 0.0f), my) >> lv;
     if (i1 - i0 > 2 || j1 - j0 > 2) return true;
+    const float2* z_of = lv == 0 ? sc.occ : sc.mips + sc.mip_off[lv];
+    const int w = sc.Mx >> lv;
     bool maybe = false;
     for (int j = j0; j <= j1; ++j)
         for (int i = i0; i <= i1; ++i) {
-            const float2 z = sc.occ[j * sc.Mx + i];
+            const float2 z = z_of[j * w + i];
             maybe |= (z.x <= z1) && (z.y >= z0) && (z.x <= z.y);
         }
     return maybe;

@@ -19,6 +19,7 @@ hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, 
                             float* gV, float* gxy, float* gxz, float* gyz, float* gmlp, hipStream_t s);
 hipError_t launch_mlp(const float* W, bool bf16, const RayParams& rp, const float* d, int64_t n, const float* F,
                       const float* T, const int32_t* n_eval, float* C, hipStream_t s);
+hipError_t launch_occ_pyramid(const float2* occ, int Mx, int My, float2* mips, int levels, hipStream_t s);
 hipError_t launch_l2(const float* C, const float* tgt, int64_t n, float* dC, double* loss, hipStream_t s);
 
 }  // namespace omerf

@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol(L):
     assert names == set(_lib.EXPORTS)
     for n in names:
         assert hasattr(L, n), n
-    assert L.om_version() == 102
+    assert L.om_version() == 103
     assert L.om_status_str(-2) == b"unsupported shape or dtype"
 
 
@@ -148,6 +148,20 @@ def test_fused_training_step_validation(L):
     bad_g = _lib.OmGrads(FAKE, 0, FAKE, FAKE, FAKE)
     assert step(FAKE, ctypes.byref(out), FAKE, ws, None, ctypes.byref(bad_g), None) == _lib.OM_ERR_INVALID
     assert "workspace" in L.om_last_error().decode() or "gradient" in L.om_last_error().decode()
+    L.om_scene_destroy(h)
+
+
+def test_occupancy_mips_validation(L):
+    rc, h = _create(L, _desc())  # occupancy 32 x 32
+    assert L.om_occupancy_mips_size(h, 0) == 0
+    assert L.om_occupancy_mips_size(h, 2) == (16 * 16 + 8 * 8) * 8
+    assert L.om_occupancy_mips_size(h, 5) == sum((32 >> lv) ** 2 for lv in range(1, 6)) * 8
+    assert L.om_occupancy_mips_size(h, 6) == -1      # 32 not divisible by 64
+    assert L.om_occupancy_mips_size(h, -1) == -1
+    assert L.om_occupancy_mips_size(None, 1) == -1
+    assert L.om_build_occupancy_mips(h, FAKE, 16 * 16 * 8 - 8, 1, None) == _lib.OM_ERR_INVALID  # too small
+    assert L.om_build_occupancy_mips(h, FAKE + 4, 4096, 1, None) == _lib.OM_ERR_INVALID        # misaligned
+    assert L.om_build_occupancy_mips(h, None, 0, 0, None) == 0                              # detach
     L.om_scene_destroy(h)
 
 
