@@ -13,8 +13,9 @@ What it computes (Oblique-MERF, arXiv 2404.09531):
   [z_min, z_max]") -- ``placement.py``;
 * MERF features: trilinear grid + three bilinear planes (Sec. 3, Eq. 2) and
   their activations (Eq. 3) -- ``field.py``;
-* volume-rendering quadrature (Eq. 1), deferred MLP (Eq. 4) and the L2 loss
-  with its float64 autograd gradient -- ``render.py``.
+* volume-rendering quadrature (Eq. 1), deferred MLP (Eq. 4), the soft
+  occupancy value (Eq. 6, 8), the L2 loss with its float64 autograd
+  gradient and the interval-span loss (Eq. 5) -- ``render.py``.
 
 Precision: float64 throughout, except the placement predicate, which is
 defined in binary32 (see ``placement.py``) so that both sides take the
@@ -27,11 +28,11 @@ from .placement import (K_CAP, box_k_interval, cell_index, lattice_points,
                         place_samples, accept_mask)
 from .field import interp_features, activations, corner_weights_1d
 from .render import (RenderParams, oracle_render, oracle_loss_and_grads,
-                     mlp_forward, composite)
+                     mlp_forward, composite, occupancy_value, occ_interval_loss)
 
 __all__ = [
     "K_CAP", "box_k_interval", "cell_index", "lattice_points", "place_samples",
     "accept_mask", "interp_features", "activations", "corner_weights_1d",
     "RenderParams", "oracle_render", "oracle_loss_and_grads", "mlp_forward",
-    "composite",
+    "composite", "occupancy_value", "occ_interval_loss",
 ]

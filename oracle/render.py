@@ -3,9 +3,10 @@
 Follows Oblique-MERF Sec. 3: Eq. 1 (quadrature C = sum_i w_i c_i,
 w_i = T_i alpha_i, alpha_i = 1 - exp(-tau_i delta_i), T_i = prod_{j<i}
 (1 - alpha_j)), Eq. 4 (deferred shading: C = sum w c^d + G(F, d),
-F = [sum w c^d, sum w f]) and Sec. 4.1, Eq. 8 (only samples inside the
-occupancy interval contribute; with epsilon = 0 the mask is 0/1 and the
-masked samples are simply not placed).
+F = [sum w c^d, sum w f]) and Sec. 4.1, Eq. 6-8 (only samples inside the
+occupancy interval contribute: with epsilon = 0 the mask is 0/1 and the
+masked samples are simply not placed; with epsilon > 0 each placed
+sample's weight is multiplied by the occupancy value M of Eq. 6).
 
 Readings where the paper is silent or ambiguous:
 
@@ -23,6 +24,13 @@ Readings where the paper is silent or ambiguous:
   after the first sample whose following transmittance T_{i+1} < t_term;
   t_term = 0 never stops.
 * Loss: L = mean over rays and the 3 channels of (C - C*)^2.
+* Occupancy value (Eq. 6) with buffer width epsilon > 0 and exponent q:
+  M = min(clamp((z - z_min)/eps, 0, 1)^q, clamp((z_max - z)/eps, 0, 1)^q),
+  which equals the paper's four cases whenever z_max - z_min >= 2 eps and
+  stays continuous when the two buffer zones overlap (the cases conflict
+  there).  Eq. 8 multiplies the weight w_i by M_i; the transmittance T is
+  left unmasked, as written.  M is read at the cell containing the
+  sample's xy (Eq. 7), the same cell the placement used.
 
 The forward and the gradient share one code path: the gradient is float64
 autograd of exactly the forward below.
@@ -36,7 +44,7 @@ import numpy as np
 import torch
 
 from .field import SOURCES, activations, feature_terms, interp_features
-from .placement import place_samples
+from .placement import cell_index, place_samples
 
 MLP_SIZES = (10, 16, 16, 3)
 
@@ -47,6 +55,25 @@ class RenderParams:
     n_max: int = 64
     t_term: float = 0.0
     c_bg: Sequence[float] = (0.0, 0.0, 0.0)
+    occ_eps: float = 0.0  # buffer-zone width epsilon of Eq. 6 (0: the hard interval)
+    occ_q: float = 2.0    # exponent q of Eq. 6
+
+
+def occupancy_value(z: torch.Tensor, zmin: torch.Tensor, zmax: torch.Tensor, eps: float, q: float):
+    """Occupancy function M of Sec. 4.1, Eq. 6, in the overlap-safe form of
+    the module docstring."""
+    rise = torch.clamp((z - zmin) / eps, 0.0, 1.0) ** q
+    fall = torch.clamp((zmax - z) / eps, 0.0, 1.0) ** q
+    return torch.minimum(rise, fall)
+
+
+def occ_interval_loss(occ: np.ndarray):
+    """Interval-span loss of Sec. 4.1, Eq. 5: sum over the grid points of
+    (z_max - z_min)^2, and its gradient [My, Mx, 2] (float64)."""
+    z = np.asarray(occ, dtype=np.float64)
+    span = z[..., 1] - z[..., 0]
+    grad = np.stack([-2.0 * span, 2.0 * span], axis=-1)
+    return float(np.sum(span * span)), grad
 
 
 def unpack_mlp(mlp):
@@ -70,11 +97,13 @@ def mlp_forward(x: torch.Tensor, mlp: torch.Tensor) -> torch.Tensor:
     return torch.sigmoid(h2 @ w3.T + b3)
 
 
-def composite(tau, cd, f, n_placed, delta: float, t_term: float = 0.0):
+def composite(tau, cd, f, n_placed, delta: float, t_term: float = 0.0, mask=None):
     """Eq. 1 evaluated front to back, one sample slot at a time.
 
     tau [R, S], cd [R, S, 3], f [R, S, 4]; slot s of ray r is a sample iff
-    s < n_placed[r].  Returns (Cd [R,3], Fs [R,4], T_n [R], n_eval [R])."""
+    s < n_placed[r].  mask [R, S] (optional): the occupancy value M of
+    Eq. 6 applied to each weight (Eq. 8), not to T.  Returns (Cd [R,3],
+    Fs [R,4], T_n [R], n_eval [R])."""
     r = tau.shape[0]
     s_max = tau.shape[1]
     T = torch.ones(r, dtype=torch.float64)
@@ -90,6 +119,8 @@ def composite(tau, cd, f, n_placed, delta: float, t_term: float = 0.0):
         a = tau[:, s] * delta
         alpha = -torch.expm1(-a)
         w = torch.where(m, T * alpha, torch.zeros_like(a))
+        if mask is not None:
+            w = w * mask[:, s]
         cd_acc = cd_acc + w[:, None] * cd[:, s]
         f_acc = f_acc + w[:, None] * f[:, s]
         T = torch.where(m, T * torch.exp(-a), T)
@@ -146,7 +177,22 @@ def _render_chunk(scene, o, d, prm: RenderParams, grad: bool, mlp_leaf=None):
     tau = torch.zeros(r, s_dim, dtype=torch.float64).index_put((ri, si), tau_s)
     cd = torch.zeros(r, s_dim, 3, dtype=torch.float64).index_put((ri, si), cd_s)
     f = torch.zeros(r, s_dim, 4, dtype=torch.float64).index_put((ri, si), f_s)
-    cd_acc, f_acc, T, n_eval = composite(tau, cd, f, n_placed, prm.delta, prm.t_term)
+    mask, occ_leaf, occ_uniq = None, None, None
+    if prm.occ_eps > 0:
+        # Eq. 6-7: the occupancy value at the cell containing each sample's xy
+        my, mx = scene["occ"].shape[0], scene["occ"].shape[1]
+        cell = (cell_index(p64[:, 1], box_lo[1], box_hi[1], my) * mx
+                + cell_index(p64[:, 0], box_lo[0], box_hi[0], mx))
+        zz_all = np.asarray(scene["occ"], dtype=np.float64).reshape(-1, 2)
+        if grad:
+            occ_uniq, inv = np.unique(cell, return_inverse=True)
+            occ_leaf = torch.from_numpy(zz_all[occ_uniq].copy()).requires_grad_(True)
+            zz = occ_leaf[torch.from_numpy(inv.reshape(-1))]
+        else:
+            zz = torch.from_numpy(zz_all[cell])
+        m_s = occupancy_value(torch.from_numpy(p64[:, 2]), zz[:, 0], zz[:, 1], prm.occ_eps, prm.occ_q)
+        mask = torch.zeros(r, s_dim, dtype=torch.float64).index_put((ri, si), m_s)
+    cd_acc, f_acc, T, n_eval = composite(tau, cd, f, n_placed, prm.delta, prm.t_term, mask)
     mlp = mlp_leaf if mlp_leaf is not None else torch.from_numpy(np.asarray(scene["mlp"], dtype=np.float64))
     x = torch.cat([cd_acc, f_acc, torch.from_numpy(d.astype(np.float64))], dim=1)
     gate = torch.from_numpy(n_placed > 0)
@@ -156,7 +202,7 @@ def _render_chunk(scene, o, d, prm: RenderParams, grad: bool, mlp_leaf=None):
     C = cd_acc + g + T[:, None] * bg[None, :]
     F = torch.cat([cd_acc, f_acc], dim=1)
     return dict(C=C, T=T, F=F, n_placed=n_placed, n_eval=n_eval.numpy().astype(np.int32),
-                k_list=k_list, tables=tables)
+                k_list=k_list, tables=tables, occ_leaf=occ_leaf, occ_uniq=occ_uniq)
 
 
 def oracle_render(scene: Dict[str, np.ndarray], o: np.ndarray, d: np.ndarray, prm: RenderParams,
@@ -191,7 +237,8 @@ def oracle_loss_and_grads(scene, o, d, prm: RenderParams, target: np.ndarray):
 
     Returns (loss, C, grads) where grads[src] = (flat row indices, [U, 8]
     gradient rows) for the four feature sources and grads['mlp'] is the
-    dense [499] gradient."""
+    dense [499] gradient; with prm.occ_eps > 0 also grads['occ'] = (flat
+    cell indices, [U, 2] gradient of (z_min, z_max))."""
     o = np.ascontiguousarray(o, dtype=np.float32)
     d = np.ascontiguousarray(d, dtype=np.float32)
     mlp_leaf = torch.from_numpy(np.asarray(scene["mlp"], dtype=np.float64).copy()).requires_grad_(True)
@@ -201,9 +248,14 @@ def oracle_loss_and_grads(scene, o, d, prm: RenderParams, target: np.ndarray):
     loss = torch.mean((C - tgt) ** 2)
     tables = res["tables"]
     leaves = [tables.leaves[s] for s in SOURCES] + [mlp_leaf]
+    if res["occ_leaf"] is not None:
+        leaves.append(res["occ_leaf"])
     gr = torch.autograd.grad(loss, leaves, allow_unused=True)
     grads = {}
     for s, g in zip(SOURCES, gr[:4]):
         grads[s] = (tables.uniq[s], (g if g is not None else torch.zeros_like(tables.leaves[s])).numpy())
     grads["mlp"] = gr[4].numpy() if gr[4] is not None else np.zeros(mlp_leaf.shape)
+    if res["occ_leaf"] is not None:
+        g = gr[5] if gr[5] is not None else torch.zeros_like(res["occ_leaf"])
+        grads["occ"] = (res["occ_uniq"], g.numpy())
     return float(loss.item()), C.detach().numpy(), grads

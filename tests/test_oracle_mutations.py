@@ -5,12 +5,14 @@ Each mutant is a small, realistic slip -- a dropped feature source, a
 transposed plane, a cell-centred instead of vertex-aligned grid, a missing
 transmittance factor, a wrong decay, a lost background term, a missing ReLU,
 a rounded instead of floored cell index, an open instead of closed interval,
-an off-by-one lattice step.
+an off-by-one lattice step, and for the soft occupancy (Eq. 5, 6, 8) the
+mask also scaling T, exponent 1, the mask ignored and an unsquared span.
 """
 import numpy as np
 import pytest
 import torch
 
+import oracle
 import oracle.field as field
 import oracle.placement as placement
 import oracle.render as render
@@ -28,6 +30,9 @@ PIN_TESTS = [
     pins.test_opaque_first_sample,
     pins.test_mlp_hand_example,
     pins.test_ert_stops_after_crossing_sample,
+    pins.test_soft_mask_single_sample_hand_value,
+    lambda: pins.test_occupancy_value_matches_paper_cases(2.0),
+    pins.test_occ_interval_loss_hand_example,
 ]
 
 
@@ -66,7 +71,7 @@ def _cell_centred(c, lo, hi, n):
     return i0, u - i0
 
 
-def _composite_no_T(tau, cd, f, n_placed, delta, t_term=0.0):
+def _composite_no_T(tau, cd, f, n_placed, delta, t_term=0.0, mask=None):
     r, s_max = tau.shape
     cd_acc = torch.zeros(r, 3, dtype=torch.float64)
     f_acc = torch.zeros(r, 4, dtype=torch.float64)
@@ -76,6 +81,8 @@ def _composite_no_T(tau, cd, f, n_placed, delta, t_term=0.0):
         m = npl > s
         a = tau[:, s] * delta
         w = torch.where(m, -torch.expm1(-a), torch.zeros_like(a))  # T dropped
+        if mask is not None:
+            w = w * mask[:, s]
         cd_acc = cd_acc + w[:, None] * cd[:, s]
         f_acc = f_acc + w[:, None] * f[:, s]
         T = torch.where(m, T * torch.exp(-a), T)
@@ -83,8 +90,8 @@ def _composite_no_T(tau, cd, f, n_placed, delta, t_term=0.0):
 
 
 def _wrap_composite_decay(orig):
-    def f(tau, cd, fe, n_placed, delta, t_term=0.0):
-        return orig(tau, cd, fe, n_placed, 2.0 * delta, t_term)
+    def f(tau, cd, fe, n_placed, delta, t_term=0.0, mask=None):
+        return orig(tau, cd, fe, n_placed, 2.0 * delta, t_term, mask)
     return f
 
 
@@ -123,6 +130,32 @@ def _no_background(orig):
     return f
 
 
+def _composite_mask_on_T(orig):
+    """The rejected reading of Eq. 8: the occupancy value also scales the
+    attenuation (T_{i+1} = T_i exp(-M_i a_i))."""
+    def f(tau, cd, fe, n_placed, delta, t_term=0.0, mask=None):
+        if mask is None:
+            return orig(tau, cd, fe, n_placed, delta, t_term, mask)
+        return orig(tau * mask, cd, fe, n_placed, delta, t_term, None)
+    return f
+
+
+def _occ_q1(orig):
+    def f(z, zmin, zmax, eps, q):
+        return orig(z, zmin, zmax, eps, 1.0)
+    return f
+
+
+def _occ_ones(z, zmin, zmax, eps, q):
+    return torch.ones_like(z)
+
+
+def _span_not_squared(occ):
+    z = np.asarray(occ, dtype=np.float64)
+    span = z[..., 1] - z[..., 0]
+    return float(np.sum(np.abs(span))), np.stack([-np.sign(span), np.sign(span)], axis=-1)
+
+
 def _both(mp, name, new):
     """Patch a field-module function in every module that bound it."""
     mp.setattr(field, name, new)
@@ -141,6 +174,14 @@ MUTANTS = {
     "open z_max": lambda mp: mp.setattr(placement, "accept_mask", _open_zmax(placement.accept_mask)),
     "no background term": lambda mp: mp.setattr(render, "_render_chunk", _no_background(render._render_chunk)),
     "lattice off by one": lambda mp: mp.setattr(placement, "lattice_points", _off_by_one(placement.lattice_points)),
+    "occupancy mask on T": lambda mp: mp.setattr(render, "composite", _composite_mask_on_T(render.composite)),
+    "occupancy exponent 1": lambda mp: (mp.setattr(render, "occupancy_value", _occ_q1(render.occupancy_value)),
+                                        mp.setattr(oracle, "occupancy_value", _occ_q1(render.occupancy_value))),
+    "occupancy mask ignored": lambda mp: (mp.setattr(render, "occupancy_value", _occ_ones),
+                                          mp.setattr(oracle, "occupancy_value", _occ_ones)),
+    "interval loss not squared": lambda mp: (mp.setattr(render, "occ_interval_loss", _span_not_squared),
+                                             mp.setattr(oracle, "occupancy_value", render.occupancy_value),
+                                             mp.setattr(oracle, "occ_interval_loss", _span_not_squared)),
 }
 
 

@@ -416,3 +416,117 @@ def test_gradient_constant_density_closed_form():
     dcd = sigma * n * DELTA * math.exp(-sigma * n * DELTA) * s
     want = np.sum(2 * (C - tgt) / 9.0 * dcd)
     assert grads["grid"][1][:, 0].sum() == pytest.approx(want, rel=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Soft occupancy (Sec. 4.1 Eq. 5, 6, 8 with epsilon > 0)
+# ---------------------------------------------------------------------------
+
+def _eq6_cases(z, zmin, zmax, eps, q):
+    """The four cases of Eq. 6 as printed (valid when zmax - zmin >= 2 eps)."""
+    if zmin + eps <= z <= zmax - eps:
+        return 1.0
+    if z < zmin or z > zmax:
+        return 0.0
+    if zmin <= z <= zmin + eps:
+        return (z - zmin) ** q / eps ** q
+    return (zmax - z) ** q / eps ** q
+
+
+@pytest.mark.parametrize("q", [2.0, 1.0])
+def test_occupancy_value_matches_paper_cases(q):
+    zmin, zmax, eps = 0.1, 0.2, 0.02
+    z = np.linspace(0.05, 0.25, 401)
+    got = oracle.occupancy_value(torch.from_numpy(z), torch.tensor(zmin, dtype=torch.float64),
+                                 torch.tensor(zmax, dtype=torch.float64), eps, q).numpy()
+    want = np.array([_eq6_cases(v, zmin, zmax, eps, q) for v in z])
+    np.testing.assert_allclose(got, want, rtol=1e-14, atol=1e-15)
+
+
+def test_soft_mask_single_sample_hand_value():
+    """Vertical ray, n_max = 1: the one sample sits at the top lattice point
+    z1 <= z_max, inside the upper buffer zone.  Eq. 8 scales its weight by
+    M = ((z_max - z1) / eps)^2 and leaves T = exp(-sigma delta) unmasked."""
+    sigma, c = 90.0, 0.25
+    b3 = np.array([0.5, -0.25, 0.125], np.float32)
+    sc = _constant_density_scene(sigma, c, b3)
+    sigma = _sigma32(sigma)
+    k1 = 1700
+    z1 = 1.0 - k1 * DELTA                       # exact in binary32
+    zmax = np.float32(z1 + 0.375 * DELTA)       # between z1 and the next lattice point up
+    sc["occ"][..., 0] = np.float32(0.01)
+    sc["occ"][..., 1] = zmax
+    eps = 4 * DELTA
+    bg = (0.25, 0.5, 0.75)
+    r = oracle.oracle_render(sc, _f32([[0.3, -0.1, 1.0]]), _f32([[0, 0, -1]]),
+                             oracle.RenderParams(n_max=1, c_bg=bg, occ_eps=eps))
+    assert r["n_placed"][0] == 1 and r["k_list"][0, 0] == k1
+    m = ((float(zmax) - z1) / eps) ** 2
+    alpha = 1 - math.exp(-sigma * DELTA)
+    s = 1 / (1 + math.exp(-float(np.float32(c))))
+    T = math.exp(-sigma * DELTA)
+    np.testing.assert_allclose(r["F"][0], m * alpha * s, rtol=1e-12)
+    assert r["T"][0] == pytest.approx(T, rel=1e-13)
+    g = 1 / (1 + np.exp(-b3.astype(np.float64)))
+    np.testing.assert_allclose(r["C"][0], m * alpha * s + g + T * np.array(bg), rtol=1e-12)
+
+
+def test_soft_mask_small_eps_is_the_hard_interval():
+    """Interval ends half a lattice step from every sample of vertical rays
+    and eps a quarter step: every placed sample has M = 1, so the soft and
+    hard renders coincide."""
+    sc = micro_scene(grid=(5, 4, 3), planes=(7, 6, 5), m=4, seed=3, std=0.6)
+    rng = np.random.default_rng(4)
+    lo = 1.0 - rng.integers(1600, 1900, (4, 4)) * DELTA + 0.5 * DELTA
+    sc["occ"][..., 0] = lo.astype(np.float32)
+    sc["occ"][..., 1] = (lo + rng.integers(5, 60, (4, 4)) * DELTA).astype(np.float32)
+    o = np.column_stack([rng.uniform(-0.95, 0.95, (40, 2)), np.ones(40)]).astype(np.float32)
+    d = np.tile(_f32([0, 0, -1]), (40, 1))
+    hard = oracle.oracle_render(sc, o, d, oracle.RenderParams(n_max=128, c_bg=(0.1, 0.2, 0.3)))
+    soft = oracle.oracle_render(sc, o, d, oracle.RenderParams(n_max=128, c_bg=(0.1, 0.2, 0.3),
+                                                              occ_eps=0.25 * DELTA))
+    assert (hard["n_placed"] > 0).all()
+    for key in ("C", "F", "T"):
+        np.testing.assert_array_equal(soft[key], hard[key])
+
+
+def test_soft_mask_occupancy_gradient_matches_fd():
+    """dL/dz_min and dL/dz_max (through M only: placement is piecewise
+    constant in the bounds) against float64 central differences that keep
+    every placement unchanged."""
+    sc, o, d, tgt = _grad_problem(seed=2)
+    rng = np.random.default_rng(7)
+    sc["occ"][..., 0] = rng.uniform(0.02, 0.08, (4, 4)).astype(np.float32)
+    sc["occ"][..., 1] = rng.uniform(0.12, 0.2, (4, 4)).astype(np.float32)
+    prm = oracle.RenderParams(n_max=256, c_bg=(0.2, 0.4, 0.6), occ_eps=0.03)
+    _, _, grads = oracle.oracle_loss_and_grads(sc, o, d, prm, tgt)
+    cells, g = grads["occ"]
+    assert np.abs(g).max() > 0
+    h = 1e-8
+    checked = 0
+    for ci, cell in enumerate(cells):
+        for b in (0, 1):
+            vals, counts = [], []
+            for s in (+1, -1):
+                sp = dict(sc)
+                occ = sc["occ"].astype(np.float64).copy()
+                occ.reshape(-1, 2)[cell, b] += s * h
+                sp["occ"] = occ
+                r = oracle.oracle_render(sp, o, d, prm)
+                vals.append(np.mean((r["C"] - tgt) ** 2))
+                counts.append(r["n_placed"])
+            if not np.array_equal(counts[0], counts[1]):
+                continue
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - g[ci, b]) <= 1e-5 * max(abs(fd), 1e-4) + 1e-9, (cell, b, fd, g[ci, b])
+            checked += 1
+    assert checked >= 8
+
+
+def test_occ_interval_loss_hand_example():
+    """Eq. 5 on a 2 x 2 plane: spans 0.1, 0.2, 0, -0.05 (an empty cell)."""
+    occ = np.array([[[0.0, 0.1], [0.1, 0.3]], [[0.2, 0.2], [0.15, 0.1]]])
+    loss, grad = oracle.occ_interval_loss(occ)
+    assert loss == pytest.approx(0.01 + 0.04 + 0.0 + 0.0025, rel=1e-12)
+    np.testing.assert_allclose(grad[..., 1], [[0.2, 0.4], [0.0, -0.1]], atol=1e-15)
+    np.testing.assert_allclose(grad[..., 0], [[-0.2, -0.4], [0.0, 0.1]], atol=1e-15)
