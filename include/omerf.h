@@ -110,6 +110,13 @@ typedef struct om_params {
     float c_bg[3];    /* background colour                                  */
     int32_t mlp_bf16; /* 0: float32 MLP; 1: bfloat16 MLP on MFMA with
                          float32 accumulation; -1: follow the scene dtype   */
+    float occ_eps;    /* soft occupancy (Sec. 4.1, Eq. 6 and 8), finite and
+                         >= 0.  0: the hard interval.  > 0: each placed
+                         sample's compositing weight is multiplied by
+                         M = min(clamp((z - z_min)/eps, 0, 1)^2,
+                         clamp((z_max - z)/eps, 0, 1)^2) of its cell (q = 2);
+                         the transmittance is not masked.  Placement is the
+                         same either way (M = 0 outside [z_min, z_max]).     */
 } om_params;
 
 /* Forward outputs, all device pointers, all REQUIRED (the backward pass
@@ -147,6 +154,10 @@ typedef struct om_grads {
     float* plane_xz;
     float* plane_yz;
     float* mlp;
+    /* Optional: gradient of (z_min, z_max), [My][Mx][2], accumulated when
+     * occ_eps > 0 (the derivative of M; placement is piecewise constant in
+     * the bounds).  NULL skips it. */
+    float* occ;
 } om_grads;
 
 /* Create a scene handle from `desc` (validated as above).  On success
@@ -271,6 +282,16 @@ int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, 
 /* Workspace bytes om_render_fwd_bwd_l2 needs for n rays and p->n_max, or
  * -1 (with om_last_error set) if n < 0 or p is invalid. */
 int64_t om_render_fwd_bwd_l2_workspace_size(int64_t n, const om_params* p);
+
+/*
+ * Interval-span regulariser of Sec. 4.1, Eq. 5, scaled by `weight` (the
+ * schedule's lambda): L = weight * sum over the My x Mx grid points of
+ * (z_max - z_min)^2.  occ: device float32 [cells][2].  loss_fp64: optional
+ * device double[1] receiving L (overwritten); grad_occ: optional device
+ * float32 [cells][2] into which dL/d(z_min, z_max) is ADDED.
+ */
+int om_occ_interval_loss(const float* occ, int64_t cells, float weight, double* loss_fp64, float* grad_occ,
+                         void* stream);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* om_last_error(void);

@@ -153,8 +153,9 @@ class Scene:
             pass
 
 
-def _params(n_max: int, delta: float, t_term: float, c_bg, mlp_bf16: int) -> _lib.OmParams:
+def _params(n_max: int, delta: float, t_term: float, c_bg, mlp_bf16: int, occ_eps: float = 0.0) -> _lib.OmParams:
     p = _lib.OmParams()
+    p.occ_eps = float(occ_eps)
     p.delta = delta
     p.n_max = int(n_max)
     p.t_term = float(t_term)
@@ -193,10 +194,12 @@ def batch_slots(n_max: int) -> int:
 
 
 def render(scene: Scene, o, d, n_max: int, delta: float = DELTA, t_term: float = 0.0,
-           c_bg=(0.0, 0.0, 0.0), mlp_bf16: int = -1, batch_wv: bool = False) -> Dict[str, torch.Tensor]:
+           c_bg=(0.0, 0.0, 0.0), mlp_bf16: int = -1, batch_wv: bool = False,
+           occ_eps: float = 0.0) -> Dict[str, torch.Tensor]:
     """Forward render; returns C [n,3], T [n], F [n,7], n_placed [n], n_eval [n]
     and, with batch_wv=True, the per-batch sums of w v [n, batch_slots(n_max), 7]
-    that let the backward skip one replay of the samples."""
+    that let the backward skip one replay of the samples.  occ_eps > 0
+    applies the soft occupancy value of Eq. 6 to the weights (Eq. 8)."""
     n = _rays(scene, o, d)
     dev = o.device
     out = dict(C=torch.empty((n, 3), dtype=torch.float32, device=dev),
@@ -206,7 +209,7 @@ def render(scene: Scene, o, d, n_max: int, delta: float = DELTA, t_term: float =
                n_eval=torch.empty((n,), dtype=torch.int32, device=dev))
     if batch_wv:
         out["batch_wv"] = torch.empty((n, batch_slots(n_max), 7), dtype=torch.float32, device=dev)
-    render_into(scene, o, d, out, n_max, delta, t_term, c_bg, mlp_bf16)
+    render_into(scene, o, d, out, n_max, delta, t_term, c_bg, mlp_bf16, occ_eps=occ_eps)
     return out
 
 
@@ -224,7 +227,8 @@ def _fwd_out(out, n: int, n_max: int):
 
 
 def render_into(scene: Scene, o, d, out: Dict[str, torch.Tensor], n_max: int, delta: float = DELTA,
-                t_term: float = 0.0, c_bg=(0.0, 0.0, 0.0), mlp_bf16: int = -1, stage: str = "all") -> None:
+                t_term: float = 0.0, c_bg=(0.0, 0.0, 0.0), mlp_bf16: int = -1, stage: str = "all",
+                occ_eps: float = 0.0) -> None:
     """Forward render into preallocated outputs (same keys as render(); an
     optional "batch_wv" entry receives the per-batch w v sums).
 
@@ -232,7 +236,7 @@ def render_into(scene: Scene, o, d, out: Dict[str, torch.Tensor], n_max: int, de
     "mlp" only om_deferred_mlp (C from F, T, n_eval)."""
     n = o.shape[0]
     fo = _fwd_out(out, n, n_max)
-    p = _params(n_max, delta, t_term, c_bg, mlp_bf16)
+    p = _params(n_max, delta, t_term, c_bg, mlp_bf16, occ_eps)
     L = _lib.lib()
     st = _lib.stream_of(o)
     if stage == "all":
@@ -249,19 +253,20 @@ def render_into(scene: Scene, o, d, out: Dict[str, torch.Tensor], n_max: int, de
 
 
 def render_backward(scene: Scene, o, d, saved: Dict[str, torch.Tensor], dL_dC, grads: Dict[str, torch.Tensor],
-                    n_max: int, delta: float = DELTA, t_term: float = 0.0, c_bg=(0.0, 0.0, 0.0)) -> None:
+                    n_max: int, delta: float = DELTA, t_term: float = 0.0, c_bg=(0.0, 0.0, 0.0),
+                    occ_eps: float = 0.0) -> None:
     """Accumulate dL/d(grid, planes, mlp) into float32 `grads` (keys grid,
     plane_xy, plane_xz, plane_yz, mlp) given dL/dC and the forward's outputs
-    (with "batch_wv" among them when the forward wrote it)."""
+    (with "batch_wv" among them when the forward wrote it).  With
+    occ_eps > 0 an optional grads["occ"] [My, Mx, 2] receives dL/d(z_min, z_max)."""
     n = _rays(scene, o, d)
     _need(dL_dC, "dL_dC", torch.float32, (n, 3))
     for key in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp"):
         _need(grads[key], f"grads[{key}]", torch.float32, scene.tensors[key].shape)
     fo = _lib.OmFwdOut(saved["C"].data_ptr(), saved["T"].data_ptr(), saved["F"].data_ptr(),
                        saved["n_placed"].data_ptr(), saved["n_eval"].data_ptr(), _batch_wv(saved, n, n_max))
-    g = _lib.OmGrads(grads["grid"].data_ptr(), grads["plane_xy"].data_ptr(), grads["plane_xz"].data_ptr(),
-                     grads["plane_yz"].data_ptr(), grads["mlp"].data_ptr())
-    p = _params(n_max, delta, t_term, c_bg, -1)
+    g = _grads(scene, grads)
+    p = _params(n_max, delta, t_term, c_bg, -1, occ_eps)
     _lib.check("om_render_backward", _lib.lib().om_render_backward(
         scene.handle, o.data_ptr(), d.data_ptr(), n, ctypes.byref(p), ctypes.byref(fo), dL_dC.data_ptr(),
         ctypes.byref(g), _lib.stream_of(o)))
@@ -280,7 +285,7 @@ def fwd_bwd_l2_workspace_size(n: int, n_max: int, delta: float = DELTA) -> int:
 def render_fwd_bwd_l2(scene: Scene, o, d, target, out: Dict[str, torch.Tensor], grads: Dict[str, torch.Tensor],
                       n_max: int, delta: float = DELTA, t_term: float = 0.0, c_bg=(0.0, 0.0, 0.0),
                       mlp_bf16: int = -1, workspace: Optional[torch.Tensor] = None,
-                      loss: Optional[torch.Tensor] = None) -> Optional[torch.Tensor]:
+                      loss: Optional[torch.Tensor] = None, occ_eps: float = 0.0) -> Optional[torch.Tensor]:
     """One fused L2 training step (om_render_fwd_bwd_l2): forward into `out`
     (keys as render()), dL/dC, float64 loss into `loss` (a device float64 [1]
     tensor, or None to skip), and the backward ADDED into float32 `grads`.
@@ -297,12 +302,37 @@ def render_fwd_bwd_l2(scene: Scene, o, d, target, out: Dict[str, torch.Tensor], 
         _need(loss, "loss", torch.float64, (1,))
     fo = _lib.OmFwdOut(out["C"].data_ptr(), out["T"].data_ptr(), out["F"].data_ptr(), out["n_placed"].data_ptr(),
                        out["n_eval"].data_ptr(), 0)
-    g = _lib.OmGrads(grads["grid"].data_ptr(), grads["plane_xy"].data_ptr(), grads["plane_xz"].data_ptr(),
-                     grads["plane_yz"].data_ptr(), grads["mlp"].data_ptr())
-    p = _params(n_max, delta, t_term, c_bg, mlp_bf16)
+    g = _grads(scene, grads)
+    p = _params(n_max, delta, t_term, c_bg, mlp_bf16, occ_eps)
     _lib.check("om_render_fwd_bwd_l2", _lib.lib().om_render_fwd_bwd_l2(
         scene.handle, o.data_ptr(), d.data_ptr(), n, ctypes.byref(p), target.data_ptr(), ctypes.byref(fo),
         workspace.data_ptr(), workspace.numel(), _lib.ptr(loss), ctypes.byref(g), _lib.stream_of(o)))
+    return loss
+
+
+def _grads(scene: Scene, grads: Dict[str, torch.Tensor]) -> _lib.OmGrads:
+    for key in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp"):
+        _need(grads[key], f"grads[{key}]", torch.float32, scene.tensors[key].shape)
+    occ = grads.get("occ")
+    if occ is not None:
+        _need(occ, "grads[occ]", torch.float32, scene.tensors["occ"].shape)
+    return _lib.OmGrads(grads["grid"].data_ptr(), grads["plane_xy"].data_ptr(), grads["plane_xz"].data_ptr(),
+                        grads["plane_yz"].data_ptr(), grads["mlp"].data_ptr(), _lib.ptr(occ))
+
+
+def occ_interval_loss(occ, weight: float = 1.0, grad: Optional[torch.Tensor] = None,
+                      with_loss: bool = True) -> Optional[torch.Tensor]:
+    """Interval-span regulariser of Eq. 5: weight * sum (z_max - z_min)^2 as a
+    device float64 [1] tensor (if with_loss), and its gradient ADDED into
+    `grad` (float32, shape of occ) when given."""
+    _need(occ, "occ", torch.float32)
+    if occ.shape[-1] != 2:
+        raise ValueError("occ must end in (z_min, z_max)")
+    if grad is not None:
+        _need(grad, "grad", torch.float32, occ.shape)
+    loss = torch.empty((1,), dtype=torch.float64, device=occ.device) if with_loss else None
+    _lib.check("om_occ_interval_loss", _lib.lib().om_occ_interval_loss(
+        occ.data_ptr(), occ.numel() // 2, float(weight), _lib.ptr(loss), _lib.ptr(grad), _lib.stream_of(occ)))
     return loss
 
 
@@ -333,17 +363,19 @@ def l2_loss_grad(C, target, dL_dC: Optional[torch.Tensor] = None, with_loss: boo
 class RenderFn(torch.autograd.Function):
     """C = render(scene) with gradients into float32 master tensors.
 
-    ``RenderFn.apply(scene, o, d, opts, grid, plane_xy, plane_xz, plane_yz, mlp)``:
+    ``RenderFn.apply(scene, o, d, opts, grid, plane_xy, plane_xz, plane_yz, mlp[, occ])``:
     the render reads the tensors the Scene points at (the float32 masters
     themselves, or bfloat16 shadows of them); the gradients are float32 and
-    are returned for the master tensors passed as the last five inputs.
-    opts = dict(n_max=..., delta=..., t_term=..., c_bg=..., mlp_bf16=...)."""
+    are returned for the master tensors passed as the last inputs, including
+    the occupancy plane when it is passed and opts["occ_eps"] > 0.
+    opts = dict(n_max=..., delta=..., t_term=..., c_bg=..., mlp_bf16=..., occ_eps=...)."""
 
     @staticmethod
-    def forward(ctx, scene, o, d, opts, grid, plane_xy, plane_xz, plane_yz, mlp):
+    def forward(ctx, scene, o, d, opts, grid, plane_xy, plane_xz, plane_yz, mlp, occ=None):
         out = render(scene, o, d, batch_wv=True, **opts)
         ctx.scene, ctx.opts = scene, opts
         ctx.masters = (grid, plane_xy, plane_xz, plane_yz, mlp)
+        ctx.occ = occ
         ctx.save_for_backward(o, d, out["C"], out["T"], out["F"], out["n_placed"], out["n_eval"], out["batch_wv"])
         ctx.mark_non_differentiable(out["T"], out["F"], out["n_placed"], out["n_eval"])
         return out["C"], out["T"], out["F"], out["n_placed"], out["n_eval"]
@@ -354,7 +386,9 @@ class RenderFn(torch.autograd.Function):
         saved = dict(C=C, T=T, F=F, n_placed=npl, n_eval=nev, batch_wv=bwv)
         grads = {k: torch.zeros(m.shape, dtype=torch.float32, device=m.device)
                  for k, m in zip(("grid", "plane_xy", "plane_xz", "plane_yz", "mlp"), ctx.masters)}
+        if ctx.occ is not None and ctx.opts.get("occ_eps", 0.0) > 0:
+            grads["occ"] = torch.zeros(ctx.occ.shape, dtype=torch.float32, device=ctx.occ.device)
         opts = {k: v for k, v in ctx.opts.items() if k != "mlp_bf16"}
         render_backward(ctx.scene, o, d, saved, gC.contiguous().float(), grads, **opts)
         return (None, None, None, None, grads["grid"], grads["plane_xy"], grads["plane_xz"], grads["plane_yz"],
-                grads["mlp"])
+                grads["mlp"], grads.get("occ"))

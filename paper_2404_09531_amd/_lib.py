@@ -22,7 +22,8 @@ EXPORTS = ("om_scene_create", "om_scene_update", "om_scene_destroy", "om_occupan
            "om_build_occupancy_mips", "om_place_samples", "om_march",
            "om_deferred_mlp", "om_render",
            "om_render_backward", "om_render_fwd_bwd_l2", "om_render_fwd_bwd_l2_workspace_size",
-           "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str", "om_version")
+           "om_occ_interval_loss", "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str",
+           "om_version")
 
 
 class OmSceneDesc(ctypes.Structure):
@@ -34,7 +35,7 @@ class OmSceneDesc(ctypes.Structure):
 
 class OmParams(ctypes.Structure):
     _fields_ = [("delta", c_float), ("n_max", c_int32), ("t_term", c_float), ("c_bg", c_float * 3),
-                ("mlp_bf16", c_int32)]
+                ("mlp_bf16", c_int32), ("occ_eps", c_float)]
 
 
 class OmFwdOut(ctypes.Structure):
@@ -44,7 +45,7 @@ class OmFwdOut(ctypes.Structure):
 
 class OmGrads(ctypes.Structure):
     _fields_ = [("grid", c_void_p), ("plane_xy", c_void_p), ("plane_xz", c_void_p), ("plane_yz", c_void_p),
-                ("mlp", c_void_p)]
+                ("mlp", c_void_p), ("occ", c_void_p)]
 
 
 _lib = None
@@ -80,6 +81,7 @@ def lib() -> ctypes.CDLL:
                                            c_void_p]
         L.om_render_fwd_bwd_l2_workspace_size.argtypes = [c_int64, POINTER(OmParams)]
         L.om_occupancy_mips_size.argtypes = [c_void_p, c_int]
+        L.om_occ_interval_loss.argtypes = [c_void_p, c_int64, c_float, c_void_p, c_void_p, c_void_p]
         L.om_build_occupancy_mips.argtypes = [c_void_p, c_void_p, c_int64, c_int, c_void_p]
         L.om_last_error.restype = c_char_p
         L.om_status_str.restype = c_char_p

@@ -145,6 +145,10 @@ int validate_params(const om_params* p, RayParams* rp) {
         return fail(OM_ERR_UNSUPPORTED, "n_max must be in [1, %d]", OM_MAX_SAMPLES);
     if (!std::isfinite(p->t_term) || p->t_term < 0.0f) return fail(OM_ERR_INVALID, "t_term must be finite and >= 0");
     if (p->mlp_bf16 < -1 || p->mlp_bf16 > 1) return fail(OM_ERR_INVALID, "mlp_bf16 must be -1, 0 or 1");
+    if (!std::isfinite(p->occ_eps) || p->occ_eps < 0.0f) return fail(OM_ERR_INVALID, "occ_eps must be finite and >= 0");
+    const float inv = p->occ_eps > 0.0f ? 1.0f / p->occ_eps : 0.0f;
+    if (!std::isfinite(inv)) return fail(OM_ERR_INVALID, "occ_eps too small");
+    rp->occ_inv_eps = inv;
     rp->delta = p->delta;
     rp->n_max = p->n_max;
     rp->t_term = p->t_term;
@@ -325,7 +329,7 @@ int om_render_backward(const om_scene* scene, const float* o, const float* d, in
         return fail(OM_ERR_INVALID, "all gradient buffers are required");
     const bool bf16 = scene->desc.dtype == OM_BF16;
     hipError_t e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, saved->F, saved->T, saved->n_eval, saved->batch_wv,
-                                    dL_dC, g->grid, g->plane_xy, g->plane_xz, g->plane_yz, g->mlp,
+                                    dL_dC, g->grid, g->plane_xy, g->plane_xz, g->plane_yz, g->mlp, g->occ,
                                     (hipStream_t)stream);
     return hip_status(e, "om_render_backward");
 }
@@ -368,8 +372,18 @@ int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, 
     e = launch_l2(out->C, target, n, dC, loss_fp64, s);
     if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2 (loss)");
     e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_eval, bw, dC, g->grid, g->plane_xy,
-                         g->plane_xz, g->plane_yz, g->mlp, s);
+                         g->plane_xz, g->plane_yz, g->mlp, g->occ, s);
     return hip_status(e, "om_render_fwd_bwd_l2 (backward)");
+}
+
+int om_occ_interval_loss(const float* occ, int64_t cells, float weight, double* loss_fp64, float* grad_occ,
+                         void* stream) {
+    if (cells <= 0) return fail(OM_ERR_INVALID, "cells must be > 0");
+    if (!occ) return fail(OM_ERR_INVALID, "occ is NULL");
+    if (!std::isfinite(weight)) return fail(OM_ERR_INVALID, "weight must be finite");
+    if (!loss_fp64 && !grad_occ) return ok();
+    return hip_status(launch_occ_loss(occ, cells, weight, loss_fp64, grad_occ, (hipStream_t)stream),
+                      "om_occ_interval_loss");
 }
 
 int om_l2_loss_fp64(const float* C, const float* target, int64_t n, double* out, void* stream) {
@@ -397,6 +411,6 @@ const char* om_status_str(int status) {
     }
 }
 
-int om_version(void) { return 103; }
+int om_version(void) { return 104; }
 
 }  // extern "C"

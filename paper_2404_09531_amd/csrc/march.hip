@@ -127,7 +127,7 @@ __device__ __forceinline__ void store_group_total(float x, int gl, float* dst) {
     if (gl == kGroup - 1) *dst = x;
 }
 
-template <class S, bool kBW>
+template <class S, bool kBW, bool kSoft>
 __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                            const float* __restrict__ d_, int64_t n,
                                                            float* __restrict__ F, float* __restrict__ T,
@@ -163,9 +163,11 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
                 float t[8];
 #pragma unroll
                 for (int c = 0; c < 8; ++c) t[c] = 0.0f;
+                float msoft = 0.0f;
                 if (act) {
-                    const Corners cn = corners_of(sc, lattice_point(ks, o, d, rp.delta));
-                    gather_half<S>(sc, cn, half, t);
+                    const float3 p = lattice_point(ks, o, d, rp.delta);
+                    gather_half<S>(sc, corners_of(sc, p), half, t);
+                    if (kSoft) msoft = occ_value(sc, p, rp.occ_inv_eps).m;
                 }
 #pragma unroll
                 for (int c = 0; c < 8; ++c) t[c] += pair_swap(t[c]);
@@ -193,6 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
                         stop = true;
                     }
                 }
+                if (kSoft) w *= msoft;              // Eq. 8: the weight, not T
                 if (s >= nb_eff || half) w = 0.0f;  // accumulate once per sample (even lane)
 #pragma unroll
                 for (int c = 0; c < 7; ++c) bacc[c] += w * v[c];
@@ -272,7 +275,7 @@ __device__ __forceinline__ void quad_gather(const SceneDev& sc, const Corners& c
     }
 }
 
-template <bool kBW>
+template <bool kBW, bool kSoft>
 __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                            const float* __restrict__ d_, int64_t n,
                                                            float* __restrict__ F, float* __restrict__ T,
@@ -296,13 +299,18 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParam
     int evals = 0, batch = 0;
     const int slots = (rp.n_max + kGroup - 1) / kGroup;
     const int placed = march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
-        float a[4], v[4][4];
+        float a[4], v[4][4], msoft[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int i = 4 * j + s;
             const int ks = __shfl(kq, i, kGroup);
             float t[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            if (i < nb) quad_gather(sc, corners_of(sc, lattice_point(ks, o, d, rp.delta)), h, ch, t);
+            msoft[j] = 0.0f;
+            if (i < nb) {
+                const float3 p = lattice_point(ks, o, d, rp.delta);
+                quad_gather(sc, corners_of(sc, p), h, ch, t);
+                if (kSoft) msoft[j] = occ_value(sc, p, rp.occ_inv_eps).m;
+            }
 #pragma unroll
             for (int c = 0; c < 4; ++c) t[c] += pair_swap(t[c]);
             a[j] = 0.0f;
@@ -347,6 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParam
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             float w = __expf(-pre[j]) * (-expm1f(-a[j]));
+            if (kSoft) w *= msoft[j];                // Eq. 8: the weight, not T
             if (4 * j + s >= nb_eff || h) w = 0.0f;  // once per sample and channel half
 #pragma unroll
             for (int c = 0; c < 4; ++c) bacc[c] += w * v[j][c];
@@ -491,17 +500,21 @@ __device__ __forceinline__ void scatter_batch_runs(const SceneDev& sc, float* gV
     scatter_plane_runs(gyz, sc.Ny, st, act, cn.yz, cn.uy, cn.uz, gt, gl, lane);
 }
 
-// One replayed sample: optical depth, density, activated colours/features.
-template <class S>
+// One replayed sample: optical depth, density, activated colours/features
+// and, for the soft occupancy, its value and derivatives.
+template <class S, bool kSoft>
 __device__ __forceinline__ void replay_sample(const SceneDev& sc, const RayParams& rp, float3 o, float3 d, int kq,
-                                              bool act, float& a, float& tau, float* v, Corners& cn) {
+                                              bool act, float& a, float& tau, float* v, Corners& cn, OccValue& oc) {
     a = 0.0f;
     tau = 0.0f;
     cn = Corners{};  // defined keys and weights on inactive lanes, which the group scans read
+    oc = OccValue{1.0f, 0.0f, 0.0f, -1};
 #pragma unroll
     for (int c = 0; c < 7; ++c) v[c] = 0.0f;
     if (act) {
-        cn = corners_of(sc, lattice_point(kq, o, d, rp.delta));
+        const float3 p = lattice_point(kq, o, d, rp.delta);
+        cn = corners_of(sc, p);
+        if (kSoft) oc = occ_value(sc, p, rp.occ_inv_eps);
         float t[8];
         gather_features_split<S>(sc, cn, t);
         tau = __expf(t[0]);
@@ -511,7 +524,20 @@ __device__ __forceinline__ void replay_sample(const SceneDev& sc, const RayParam
     }
 }
 
-template <class S>
+// z_min / z_max gradient of the soft occupancy: run sums over the samples
+// that share an occupancy cell, one pair of atomics per run.
+__device__ __forceinline__ void scatter_occ(float* gocc, bool act, const OccValue& oc, float gm, int gl, int lane) {
+    float g[8] = {gm * oc.dzmin, gm * oc.dzmax, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const Runs rn = g_runs((uint32_t)oc.cell, act, gl);
+    const int lmax = g_max(act ? rn.len : 0);
+    g_seg_sum2(g, rn.len, lmax);
+    if (rn.tail) {
+        if (g[0] != 0.0f) unsafeAtomicAdd(gocc + (size_t)oc.cell * 2, g[0]);
+        if (g[1] != 0.0f) unsafeAtomicAdd(gocc + (size_t)oc.cell * 2 + 1, g[1]);
+    }
+}
+
+template <class S, bool kSoft>
 __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                       const float* __restrict__ d_, int64_t n, int64_t chunk,
                                                       const float* __restrict__ Fs, const float* __restrict__ Ts,
@@ -519,7 +545,8 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
                                                       const float* __restrict__ BW,
                                                       const float* __restrict__ dC, float* __restrict__ gV,
                                                       float* __restrict__ gxy, float* __restrict__ gxz,
-                                                      float* __restrict__ gyz, float* __restrict__ gmlp) {
+                                                      float* __restrict__ gyz, float* __restrict__ gmlp,
+                                                      float* __restrict__ gocc) {
     __shared__ int qs[kGroupsPerBlock][kQueue];
     __shared__ float sW[512];
     __shared__ __attribute__((aligned(16))) Stage stages[kGroupsPerBlock];
@@ -617,10 +644,11 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
                 const bool act = gl < nb_eff;
                 float a, tau, v[7];
                 Corners cn;
-                replay_sample<S>(sc, rp, o, d, kq, act, a, tau, v, cn);
+                OccValue oc;
+                replay_sample<S, kSoft>(sc, rp, o, d, kq, act, a, tau, v, cn, oc);
                 const float incl = g_scan_incl(a, gl);
                 const float excl = g_shift_up1(incl);
-                const float w = act ? __expf(-(carry + excl)) * (-expm1f(-a)) : 0.0f;
+                const float w = act ? __expf(-(carry + excl)) * (-expm1f(-a)) * (kSoft ? oc.m : 1.0f) : 0.0f;
                 float gv = 0.0f;
 #pragma unroll
                 for (int c = 0; c < 7; ++c) gv += g7[c] * v[c];
@@ -654,12 +682,15 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
             const bool act = gl < nb_eff;
             float a, tau, v[7];
             Corners cn;
-            replay_sample<S>(sc, rp, o, d, kq, act, a, tau, v, cn);
+            OccValue oc;
+            replay_sample<S, kSoft>(sc, rp, o, d, kq, act, a, tau, v, cn, oc);
             const float incl = g_scan_incl(a, gl);
             const float excl = g_shift_up1(incl);
             const float Ti = __expf(-(carry + excl));
             const float Tnext = __expf(-(carry + incl));
-            const float w = act ? Ti * (-expm1f(-a)) : 0.0f;
+            const float w0 = act ? Ti * (-expm1f(-a)) : 0.0f;  // Eq. 1 weight
+            const float msoft = kSoft ? oc.m : 1.0f;             // Eq. 8 scales the weight, not T
+            const float w = w0 * msoft;
             float gv = 0.0f;
 #pragma unroll
             for (int c = 0; c < 7; ++c) gv += g7[c] * v[c];
@@ -672,10 +703,11 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
                 if ((nxt >> 4) == s) after = __shfl(R[s], nxt & 15, kGroup);
             const float suffix = rin + after;
             float gt[8];
-            gt[0] = (Tnext * gv - suffix - Tn * gT) * rp.delta * tau;
+            gt[0] = (Tnext * msoft * gv - suffix - Tn * gT) * rp.delta * tau;
 #pragma unroll
             for (int c = 0; c < 7; ++c) gt[c + 1] = w * g7[c] * v[c] * (1.0f - v[c]);
             scatter_batch_runs(sc, gV, gxy, gxz, gyz, stage, act, cn, gt, gl, lane);
+            if (kSoft && gocc) scatter_occ(gocc, act, oc, w0 * gv, gl, lane);  // dL/dM = w0 (g7 . v)
             carry += __shfl(incl, kGroup - 1, kGroup);
             done += nb_eff;
             ++b;
@@ -700,34 +732,44 @@ hipError_t launch_place(const SceneDev& sc, const RayParams& rp, const float* o,
     return hipGetLastError();
 }
 
-hipError_t launch_march_fwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
+template <bool kSoft>
+static void launch_fwd_soft(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
                             int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, float* batch_wv,
                             hipStream_t s) {
-    // The per-batch sums are a separate specialisation, so the render path
-    // carries none of their code.
     const dim3 grid(blocks_for(n)), block(kBlock);
     if (bf16) {
         if (batch_wv)
-            hipLaunchKernelGGL((k_march_fwd<BF16Store, true>), grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed,
-                               n_eval, batch_wv);
+            hipLaunchKernelGGL((k_march_fwd<BF16Store, true, kSoft>), grid, block, 0, s, sc, rp, o, d, n, F, T,
+                               n_placed, n_eval, batch_wv);
         else
-            hipLaunchKernelGGL((k_march_fwd<BF16Store, false>), grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed,
-                               n_eval, batch_wv);
+            hipLaunchKernelGGL((k_march_fwd<BF16Store, false, kSoft>), grid, block, 0, s, sc, rp, o, d, n, F, T,
+                               n_placed, n_eval, batch_wv);
     } else {
         if (batch_wv)
-            hipLaunchKernelGGL(k_march_fwd_f32q<true>, grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed, n_eval,
-                               batch_wv);
+            hipLaunchKernelGGL((k_march_fwd_f32q<true, kSoft>), grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed,
+                               n_eval, batch_wv);
         else
-            hipLaunchKernelGGL(k_march_fwd_f32q<false>, grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed, n_eval,
-                               batch_wv);
+            hipLaunchKernelGGL((k_march_fwd_f32q<false, kSoft>), grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed,
+                               n_eval, batch_wv);
     }
+}
+
+hipError_t launch_march_fwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
+                            int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, float* batch_wv,
+                            hipStream_t s) {
+    // The per-batch sums and the soft occupancy are separate
+    // specialisations, so the plain render path carries neither.
+    if (rp.occ_inv_eps > 0.0f)
+        launch_fwd_soft<true>(sc, bf16, rp, o, d, n, F, T, n_placed, n_eval, batch_wv, s);
+    else
+        launch_fwd_soft<false>(sc, bf16, rp, o, d, n, F, T, n_placed, n_eval, batch_wv, s);
     return hipGetLastError();
 }
 
 hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
                             int64_t n, const float* F, const float* T, const int32_t* n_eval, const float* batch_wv,
-                            const float* dC,
-                            float* gV, float* gxy, float* gxz, float* gyz, float* gmlp, hipStream_t s) {
+                            const float* dC, float* gV, float* gxy, float* gxz, float* gyz, float* gmlp, float* gocc,
+                            hipStream_t s) {
     // Persistent blocks, each owning a contiguous chunk of rays, so the MLP
     // weight gradients are reduced in LDS over many rays before one set of
     // global atomics per block.
@@ -737,12 +779,23 @@ hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, 
     int64_t chunk = (n + nb - 1) / nb;
     chunk = (chunk + kGroupsPerBlock - 1) / kGroupsPerBlock * kGroupsPerBlock;
     nb = (n + chunk - 1) / chunk;
-    if (bf16)
-        hipLaunchKernelGGL(k_march_bwd<BF16Store>, dim3((unsigned)nb), dim3(kBlock), 0, s, sc, rp, o, d, n, chunk, F, T,
-                           n_eval, batch_wv, dC, gV, gxy, gxz, gyz, gmlp);
-    else
-        hipLaunchKernelGGL(k_march_bwd<F32Store>, dim3((unsigned)nb), dim3(kBlock), 0, s, sc, rp, o, d, n, chunk, F, T,
-                           n_eval, batch_wv, dC, gV, gxy, gxz, gyz, gmlp);
+    const dim3 grid((unsigned)nb), block(kBlock);
+    const bool soft = rp.occ_inv_eps > 0.0f;
+    if (bf16) {
+        if (soft)
+            hipLaunchKernelGGL((k_march_bwd<BF16Store, true>), grid, block, 0, s, sc, rp, o, d, n, chunk, F, T, n_eval,
+                               batch_wv, dC, gV, gxy, gxz, gyz, gmlp, gocc);
+        else
+            hipLaunchKernelGGL((k_march_bwd<BF16Store, false>), grid, block, 0, s, sc, rp, o, d, n, chunk, F, T,
+                               n_eval, batch_wv, dC, gV, gxy, gxz, gyz, gmlp, gocc);
+    } else {
+        if (soft)
+            hipLaunchKernelGGL((k_march_bwd<F32Store, true>), grid, block, 0, s, sc, rp, o, d, n, chunk, F, T, n_eval,
+                               batch_wv, dC, gV, gxy, gxz, gyz, gmlp, gocc);
+        else
+            hipLaunchKernelGGL((k_march_bwd<F32Store, false>), grid, block, 0, s, sc, rp, o, d, n, chunk, F, T, n_eval,
+                               batch_wv, dC, gV, gxy, gxz, gyz, gmlp, gocc);
+    }
     return hipGetLastError();
 }
 

@@ -227,4 +227,38 @@ hipError_t launch_occ_pyramid(const float2* occ, int Mx, int My, float2* mips, i
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Interval-span regulariser (Eq. 5): weight * sum (z_max - z_min)^2 in
+// float64, and its gradient added to grad_occ.
+// ---------------------------------------------------------------------------
+__global__ void k_occ_loss(const float2* __restrict__ occ, int64_t cells, float weight, double* __restrict__ loss,
+                           float2* __restrict__ grad) {
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += (int64_t)gridDim.x * blockDim.x) {
+        const float2 z = occ[i];
+        const double span = (double)z.y - (double)z.x;
+        acc += span * span;
+        if (grad) {
+            const float g = (float)(2.0 * (double)weight * span);
+            float2 cur = grad[i];
+            cur.x -= g;
+            cur.y += g;
+            grad[i] = cur;
+        }
+    }
+    if (loss) {
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if ((threadIdx.x & 63) == 0 && acc != 0.0) atomicAdd(loss, acc * (double)weight);
+    }
+}
+
+hipError_t launch_occ_loss(const float* occ, int64_t cells, float weight, double* loss, float* grad, hipStream_t s) {
+    if (loss) hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, loss);
+    int64_t blocks = (cells + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_occ_loss, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const float2*>(occ),
+                       cells, weight, loss, reinterpret_cast<float2*>(grad));
+    return hipGetLastError();
+}
+
 }  // namespace omerf

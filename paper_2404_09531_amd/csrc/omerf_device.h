@@ -54,6 +54,7 @@ struct RayParams {
     int n_max;
     float t_term;
     float bg0, bg1, bg2;
+    float occ_inv_eps;  // 1 / epsilon of the soft occupancy value (Eq. 6); 0: hard interval
 };
 
 // MLP parameter offsets in the packed vector.
@@ -124,6 +125,37 @@ __device__ __forceinline__ bool column_maybe(const SceneDev& sc, float3 o, float
             maybe |= (z.x <= z1) && (z.y >= z0) && (z.x <= z.y);
         }
     return maybe;
+}
+
+// Soft occupancy value of Eq. 6 (q = 2) at a placed sample p, read at the
+// cell containing p's xy (Eq. 7), in the form min(rise^2, fall^2) with
+// rise = clamp((z - z_min) / eps, 0, 1) and fall = clamp((z_max - z) / eps,
+// 0, 1), which equals the four cases of Eq. 6 whenever z_max - z_min >= 2 eps
+// and stays continuous when the buffer zones overlap.  Also returns
+// dM/dz_min and dM/dz_max, with the conventions of a float64 autograd of
+// that expression: a clamp passes the derivative on its closed range, and a
+// tie of the minimum splits it between the two sides.
+struct OccValue {
+    float m, dzmin, dzmax;
+    int cell;
+};
+
+__device__ __forceinline__ OccValue occ_value(const SceneDev& sc, float3 p, float inv_eps) {
+    const float fi = fminf(fmaxf(floorf(p.x * sc.occ_sx) - sc.occ_ox, 0.0f), (float)(sc.Mx - 1));
+    const float fj = fminf(fmaxf(floorf(p.y * sc.occ_sy) - sc.occ_oy, 0.0f), (float)(sc.My - 1));
+    OccValue v;
+    v.cell = (int)fj * sc.Mx + (int)fi;
+    const float2 z = sc.occ[v.cell];
+    const float ur = (p.z - z.x) * inv_eps, uf = (z.y - p.z) * inv_eps;
+    const float r = fminf(fmaxf(ur, 0.0f), 1.0f), f = fminf(fmaxf(uf, 0.0f), 1.0f);
+    const float mr = r * r, mf = f * f;
+    v.m = fminf(mr, mf);
+    const float sr = mr < mf ? 1.0f : (mr == mf ? 0.5f : 0.0f);
+    const float dr = (ur >= 0.0f && ur <= 1.0f) ? 2.0f * r * inv_eps : 0.0f;
+    const float df = (uf >= 0.0f && uf <= 1.0f) ? 2.0f * f * inv_eps : 0.0f;
+    v.dzmin = -sr * dr;
+    v.dzmax = (1.0f - sr) * df;
+    return v;
 }
 
 // Conservative candidate range [k_lo, k_hi] for the closed box: every k whose
@@ -441,6 +473,22 @@ __device__ __forceinline__ void g_seg_sum8(float* x, int len, int lmax) {
         for (int c = 0; c < 8; ++c) {
             const float y = dpp_row<kRowShr | 8>(x[c]);
             x[c] = len >= 8 ? x[c] + y : x[c];
+        }
+    }
+}
+
+// g_seg_sum8 for the first 2 of the values.
+__device__ __forceinline__ void g_seg_sum2(float* x, int len, int lmax) {
+#pragma unroll
+    for (int st = 1; st < kGroup; st <<= 1) {
+        if (lmax >= st) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float y = st == 1 ? dpp_row<kRowShr | 1>(x[c])
+                                : st == 2 ? dpp_row<kRowShr | 2>(x[c])
+                                : st == 4 ? dpp_row<kRowShr | 4>(x[c]) : dpp_row<kRowShr | 8>(x[c]);
+                x[c] = len >= st ? x[c] + y : x[c];
+            }
         }
     }
 }

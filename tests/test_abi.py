@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol(L):
     assert names == set(_lib.EXPORTS)
     for n in names:
         assert hasattr(L, n), n
-    assert L.om_version() == 103
+    assert L.om_version() == 104
     assert L.om_status_str(-2) == b"unsupported shape or dtype"
 
 
@@ -104,6 +104,9 @@ def test_render_argument_errors(L):
         (_params(t_term=float("nan")), 4, _lib.OM_ERR_INVALID),
         (_params(t_term=-1.0), 4, _lib.OM_ERR_INVALID),
         (_params(mlp_bf16=3), 4, _lib.OM_ERR_INVALID),
+        (_params(occ_eps=-0.01), 4, _lib.OM_ERR_INVALID),
+        (_params(occ_eps=float("inf")), 4, _lib.OM_ERR_INVALID),
+        (_params(occ_eps=1e-45), 4, _lib.OM_ERR_INVALID),  # 1/eps overflows
         (_params(), -1, _lib.OM_ERR_INVALID),
         (_params(), 1 << 31, _lib.OM_ERR_UNSUPPORTED),
     ]
@@ -114,14 +117,14 @@ def test_render_argument_errors(L):
     missing = _lib.OmFwdOut(FAKE, 0, FAKE, FAKE, FAKE)
     assert L.om_render(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(missing), None) == _lib.OM_ERR_INVALID
     assert L.om_render(None, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(out), None) == _lib.OM_ERR_INVALID
-    g = _lib.OmGrads(FAKE, FAKE, FAKE, 0, FAKE)
+    g = _lib.OmGrads(FAKE, FAKE, FAKE, 0, FAKE, 0)
     assert L.om_render_backward(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(out), FAKE,
                                 ctypes.byref(g), None) == _lib.OM_ERR_INVALID
     # the optional per-batch sums must be float-aligned when given
     bad_bw = _lib.OmFwdOut(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE + 2)
     assert L.om_render(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(bad_bw), None) == _lib.OM_ERR_INVALID
     assert L.om_march(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(bad_bw), None) == _lib.OM_ERR_INVALID
-    g_ok = _lib.OmGrads(FAKE, FAKE, FAKE, FAKE, FAKE)
+    g_ok = _lib.OmGrads(FAKE, FAKE, FAKE, FAKE, FAKE, 0)
     assert L.om_render_backward(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(bad_bw), FAKE,
                                 ctypes.byref(g_ok), None) == _lib.OM_ERR_INVALID
     assert L.om_place_samples(h, FAKE, FAKE, 4, ctypes.byref(_params()), 0, FAKE, None) == _lib.OM_ERR_INVALID
@@ -140,12 +143,12 @@ def test_fused_training_step_validation(L):
     assert L.om_render_fwd_bwd_l2_workspace_size(n, ctypes.byref(_params(n_max=0))) == -1
     rc, h = _create(L, _desc())
     out = _lib.OmFwdOut(FAKE, FAKE, FAKE, FAKE, FAKE, 0)
-    g = _lib.OmGrads(FAKE, FAKE, FAKE, FAKE, FAKE)
+    g = _lib.OmGrads(FAKE, FAKE, FAKE, FAKE, FAKE, 0)
     step = lambda *a: L.om_render_fwd_bwd_l2(h, FAKE, FAKE, n, ctypes.byref(p), *a)  # noqa: E731
     assert step(FAKE, ctypes.byref(out), FAKE, ws - 1, None, ctypes.byref(g), None) == _lib.OM_ERR_INVALID
     assert step(FAKE, ctypes.byref(out), FAKE + 16, ws, None, ctypes.byref(g), None) == _lib.OM_ERR_INVALID
     assert step(None, ctypes.byref(out), FAKE, ws, None, ctypes.byref(g), None) == _lib.OM_ERR_INVALID
-    bad_g = _lib.OmGrads(FAKE, 0, FAKE, FAKE, FAKE)
+    bad_g = _lib.OmGrads(FAKE, 0, FAKE, FAKE, FAKE, 0)
     assert step(FAKE, ctypes.byref(out), FAKE, ws, None, ctypes.byref(bad_g), None) == _lib.OM_ERR_INVALID
     assert "workspace" in L.om_last_error().decode() or "gradient" in L.om_last_error().decode()
     L.om_scene_destroy(h)
@@ -163,6 +166,23 @@ def test_occupancy_mips_validation(L):
     assert L.om_build_occupancy_mips(h, FAKE + 4, 4096, 1, None) == _lib.OM_ERR_INVALID        # misaligned
     assert L.om_build_occupancy_mips(h, None, 0, 0, None) == 0                              # detach
     L.om_scene_destroy(h)
+
+
+def test_occ_interval_loss_validation(L):
+    assert L.om_occ_interval_loss(FAKE, 0, 1.0, FAKE, FAKE, None) == _lib.OM_ERR_INVALID
+    assert L.om_occ_interval_loss(None, 4, 1.0, FAKE, FAKE, None) == _lib.OM_ERR_INVALID
+    assert L.om_occ_interval_loss(FAKE, 4, float("nan"), FAKE, FAKE, None) == _lib.OM_ERR_INVALID
+    assert L.om_occ_interval_loss(FAKE, 4, 1.0, None, None, None) == 0  # nothing requested: no device work
+
+
+def test_struct_layouts_match_header():
+    """om_params ends with occ_eps; om_grads with occ."""
+    hdr = open(os.path.join(ROOT, "include", "omerf.h")).read()
+    for name, cls in (("om_params", _lib.OmParams), ("om_grads", _lib.OmGrads)):
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), hdr, re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        fields = re.findall(r"(\w+)(?:\[\d+\])?;", body)
+        assert fields == [f for f, _ in cls._fields_], name
 
 
 def test_fwd_out_layout_matches_header():

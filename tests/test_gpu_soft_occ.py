@@ -1,0 +1,109 @@
+"""Soft occupancy (Sec. 4.1, Eq. 5, 6, 8 with epsilon > 0) on the GPU
+against the float64 oracle: forward colours, features and transmittance
+(float32 bar 1e-5, bfloat16 storage against the oracle of the rounded
+scene), gradients into features, MLP and the occupancy bounds (the
+backward bars of test_gpu_backward), and the interval-span loss.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2404_09531_amd as om
+import scenegen
+from tests.gpu_util import bf16_round, log, rays_to, upload_scene
+from tests.test_gpu_backward import SOURCES, _check_against_oracle
+
+pytestmark = pytest.mark.gpu
+
+BG = (0.25, 0.5, 0.75)
+EPS = 0.01  # the tiny scene's intervals are 0.06 wide: a third of each lies in a buffer zone
+
+
+@pytest.fixture(scope="module")
+def tiny_soft():
+    sc = scenegen.make_scene(scenegen.TINY)
+    pert = scenegen.perturb_scene(sc, 0.05, seed=2)
+    o, d = scenegen.oblique_rays(512, seed=3)
+    target = oracle.oracle_render(pert, o, d, oracle.RenderParams(n_max=64, c_bg=BG, occ_eps=EPS),
+                                  keep_k=False)["C"].astype(np.float32)
+    return sc, o, d, target
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_soft_forward_matches_oracle(tiny_soft, dtype):
+    sc, o, d, _ = tiny_soft
+    log(f"test_soft_forward_matches_oracle: {dtype}, eps={EPS}")
+    ref_sc = sc if dtype == torch.float32 else {**sc, **{k: bf16_round(sc[k]) for k in SOURCES}}
+    scene, _ = upload_scene(sc, dtype=dtype)
+    og, dg = rays_to(o, d)
+    for t_term in (0.0, 1e-2):
+        res = om.render(scene, og, dg, n_max=64, c_bg=BG, mlp_bf16=0, occ_eps=EPS, t_term=t_term)
+        ref = oracle.oracle_render(ref_sc, o, d, oracle.RenderParams(n_max=64, c_bg=BG, occ_eps=EPS, t_term=t_term),
+                                   keep_k=False)
+        ne = res["n_eval"].cpu().numpy()
+        same = ne == ref["n_eval"]
+        assert same.mean() > 0.99
+        for key in ("C", "F", "T"):
+            err = np.abs(res[key].double().cpu().numpy()[same] - ref[key][same]).max()
+            log(f"  t_term={t_term}: max |{key} - oracle| = {err:.2e}")
+            assert err <= 1e-5, key
+    # the soft mask changes the colours (it is not a no-op)
+    hard = oracle.oracle_render(ref_sc, o, d, oracle.RenderParams(n_max=64, c_bg=BG), keep_k=False)
+    assert np.abs(hard["C"] - ref["C"]).max() > 1e-3
+
+
+@pytest.mark.parametrize("batch_wv", [False, True])
+def test_soft_backward_matches_oracle(tiny_soft, batch_wv):
+    sc, o, d, target = tiny_soft
+    log(f"test_soft_backward_matches_oracle: batch sums {batch_wv}")
+    scene, t = upload_scene(sc)
+    og, dg = rays_to(o, d)
+    tg = torch.from_numpy(target).to(og.device)
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG, occ_eps=EPS, batch_wv=batch_wv)
+    dC, loss = om.l2_loss_grad(res["C"], tg)
+    grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp", "occ")}
+    om.render_backward(scene, og, dg, res, dC, grads, n_max=64, c_bg=BG, occ_eps=EPS)
+    g = {k: v.double().cpu().numpy() for k, v in grads.items()}
+    ref_loss, _, ref = oracle.oracle_loss_and_grads(sc, o, d, oracle.RenderParams(n_max=64, c_bg=BG, occ_eps=EPS),
+                                                    target.astype(np.float64))
+    assert abs(loss.item() - ref_loss) <= 1e-3 * ref_loss
+    _check_against_oracle(sc, g, ref)
+    cells, rows = ref["occ"]
+    go = g["occ"].reshape(-1, 2)
+    scale = np.abs(rows).max()
+    assert scale > 0
+    excess = np.abs(go[cells] - rows) - (1e-3 * np.abs(rows) + 2e-6 * scale)
+    log(f"  occupancy gradient: {len(cells)} cells, max |g| {scale:.3e}, worst excess {excess.max() / scale:.2e}")
+    assert excess.max() <= 0
+    mask = np.ones(go.shape[0], bool)
+    mask[cells] = False
+    assert np.all(go[mask] == 0)
+
+
+def test_soft_render_fn_returns_occupancy_gradient(tiny_soft):
+    sc, o, d, target = tiny_soft
+    log("test_soft_render_fn_returns_occupancy_gradient")
+    scene, t = upload_scene(sc)
+    og, dg = rays_to(o, d)
+    masters = [t[k].clone().requires_grad_(True) for k in (*SOURCES, "mlp", "occ")]
+    C, *_ = om.RenderFn.apply(scene, og, dg, dict(n_max=64, c_bg=BG, occ_eps=EPS), *masters)
+    loss = ((C - torch.from_numpy(target).to(og.device)) ** 2).mean()
+    loss.backward()
+    _, _, ref = oracle.oracle_loss_and_grads(sc, o, d, oracle.RenderParams(n_max=64, c_bg=BG, occ_eps=EPS),
+                                             target.astype(np.float64))
+    cells, rows = ref["occ"]
+    go = masters[-1].grad.double().cpu().numpy().reshape(-1, 2)
+    assert np.abs(go[cells] - rows).max() <= 1e-3 * np.abs(rows).max()
+
+
+def test_occ_interval_loss_matches_eq5():
+    sc = scenegen.make_scene(scenegen.TOWERS)
+    occ = torch.from_numpy(sc["occ"]).cuda()
+    log("test_occ_interval_loss_matches_eq5: 512 x 512 cells")
+    grad = torch.full_like(occ, 0.5)
+    w = float(np.float32(0.3))  # the weight crosses the boundary as a float32
+    loss = om.occ_interval_loss(occ, weight=w, grad=grad)
+    ref_loss, ref_grad = oracle.occ_interval_loss(sc["occ"])
+    assert loss.item() == pytest.approx(w * ref_loss, rel=1e-12)
+    np.testing.assert_allclose(grad.double().cpu().numpy(), 0.5 + w * ref_grad, rtol=1e-6, atol=1e-7)
