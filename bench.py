@@ -36,8 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--t-term", type=float, default=0.0)
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and fwd+bwd forms")
-    ap.add_argument("--forms", default="bf16_render,fp32_fwd_bwd,bf16_render_4k_x8,high_altitude_mips,"
-                                       "towers_bf16_fwd_bwd",
+    ap.add_argument("--forms", default="bf16_render,fp32_fwd_bwd,fp32_fwd_bwd_soft_occ,bf16_render_4k_x8,"
+                                       "high_altitude_mips,towers_bf16_fwd_bwd",
                     help="comma-separated subset of forms to run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--crop", type=int, default=256, help="side of the centre crop timed on the CPU oracle")
@@ -121,8 +121,11 @@ def form_bf16_render(om, torch, t, og, dg, out, kw, samples, n, a):
             "max_abs_vs_fp32_render": float((outb["C"] - out["C"]).abs().max().item())}
 
 
-def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a):
-    """float32 forward + L2 loss gradient + backward on 2^18 rays of 16 cameras."""
+def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a, occ_eps=0.0):
+    """float32 forward + L2 loss gradient + backward on 2^18 rays of 16 cameras
+    (with occ_eps > 0: the soft occupancy of Eq. 6/8 and the gradient of
+    the occupancy bounds)."""
+    kw = dict(kw, occ_eps=occ_eps)
     dev = out["C"].device
     cfg2, rec2 = scenegen.workload("train-2^18")
     o2, d2 = scenegen.make_rays(rec2)
@@ -133,7 +136,8 @@ def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a):
     g = torch.Generator(device=dev)
     g.manual_seed(2)
     target = (out2["C"] + 0.05 * torch.randn(out2["C"].shape, device=dev, generator=g)).contiguous()
-    grads = {k: torch.zeros(t[k].shape, device=dev) for k in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp")}
+    keys = ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp") + (("occ",) if occ_eps > 0 else ())
+    grads = {k: torch.zeros(t[k].shape, device=dev) for k in keys}
     dC = torch.empty_like(out2["C"])
     fwd = lambda: om.render_into(scene, o2g, d2g, out2, **kw)  # noqa: E731
     lossg = lambda: om.l2_loss_grad(out2["C"], target, dL_dC=dC, with_loss=False)  # noqa: E731
@@ -142,7 +146,8 @@ def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a):
     tot, (f_ms, l_ms, b_ms) = time_stages([fwd, lossg, bwd], steps, a.warmup, torch)
     ms = tot / steps
     s2 = int(out2["n_eval"].sum().item())
-    return {"workload": "2^18 rays, 16 cameras 1920x1080, oblique scene", "rays": n2,
+    return {"workload": "2^18 rays, 16 cameras 1920x1080, oblique scene" + (f", soft occupancy eps {occ_eps}"
+                                                                             if occ_eps > 0 else ""), "rays": n2,
             "Mrays_per_s": round(n2 / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4),
             "fwd_ms": round(f_ms, 4), "loss_ms": round(l_ms, 4), "bwd_ms": round(b_ms, 4),
             "samples_per_ray": round(s2 / n2, 1), "targets": "forward colours + N(0, 0.05), seeded"}
@@ -303,6 +308,8 @@ def main():
         forms["bf16_render"] = form_bf16_render(om, torch, t, og, dg, out, kw, samples, n, a)
     if "fp32_fwd_bwd" in want:
         forms["fp32_fwd_bwd"] = form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a)
+    if "fp32_fwd_bwd_soft_occ" in want:
+        forms["fp32_fwd_bwd_soft_occ"] = form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a, occ_eps=0.01)
     if "bf16_render_4k_x8" in want:
         forms["bf16_render_4k_x8"] = form_bf16_4k(om, scenegen, torch, t, kw, a)
     if "high_altitude_mips" in want:
