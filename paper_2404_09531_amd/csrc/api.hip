@@ -101,7 +101,6 @@ int validate_desc(const om_scene_desc* d, SceneDev* out) {
     SceneDev s;
     s.mips = nullptr;  // no pyramid until om_build_occupancy_mips attaches one
     s.mip_levels = 0;
-    for (int l = 0; l <= kMaxMipLevels; ++l) s.mip_off[l] = 0;
     s.grid = d->grid;
     s.pxy = d->plane_xy;
     s.pxz = d->plane_xz;
@@ -232,11 +231,6 @@ int om_build_occupancy_mips(om_scene* scene, void* mips, int64_t mips_bytes, int
         return fail(OM_ERR_INVALID, "mips holds %lld bytes, %lld needed", (long long)mips_bytes, (long long)need);
     hipError_t e = launch_occ_pyramid(dev.occ, dev.Mx, dev.My, static_cast<float2*>(mips), levels, (hipStream_t)stream);
     if (e != hipSuccess) return hip_status(e, "om_build_occupancy_mips");
-    int off = 0;
-    for (int l = 1; l <= levels; ++l) {
-        dev.mip_off[l] = off;
-        off += (dev.Mx >> l) * (dev.My >> l);
-    }
     dev.mips = static_cast<const float2*>(mips);
     dev.mip_levels = levels;
     return ok();

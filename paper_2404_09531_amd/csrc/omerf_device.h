@@ -41,12 +41,12 @@ struct SceneDev {
     float lo0, lo1, lo2, hi0, hi1, hi2;
     float occ_sx, occ_sy, occ_ox, occ_oy;  // cell = floor(p * s) - o
     AxisMap gx, gy, gz, px, py, pz;
-    // Optional occupancy pyramid: level l (1..mip_levels) at mips + mip_off[l],
-    // (My >> l) x (Mx >> l) blocks of 2^l x 2^l cells, each holding
-    // (min z_min, max z_max) over its non-empty cells.
+    // Optional occupancy pyramid: levels l = 1..mip_levels one after the
+    // other, (My >> l) x (Mx >> l) blocks of 2^l x 2^l cells each holding
+    // (min z_min, max z_max) over its non-empty cells; level l starts at
+    // entry (Mx My - (Mx >> (l-1)) (My >> (l-1))) / 3 (a geometric sum).
     const float2* mips;
     int mip_levels;
-    int mip_off[kMaxMipLevels + 1];
 };
 
 struct RayParams {
@@ -116,7 +116,8 @@ __device__ __forceinline__ bool column_maybe(const SceneDev& sc, float3 o, float
     const int j0 = (int)fminf(fmaxf(floorf(y0 * sc.occ_sy) - sc.occ_oy, 0.0f), my) >> lv;
     const int j1 = (int)fminf(fmaxf(floorf(y1 * sc.occ_sy) - sc.occ_oy, 0.0f), my) >> lv;
     if (i1 - i0 > 2 || j1 - j0 > 2) return true;
-    const float2* z_of = lv == 0 ? sc.occ : sc.mips + sc.mip_off[lv];
+    const float2* z_of =
+        lv == 0 ? sc.occ : sc.mips + (sc.Mx * sc.My - (sc.Mx >> (lv - 1)) * (sc.My >> (lv - 1))) / 3;
     const int w = sc.Mx >> lv;
     bool maybe = false;
     for (int j = j0; j <= j1; ++j)
