@@ -15,7 +15,8 @@ What it computes (Oblique-MERF, arXiv 2404.09531):
   their activations (Eq. 3) -- ``field.py``;
 * volume-rendering quadrature (Eq. 1), deferred MLP (Eq. 4), the soft
   occupancy value (Eq. 6, 8), the L2 loss with its float64 autograd
-  gradient and the interval-span loss (Eq. 5) -- ``render.py``.
+  gradient, the interval-span loss (Eq. 5), the view-direction encoding of
+  the deferred MLP and the view-smoothness loss (Eq. 9-10) -- ``render.py``.
 
 Precision: float64 throughout, except the placement predicate, which is
 defined in binary32 (see ``placement.py``) so that both sides take the
@@ -28,11 +29,12 @@ from .placement import (K_CAP, box_k_interval, cell_index, lattice_points,
                         place_samples, accept_mask)
 from .field import interp_features, activations, corner_weights_1d
 from .render import (RenderParams, oracle_render, oracle_loss_and_grads,
-                     mlp_forward, composite, occupancy_value, occ_interval_loss)
+                     mlp_forward, composite, occupancy_value, occ_interval_loss,
+                     encode_dir, smooth_loss)
 
 __all__ = [
     "K_CAP", "box_k_interval", "cell_index", "lattice_points", "place_samples",
     "accept_mask", "interp_features", "activations", "corner_weights_1d",
     "RenderParams", "oracle_render", "oracle_loss_and_grads", "mlp_forward",
-    "composite", "occupancy_value", "occ_interval_loss",
+    "composite", "occupancy_value", "occ_interval_loss", "encode_dir", "smooth_loss",
 ]

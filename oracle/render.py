@@ -16,10 +16,14 @@ Readings where the paper is silent or ambiguous:
 * Background: C = sum w c^d + [n_placed > 0] G(F, d) + T_n c_bg, where T_n
   is the transmittance after the last evaluated sample and c_bg a call
   parameter.  A ray with no sample returns exactly c_bg.
-* G is 10 -> 16 -> 16 -> 3 with ReLU, ReLU, sigmoid; input order
-  [sum w c^d (3), sum w f (4), d (3)] with the raw unit direction d.
-  Parameters are packed [W1 (16x10), b1, W2 (16x16), b2, W3 (3x16), b3],
-  weights row-major (out, in).
+* G is N -> 16 -> 16 -> 3 with ReLU, ReLU, sigmoid; input order
+  [sum w c^d (3), sum w f (4), enc(d)].  enc(d) is the raw unit direction
+  d (N = 10), or, with L view-direction frequencies (the paper's deferred
+  MLP uses four, as in MERF), [d, sin(2^0 d), cos(2^0 d), ...,
+  sin(2^(L-1) d), cos(2^(L-1) d)] with each term a 3-vector
+  (N = 7 + 3 (1 + 2 L); 34 for L = 4).  Parameters are packed
+  [W1 (16xN), b1, W2 (16x16), b2, W3 (3x16), b3], weights row-major
+  (out, in); N follows from the packed size.
 * Early ray termination (not in the paper): with t_term > 0 a ray stops
   after the first sample whose following transmittance T_{i+1} < t_term;
   t_term = 0 never stops.
@@ -67,6 +71,29 @@ def occupancy_value(z: torch.Tensor, zmin: torch.Tensor, zmax: torch.Tensor, eps
     return torch.minimum(rise, fall)
 
 
+def smooth_loss(F: np.ndarray, d: np.ndarray, perturb: np.ndarray, mlp: np.ndarray, freqs: int = 0,
+                weight: float = 1.0):
+    """View-smoothness regulariser of Sec. 4.2, Eq. 9-10:
+    L = weight * sum_r sum_p S(d_r, s_rp) ||G(F_r, s_rp) - G(F_r, d_r)||^2
+    with s_rp = d_r + delta_rp and S the cosine similarity.  The Gaussian
+    perturbations delta ~ N(0, Sigma) of Eq. 9 are drawn by the caller and
+    passed in as `perturb` [R, P, 3]; s is used as it is (not renormalised),
+    as written.  F [R, 7] (the composited features of Eq. 4), d [R, 3].
+    Returns (loss, dL/dF [R, 7], dL/dmlp [n_params]) in float64."""
+    Ft = torch.from_numpy(np.asarray(F, dtype=np.float64)).requires_grad_(True)
+    W = torch.from_numpy(np.asarray(mlp, dtype=np.float64)).requires_grad_(True)
+    dt = torch.from_numpy(np.asarray(d, dtype=np.float64))
+    st = dt[:, None, :] + torch.from_numpy(np.asarray(perturb, dtype=np.float64))
+    g_d = mlp_forward(torch.cat([Ft, encode_dir(dt, freqs)], dim=1), W)
+    r, p = st.shape[0], st.shape[1]
+    Fp = Ft[:, None, :].expand(r, p, 7)
+    g_s = mlp_forward(torch.cat([Fp, encode_dir(st, freqs)], dim=2).reshape(r * p, -1), W).reshape(r, p, 3)
+    cos = (st * dt[:, None, :]).sum(-1) / (torch.linalg.norm(st, dim=-1) * torch.linalg.norm(dt, dim=-1)[:, None])
+    loss = weight * (cos * ((g_s - g_d[:, None, :]) ** 2).sum(-1)).sum()
+    gF, gW = torch.autograd.grad(loss, [Ft, W])
+    return float(loss.item()), gF.numpy(), gW.numpy()
+
+
 def occ_interval_loss(occ: np.ndarray):
     """Interval-span loss of Sec. 4.1, Eq. 5: sum over the grid points of
     (z_max - z_min)^2, and its gradient [My, Mx, 2] (float64)."""
@@ -76,11 +103,28 @@ def occ_interval_loss(occ: np.ndarray):
     return float(np.sum(span * span)), grad
 
 
+def mlp_input_width(n_params: int) -> int:
+    """N of the packed N -> 16 -> 16 -> 3 parameter vector."""
+    rest = 16 + 16 * 16 + 16 + 3 * 16 + 3
+    if (n_params - rest) % 16:
+        raise ValueError(f"{n_params} is not an N x 16 x 16 x 3 parameter count")
+    return (n_params - rest) // 16
+
+
+def encode_dir(d: torch.Tensor, freqs: int) -> torch.Tensor:
+    """View-direction input of the deferred MLP (see the module docstring)."""
+    parts = [d]
+    for k in range(freqs):
+        parts += [torch.sin(d * 2.0 ** k), torch.cos(d * 2.0 ** k)]
+    return torch.cat(parts, dim=-1)
+
+
 def unpack_mlp(mlp):
     """Split the packed parameter vector into (W1, b1, W2, b2, W3, b3)."""
     out = []
     off = 0
-    for fin, fout in zip(MLP_SIZES[:-1], MLP_SIZES[1:]):
+    sizes = (mlp_input_width(mlp.shape[0]),) + MLP_SIZES[1:]
+    for fin, fout in zip(sizes[:-1], sizes[1:]):
         out.append(mlp[off:off + fout * fin].reshape(fout, fin))
         off += fout * fin
         out.append(mlp[off:off + fout])
@@ -194,7 +238,8 @@ def _render_chunk(scene, o, d, prm: RenderParams, grad: bool, mlp_leaf=None):
         mask = torch.zeros(r, s_dim, dtype=torch.float64).index_put((ri, si), m_s)
     cd_acc, f_acc, T, n_eval = composite(tau, cd, f, n_placed, prm.delta, prm.t_term, mask)
     mlp = mlp_leaf if mlp_leaf is not None else torch.from_numpy(np.asarray(scene["mlp"], dtype=np.float64))
-    x = torch.cat([cd_acc, f_acc, torch.from_numpy(d.astype(np.float64))], dim=1)
+    freqs = int(scene.get("dir_freqs", 0))
+    x = torch.cat([cd_acc, f_acc, encode_dir(torch.from_numpy(d.astype(np.float64)), freqs)], dim=1)
     gate = torch.from_numpy(n_placed > 0)
     g = mlp_forward(x, mlp)
     g = torch.where(gate[:, None], g, torch.zeros_like(g))

@@ -46,6 +46,17 @@ DELTA = 0.25 / 512.0
 CHANNELS = 8
 MLP_SHAPE = (10, 16, 16, 3)
 MLP_NPARAMS = 16 * 10 + 16 + 16 * 16 + 16 + 3 * 16 + 3  # 499
+
+
+def mlp_inputs(dir_freqs: int) -> int:
+    """Deferred-MLP input width: 7 features + the view direction, raw (3) or
+    with `dir_freqs` sine/cosine frequencies per component (3 + 6 freqs)."""
+    return 7 + 3 * (1 + 2 * dir_freqs)
+
+
+def mlp_nparams(dir_freqs: int) -> int:
+    n = mlp_inputs(dir_freqs)
+    return 16 * n + 16 + 16 * 16 + 16 + 3 * 16 + 3
 BASE_HEIGHT = 0.12
 HEIGHT_AMP = 0.05
 DENSITY_PEAK = 8.0
@@ -65,6 +76,7 @@ class SceneConfig:
     n_buildings: int = 0                # box buildings (footprint 2-8 cells)
     building_max_h: float = 0.2
     tower_fraction: float = 0.0         # fraction of cells covered by towers
+    dir_freqs: int = 0                  # view-direction frequencies of the deferred MLP input
     seed: int = 0
     name: str = "custom"
 
@@ -160,16 +172,17 @@ def _towers(m: int, fraction: float, seq) -> np.ndarray:
     return thick
 
 
-def _mlp_params(seq) -> np.ndarray:
+def _mlp_params(seq, dir_freqs: int = 0) -> np.ndarray:
     """Xavier-uniform weights, biases U(-0.1, 0.1); packed W1 b1 W2 b2 W3 b3."""
     g = np.random.Generator(np.random.PCG64(seq))
+    shape = (mlp_inputs(dir_freqs),) + MLP_SHAPE[1:]
     parts = []
-    for fin, fout in zip(MLP_SHAPE[:-1], MLP_SHAPE[1:]):
+    for fin, fout in zip(shape[:-1], shape[1:]):
         a = math.sqrt(6.0 / (fin + fout))
         parts.append(g.uniform(-a, a, (fout, fin)).reshape(-1))
         parts.append(g.uniform(-0.1, 0.1, fout))
     out = np.concatenate(parts).astype(np.float32)
-    assert out.size == MLP_NPARAMS
+    assert out.size == mlp_nparams(dir_freqs)
     return out
 
 
@@ -238,7 +251,7 @@ def make_scene(cfg: SceneConfig, seed: Optional[int] = None) -> Dict[str, np.nda
         p[..., 0] *= np.float32(0.1)
         planes[name] = p
 
-    return dict(grid=grid, occ=occ, mlp=_mlp_params(s_mlp),
+    return dict(grid=grid, occ=occ, mlp=_mlp_params(s_mlp, cfg.dir_freqs), dir_freqs=cfg.dir_freqs,
                 box_lo=np.array(BOX_LO), box_hi=np.array(BOX_HI), **planes)
 
 

@@ -33,6 +33,8 @@ PIN_TESTS = [
     pins.test_soft_mask_single_sample_hand_value,
     lambda: pins.test_occupancy_value_matches_paper_cases(2.0),
     pins.test_occ_interval_loss_hand_example,
+    pins.test_direction_encoding_hand_values,
+    pins.test_smooth_loss_hand_example,
 ]
 
 
@@ -156,6 +158,29 @@ def _span_not_squared(occ):
     return float(np.sum(np.abs(span))), np.stack([-np.sign(span), np.sign(span)], axis=-1)
 
 
+def _encode_linear_freqs(d, freqs):
+    parts = [d]
+    for k in range(freqs):
+        parts += [torch.sin(d * (k + 1)), torch.cos(d * (k + 1))]
+    return torch.cat(parts, dim=-1)
+
+
+def _smooth_no_cos(orig):
+    """Drops the cosine weighting of Eq. 10 (every perturbation weighs 1)."""
+    def f(F, d, perturb, mlp, freqs=0, weight=1.0):
+        Ft = torch.from_numpy(np.asarray(F, dtype=np.float64))
+        W = torch.from_numpy(np.asarray(mlp, dtype=np.float64))
+        dt = torch.from_numpy(np.asarray(d, dtype=np.float64))
+        st = dt[:, None, :] + torch.from_numpy(np.asarray(perturb, dtype=np.float64))
+        g_d = render.mlp_forward(torch.cat([Ft, render.encode_dir(dt, freqs)], dim=1), W)
+        r, p = st.shape[0], st.shape[1]
+        x = torch.cat([Ft[:, None, :].expand(r, p, 7), render.encode_dir(st, freqs)], dim=2).reshape(r * p, -1)
+        g_s = render.mlp_forward(x, W).reshape(r, p, 3)
+        loss = weight * ((g_s - g_d[:, None, :]) ** 2).sum()
+        return float(loss), np.zeros_like(np.asarray(F)), np.zeros_like(np.asarray(mlp))
+    return f
+
+
 def _both(mp, name, new):
     """Patch a field-module function in every module that bound it."""
     mp.setattr(field, name, new)
@@ -179,6 +204,10 @@ MUTANTS = {
                                         mp.setattr(oracle, "occupancy_value", _occ_q1(render.occupancy_value))),
     "occupancy mask ignored": lambda mp: (mp.setattr(render, "occupancy_value", _occ_ones),
                                           mp.setattr(oracle, "occupancy_value", _occ_ones)),
+    "encoding frequencies k, not 2^k": lambda mp: (mp.setattr(render, "encode_dir", _encode_linear_freqs),
+                                                   mp.setattr(oracle, "encode_dir", _encode_linear_freqs)),
+    "smoothness without cosine weight": lambda mp: (mp.setattr(render, "smooth_loss", _smooth_no_cos(None)),
+                                                    mp.setattr(oracle, "smooth_loss", _smooth_no_cos(None))),
     "interval loss not squared": lambda mp: (mp.setattr(render, "occ_interval_loss", _span_not_squared),
                                              mp.setattr(oracle, "occupancy_value", render.occupancy_value),
                                              mp.setattr(oracle, "occ_interval_loss", _span_not_squared)),

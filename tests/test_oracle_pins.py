@@ -530,3 +530,93 @@ def test_occ_interval_loss_hand_example():
     assert loss == pytest.approx(0.01 + 0.04 + 0.0 + 0.0025, rel=1e-12)
     np.testing.assert_allclose(grad[..., 1], [[0.2, 0.4], [0.0, -0.1]], atol=1e-15)
     np.testing.assert_allclose(grad[..., 0], [[-0.2, -0.4], [0.0, 0.1]], atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# View-direction encoding and view-smoothness loss (Sec. 4.2, Eq. 9-10)
+# ---------------------------------------------------------------------------
+
+def test_direction_encoding_hand_values():
+    """Four frequencies (the paper's deferred MLP, as in MERF): [d, sin(2^k d),
+    cos(2^k d)] for k = 0..3, 27 values, at a hand-checked direction."""
+    d = torch.tensor([[0.6, 0.0, -0.8]], dtype=torch.float64)
+    e = oracle.encode_dir(d, 4).numpy()[0]
+    assert e.shape == (27,)
+    np.testing.assert_allclose(e[:3], [0.6, 0.0, -0.8], rtol=0, atol=0)
+    np.testing.assert_allclose(e[3:6], [math.sin(0.6), 0.0, math.sin(-0.8)], rtol=1e-15)
+    np.testing.assert_allclose(e[6:9], [math.cos(0.6), 1.0, math.cos(-0.8)], rtol=1e-15)
+    np.testing.assert_allclose(e[21:24], [math.sin(4.8), 0.0, math.sin(-6.4)], rtol=1e-14)
+    np.testing.assert_allclose(e[24:27], [math.cos(4.8), 1.0, math.cos(-6.4)], rtol=1e-14)
+
+
+def _dir_mlp(n_in):
+    """An MLP that reads only the view direction's x through one hidden path:
+    h1_0 = relu(2 d_x + 0.5), h2_0 = relu(h1_0), G = sigmoid(h2_0 - 1) on all
+    three outputs."""
+    w1 = np.zeros((16, n_in))
+    w1[0, 7] = 2.0
+    b1 = np.zeros(16)
+    b1[0] = 0.5
+    w2 = np.zeros((16, 16))
+    w2[0, 0] = 1.0
+    w3 = np.zeros((3, 16))
+    w3[:, 0] = 1.0
+    b3 = np.full(3, -1.0)
+    return np.concatenate([w1.ravel(), b1, w2.ravel(), np.zeros(16), w3.ravel(), b3])
+
+
+def test_smooth_loss_hand_example():
+    """One ray, two perturbations: L = sum_p cos(d, s_p) * 3 (G(s_p) - G(d))^2
+    with G(v) = sigmoid(relu(2 v_x + 0.5) - 1), worked out by hand."""
+    F = np.zeros((1, 7))
+    d = np.array([[0.0, 0.0, -1.0]])
+    pert = np.array([[[0.3, 0.0, 0.0], [-0.1, 0.2, 0.0]]])
+    sig = lambda x: 1 / (1 + math.exp(-x))  # noqa: E731
+    g = lambda vx: sig(max(2 * vx + 0.5, 0.0) - 1.0)  # noqa: E731
+    want = 0.0
+    for dx, dy, dz in pert[0]:
+        s = np.array([dx, dy, -1.0 + dz])
+        cos = -s[2] / np.linalg.norm(s)
+        want += cos * 3 * (g(s[0]) - g(0.0)) ** 2
+    loss, gF, gW = oracle.smooth_loss(F, d, pert, _dir_mlp(10), freqs=0, weight=1.0)
+    assert loss == pytest.approx(want, rel=1e-13)
+    np.testing.assert_allclose(gF, 0.0, atol=0)  # F enters only weights that are zero
+    assert np.abs(gW).max() > 0
+
+
+def test_smooth_loss_zero_cases():
+    """No perturbation, or an MLP blind to the direction: L = 0 and no gradient."""
+    rng = np.random.default_rng(3)
+    F = rng.normal(size=(5, 7))
+    d = rng.normal(size=(5, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    mlp = rng.normal(0, 0.4, 16 * 34 + 339)
+    loss, gF, gW = oracle.smooth_loss(F, d, np.zeros((5, 3, 3)), mlp, freqs=4)
+    assert loss == 0.0 and not gF.any() and not gW.any()
+    blind = mlp.copy()
+    blind[:16 * 34].reshape(16, 34)[:, 7:] = 0.0
+    loss, gF, gW = oracle.smooth_loss(F, d, rng.normal(0, 0.3, (5, 3, 3)), blind, freqs=4)
+    assert loss == 0.0
+
+
+@pytest.mark.parametrize("freqs", [0, 4])
+def test_smooth_loss_gradient_matches_fd(freqs):
+    rng = np.random.default_rng(8)
+    n_in = 7 + 3 * (1 + 2 * freqs)
+    F = rng.uniform(0, 1, (6, 7))
+    d = rng.normal(size=(6, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    pert = rng.normal(0, 0.3, (6, 4, 3))
+    mlp = rng.normal(0, 0.5, 16 * n_in + 339)
+    loss, gF, gW = oracle.smooth_loss(F, d, pert, mlp, freqs=freqs, weight=0.7)
+    h = 1e-6
+    for arr, g, picks in ((F, gF, [(0, 0), (3, 5), (5, 6)]), (mlp, gW, [(i,) for i in rng.choice(mlp.size, 8, replace=False)])):
+        for idx in picks:
+            vals = []
+            for s in (+1, -1):
+                a = arr.copy()
+                a[idx] += s * h
+                args = (a, d, pert, mlp) if arr is F else (F, d, pert, a)
+                vals.append(oracle.smooth_loss(*args, freqs=freqs, weight=0.7)[0])
+            fd = (vals[0] - vals[1]) / (2 * h)
+            assert abs(fd - g[idx]) <= 1e-6 * max(abs(fd), 1e-3), (idx, fd, g[idx])
