@@ -82,6 +82,13 @@ def smooth_loss(F: np.ndarray, d: np.ndarray, perturb: np.ndarray, mlp: np.ndarr
     Returns (loss, dL/dF [R, 7], dL/dmlp [n_params]) in float64."""
     Ft = torch.from_numpy(np.asarray(F, dtype=np.float64)).requires_grad_(True)
     W = torch.from_numpy(np.asarray(mlp, dtype=np.float64)).requires_grad_(True)
+    loss = _smooth_term(Ft, np.asarray(d), np.asarray(perturb), W, freqs, weight)
+    gF, gW = torch.autograd.grad(loss, [Ft, W])
+    return float(loss.item()), gF.numpy(), gW.numpy()
+
+
+def _smooth_term(Ft: torch.Tensor, d: np.ndarray, perturb: np.ndarray, W: torch.Tensor, freqs: int, weight: float):
+    """The float64 graph of the smoothness loss of Eq. 9-10 (see smooth_loss)."""
     dt = torch.from_numpy(np.asarray(d, dtype=np.float64))
     st = dt[:, None, :] + torch.from_numpy(np.asarray(perturb, dtype=np.float64))
     g_d = mlp_forward(torch.cat([Ft, encode_dir(dt, freqs)], dim=1), W)
@@ -89,9 +96,7 @@ def smooth_loss(F: np.ndarray, d: np.ndarray, perturb: np.ndarray, mlp: np.ndarr
     Fp = Ft[:, None, :].expand(r, p, 7)
     g_s = mlp_forward(torch.cat([Fp, encode_dir(st, freqs)], dim=2).reshape(r * p, -1), W).reshape(r, p, 3)
     cos = (st * dt[:, None, :]).sum(-1) / (torch.linalg.norm(st, dim=-1) * torch.linalg.norm(dt, dim=-1)[:, None])
-    loss = weight * (cos * ((g_s - g_d[:, None, :]) ** 2).sum(-1)).sum()
-    gF, gW = torch.autograd.grad(loss, [Ft, W])
-    return float(loss.item()), gF.numpy(), gW.numpy()
+    return weight * (cos * ((g_s - g_d[:, None, :]) ** 2).sum(-1)).sum()
 
 
 def occ_interval_loss(occ: np.ndarray):
@@ -277,12 +282,15 @@ def oracle_render(scene: Dict[str, np.ndarray], o: np.ndarray, d: np.ndarray, pr
     return out
 
 
-def oracle_loss_and_grads(scene, o, d, prm: RenderParams, target: np.ndarray):
-    """L2 loss (mean over rays x 3) and its float64 gradient.
+def oracle_loss_and_grads(scene, o, d, prm: RenderParams, target: np.ndarray, smooth: Optional[dict] = None):
+    """L2 loss (mean over rays x 3) and its float64 gradient.  With
+    smooth = dict(perturb=[n, P, 3], weight=w) the loss also holds the
+    view-smoothness term of Eq. 9-10 on the rays' composited features F
+    (the training objective of Eq. 10 without its other regularisers).
 
     Returns (loss, C, grads) where grads[src] = (flat row indices, [U, 8]
     gradient rows) for the four feature sources and grads['mlp'] is the
-    dense [499] gradient; with prm.occ_eps > 0 also grads['occ'] = (flat
+    dense [n_params] gradient; with prm.occ_eps > 0 also grads['occ'] = (flat
     cell indices, [U, 2] gradient of (z_min, z_max))."""
     o = np.ascontiguousarray(o, dtype=np.float32)
     d = np.ascontiguousarray(d, dtype=np.float32)
@@ -291,6 +299,9 @@ def oracle_loss_and_grads(scene, o, d, prm: RenderParams, target: np.ndarray):
     C = res["C"]
     tgt = torch.from_numpy(np.asarray(target, dtype=np.float64))
     loss = torch.mean((C - tgt) ** 2)
+    if smooth is not None:
+        loss = loss + _smooth_term(res["F"], d, smooth["perturb"], mlp_leaf, int(scene.get("dir_freqs", 0)),
+                                   float(smooth["weight"]))
     tables = res["tables"]
     leaves = [tables.leaves[s] for s in SOURCES] + [mlp_leaf]
     if res["occ_leaf"] is not None:

@@ -297,6 +297,17 @@ def oblique_rays(n: int, seed: int = 1, pitch_deg=(30.0, 60.0), origin_z: float 
     return o.astype(np.float32), d.astype(np.float32)
 
 
+SMOOTH_SIGMA2 = 0.3  # per-component variance of the direction perturbation (Sigma = 0.3 I)
+
+
+def view_perturbations(n: int, count: int, seed: int, variance: float = SMOOTH_SIGMA2) -> np.ndarray:
+    """Gaussian direction perturbations delta ~ N(0, variance I), float32
+    [n, count, 3], for the view-smoothness loss; the loss adds them to the
+    ray directions."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    return (g.standard_normal((n, count, 3)) * math.sqrt(variance)).astype(np.float32)
+
+
 def camera_rays(width: int, height: int, pitch_deg: float, yaw_deg: float,
                 aim=(0.0, 0.0, BASE_HEIGHT), origin_z: float = 1.0, hfov_deg: float = 60.0,
                 pixels: Optional[np.ndarray] = None) -> Tuple[np.ndarray, np.ndarray]:

@@ -620,3 +620,37 @@ def test_smooth_loss_gradient_matches_fd(freqs):
                 vals.append(oracle.smooth_loss(*args, freqs=freqs, weight=0.7)[0])
             fd = (vals[0] - vals[1]) / (2 * h)
             assert abs(fd - g[idx]) <= 1e-6 * max(abs(fd), 1e-3), (idx, fd, g[idx])
+
+
+def test_loss_with_smooth_term_is_l2_plus_smooth_of_rendered_features():
+    """oracle_loss_and_grads(smooth=...) is the L2 loss plus smooth_loss on
+    the rendered F (values), and its gradient in a feature row and in MLP
+    entries matches central differences of that sum (the F path of the
+    smoothness term reaches the features)."""
+    sc, o, d, tgt = _grad_problem()
+    prm = oracle.RenderParams(n_max=256, c_bg=(0.2, 0.4, 0.6))
+    rng = np.random.default_rng(4)
+    pert = rng.normal(0, 0.5, (o.shape[0], 3, 3))
+    w = 0.3
+
+    def total(s):
+        r = oracle.oracle_render(s, o, d, prm, keep_k=False)
+        return np.mean((r["C"] - tgt) ** 2) + oracle.smooth_loss(r["F"], d, pert, s["mlp"], 0, w)[0]
+
+    loss, _, grads = oracle.oracle_loss_and_grads(sc, o, d, prm, tgt, smooth=dict(perturb=pert, weight=w))
+    plain, _, plain_grads = oracle.oracle_loss_and_grads(sc, o, d, prm, tgt)
+    assert abs(loss - total(sc)) <= 1e-12 * abs(loss) and loss > plain
+    u, g = grads["grid"]
+    gp = dict(zip(plain_grads["grid"][0].tolist(), plain_grads["grid"][1]))
+    row = int(np.argmax(np.abs(g - np.stack([gp[int(k)] for k in u])).sum(1)))
+    picks = [("grid", int(u[row]) * 8 + c) for c in range(8)] + [("mlp", int(i)) for i in rng.choice(499, 6, replace=False)]
+    h = 1e-6
+    for src, e in picks:
+        gdense = grads["mlp"][e] if src == "mlp" else g[row, e % 8]
+        vals = []
+        for s in (+1, -1):
+            sp = {k: (v.astype(np.float64).copy() if k == src else v) for k, v in sc.items()}
+            sp[src].reshape(-1)[e] += s * h
+            vals.append(total(sp))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - gdense) <= 1e-6 * max(abs(fd), 1e-3), (src, e, fd, gdense)
