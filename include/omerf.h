@@ -99,8 +99,16 @@ typedef struct om_scene_desc {
     const void* plane_xz;   /* device, [Nz][Nx][8] of dtype     */
     const void* plane_yz;   /* device, [Nz][Ny][8] of dtype     */
     const float* occ;       /* device, [My][Mx][2] float32      */
-    const float* mlp;       /* device, float32[499]             */
+    const float* mlp;       /* device, float32[OM_MLP_NPARAMS(dir_freqs)] */
+    int32_t dir_freqs;      /* view-direction input of the deferred MLP:
+                               0: x = [F (7), d (3)];  4: x = [F, d,
+                               sin(2^k d), cos(2^k d) for k = 0..3] (34
+                               inputs; Sec. 4.2).  Other values rejected. */
 } om_scene_desc;
+
+/* Packed MLP parameters for an N -> 16 -> 16 -> 3 network: W1 [16][N], b1,
+ * W2 [16][16], b2, W3 [3][16], b3, N = 10 + 6 dir_freqs (499 or 883). */
+#define OM_MLP_NPARAMS(dir_freqs) (16 * (10 + 6 * (dir_freqs)) + 16 + 256 + 16 + 48 + 3)
 
 /* Per-call render parameters. */
 typedef struct om_params {
@@ -147,7 +155,7 @@ typedef struct om_fwd_out {
 
 /* Gradient buffers (device, float32, caller-zeroed or holding a running
  * sum: the backward pass ACCUMULATES into them).  Shapes match the scene:
- * grid [Lz][Ly][Lx][8], planes as the scene, mlp [499]. */
+ * grid [Lz][Ly][Lx][8], planes as the scene, mlp [OM_MLP_NPARAMS]. */
 typedef struct om_grads {
     float* grid;
     float* plane_xy;
@@ -242,6 +250,36 @@ int om_deferred_mlp(const om_scene* scene, const float* d, int64_t n, const om_p
 int om_render_backward(const om_scene* scene, const float* o, const float* d, int64_t n,
                        const om_params* p, const om_fwd_out* saved, const float* dL_dC,
                        const om_grads* g, void* stream);
+
+/*
+ * om_render_backward with an extra upstream gradient on the composited
+ * features: dL_dF (device float32 [n][7], or NULL = zero) is the gradient
+ * of a loss term that reads F directly (the view-smoothness loss of
+ * om_smooth_loss), added to what flows back from dL_dC before the march
+ * backward distributes it over the samples.  om_render_backward(...) is
+ * om_render_backward_ex(..., dL_dC, NULL, g, stream).
+ */
+int om_render_backward_ex(const om_scene* scene, const float* o, const float* d, int64_t n,
+                          const om_params* p, const om_fwd_out* saved, const float* dL_dC,
+                          const float* dL_dF, const om_grads* g, void* stream);
+
+/*
+ * View-smoothness regulariser of Sec. 4.2 (Eq. 9-10) on the deferred MLP G
+ * of the scene: L = weight * sum_r sum_p S(d_r, s_rp) ||G(F_r, s_rp) -
+ * G(F_r, d_r)||^2 with s_rp = d_r + perturb[r][p] (used as it is, not
+ * renormalised) and S the cosine similarity.  The Gaussian perturbations
+ * of Eq. 9 are drawn by the caller.  F: device float32 [n][7] (the
+ * composited features of om_render); d: [n][3]; perturb: [n][P][3],
+ * 1 <= P <= 64; no direction or d + perturb may be the zero vector.
+ * loss_fp64: optional device double[1] (overwritten); dL_dF: optional
+ * device float32 [n][7] into which dL/dF is ADDED (pass it to
+ * om_render_backward_ex); grad_mlp: optional device float32
+ * [OM_MLP_NPARAMS] into which dL/dW is ADDED (float32 atomics, order not
+ * deterministic).  Evaluated in float32 regardless of the scene dtype.
+ */
+int om_smooth_loss(const om_scene* scene, const float* F, const float* d, int64_t n,
+                   const float* perturb, int32_t P, float weight, double* loss_fp64,
+                   float* dL_dF, float* grad_mlp, void* stream);
 
 /*
  * L2 loss in float64, for finite-difference gradient checks:

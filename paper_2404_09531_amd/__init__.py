@@ -26,10 +26,20 @@ from . import _lib
 from ._lib import OM_BF16, OM_F32, OM_MAX_SAMPLES, OmerfError
 
 DELTA = 0.25 / 512  # lattice step: box height / 512 (2^-11)
-MLP_NPARAMS = 499
+MLP_NPARAMS = 499  # N = 10 inputs (no direction encoding)
 
-__all__ = ["Scene", "place_samples", "render", "render_backward", "RenderFn", "l2_loss_fp64", "l2_loss_grad",
-           "DELTA", "OmerfError", "OM_MAX_SAMPLES", "to_bf16"]
+
+def mlp_nparams(dir_freqs: int = 0) -> int:
+    """Packed parameter count of the N -> 16 -> 16 -> 3 deferred MLP with
+    N = 10 + 6 dir_freqs inputs (499 or 883)."""
+    return 16 * (10 + 6 * dir_freqs) + 16 + 256 + 16 + 48 + 3
+
+
+_FREQS_OF = {mlp_nparams(0): 0, mlp_nparams(4): 4}
+
+__all__ = ["Scene", "place_samples", "render", "render_backward", "RenderFn", "SmoothFn", "smooth_loss",
+           "l2_loss_fp64", "l2_loss_grad", "occ_interval_loss", "mlp_nparams", "DELTA", "OmerfError",
+           "OM_MAX_SAMPLES", "to_bf16"]
 
 
 def _need(t: torch.Tensor, name: str, dtype, shape=None) -> None:
@@ -55,7 +65,8 @@ class Scene:
 
     grid [Lz,Ly,Lx,8], plane_xy [Ny,Nx,8], plane_xz [Nz,Nx,8], plane_yz
     [Nz,Ny,8] (all float32 or all bfloat16), occ float32 [My,Mx,2],
-    mlp float32 [499].  The tensors are referenced (kept alive) by the
+    mlp float32 [499] (MLP input [F, d]) or [883] (input [F, d, sin/cos of
+    2^k d for k = 0..3], Sec. 4.2); the width selects the encoding.  The tensors are referenced (kept alive) by the
     Scene, never copied."""
 
     def __init__(self, grid, plane_xy, plane_xz, plane_yz, occ, mlp,
@@ -80,7 +91,9 @@ class Scene:
         _need(plane_yz, "plane_yz", dt, (nz, ny, 8))
         my, mx = occ.shape[:2]
         _need(occ, "occ", torch.float32, (my, mx, 2))
-        _need(mlp, "mlp", torch.float32, (MLP_NPARAMS,))
+        _need(mlp, "mlp", torch.float32)
+        if mlp.dim() != 1 or mlp.numel() not in _FREQS_OF:
+            raise ValueError(f"mlp must be float32 [{mlp_nparams(0)}] or [{mlp_nparams(4)}], got {tuple(mlp.shape)}")
         d = _lib.OmSceneDesc()
         d.box_lo[:] = list(box_lo)
         d.box_hi[:] = list(box_hi)
@@ -91,6 +104,8 @@ class Scene:
         d.grid, d.plane_xy, d.plane_xz, d.plane_yz = grid.data_ptr(), plane_xy.data_ptr(), plane_xz.data_ptr(), \
             plane_yz.data_ptr()
         d.occ, d.mlp = occ.data_ptr(), mlp.data_ptr()
+        d.dir_freqs = _FREQS_OF[mlp.numel()]
+        self.dir_freqs = d.dir_freqs
         self._desc = d
         self.tensors = dict(grid=grid, plane_xy=plane_xy, plane_xz=plane_xz, plane_yz=plane_yz, occ=occ, mlp=mlp)
         self.dtype = dt
@@ -254,22 +269,26 @@ def render_into(scene: Scene, o, d, out: Dict[str, torch.Tensor], n_max: int, de
 
 def render_backward(scene: Scene, o, d, saved: Dict[str, torch.Tensor], dL_dC, grads: Dict[str, torch.Tensor],
                     n_max: int, delta: float = DELTA, t_term: float = 0.0, c_bg=(0.0, 0.0, 0.0),
-                    occ_eps: float = 0.0) -> None:
+                    occ_eps: float = 0.0, dL_dF: Optional[torch.Tensor] = None) -> None:
     """Accumulate dL/d(grid, planes, mlp) into float32 `grads` (keys grid,
     plane_xy, plane_xz, plane_yz, mlp) given dL/dC and the forward's outputs
     (with "batch_wv" among them when the forward wrote it).  With
-    occ_eps > 0 an optional grads["occ"] [My, Mx, 2] receives dL/d(z_min, z_max)."""
+    occ_eps > 0 an optional grads["occ"] [My, Mx, 2] receives dL/d(z_min, z_max).
+    dL_dF (float32 [n, 7], optional) is an extra upstream gradient on the
+    composited features, e.g. from smooth_loss."""
     n = _rays(scene, o, d)
     _need(dL_dC, "dL_dC", torch.float32, (n, 3))
+    if dL_dF is not None:
+        _need(dL_dF, "dL_dF", torch.float32, (n, 7))
     for key in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp"):
         _need(grads[key], f"grads[{key}]", torch.float32, scene.tensors[key].shape)
     fo = _lib.OmFwdOut(saved["C"].data_ptr(), saved["T"].data_ptr(), saved["F"].data_ptr(),
                        saved["n_placed"].data_ptr(), saved["n_eval"].data_ptr(), _batch_wv(saved, n, n_max))
     g = _grads(scene, grads)
     p = _params(n_max, delta, t_term, c_bg, -1, occ_eps)
-    _lib.check("om_render_backward", _lib.lib().om_render_backward(
+    _lib.check("om_render_backward_ex", _lib.lib().om_render_backward_ex(
         scene.handle, o.data_ptr(), d.data_ptr(), n, ctypes.byref(p), ctypes.byref(fo), dL_dC.data_ptr(),
-        ctypes.byref(g), _lib.stream_of(o)))
+        _lib.ptr(dL_dF), ctypes.byref(g), _lib.stream_of(o)))
 
 
 def fwd_bwd_l2_workspace_size(n: int, n_max: int, delta: float = DELTA) -> int:
@@ -336,6 +355,54 @@ def occ_interval_loss(occ, weight: float = 1.0, grad: Optional[torch.Tensor] = N
     return loss
 
 
+def smooth_loss(scene: Scene, F, d, perturb, weight: float = 1.0, dL_dF: Optional[torch.Tensor] = None,
+                grad_mlp: Optional[torch.Tensor] = None, with_loss: bool = True) -> Optional[torch.Tensor]:
+    """View-smoothness regulariser of Sec. 4.2 (Eq. 9-10) on the scene's MLP
+    (om_smooth_loss): weight * sum_r sum_p cos(d_r, s_rp) ||G(F_r, s_rp) -
+    G(F_r, d_r)||^2 with s_rp = d_r + perturb[r, p].  F float32 [n, 7], d
+    [n, 3], perturb [n, P, 3] (the caller's Gaussian draws).  Returns the
+    float64 loss as a device [1] tensor (if with_loss); dL/dF and dL/dmlp
+    are ADDED into dL_dF / grad_mlp when given."""
+    n = F.shape[0]
+    _need(F, "F", torch.float32, (n, 7))
+    _need(d, "d", torch.float32, (n, 3))
+    _need(perturb, "perturb", torch.float32)
+    if perturb.dim() != 3 or perturb.shape[0] != n or perturb.shape[2] != 3:
+        raise ValueError(f"perturb must be [n, P, 3] with n = {n}, got {tuple(perturb.shape)}")
+    if dL_dF is not None:
+        _need(dL_dF, "dL_dF", torch.float32, (n, 7))
+    if grad_mlp is not None:
+        _need(grad_mlp, "grad_mlp", torch.float32, scene.tensors["mlp"].shape)
+    loss = torch.empty((1,), dtype=torch.float64, device=F.device) if with_loss else None
+    _lib.check("om_smooth_loss", _lib.lib().om_smooth_loss(
+        scene.handle, F.data_ptr(), d.data_ptr(), n, perturb.data_ptr(), perturb.shape[1], float(weight),
+        _lib.ptr(loss), _lib.ptr(dL_dF), _lib.ptr(grad_mlp), _lib.stream_of(F)))
+    return loss
+
+
+class SmoothFn(torch.autograd.Function):
+    """L_smooth = smooth_loss(scene, F, d, perturb, weight) as a float64
+    scalar, differentiable in F and in the float32 MLP master passed last.
+    ``SmoothFn.apply(scene, F, d, perturb, weight, mlp)``.  The loss and both
+    gradients come out of one kernel call in the forward; the backward scales
+    them by the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, scene, F, d, perturb, weight, mlp):
+        F = F.detach().contiguous()
+        gF = torch.zeros_like(F)
+        gW = torch.zeros(mlp.shape, dtype=torch.float32, device=mlp.device)
+        loss = smooth_loss(scene, F, d, perturb, weight, dL_dF=gF, grad_mlp=gW)
+        ctx.save_for_backward(gF, gW)
+        return loss.reshape(())
+
+    @staticmethod
+    def backward(ctx, g):
+        gF, gW = ctx.saved_tensors
+        s = g.to(torch.float32)
+        return None, gF * s, None, None, None, gW * s
+
+
 def l2_loss_fp64(C, target) -> torch.Tensor:
     """float64 mean over rays x 3 of (C - target)^2, as a 1-element device tensor."""
     n = C.shape[0]
@@ -367,7 +434,9 @@ class RenderFn(torch.autograd.Function):
     the render reads the tensors the Scene points at (the float32 masters
     themselves, or bfloat16 shadows of them); the gradients are float32 and
     are returned for the master tensors passed as the last inputs, including
-    the occupancy plane when it is passed and opts["occ_eps"] > 0.
+    the occupancy plane when it is passed and opts["occ_eps"] > 0.  The
+    composited features F (third output) are differentiable too: a loss on
+    them (SmoothFn) flows back into the same master gradients.
     opts = dict(n_max=..., delta=..., t_term=..., c_bg=..., mlp_bf16=..., occ_eps=...)."""
 
     @staticmethod
@@ -377,11 +446,11 @@ class RenderFn(torch.autograd.Function):
         ctx.masters = (grid, plane_xy, plane_xz, plane_yz, mlp)
         ctx.occ = occ
         ctx.save_for_backward(o, d, out["C"], out["T"], out["F"], out["n_placed"], out["n_eval"], out["batch_wv"])
-        ctx.mark_non_differentiable(out["T"], out["F"], out["n_placed"], out["n_eval"])
+        ctx.mark_non_differentiable(out["T"], out["n_placed"], out["n_eval"])
         return out["C"], out["T"], out["F"], out["n_placed"], out["n_eval"]
 
     @staticmethod
-    def backward(ctx, gC, *_unused):
+    def backward(ctx, gC, _gT, gF, *_unused):
         o, d, C, T, F, npl, nev, bwv = ctx.saved_tensors
         saved = dict(C=C, T=T, F=F, n_placed=npl, n_eval=nev, batch_wv=bwv)
         grads = {k: torch.zeros(m.shape, dtype=torch.float32, device=m.device)
@@ -389,6 +458,9 @@ class RenderFn(torch.autograd.Function):
         if ctx.occ is not None and ctx.opts.get("occ_eps", 0.0) > 0:
             grads["occ"] = torch.zeros(ctx.occ.shape, dtype=torch.float32, device=ctx.occ.device)
         opts = {k: v for k, v in ctx.opts.items() if k != "mlp_bf16"}
-        render_backward(ctx.scene, o, d, saved, gC.contiguous().float(), grads, **opts)
+        if gC is None:
+            gC = torch.zeros_like(C)
+        dF = gF.contiguous().float() if gF is not None else None
+        render_backward(ctx.scene, o, d, saved, gC.contiguous().float(), grads, dL_dF=dF, **opts)
         return (None, None, None, None, grads["grid"], grads["plane_xy"], grads["plane_xz"], grads["plane_yz"],
                 grads["mlp"], grads.get("occ"))

@@ -92,6 +92,7 @@ int validate_desc(const om_scene_desc* d, SceneDev* out) {
     if ((int64_t)d->occ_dims[0] * d->occ_dims[1] >= (int64_t)1 << 31)
         return fail(OM_ERR_UNSUPPORTED, "occupancy plane too large");
     if (d->dtype != OM_F32 && d->dtype != OM_BF16) return fail(OM_ERR_UNSUPPORTED, "dtype must be OM_F32 or OM_BF16");
+    if (d->dir_freqs != 0 && d->dir_freqs != 4) return fail(OM_ERR_UNSUPPORTED, "dir_freqs must be 0 or 4");
     const void* ptrs[6] = {d->grid, d->plane_xy, d->plane_xz, d->plane_yz, d->occ, d->mlp};
     const char* names[6] = {"grid", "plane_xy", "plane_xz", "plane_yz", "occ", "mlp"};
     for (int i = 0; i < 6; ++i) {
@@ -107,6 +108,7 @@ int validate_desc(const om_scene_desc* d, SceneDev* out) {
     s.pyz = d->plane_yz;
     s.occ = reinterpret_cast<const float2*>(d->occ);
     s.mlp = d->mlp;
+    s.mlp_in = 10 + 6 * d->dir_freqs;
     s.Lx = d->grid_dims[0];
     s.Ly = d->grid_dims[1];
     s.Lz = d->grid_dims[2];
@@ -289,7 +291,7 @@ int om_deferred_mlp(const om_scene* scene, const float* d, int64_t n, const om_p
     RayParams rp;
     int rc = check_fwd(scene, nullptr, d, n, p, out, false, true, &rp);
     if (rc != OM_OK || n == 0) return rc == OM_OK ? ok() : rc;
-    return hip_status(launch_mlp(scene->dev.mlp, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval,
+    return hip_status(launch_mlp(scene->dev.mlp, scene->dev.mlp_in, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval,
                                  out->C, (hipStream_t)stream), "om_deferred_mlp");
 }
 
@@ -303,12 +305,18 @@ int om_render(const om_scene* scene, const float* o, const float* d, int64_t n, 
     hipError_t e = launch_march_fwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_placed, out->n_eval,
                                     out->batch_wv, s);
     if (e != hipSuccess) return hip_status(e, "om_render (march)");
-    e = launch_mlp(scene->dev.mlp, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval, out->C, s);
+    e = launch_mlp(scene->dev.mlp, scene->dev.mlp_in, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval, out->C, s);
     return hip_status(e, "om_render (mlp)");
 }
 
 int om_render_backward(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
                        const om_fwd_out* saved, const float* dL_dC, const om_grads* g, void* stream) {
+    return om_render_backward_ex(scene, o, d, n, p, saved, dL_dC, nullptr, g, stream);
+}
+
+int om_render_backward_ex(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                          const om_fwd_out* saved, const float* dL_dC, const float* dL_dF, const om_grads* g,
+                          void* stream) {
     int rc = check_rays(scene, o, d, n);
     if (rc != OM_OK) return rc;
     RayParams rp;
@@ -323,7 +331,7 @@ int om_render_backward(const om_scene* scene, const float* o, const float* d, in
         return fail(OM_ERR_INVALID, "all gradient buffers are required");
     const bool bf16 = scene->desc.dtype == OM_BF16;
     hipError_t e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, saved->F, saved->T, saved->n_eval, saved->batch_wv,
-                                    dL_dC, g->grid, g->plane_xy, g->plane_xz, g->plane_yz, g->mlp, g->occ,
+                                    dL_dC, dL_dF, g->grid, g->plane_xy, g->plane_xz, g->plane_yz, g->mlp, g->occ,
                                     (hipStream_t)stream);
     return hip_status(e, "om_render_backward");
 }
@@ -361,13 +369,27 @@ int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, 
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_march_fwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_placed, out->n_eval, bw, s);
     if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2 (march)");
-    e = launch_mlp(scene->dev.mlp, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval, out->C, s);
+    e = launch_mlp(scene->dev.mlp, scene->dev.mlp_in, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval, out->C, s);
     if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2 (mlp)");
     e = launch_l2(out->C, target, n, dC, loss_fp64, s);
     if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2 (loss)");
-    e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_eval, bw, dC, g->grid, g->plane_xy,
+    e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_eval, bw, dC, nullptr, g->grid, g->plane_xy,
                          g->plane_xz, g->plane_yz, g->mlp, g->occ, s);
     return hip_status(e, "om_render_fwd_bwd_l2 (backward)");
+}
+
+int om_smooth_loss(const om_scene* scene, const float* F, const float* d, int64_t n, const float* perturb, int32_t P,
+                   float weight, double* loss_fp64, float* dL_dF, float* grad_mlp, void* stream) {
+    if (!scene) return fail(OM_ERR_INVALID, "scene is NULL");
+    if (n < 0) return fail(OM_ERR_INVALID, "n must be >= 0");
+    if (P < 1 || P > 64) return fail(OM_ERR_INVALID, "P must be in 1 .. 64");
+    if (!std::isfinite(weight)) return fail(OM_ERR_INVALID, "weight must be finite");
+    if (n > 0 && (!F || !d || !perturb)) return fail(OM_ERR_INVALID, "F, d and perturb are required");
+    if (!loss_fp64 && !dL_dF && !grad_mlp) return ok();
+    if (n == 0 && !loss_fp64) return ok();
+    return hip_status(launch_smooth(scene->dev.mlp, scene->dev.mlp_in, F, d, n, perturb, P, weight, loss_fp64, dL_dF,
+                                    grad_mlp, (hipStream_t)stream),
+                      "om_smooth_loss");
 }
 
 int om_occ_interval_loss(const float* occ, int64_t cells, float weight, double* loss_fp64, float* grad_occ,
@@ -405,6 +427,6 @@ const char* om_status_str(int status) {
     }
 }
 
-int om_version(void) { return 104; }
+int om_version(void) { return 105; }
 
 }  // extern "C"

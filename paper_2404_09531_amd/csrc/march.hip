@@ -537,20 +537,21 @@ __device__ __forceinline__ void scatter_occ(float* gocc, bool act, const OccValu
     }
 }
 
-template <class S, bool kSoft>
+template <class S, bool kSoft, int NIN>
 __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                       const float* __restrict__ d_, int64_t n, int64_t chunk,
                                                       const float* __restrict__ Fs, const float* __restrict__ Ts,
                                                       const int32_t* __restrict__ n_eval,
                                                       const float* __restrict__ BW,
-                                                      const float* __restrict__ dC, float* __restrict__ gV,
+                                                      const float* __restrict__ dC,
+                                                      const float* __restrict__ dF, float* __restrict__ gV,
                                                       float* __restrict__ gxy, float* __restrict__ gxz,
                                                       float* __restrict__ gyz, float* __restrict__ gmlp,
                                                       float* __restrict__ gocc) {
     __shared__ int qs[kGroupsPerBlock][kQueue];
-    __shared__ float sW[512];
+    __shared__ float sW[kMlpMaxSize];
     __shared__ __attribute__((aligned(16))) Stage stages[kGroupsPerBlock];
-    for (int i = threadIdx.x; i < 512; i += kBlock) sW[i] = 0.0f;
+    for (int i = threadIdx.x; i < kMlpMaxSize; i += kBlock) sW[i] = 0.0f;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kGroup - 1);
@@ -563,55 +564,27 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
     for (int64_t ray = start + gid; ray < stop_r; ray += kGroupsPerBlock) {
         const float3 o = load3(o_, ray), d = load3(d_, ray);
         const int ne = n_eval[ray];
-        float x[10];
-#pragma unroll
-        for (int c = 0; c < 7; ++c) x[c] = Fs[ray * 7 + c];
-        x[7] = d.x;
-        x[8] = d.y;
-        x[9] = d.z;
         const float Tn = Ts[ray];
         const float dc0 = dC[ray * 3 + 0], dc1 = dC[ray * 3 + 1], dc2 = dC[ray * 3 + 2];
-        float g7[7];
-        g7[0] = dc0;
-        g7[1] = dc1;
-        g7[2] = dc2;
-        g7[3] = g7[4] = g7[5] = g7[6] = 0.0f;
         if (ne <= 0) continue;  // no sample: C = c_bg, no parameter gradient
+        // g7 = dL/dF: the diffuse part of dL/dC, the deferred MLP G (Eq. 4)
+        // backward (hidden unit h per lane) and an optional dL/dF from
+        // losses on F itself.
+        float g7[7];
         {
-            // Deferred MLP G (Eq. 4) for hidden unit h, forward then backward.
-            float z1 = W[kB1 + h];
+            float x[NIN];
+            mlp_input<NIN>(Fs + ray * 7, d, x);
+            const MlpAct act = group_mlp_fwd<NIN>(W, x, h);
+            const float dG[3] = {dc0, dc1, dc2};
+            g7[0] = dc0;
+            g7[1] = dc1;
+            g7[2] = dc2;
+            g7[3] = g7[4] = g7[5] = g7[6] = 0.0f;
+            group_mlp_bwd<NIN>(W, x, h, act, dG, sW, g7);
+            if (dF) {
 #pragma unroll
-            for (int c = 0; c < 10; ++c) z1 += W[kW1 + h * 10 + c] * x[c];
-            const float h1 = fmaxf(z1, 0.0f);
-            float z2 = W[kB2 + h];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) z2 += W[kW2 + h * 16 + j] * __shfl(h1, j, kGroup);
-            const float h2 = fmaxf(z2, 0.0f);
-            float dz3[3];
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const float z3 = W[kB3 + r] + g_sum(W[kW3 + r * 16 + h] * h2);
-                const float g = sigmoidf_fast(z3);
-                dz3[r] = (r == 0 ? dc0 : r == 1 ? dc1 : dc2) * g * (1.0f - g);
+                for (int c = 0; c < 7; ++c) g7[c] += dF[ray * 7 + c];
             }
-            const float dh2 = W[kW3 + h] * dz3[0] + W[kW3 + 16 + h] * dz3[1] + W[kW3 + 32 + h] * dz3[2];
-            const float dz2 = z2 > 0.0f ? dh2 : 0.0f;
-            float dh1 = 0.0f;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                dh1 += W[kW2 + j * 16 + h] * __shfl(dz2, j, kGroup);
-                atomicAdd(&sW[kW2 + h * 16 + j], dz2 * __shfl(h1, j, kGroup));
-            }
-            const float dz1 = z1 > 0.0f ? dh1 : 0.0f;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) g7[c] += g_sum(W[kW1 + h * 10 + c] * dz1);
-#pragma unroll
-            for (int c = 0; c < 10; ++c) atomicAdd(&sW[kW1 + h * 10 + c], dz1 * x[c]);
-            atomicAdd(&sW[kB1 + h], dz1);
-            atomicAdd(&sW[kB2 + h], dz2);
-#pragma unroll
-            for (int r = 0; r < 3; ++r) atomicAdd(&sW[kW3 + r * 16 + h], dz3[r] * h2);
-            if (h < 3) atomicAdd(&sW[kB3 + h], h == 0 ? dz3[0] : h == 1 ? dz3[1] : dz3[2]);
         }
         const float gT = dc0 * rp.bg0 + dc1 * rp.bg1 + dc2 * rp.bg2;
 
@@ -715,7 +688,7 @@ __global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp,
         });
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < 499; i += kBlock) {
+    for (int i = threadIdx.x; i < MlpLayout<NIN>::SIZE; i += kBlock) {
         const float v = sW[i];
         if (v != 0.0f) unsafeAtomicAdd(gmlp + i, v);
     }
@@ -766,10 +739,23 @@ hipError_t launch_march_fwd(const SceneDev& sc, bool bf16, const RayParams& rp, 
     return hipGetLastError();
 }
 
+template <class S, bool kSoft>
+static void launch_bwd_nin(const SceneDev& sc, const RayParams& rp, const float* o, const float* d, int64_t n,
+                           int64_t chunk, dim3 grid, const float* F, const float* T, const int32_t* n_eval,
+                           const float* batch_wv, const float* dC, const float* dF, float* gV, float* gxy, float* gxz,
+                           float* gyz, float* gmlp, float* gocc, hipStream_t s) {
+    if (sc.mlp_in == 34)
+        hipLaunchKernelGGL((k_march_bwd<S, kSoft, 34>), grid, dim3(kBlock), 0, s, sc, rp, o, d, n, chunk, F, T, n_eval,
+                           batch_wv, dC, dF, gV, gxy, gxz, gyz, gmlp, gocc);
+    else
+        hipLaunchKernelGGL((k_march_bwd<S, kSoft, 10>), grid, dim3(kBlock), 0, s, sc, rp, o, d, n, chunk, F, T, n_eval,
+                           batch_wv, dC, dF, gV, gxy, gxz, gyz, gmlp, gocc);
+}
+
 hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
                             int64_t n, const float* F, const float* T, const int32_t* n_eval, const float* batch_wv,
-                            const float* dC, float* gV, float* gxy, float* gxz, float* gyz, float* gmlp, float* gocc,
-                            hipStream_t s) {
+                            const float* dC, const float* dF, float* gV, float* gxy, float* gxz, float* gyz,
+                            float* gmlp, float* gocc, hipStream_t s) {
     // Persistent blocks, each owning a contiguous chunk of rays, so the MLP
     // weight gradients are reduced in LDS over many rays before one set of
     // global atomics per block.
@@ -779,22 +765,22 @@ hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, 
     int64_t chunk = (n + nb - 1) / nb;
     chunk = (chunk + kGroupsPerBlock - 1) / kGroupsPerBlock * kGroupsPerBlock;
     nb = (n + chunk - 1) / chunk;
-    const dim3 grid((unsigned)nb), block(kBlock);
+    const dim3 grid((unsigned)nb);
     const bool soft = rp.occ_inv_eps > 0.0f;
     if (bf16) {
         if (soft)
-            hipLaunchKernelGGL((k_march_bwd<BF16Store, true>), grid, block, 0, s, sc, rp, o, d, n, chunk, F, T, n_eval,
-                               batch_wv, dC, gV, gxy, gxz, gyz, gmlp, gocc);
+            launch_bwd_nin<BF16Store, true>(sc, rp, o, d, n, chunk, grid, F, T, n_eval, batch_wv, dC, dF, gV, gxy, gxz,
+                                            gyz, gmlp, gocc, s);
         else
-            hipLaunchKernelGGL((k_march_bwd<BF16Store, false>), grid, block, 0, s, sc, rp, o, d, n, chunk, F, T,
-                               n_eval, batch_wv, dC, gV, gxy, gxz, gyz, gmlp, gocc);
+            launch_bwd_nin<BF16Store, false>(sc, rp, o, d, n, chunk, grid, F, T, n_eval, batch_wv, dC, dF, gV, gxy, gxz,
+                                             gyz, gmlp, gocc, s);
     } else {
         if (soft)
-            hipLaunchKernelGGL((k_march_bwd<F32Store, true>), grid, block, 0, s, sc, rp, o, d, n, chunk, F, T, n_eval,
-                               batch_wv, dC, gV, gxy, gxz, gyz, gmlp, gocc);
+            launch_bwd_nin<F32Store, true>(sc, rp, o, d, n, chunk, grid, F, T, n_eval, batch_wv, dC, dF, gV, gxy, gxz,
+                                           gyz, gmlp, gocc, s);
         else
-            hipLaunchKernelGGL((k_march_bwd<F32Store, false>), grid, block, 0, s, sc, rp, o, d, n, chunk, F, T, n_eval,
-                               batch_wv, dC, gV, gxy, gxz, gyz, gmlp, gocc);
+            launch_bwd_nin<F32Store, false>(sc, rp, o, d, n, chunk, grid, F, T, n_eval, batch_wv, dC, dF, gV, gxy, gxz,
+                                            gyz, gmlp, gocc, s);
     }
     return hipGetLastError();
 }

@@ -1,7 +1,8 @@
 // mlp.hip -- deferred view-dependent MLP (Eq. 4) and the L2 loss kernels.
 //
 // C = F[0:3] + [n_eval > 0] G(F, d) + T c_bg,  G = sigmoid(W3 relu(W2 relu(W1 x + b1) + b2) + b3),
-// x = [F (7), d (3)].
+// x = [F (7), enc(d)] with enc(d) = d or d with four sine/cosine
+// frequencies (NIN = 10 or 34, see mlp_input).
 //
 // k_mlp_f32      : one lane per ray, float32 FMA, weights read through the
 //                  scalar path (uniform addresses).
@@ -17,31 +18,32 @@
 
 namespace omerf {
 
+template <int NIN>
 __global__ __launch_bounds__(kBlock) void k_mlp_f32(const float* __restrict__ W, RayParams rp,
                                                     const float* __restrict__ d_, int64_t n,
                                                     const float* __restrict__ F, const float* __restrict__ T,
                                                     const int32_t* __restrict__ n_eval, float* __restrict__ C) {
+    using L = MlpLayout<NIN>;
     const int64_t r = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (r >= n) return;
-    float x[10];
+    float f7[7];
 #pragma unroll
-    for (int c = 0; c < 7; ++c) x[c] = F[r * 7 + c];
-    x[7] = d_[r * 3 + 0];
-    x[8] = d_[r * 3 + 1];
-    x[9] = d_[r * 3 + 2];
+    for (int c = 0; c < 7; ++c) f7[c] = F[r * 7 + c];
+    float x[NIN];
+    mlp_input<NIN>(f7, make_float3(d_[r * 3 + 0], d_[r * 3 + 1], d_[r * 3 + 2]), x);
     float h1[16], h2[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        float z = W[kB1 + j];
+        float z = W[L::B1 + j];
 #pragma unroll
-        for (int c = 0; c < 10; ++c) z += W[kW1 + j * 10 + c] * x[c];
+        for (int c = 0; c < NIN; ++c) z += W[L::W1 + j * NIN + c] * x[c];
         h1[j] = fmaxf(z, 0.0f);
     }
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        float z = W[kB2 + j];
+        float z = W[L::B2 + j];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) z += W[kW2 + j * 16 + c] * h1[c];
+        for (int c = 0; c < 16; ++c) z += W[L::W2 + j * 16 + c] * h1[c];
         h2[j] = fmaxf(z, 0.0f);
     }
     const bool gate = n_eval[r] > 0;
@@ -49,9 +51,9 @@ __global__ __launch_bounds__(kBlock) void k_mlp_f32(const float* __restrict__ W,
     const float bg[3] = {rp.bg0, rp.bg1, rp.bg2};
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
-        float z = W[kB3 + o];
+        float z = W[L::B3 + o];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) z += W[kW3 + o * 16 + c] * h2[c];
+        for (int c = 0; c < 16; ++c) z += W[L::W3 + o * 16 + c] * h2[c];
         const float g = gate ? sigmoidf_fast(z) : 0.0f;
         C[r * 3 + o] = x[o] + g + t * bg[o];
     }
@@ -76,23 +78,48 @@ __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
     return v;
 }
 
+// Entry k of the MLP input x = [F (7), enc(d)] (see mlp_input).
+template <int NIN>
+__device__ __forceinline__ float mlp_x_at(const float* F7, const float* d3, int k) {
+    if (k < 7) return F7[k];
+    if (k < 10) return d3[k - 7];
+    if (NIN == 10 || k >= NIN) return 0.0f;
+    const int e = k - 10, f = e / 6, rr = e - 6 * f, comp = rr < 3 ? rr : rr - 3;
+    const float v = (float)(1 << f) * d3[comp];
+    float sn, cs;
+    sincosf(v, &sn, &cs);
+    return rr < 3 ? sn : cs;
+}
+
+template <int NIN>
 __global__ __launch_bounds__(kBlock) void k_mlp_bf16(const float* __restrict__ W, RayParams rp,
                                                      const float* __restrict__ d_, int64_t n,
                                                      const float* __restrict__ F, const float* __restrict__ T,
                                                      const int32_t* __restrict__ n_eval, float* __restrict__ C) {
+    using L = MlpLayout<NIN>;
+    constexpr int KT = (NIN + 15) / 16;  // k-tiles of layer 1 (zero padded)
     const int lane = threadIdx.x & 63;
     const int col = lane & 15;  // ray within the tile / row of A
     const int q = lane >> 4;    // k-block (A, B) / row-block (C, D)
-    // A operands: row `col`, k = 4q .. 4q+3 (zero padded).
-    float a1[4], a2[4], a3[4];
+    // A operands: row `col`, k = 16 kt + 4q .. +3 (zero padded).
+    bf16x4 A1[KT];
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+        float a1[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 16 * kt + 4 * q + j;
+            a1[j] = k < NIN ? W[L::W1 + col * NIN + k] : 0.0f;
+        }
+        A1[kt] = pack4(a1[0], a1[1], a1[2], a1[3]);
+    }
+    float a2[4], a3[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int k = 4 * q + j;
-        a1[j] = k < 10 ? W[kW1 + col * 10 + k] : 0.0f;
-        a2[j] = W[kW2 + col * 16 + k];
-        a3[j] = col < 3 ? W[kW3 + col * 16 + k] : 0.0f;
+        a2[j] = W[L::W2 + col * 16 + k];
+        a3[j] = col < 3 ? W[L::W3 + col * 16 + k] : 0.0f;
     }
-    const bf16x4 A1 = pack4(a1[0], a1[1], a1[2], a1[3]);
     const bf16x4 A2 = pack4(a2[0], a2[1], a2[2], a2[3]);
     const bf16x4 A3 = pack4(a3[0], a3[1], a3[2], a3[3]);
     // Accumulator initial values: bias of output row 4q + i.
@@ -100,9 +127,9 @@ __global__ __launch_bounds__(kBlock) void k_mlp_bf16(const float* __restrict__ W
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int m = 4 * q + i;
-        c1[i] = W[kB1 + m];
-        c2[i] = W[kB2 + m];
-        c3[i] = m < 3 ? W[kB3 + m] : 0.0f;
+        c1[i] = W[L::B1 + m];
+        c2[i] = W[L::B2 + m];
+        c3[i] = m < 3 ? W[L::B3 + m] : 0.0f;
     }
     const int64_t tiles = (n + 15) / 16;
     const int64_t wave = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
@@ -110,29 +137,33 @@ __global__ __launch_bounds__(kBlock) void k_mlp_bf16(const float* __restrict__ W
     for (int64_t tile = wave; tile < tiles; tile += nwaves) {
         const int64_t r = tile * 16 + col;
         const bool valid = r < n;
-        // B operand of layer 1: x[k] of ray `col`, k = 4q .. 4q+3.
-        float xv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        float f7[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, d3[3] = {0.f, 0.f, 0.f};
         if (valid) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = 4 * q + j;
-                xv[j] = k < 7 ? F[r * 7 + k] : (k < 10 ? d_[r * 3 + (k - 7)] : 0.0f);
-            }
+            for (int c = 0; c < 7; ++c) f7[c] = F[r * 7 + c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) d3[c] = d_[r * 3 + c];
         }
-        const bf16x4 B1 = pack4(xv[0], xv[1], xv[2], xv[3]);
-        f32x4 h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A1, B1, c1, 0, 0, 0);
+        // Layer 1 over the k-tiles: B operand x[k] of ray `col`, k = 16 kt + 4q .. +3.
+        f32x4 h = c1;
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+            float xv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) xv[j] = valid ? mlp_x_at<NIN>(f7, d3, 16 * kt + 4 * q + j) : 0.0f;
+            h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A1[kt], pack4(xv[0], xv[1], xv[2], xv[3]), h, 0, 0, 0);
+        }
         const bf16x4 B2 = pack4(fmaxf(h[0], 0.0f), fmaxf(h[1], 0.0f), fmaxf(h[2], 0.0f), fmaxf(h[3], 0.0f));
         h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A2, B2, c2, 0, 0, 0);
         const bf16x4 B3 = pack4(fmaxf(h[0], 0.0f), fmaxf(h[1], 0.0f), fmaxf(h[2], 0.0f), fmaxf(h[3], 0.0f));
         h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A3, B3, c3, 0, 0, 0);
-        // Rows 0..2 of the output live in lanes with q == 0; those lanes
-        // also hold F[0..3] of their ray in xv.
+        // Rows 0..2 of the output live in lanes with q == 0.
         if (q == 0 && valid) {
             const bool gate = n_eval[r] > 0;
             const float t = T[r];
-            C[r * 3 + 0] = xv[0] + (gate ? sigmoidf_fast(h[0]) : 0.0f) + t * rp.bg0;
-            C[r * 3 + 1] = xv[1] + (gate ? sigmoidf_fast(h[1]) : 0.0f) + t * rp.bg1;
-            C[r * 3 + 2] = xv[2] + (gate ? sigmoidf_fast(h[2]) : 0.0f) + t * rp.bg2;
+            C[r * 3 + 0] = f7[0] + (gate ? sigmoidf_fast(h[0]) : 0.0f) + t * rp.bg0;
+            C[r * 3 + 1] = f7[1] + (gate ? sigmoidf_fast(h[1]) : 0.0f) + t * rp.bg1;
+            C[r * 3 + 2] = f7[2] + (gate ? sigmoidf_fast(h[2]) : 0.0f) + t * rp.bg2;
         }
     }
 }
@@ -166,17 +197,26 @@ __global__ __launch_bounds__(kBlock) void k_l2(const float* __restrict__ C, cons
     }
 }
 
-hipError_t launch_mlp(const float* W, bool bf16, const RayParams& rp, const float* d, int64_t n, const float* F,
-                      const float* T, const int32_t* n_eval, float* C, hipStream_t s) {
+template <int NIN>
+static void launch_mlp_nin(const float* W, bool bf16, const RayParams& rp, const float* d, int64_t n, const float* F,
+                           const float* T, const int32_t* n_eval, float* C, hipStream_t s) {
     if (bf16) {
         const int64_t tiles = (n + 15) / 16;
         int64_t blocks = (tiles + 3) / 4;
         if (blocks > 8192) blocks = 8192;
-        hipLaunchKernelGGL(k_mlp_bf16, dim3((unsigned)blocks), dim3(kBlock), 0, s, W, rp, d, n, F, T, n_eval, C);
+        hipLaunchKernelGGL(k_mlp_bf16<NIN>, dim3((unsigned)blocks), dim3(kBlock), 0, s, W, rp, d, n, F, T, n_eval, C);
     } else {
         const unsigned blocks = (unsigned)((n + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_mlp_f32, dim3(blocks), dim3(kBlock), 0, s, W, rp, d, n, F, T, n_eval, C);
+        hipLaunchKernelGGL(k_mlp_f32<NIN>, dim3(blocks), dim3(kBlock), 0, s, W, rp, d, n, F, T, n_eval, C);
     }
+}
+
+hipError_t launch_mlp(const float* W, int mlp_in, bool bf16, const RayParams& rp, const float* d, int64_t n,
+                      const float* F, const float* T, const int32_t* n_eval, float* C, hipStream_t s) {
+    if (mlp_in == 34)
+        launch_mlp_nin<34>(W, bf16, rp, d, n, F, T, n_eval, C, s);
+    else
+        launch_mlp_nin<10>(W, bf16, rp, d, n, F, T, n_eval, C, s);
     return hipGetLastError();
 }
 
@@ -258,6 +298,101 @@ hipError_t launch_occ_loss(const float* occ, int64_t cells, float weight, double
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_occ_loss, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const float2*>(occ),
                        cells, weight, loss, reinterpret_cast<float2*>(grad));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// View-smoothness loss (Sec. 4.2, Eq. 9-10):
+// L = weight sum_r sum_p S(d_r, s_rp) ||G(F_r, s_rp) - G(F_r, d_r)||^2,
+// s_rp = d_r + delta_rp (the caller draws delta ~ N(0, Sigma)), S the
+// cosine similarity.  One ray per 16-lane group, one hidden unit per lane:
+// G at d and at the P perturbed directions, then the backward of each
+// evaluation into LDS-reduced MLP gradients and dL/dF (added to dF).
+// ---------------------------------------------------------------------------
+template <int NIN>
+__global__ __launch_bounds__(kBlock) void k_smooth(const float* __restrict__ W, const float* __restrict__ F,
+                                                   const float* __restrict__ d_, int64_t n, int64_t chunk,
+                                                   const float* __restrict__ perturb, int P, float weight,
+                                                   double* __restrict__ loss, float* __restrict__ dF,
+                                                   float* __restrict__ gmlp) {
+    __shared__ float sW[kMlpMaxSize];
+    for (int i = threadIdx.x; i < kMlpMaxSize; i += kBlock) sW[i] = 0.0f;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (kGroup - 1);
+    const int gid = threadIdx.x / kGroup;
+    const int64_t start = (int64_t)xcd_block(blockIdx.x, gridDim.x) * chunk;
+    const int64_t stop_r = min(n, start + chunk);
+    double acc = 0.0;
+    for (int64_t ray = start + gid; ray < stop_r; ray += kGroupsPerBlock) {
+        float f7[7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) f7[c] = F[ray * 7 + c];
+        const float3 d = make_float3(d_[ray * 3 + 0], d_[ray * 3 + 1], d_[ray * 3 + 2]);
+        const float dn = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+        MlpAct ad;
+        {
+            float xd[NIN];
+            mlp_input<NIN>(f7, d, xd);
+            ad = group_mlp_fwd<NIN>(W, xd, gl);
+        }
+        float gd[3] = {0.0f, 0.0f, 0.0f};  // dL/dG at d
+        float g7[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        for (int p = 0; p < P; ++p) {
+            const float* dp = perturb + ((size_t)ray * P + p) * 3;
+            const float3 sv = make_float3(d.x + dp[0], d.y + dp[1], d.z + dp[2]);
+            float xs[NIN];
+            mlp_input<NIN>(f7, sv, xs);
+            const MlpAct as = group_mlp_fwd<NIN>(W, xs, gl);
+            const float sn = sqrtf(sv.x * sv.x + sv.y * sv.y + sv.z * sv.z);
+            const float cosv = (d.x * sv.x + d.y * sv.y + d.z * sv.z) / (dn * sn);
+            float e2 = 0.0f, gs[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float diff = as.g[c] - ad.g[c];
+                e2 += diff * diff;
+                gs[c] = 2.0f * weight * cosv * diff;
+                gd[c] -= gs[c];
+            }
+            acc += (double)weight * (double)cosv * (double)e2;
+            group_mlp_bwd<NIN>(W, xs, gl, as, gs, sW, g7);
+        }
+        {
+            float xd[NIN];  // recomputed: not held live across the perturbation loop
+            mlp_input<NIN>(f7, d, xd);
+            group_mlp_bwd<NIN>(W, xd, gl, ad, gd, sW, g7);
+        }
+        if (dF && gl == 0) {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) dF[ray * 7 + c] += g7[c];
+        }
+    }
+    if (loss && gl == 0 && acc != 0.0) atomicAdd(loss, acc);
+    __syncthreads();
+    if (gmlp) {
+        for (int i = threadIdx.x; i < MlpLayout<NIN>::SIZE; i += kBlock) {
+            const float v = sW[i];
+            if (v != 0.0f) unsafeAtomicAdd(gmlp + i, v);
+        }
+    }
+}
+
+hipError_t launch_smooth(const float* W, int mlp_in, const float* F, const float* d, int64_t n, const float* perturb,
+                         int P, float weight, double* loss, float* dF, float* gmlp, hipStream_t s) {
+    if (loss) hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, loss);
+    if (n == 0) return hipGetLastError();
+    const int64_t max_blocks = 4096;
+    int64_t nb = (n + kGroupsPerBlock - 1) / kGroupsPerBlock;
+    if (nb > max_blocks) nb = max_blocks;
+    int64_t chunk = (n + nb - 1) / nb;
+    chunk = (chunk + kGroupsPerBlock - 1) / kGroupsPerBlock * kGroupsPerBlock;
+    nb = (n + chunk - 1) / chunk;
+    if (mlp_in == 34)
+        hipLaunchKernelGGL(k_smooth<34>, dim3((unsigned)nb), dim3(kBlock), 0, s, W, F, d, n, chunk, perturb, P, weight,
+                           loss, dF, gmlp);
+    else
+        hipLaunchKernelGGL(k_smooth<10>, dim3((unsigned)nb), dim3(kBlock), 0, s, W, F, d, n, chunk, perturb, P, weight,
+                           loss, dF, gmlp);
     return hipGetLastError();
 }
 

@@ -47,6 +47,7 @@ struct SceneDev {
     // entry (Mx My - (Mx >> (l-1)) (My >> (l-1))) / 3 (a geometric sum).
     const float2* mips;
     int mip_levels;
+    int mlp_in;  // deferred-MLP input width: 10 or 34
 };
 
 struct RayParams {
@@ -57,8 +58,16 @@ struct RayParams {
     float occ_inv_eps;  // 1 / epsilon of the soft occupancy value (Eq. 6); 0: hard interval
 };
 
-// MLP parameter offsets in the packed vector.
-constexpr int kW1 = 0, kB1 = 160, kW2 = 176, kB2 = 432, kW3 = 448, kB3 = 496;
+// Deferred MLP of Eq. 4, NIN -> 16 -> 16 -> 3, packed [W1 (16 x NIN), b1,
+// W2 (16 x 16), b2, W3 (3 x 16), b3], weights row-major (out, in).  NIN is
+// 10 (7 features + the raw view direction) or 34 (the direction with four
+// sine/cosine frequencies).
+template <int NIN>
+struct MlpLayout {
+    static constexpr int W1 = 0, B1 = 16 * NIN, W2 = B1 + 16, B2 = W2 + 256, W3 = B2 + 16, B3 = W3 + 48;
+    static constexpr int SIZE = B3 + 3;
+};
+constexpr int kMlpMaxSize = MlpLayout<34>::SIZE;  // 883
 
 // ---------------------------------------------------------------------------
 // Lattice point and placement predicate (Sec. 4.1 Eq. 6-7 at epsilon = 0).
@@ -591,6 +600,82 @@ __device__ __forceinline__ void gather_half(const SceneDev& sc, const Corners& c
 __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
     const uint32_t per = nb / 8, rem = nb % 8, x = b % 8, i = b / 8;
     return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
+// ---------------------------------------------------------------------------
+// Deferred MLP input and the group-cooperative MLP (one hidden unit per lane
+// of a 16-lane group), shared by the backward march and the smoothness loss.
+// ---------------------------------------------------------------------------
+// x = [F (7), enc(d)]: enc(d) = d, or [d, sin(2^0 d), cos(2^0 d), ...,
+// sin(2^3 d), cos(2^3 d)] (each term a 3-vector) for NIN = 34.
+template <int NIN>
+__device__ __forceinline__ void mlp_input(const float* F7, float3 d, float* x) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) x[c] = F7[c];
+    x[7] = d.x;
+    x[8] = d.y;
+    x[9] = d.z;
+    if (NIN == 34) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float sc = (float)(1 << k);  // exact scaling
+            sincosf(sc * d.x, &x[10 + 6 * k + 0], &x[13 + 6 * k + 0]);
+            sincosf(sc * d.y, &x[10 + 6 * k + 1], &x[13 + 6 * k + 1]);
+            sincosf(sc * d.z, &x[10 + 6 * k + 2], &x[13 + 6 * k + 2]);
+        }
+    }
+}
+
+struct MlpAct {
+    float z1, h1, z2, h2;  // this lane's hidden unit, both layers
+    float g[3];            // G (after the sigmoid), the same on every lane
+};
+
+template <int NIN>
+__device__ __forceinline__ MlpAct group_mlp_fwd(const float* W, const float* x, int h) {
+    using L = MlpLayout<NIN>;
+    MlpAct a;
+    a.z1 = W[L::B1 + h];
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) a.z1 += W[L::W1 + h * NIN + c] * x[c];
+    a.h1 = fmaxf(a.z1, 0.0f);
+    a.z2 = W[L::B2 + h];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) a.z2 += W[L::W2 + h * 16 + j] * __shfl(a.h1, j, kGroup);
+    a.h2 = fmaxf(a.z2, 0.0f);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) a.g[r] = sigmoidf_fast(W[L::B3 + r] + g_sum(W[L::W3 + r * 16 + h] * a.h2));
+    return a;
+}
+
+// Backward of group_mlp_fwd for dL/dG = dG (the same on every lane): adds
+// the parameter gradients into the LDS array sW (distinct addresses per
+// lane) and dL/dx[0..6] into dx7 (the same on every lane).
+template <int NIN>
+__device__ __forceinline__ void group_mlp_bwd(const float* W, const float* x, int h, const MlpAct& a,
+                                              const float* dG, float* sW, float* dx7) {
+    using L = MlpLayout<NIN>;
+    float dz3[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) dz3[r] = dG[r] * a.g[r] * (1.0f - a.g[r]);
+    const float dh2 = W[L::W3 + h] * dz3[0] + W[L::W3 + 16 + h] * dz3[1] + W[L::W3 + 32 + h] * dz3[2];
+    const float dz2 = a.z2 > 0.0f ? dh2 : 0.0f;
+    float dh1 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        dh1 += W[L::W2 + j * 16 + h] * __shfl(dz2, j, kGroup);
+        atomicAdd(&sW[L::W2 + h * 16 + j], dz2 * __shfl(a.h1, j, kGroup));
+    }
+    const float dz1 = a.z1 > 0.0f ? dh1 : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) dx7[c] += g_sum(W[L::W1 + h * NIN + c] * dz1);
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) atomicAdd(&sW[L::W1 + h * NIN + c], dz1 * x[c]);
+    atomicAdd(&sW[L::B1 + h], dz1);
+    atomicAdd(&sW[L::B2 + h], dz2);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) atomicAdd(&sW[L::W3 + r * 16 + h], dz3[r] * a.h2);
+    if (h < 3) atomicAdd(&sW[L::B3 + h], h == 0 ? dz3[0] : h == 1 ? dz3[1] : dz3[2]);
 }
 
 }  // namespace omerf

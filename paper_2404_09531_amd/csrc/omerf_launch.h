@@ -15,9 +15,11 @@ hipError_t launch_march_fwd(const SceneDev& sc, bool bf16, const RayParams& rp, 
                             hipStream_t s);
 hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
                             int64_t n, const float* F, const float* T, const int32_t* n_eval, const float* batch_wv,
-                            const float* dC, float* gV, float* gxy, float* gxz, float* gyz, float* gmlp,
-                            float* gocc, hipStream_t s);
-hipError_t launch_mlp(const float* W, bool bf16, const RayParams& rp, const float* d, int64_t n, const float* F,
+                            const float* dC, const float* dF, float* gV, float* gxy, float* gxz, float* gyz,
+                            float* gmlp, float* gocc, hipStream_t s);
+hipError_t launch_smooth(const float* W, int mlp_in, const float* F, const float* d, int64_t n, const float* perturb,
+                         int P, float weight, double* loss, float* dF, float* gmlp, hipStream_t s);
+hipError_t launch_mlp(const float* W, int mlp_in, bool bf16, const RayParams& rp, const float* d, int64_t n, const float* F,
                       const float* T, const int32_t* n_eval, float* C, hipStream_t s);
 hipError_t launch_occ_pyramid(const float2* occ, int Mx, int My, float2* mips, int levels, hipStream_t s);
 hipError_t launch_occ_loss(const float* occ, int64_t cells, float weight, double* loss, float* grad, hipStream_t s);

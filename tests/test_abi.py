@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol(L):
     assert names == set(_lib.EXPORTS)
     for n in names:
         assert hasattr(L, n), n
-    assert L.om_version() == 104
+    assert L.om_version() == 105
     assert L.om_status_str(-2) == b"unsupported shape or dtype"
 
 
@@ -71,6 +71,8 @@ def test_scene_validation(L):
         (dict(grid=None), _lib.OM_ERR_INVALID),
         (dict(occ=FAKE + 4), _lib.OM_ERR_INVALID),                    # misaligned
         (dict(grid_dims=[2048, 2048, 1024]), _lib.OM_ERR_UNSUPPORTED),  # 2^32 vertices
+        (dict(dir_freqs=2), _lib.OM_ERR_UNSUPPORTED),                 # only 0 or 4 frequencies
+        (dict(dir_freqs=-4), _lib.OM_ERR_UNSUPPORTED),
     ]
     for kw, code in bad:
         rc, h = _create(L, _desc(**kw))
@@ -178,7 +180,8 @@ def test_occ_interval_loss_validation(L):
 def test_struct_layouts_match_header():
     """om_params ends with occ_eps; om_grads with occ."""
     hdr = open(os.path.join(ROOT, "include", "omerf.h")).read()
-    for name, cls in (("om_params", _lib.OmParams), ("om_grads", _lib.OmGrads)):
+    for name, cls in (("om_scene_desc", _lib.OmSceneDesc), ("om_params", _lib.OmParams),
+                      ("om_grads", _lib.OmGrads)):
         body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), hdr, re.S).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = re.findall(r"(\w+)(?:\[\d+\])?;", body)
@@ -199,4 +202,34 @@ def test_scene_update_keeps_handle_on_error(L):
     rc, h = _create(L, _desc())
     assert L.om_scene_update(h, ctypes.byref(_desc(occ_dims=[24, 32]))) == _lib.OM_ERR_UNSUPPORTED
     assert L.om_scene_update(h, ctypes.byref(_desc(grid_dims=[8, 8, 8]))) == 0
+    L.om_scene_destroy(h)
+
+
+def test_dir_freqs_accepted(L):
+    rc, h = _create(L, _desc(dir_freqs=4))
+    assert rc == 0 and h.value
+    L.om_scene_destroy(h)
+
+
+def test_smooth_loss_validation(L):
+    """om_smooth_loss rejects bad arguments before touching device memory."""
+    rc, h = _create(L, _desc())
+    f = ctypes.c_void_p(FAKE)
+    cases = [
+        (dict(P=0), _lib.OM_ERR_INVALID),
+        (dict(P=65), _lib.OM_ERR_INVALID),
+        (dict(weight=math.nan), _lib.OM_ERR_INVALID),
+        (dict(F=None), _lib.OM_ERR_INVALID),
+        (dict(perturb=None), _lib.OM_ERR_INVALID),
+        (dict(n=-1), _lib.OM_ERR_INVALID),
+        (dict(scene=None), _lib.OM_ERR_INVALID),
+    ]
+    for kw, code in cases:
+        a = dict(scene=h, F=f, d=f, n=16, perturb=f, P=4, weight=1.0)
+        a.update(kw)
+        rc = L.om_smooth_loss(a["scene"], a["F"], a["d"], a["n"], a["perturb"], a["P"], a["weight"], f, f, f, None)
+        assert rc == code, (kw, rc)
+    # nothing requested, or no rays and no loss: a no-op that launches nothing
+    assert L.om_smooth_loss(h, f, f, 16, f, 4, 1.0, None, None, None, None) == 0
+    assert L.om_smooth_loss(h, None, None, 0, None, 4, 1.0, None, f, f, None) == 0
     L.om_scene_destroy(h)
