@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--t-term", type=float, default=0.0)
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and fwd+bwd forms")
-    ap.add_argument("--forms", default="bf16_render,fp32_fwd_bwd,fp32_fwd_bwd_soft_occ,bf16_render_4k_x8,"
+    ap.add_argument("--forms", default="bf16_render,fp32_fwd_bwd,fp32_fwd_bwd_soft_occ,fp32_fwd_bwd_enc_smooth,"
+                                       "bf16_render_4k_x8,"
                                        "high_altitude_mips,towers_bf16_fwd_bwd",
                     help="comma-separated subset of forms to run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -151,6 +152,50 @@ def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a, occ_eps=0.0):
             "Mrays_per_s": round(n2 / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4),
             "fwd_ms": round(f_ms, 4), "loss_ms": round(l_ms, 4), "bwd_ms": round(b_ms, 4),
             "samples_per_ray": round(s2 / n2, 1), "targets": "forward colours + N(0, 0.05), seeded"}
+
+
+SMOOTH_RAYS = 1 << 10  # directions per step in the view-smoothness loss
+SMOOTH_P = 4  # perturbed directions per ray
+
+
+def form_fp32_enc_smooth(om, scenegen, torch, t, kw, a):
+    """The training step of form_fp32_fwd_bwd with the four-frequency
+    direction encoding (34-input deferred MLP) and the view-smoothness loss
+    of Eq. 9-10 on the first 2^10 rays of the batch (4 Gaussian
+    perturbations each, Sigma = 0.3 I): forward, L2 gradient, smoothness loss
+    + dL/dF, backward with dL/dF."""
+    dev = t["grid"].device
+    mlp = torch.from_numpy(scenegen.mlp_params(4, seed=7)).to(dev)
+    scene = om.Scene(t["grid"], t["plane_xy"], t["plane_xz"], t["plane_yz"], t["occ"], mlp)
+    _, rec2 = scenegen.workload("train-2^18")
+    o2, d2 = scenegen.make_rays(rec2)
+    n2 = o2.shape[0]
+    o2g, d2g = torch.from_numpy(o2).to(dev), torch.from_numpy(d2).to(dev)
+    out2 = _outputs(torch, n2, dev, om.batch_slots(kw["n_max"]))
+    om.render_into(scene, o2g, d2g, out2, **kw)
+    g = torch.Generator(device=dev)
+    g.manual_seed(2)
+    target = (out2["C"] + 0.05 * torch.randn(out2["C"].shape, device=dev, generator=g)).contiguous()
+    pert = torch.from_numpy(scenegen.view_perturbations(SMOOTH_RAYS, SMOOTH_P, seed=4)).to(dev)
+    grads = {k: torch.zeros(t[k].shape, device=dev) for k in ("grid", "plane_xy", "plane_xz", "plane_yz")}
+    grads["mlp"] = torch.zeros_like(mlp)
+    dC = torch.empty_like(out2["C"])
+    dF = torch.zeros_like(out2["F"])
+    Fs, ds, dFs = out2["F"][:SMOOTH_RAYS], d2g[:SMOOTH_RAYS], dF[:SMOOTH_RAYS]
+    w = 0.1
+    fwd = lambda: om.render_into(scene, o2g, d2g, out2, **kw)  # noqa: E731
+    lossg = lambda: om.l2_loss_grad(out2["C"], target, dL_dC=dC, with_loss=False)  # noqa: E731
+    smooth = lambda: om.smooth_loss(scene, Fs, ds, pert, w, dL_dF=dFs, grad_mlp=grads["mlp"],  # noqa: E731
+                                    with_loss=False)
+    bwd = lambda: om.render_backward(scene, o2g, d2g, out2, dC, grads, dL_dF=dF, **kw)  # noqa: E731
+    steps = max(3, a.steps // 2)
+    tot, (f_ms, l_ms, s_ms, b_ms) = time_stages([fwd, lossg, smooth, bwd], steps, a.warmup, torch)
+    ms = tot / steps
+    return {"workload": "2^18 rays, 16 cameras 1920x1080, oblique scene, 34-input MLP, "
+                        f"smoothness on {SMOOTH_RAYS} rays x {SMOOTH_P} perturbations", "rays": n2,
+            "Mrays_per_s": round(n2 / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4),
+            "fwd_ms": round(f_ms, 4), "loss_ms": round(l_ms, 4), "smooth_ms": round(s_ms, 4),
+            "bwd_ms": round(b_ms, 4)}
 
 
 def form_bf16_4k(om, scenegen, torch, t, kw, a):
@@ -310,6 +355,8 @@ def main():
         forms["fp32_fwd_bwd"] = form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a)
     if "fp32_fwd_bwd_soft_occ" in want:
         forms["fp32_fwd_bwd_soft_occ"] = form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a, occ_eps=0.01)
+    if "fp32_fwd_bwd_enc_smooth" in want:
+        forms["fp32_fwd_bwd_enc_smooth"] = form_fp32_enc_smooth(om, scenegen, torch, t, kw, a)
     if "bf16_render_4k_x8" in want:
         forms["bf16_render_4k_x8"] = form_bf16_4k(om, scenegen, torch, t, kw, a)
     if "high_altitude_mips" in want:

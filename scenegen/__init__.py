@@ -186,6 +186,12 @@ def _mlp_params(seq, dir_freqs: int = 0) -> np.ndarray:
     return out
 
 
+def mlp_params(dir_freqs: int, seed: int) -> np.ndarray:
+    """Stand-alone seeded deferred-MLP parameter vector (same recipe as the
+    scene's), e.g. to pair a built scene with the 34-input MLP."""
+    return _mlp_params(np.random.SeedSequence(seed), dir_freqs)
+
+
 def make_scene(cfg: SceneConfig, seed: Optional[int] = None) -> Dict[str, np.ndarray]:
     """Build the seeded synthetic scene for `cfg`.
 
