@@ -408,96 +408,161 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParam
 // suffix is summed from its own terms (never as a total minus a prefix), so
 // samples behind opaque surfaces keep their relative accuracy.
 //
-// Scatter: per batch and per feature source, consecutive samples of a ray
-// that share a cell (or texel) are summed onto the last lane of their run
-// with DPP, so each corner gets one contribution per run; the run tails
-// stage two row-adjacent corners (64 contiguous bytes) in LDS, and the group
-// adds each staged pair to global memory with one atomic instruction whose
-// 16 lanes cover those 64 bytes.  Device-memory float atomics are performed
-// beyond L2, one request per 64-byte segment of an instruction, so
-// contiguous lanes are ~16x cheaper than scattered ones.
+// Scatter: per batch and per feature source, the contributions of the
+// batch's samples to each vertex are summed with DPP over the run of
+// samples that share it, and the group adds them to global memory one
+// 64-byte segment (two row-adjacent vertices) per atomic instruction, each
+// segment once per batch (see scatter_row_class).  Device-memory float
+// atomics are performed beyond L2, one request per 64-byte segment an
+// instruction touches, so the request count is what the scatter minimises.
 // ---------------------------------------------------------------------------
 constexpr int kBatchSlots = 1024 / kGroup / kGroup;  // registers holding batch totals (n_max <= 1024)
 
-// Row-list scatter.  Per source, the samples sharing a cell form runs (see
-// g_runs); for every pair of corners adjacent along the row axis (two
-// contiguous 32-byte rows) each run's totals are summed onto its tail lane,
-// the tails stage their 16 floats in LDS at their rank, and the group flushes
-// one staged pair per instruction: 16 lanes x 4 B = 64 contiguous bytes.
+// Segment scatter.  Device-memory float atomics cost one request per
+// 64-byte segment an instruction touches, and a float32 vertex is 32 bytes,
+// so the unit of work is the segment {2s, 2s+1} of a row: one instruction
+// whose 16 lanes add both vertices' 8 channels.  Per batch and feature
+// source, the rows a sample touches are split into classes by the parities
+// of their row coordinates (4 classes for the grid, 2 for a plane): each
+// sample has exactly one row in each class, and a vertex stays in the same
+// class, as the even-x (E) or odd-x (O) vertex of the sample's corner pair,
+// for every sample whose cell it bounds.  The samples bounding a vertex are
+// consecutive along the ray (the union of the cells around a vertex is
+// convex), so per class the samples with equal E (or O) vertex form one run
+// of lanes; its tail gets the vertex total from a segmented sum.  A lane
+// whose cell has even x holds the E and O vertices of one segment, which
+// pairs its E run with its O run: each paired segment is flushed once with
+// both halves, an unpaired vertex with one half.
 struct Stage {
-    float v[kGroup][16];
-    int row[kGroup];
+    float v[kGroup][16];    // one segment per record: E vertex (0..7), O vertex (8..15)
+    uint32_t base[kGroup];  // flat index of the segment's first vertex
 };
 
-__device__ __forceinline__ void flush_pair(float* G, Stage& st, const Runs& rn, int rank, int nt, uint32_t row0,
-                                           float w0, float w1, const float* gt, int lmax, int gl) {
-    float4* q = reinterpret_cast<float4*>(st.v[rank]);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {  // the two rows one after the other: fewer live registers
-        const float w = h ? w1 : w0;
+// Lanes [t - len, t] of a group as a bit mask.
+__device__ __forceinline__ uint32_t run_mask(int t, int len) {
+    return ((2u << t) - 1u) & ~((1u << (t - len)) - 1u);
+}
+
+// Stages a segment whose lower vertex has no contribution.
+__device__ __forceinline__ void stage_upper(Stage& st, int rank, uint32_t base, const float* v) {
+    float4* q4 = reinterpret_cast<float4*>(st.v[rank]);
+    q4[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    q4[1] = q4[0];
+    q4[2] = make_float4(v[0], v[1], v[2], v[3]);
+    q4[3] = make_float4(v[4], v[5], v[6], v[7]);
+    st.base[rank] = base;
+}
+
+// Adds the first n staged segments to G, one 64-byte atomic instruction each.
+__device__ __forceinline__ void flush_segments(float* G, const Stage& st, int n, int gl) {
+    for (int i = 0; i < n; ++i) {
+        const float val = st.v[i][gl];
+        const uint32_t base = st.base[i];
+        if (val != 0.0f) unsafeAtomicAdd(G + (size_t)base * 8 + gl, val);
+    }
+}
+
+// One row class of one source.  Per lane: the flat index of the first
+// vertex of its row in this class, the cell's index x along the row (the
+// corners are x and x + 1), the row's weight wr and the fraction fx along
+// the row; gt = dL/dt of the sample.  The E runs are staged at their rank,
+// each with its paired O run's totals (or zeros) in the upper half, and
+// followed by the unpaired O runs (lower half zero), and flushed together
+// (in two rounds if they exceed the 16 records).
+__device__ __forceinline__ void scatter_row_class(float* G, Stage& st, bool act, uint32_t rowbase, int x, float wr,
+                                                  float fx, const float* gt, int gl, int lane) {
+    const bool xodd = (x & 1) != 0;
+    const uint32_t ve = rowbase + (uint32_t)(xodd ? x + 1 : x);
+    const uint32_t vo = rowbase + (uint32_t)(xodd ? x : x + 1);
+    const float we = wr * (xodd ? fx : 1.0f - fx);
+    const float wo = wr * (xodd ? 1.0f - fx : fx);
+    const Runs re = g_runs(ve, act, gl), ro = g_runs(vo, act, gl);
+    const uint32_t tme = g_ballot(re.tail, lane);
+    const uint32_t evm = g_ballot(act && !xodd, lane);  // lanes holding both vertices of one segment
+    float4* q4 = nullptr;
+    {
         float v[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) v[c] = w * gt[c];
-        g_seg_sum8(v, rn.len, lmax);
-        if (rn.tail) {
-            q[2 * h] = make_float4(v[0], v[1], v[2], v[3]);
-            q[2 * h + 1] = make_float4(v[4], v[5], v[6], v[7]);
+        for (int c = 0; c < 8; ++c) v[c] = we * gt[c];
+        g_seg_sum8(v, re.len, g_max(act ? re.len : 0));
+        if (re.tail) {
+            const int rank = __popc(tme & ((1u << gl) - 1u));
+            q4 = reinterpret_cast<float4*>(st.v[rank]);
+            q4[0] = make_float4(v[0], v[1], v[2], v[3]);
+            q4[1] = make_float4(v[4], v[5], v[6], v[7]);
+            if (!(evm & run_mask(gl, re.len))) {  // no O run to pair with
+                q4[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                q4[3] = q4[2];
+            }
+            st.base[rank] = ve;
         }
     }
-    if (rn.tail) st.row[rank] = (int)row0;
-    wave_order();
-    for (int e = 0; e < nt; ++e) {
-        const float val = st.v[e][gl];
-        const uint32_t r = (uint32_t)st.row[e];
-        if (val != 0.0f) unsafeAtomicAdd(G + (size_t)r * 8 + gl, val);
+    const int lmo = g_max(act ? ro.len : 0);
+    bool unpaired = false;
+    {
+        float v[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[c] = wo * gt[c];
+        g_seg_sum8(v, ro.len, lmo);
+        if (ro.tail) {
+            const uint32_t ev = evm & run_mask(gl, ro.len);
+            if (ev) {  // paired with the E run through its first even-x lane f
+                const int f = __ffs(ev) - 1;
+                const int et = f + __ffs(tme >> f) - 1;
+                q4 = reinterpret_cast<float4*>(st.v[__popc(tme & ((1u << et) - 1u))]);
+                q4[2] = make_float4(v[0], v[1], v[2], v[3]);
+                q4[3] = make_float4(v[4], v[5], v[6], v[7]);
+            } else {
+                unpaired = true;
+            }
+        }
+        const uint32_t um = g_ballot(unpaired, lane);
+        const int ne = __popc(tme), nu = __popc(um);
+        const int urank = __popc(um & ((1u << gl) - 1u));
+        if (ne + nu <= kGroup) {  // usual case: one flush for both kinds
+            if (unpaired) stage_upper(st, ne + urank, vo - 1u, v);
+            wave_order();
+            flush_segments(G, st, ne + nu, gl);
+            wave_order();
+            return;
+        }
+        wave_order();
+        flush_segments(G, st, ne, gl);
+        wave_order();
+        if (unpaired) stage_upper(st, urank, vo - 1u, v);
+        wave_order();
+        flush_segments(G, st, nu, gl);
+        wave_order();
     }
-    wave_order();
 }
 
-struct RunSet {
-    Runs rn;
-    int lmax, rank, nt;
-};
-
-__device__ __forceinline__ RunSet run_set(uint32_t key, bool act, int gl, int lane) {
-    RunSet r;
-    r.rn = g_runs(key, act, gl);
-    r.lmax = g_max(act ? r.rn.len : 0);
-    const uint32_t tm = g_ballot(r.rn.tail, lane);
-    r.nt = __popc(tm);
-    r.rank = __popc(tm & ((1u << gl) - 1u));
-    return r;
-}
-
-__device__ __forceinline__ void scatter_plane_runs(float* gP, int na, Stage& st, bool act, uint32_t key, float fa,
-                                                   float fb, const float* gt, int gl, int lane) {
-    const RunSet rs = run_set(key, act, gl, lane);
-    const float a0 = 1.0f - fa, a1 = fa;
-#pragma unroll 1
-    for (int p = 0; p < 2; ++p) {
-        const float wb = p ? fb : 1.0f - fb;
-        flush_pair(gP, st, rs.rn, rs.rank, rs.nt, key + (p ? (uint32_t)na : 0u), a0 * wb, a1 * wb, gt, rs.lmax, gl);
-    }
+// The row of class q (parity bit q) among rows i and i + 1, and its weight
+// (1 - f for row i, f for row i + 1).
+__device__ __forceinline__ int class_row(int i, int q, float f, float& w) {
+    const int d = (i ^ q) & 1;
+    w = d ? f : 1.0f - f;
+    return i + d;
 }
 
 __device__ __forceinline__ void scatter_batch_runs(const SceneDev& sc, float* gV, float* gxy, float* gxz, float* gyz,
                                                    Stage& st, bool act, const Corners& cn, const float* gt, int gl,
                                                    int lane) {
-    {
-        const RunSet rs = run_set(cn.g, act, gl, lane);
-        const float x0w = 1.0f - cn.fx, x1w = cn.fx, y0w = 1.0f - cn.fy, y1w = cn.fy;
-        const float z0w = 1.0f - cn.fz, z1w = cn.fz;
-        const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
 #pragma unroll 1
-        for (int p = 0; p < 4; ++p) {
-            const float yw = (p & 1) ? y1w : y0w, zw = (p >> 1) ? z1w : z0w;
-            flush_pair(gV, st, rs.rn, rs.rank, rs.nt, cn.g + ((p & 1) ? sy : 0u) + ((p >> 1) ? sz : 0u),
-                       x0w * yw * zw, x1w * yw * zw, gt, rs.lmax, gl);
-        }
+    for (int q = 0; q < 4; ++q) {
+        float wy, wz;
+        const int y = class_row(cn.iy, q & 1, cn.fy, wy), z = class_row(cn.iz, q >> 1, cn.fz, wz);
+        const uint32_t rowbase = ((uint32_t)z * (uint32_t)sc.Ly + (uint32_t)y) * (uint32_t)sc.Lx;
+        scatter_row_class(gV, st, act, rowbase, cn.ix, wy * wz, cn.fx, gt, gl, lane);
     }
-    scatter_plane_runs(gxy, sc.Nx, st, act, cn.xy, cn.ux, cn.uy, gt, gl, lane);
-    scatter_plane_runs(gxz, sc.Nx, st, act, cn.xz, cn.ux, cn.uz, gt, gl, lane);
-    scatter_plane_runs(gyz, sc.Ny, st, act, cn.yz, cn.uy, cn.uz, gt, gl, lane);
+#pragma unroll 1
+    for (int q = 0; q < 2; ++q) {
+        float w;
+        int r = class_row(cn.jy, q, cn.uy, w);
+        scatter_row_class(gxy, st, act, (uint32_t)r * (uint32_t)sc.Nx, cn.jx, w, cn.ux, gt, gl, lane);
+        r = class_row(cn.jz, q, cn.uz, w);
+        scatter_row_class(gxz, st, act, (uint32_t)r * (uint32_t)sc.Nx, cn.jx, w, cn.ux, gt, gl, lane);
+        scatter_row_class(gyz, st, act, (uint32_t)r * (uint32_t)sc.Ny, cn.jy, w, cn.uy, gt, gl, lane);
+    }
 }
 
 // One replayed sample: optical depth, density, activated colours/features
@@ -538,7 +603,7 @@ __device__ __forceinline__ void scatter_occ(float* gocc, bool act, const OccValu
 }
 
 template <class S, bool kSoft, int NIN>
-__global__ __launch_bounds__(kBlock) void k_march_bwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
+__global__ __launch_bounds__(kBlock, NIN == 10 ? 4 : 1) void k_march_bwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                       const float* __restrict__ d_, int64_t n, int64_t chunk,
                                                       const float* __restrict__ Fs, const float* __restrict__ Ts,
                                                       const int32_t* __restrict__ n_eval,
