@@ -6,7 +6,9 @@ transposed plane, a cell-centred instead of vertex-aligned grid, a missing
 transmittance factor, a wrong decay, a lost background term, a missing ReLU,
 a rounded instead of floored cell index, an open instead of closed interval,
 an off-by-one lattice step, and for the soft occupancy (Eq. 5, 6, 8) the
-mask also scaling T, exponent 1, the mask ignored and an unsquared span.
+mask also scaling T, exponent 1, the mask ignored and an unsquared span;
+for the 8-bit storage (Sec. 4.4) ties rounded up, a 256-level step and a
+code that wraps instead of clamping.
 """
 import numpy as np
 import pytest
@@ -15,6 +17,7 @@ import torch
 import oracle
 import oracle.field as field
 import oracle.placement as placement
+import oracle.quant as quant
 import oracle.render as render
 from tests import test_oracle_pins as pins
 
@@ -35,6 +38,9 @@ PIN_TESTS = [
     pins.test_occ_interval_loss_hand_example,
     pins.test_direction_encoding_hand_values,
     pins.test_smooth_loss_hand_example,
+    pins.test_quantize_u8_hand_values,
+    pins.test_quant_params_span_the_range,
+    pins.test_u8_scene_render_is_render_of_decoded_scene,
 ]
 
 
@@ -181,6 +187,25 @@ def _smooth_no_cos(orig):
     return f
 
 
+def _quantize_half_up(x, lo, step):
+    x = np.asarray(x, dtype=np.float32)
+    y = (x - np.asarray(lo, np.float32)).astype(np.float32) * quant._inverse(step)
+    y = np.floor(y.astype(np.float32) + np.float32(0.5))
+    return np.clip(np.where(np.isnan(y), 0.0, y), 0.0, 255.0).astype(np.uint8)
+
+
+def _params_256(minmax):
+    mm = np.asarray(minmax, dtype=np.float32)
+    return mm[:, 0].copy(), ((mm[:, 1] - mm[:, 0]) / np.float32(256.0)).astype(np.float32)
+
+
+def _quantize_wrap(x, lo, step):
+    x = np.asarray(x, dtype=np.float32)
+    with np.errstate(invalid="ignore", over="ignore"):
+        y = np.rint((x - np.asarray(lo, np.float32)).astype(np.float32) * quant._inverse(step))
+    return np.where(np.isfinite(y), y, 0.0).astype(np.int64).astype(np.uint8)
+
+
 def _both(mp, name, new):
     """Patch a field-module function in every module that bound it."""
     mp.setattr(field, name, new)
@@ -208,6 +233,12 @@ MUTANTS = {
                                                    mp.setattr(oracle, "encode_dir", _encode_linear_freqs)),
     "smoothness without cosine weight": lambda mp: (mp.setattr(render, "smooth_loss", _smooth_no_cos(None)),
                                                     mp.setattr(oracle, "smooth_loss", _smooth_no_cos(None))),
+    "8-bit ties rounded up": lambda mp: (mp.setattr(quant, "quantize_u8", _quantize_half_up),
+                                         mp.setattr(oracle, "quantize_u8", _quantize_half_up)),
+    "8-bit step over 256 levels": lambda mp: (mp.setattr(quant, "quant_params", _params_256),
+                                              mp.setattr(oracle, "quant_params", _params_256)),
+    "8-bit code wraps instead of clamping": lambda mp: (mp.setattr(quant, "quantize_u8", _quantize_wrap),
+                                                        mp.setattr(oracle, "quantize_u8", _quantize_wrap)),
     "interval loss not squared": lambda mp: (mp.setattr(render, "occ_interval_loss", _span_not_squared),
                                              mp.setattr(oracle, "occupancy_value", render.occupancy_value),
                                              mp.setattr(oracle, "occ_interval_loss", _span_not_squared)),

@@ -654,3 +654,74 @@ def test_loss_with_smooth_term_is_l2_plus_smooth_of_rendered_features():
             vals.append(total(sp))
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - gdense) <= 1e-6 * max(abs(fd), 1e-3), (src, e, fd, gdense)
+
+
+# ---------------------------------------------------------------------------
+# 8-bit feature storage (Sec. 4.4): code decision, parameters, round trip.
+# ---------------------------------------------------------------------------
+def test_quantize_u8_hand_values():
+    """lo = -1, step = 0.5 (inv = 2): codes by hand, ties to even, clamping."""
+    lo = np.full(8, -1.0, np.float32)
+    step = np.full(8, 0.5, np.float32)
+    x = np.array([-1.0, -0.75, -0.25, 0.0, 126.5, 126.25, 200.0, -5.0], np.float32)
+    # (x + 1) * 2 = 0, 0.5, 1.5, 2, 255, 254.5, 402, -8
+    want = np.array([0, 0, 2, 2, 255, 254, 255, 0], np.uint8)
+    got = oracle.quantize_u8(np.tile(x[:, None], (1, 8)), lo, step)
+    assert (got == want[:, None]).all()
+    special = np.array([np.nan, np.inf, -np.inf, 0.0, 0, 0, 0, 0], np.float32)[None, :]
+    assert oracle.quantize_u8(special, lo, step)[0, :3].tolist() == [0, 255, 0]
+
+
+def test_quant_params_span_the_range():
+    """lo = min and step = (max - min)/255: the channel's minimum encodes as 0
+    and its maximum as 255; a constant channel has step 0 and decodes exactly."""
+    rng = np.random.default_rng(0)
+    x = (rng.standard_normal((500, 8)) * 0.5).astype(np.float32)
+    x[:, 5] = 0.375
+    mm = oracle.feature_range(x)
+    assert np.array_equal(mm[:, 0], x.min(0)) and np.array_equal(mm[:, 1], x.max(0))
+    lo, step = oracle.quant_params(mm)
+    assert step[5] == 0.0 and np.allclose(step[:5], (x.max(0) - x.min(0))[:5] / 255.0, rtol=1e-6)
+    q = oracle.quantize_u8(x, lo, step)
+    for c in range(8):
+        if c == 5:
+            assert (q[:, c] == 0).all() and (oracle.dequantize(q[:, c], lo[c], step[c]) == 0.375).all()
+            continue
+        assert q[np.argmin(x[:, c]), c] == 0 and q[np.argmax(x[:, c]), c] == 255
+
+
+def test_quantize_round_trip_within_half_step():
+    rng = np.random.default_rng(1)
+    x = (rng.standard_normal((4000, 8)) * 0.7).astype(np.float32)
+    lo, step = oracle.quant_params(oracle.feature_range(x))
+    err = np.abs(oracle.dequantize(oracle.quantize_u8(x, lo, step), lo, step) - x)
+    assert (err <= 0.5 * step.astype(np.float64) * (1 + 1e-5) + 1e-12).all()
+    # codes are fixed points: decoding a code and encoding it again returns it
+    q = rng.integers(0, 256, (300, 8)).astype(np.uint8)
+    back = oracle.quantize_u8(oracle.dequantize(q, lo, step).astype(np.float32), lo, step)
+    assert np.array_equal(back, q)
+
+
+def test_u8_scene_render_is_render_of_decoded_scene():
+    """Features that sit exactly on the codes of lo = -2, step = 2^-6 (each
+    channel holding both end codes, so the ranges give back these
+    parameters) survive the 8-bit scene round trip bit for bit, and the
+    render of the 8-bit scene equals the float render exactly."""
+    import scenegen
+    sc = micro_scene(grid=(5, 4, 3), planes=(7, 6, 5), m=4, zmin=0.02, zmax=0.2)
+    rng = np.random.default_rng(3)
+    for src in oracle.quant.SOURCES:
+        q = rng.integers(0, 256, sc[src].shape)
+        q.reshape(-1, 8)[0], q.reshape(-1, 8)[1] = 0, 255
+        sc[src] = (-2.0 + q * 2.0 ** -6).astype(np.float32)
+    sc["grid"][..., 0] += np.float32(3.0)  # still on the codes of its own range (lo = 1)
+    q8 = oracle.quantize_scene(sc)
+    assert np.array_equal(q8["quant_step"], np.full((4, 8), 2.0 ** -6, np.float32))
+    dec = oracle.dequantize_scene(q8)
+    for src in oracle.quant.SOURCES:
+        assert q8[src].dtype == np.uint8 and np.array_equal(dec[src], sc[src].astype(np.float64)), src
+    o, d = scenegen.oblique_rays(24, seed=4, origin_z=0.6)
+    prm = oracle.RenderParams(n_max=256, c_bg=(0.2, 0.4, 0.6))
+    a = oracle.oracle_render(dec, o, d, prm, keep_k=False)
+    b = oracle.oracle_render(sc, o, d, prm, keep_k=False)
+    assert np.array_equal(a["C"], b["C"]) and (a["n_placed"] > 0).sum() > 10
