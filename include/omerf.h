@@ -65,6 +65,7 @@ extern "C" {
 /* Storage types of the feature grid and planes. */
 #define OM_F32 0
 #define OM_BF16 1
+#define OM_U8 2 /* 8-bit codes, decoded per source and channel (quant_lo, quant_step) */
 
 #define OM_MLP_NPARAMS 499
 #define OM_CHANNELS 8
@@ -84,7 +85,8 @@ typedef struct om_scene om_scene; /* opaque handle, host metadata only */
  *    box_lo[a] * occ_dims[a] / (box_hi[a] - box_lo[a]) an integer (a = x, y),
  *    so the containing occupancy cell is an exact floor;
  *  - every feature source has fewer than 2^31 vertices;
- *  - dtype is OM_F32 or OM_BF16 (bf16 = the upper 16 bits of a binary32);
+ *  - dtype is OM_F32, OM_BF16 (bf16 = the upper 16 bits of a binary32) or
+ *    OM_U8 (render only; quant_lo and quant_step finite, quant_step >= 0);
  *  - all pointers non-NULL and 16-byte aligned.
  */
 typedef struct om_scene_desc {
@@ -93,7 +95,7 @@ typedef struct om_scene_desc {
     int32_t grid_dims[3];   /* Lx, Ly, Lz */
     int32_t plane_dims[3];  /* Nx, Ny, Nz */
     int32_t occ_dims[2];    /* Mx, My     */
-    int32_t dtype;          /* OM_F32 or OM_BF16 */
+    int32_t dtype;          /* OM_F32, OM_BF16 or OM_U8 */
     const void* grid;       /* device, [Lz][Ly][Lx][8] of dtype */
     const void* plane_xy;   /* device, [Ny][Nx][8] of dtype     */
     const void* plane_xz;   /* device, [Nz][Nx][8] of dtype     */
@@ -104,6 +106,12 @@ typedef struct om_scene_desc {
                                0: x = [F (7), d (3)];  4: x = [F, d,
                                sin(2^k d), cos(2^k d) for k = 0..3] (34
                                inputs; Sec. 4.2).  Other values rejected. */
+    /* OM_U8 only (ignored otherwise): channel c of source s (0 grid, 1 XY,
+     * 2 XZ, 3 YZ) stores a byte q that stands for
+     * quant_lo[s][c] + q * quant_step[s][c] (Sec. 4.4: baked features kept
+     * as 8-bit images).  Copied when the handle is created or updated. */
+    float quant_lo[4][8];
+    float quant_step[4][8];
 } om_scene_desc;
 
 /* Packed MLP parameters for an N -> 16 -> 16 -> 3 network: W1 [16][N], b1,
@@ -117,7 +125,8 @@ typedef struct om_params {
     float t_term;     /* early-termination threshold, 0 = never stop        */
     float c_bg[3];    /* background colour                                  */
     int32_t mlp_bf16; /* 0: float32 MLP; 1: bfloat16 MLP on MFMA with
-                         float32 accumulation; -1: follow the scene dtype   */
+                         float32 accumulation; -1: bfloat16 for OM_BF16
+                         scenes, float32 otherwise                          */
     float occ_eps;    /* soft occupancy (Sec. 4.1, Eq. 6 and 8), finite and
                          >= 0.  0: the hard interval.  > 0: each placed
                          sample's compositing weight is multiplied by
@@ -146,7 +155,7 @@ typedef struct om_fwd_out {
      * Slots from ceil(n_eval / OM_BATCH) on are not written.  The march
      * writes it when non-NULL; om_render_backward reads it when non-NULL
      * and otherwise recomputes these sums with an extra replay of the
-     * samples. */
+     * samples.  Must be NULL for OM_U8 scenes (render only). */
     float* batch_wv;
 } om_fwd_out;
 
@@ -245,7 +254,8 @@ int om_deferred_mlp(const om_scene* scene, const float* d, int64_t n, const om_p
  * ADDED with float32 atomics into g (grid, planes, MLP; no ray gradient);
  * per-sample features are recomputed, not stored.  Summation order of the
  * atomics is not deterministic.  The MLP part is differentiated in float32
- * regardless of p->mlp_bf16.
+ * regardless of p->mlp_bf16.  OM_U8 scenes are render-only: the
+ * backward and the fused step return OM_ERR_UNSUPPORTED for them.
  */
 int om_render_backward(const om_scene* scene, const float* o, const float* d, int64_t n,
                        const om_params* p, const om_fwd_out* saved, const float* dL_dC,
@@ -330,6 +340,26 @@ int64_t om_render_fwd_bwd_l2_workspace_size(int64_t n, const om_params* p);
  */
 int om_occ_interval_loss(const float* occ, int64_t cells, float weight, double* loss_fp64, float* grad_occ,
                          void* stream);
+
+/*
+ * Baking to 8-bit storage (Sec. 4.4).  For one feature source, x: device
+ * float32 [n][8] (no NaN), n >= 1.
+ *  - om_feature_range: per-channel (min, max) into the device float32
+ *    [8][2] buffer minmax (overwritten; it also serves as the reduction's
+ *    scratch, so it must not alias x).
+ *  - om_quant_params (host only): from a host copy of minmax, the
+ *    per-channel lo = min and step = fl32((max - min) / 255) (host float[8]
+ *    each), so that the codes 0..255 span the channel's range.
+ *  - om_quantize_u8: out (device uint8 [n][8]) receives
+ *    q = clamp(rint(fl32(fl32(x - lo) * inv)), 0, 255) per channel, with
+ *    inv = fl32(1 / step) (0 when step = 0) and lo, step host float[8];
+ *    the rounding is to nearest, ties to even; NaN encodes as 0.
+ * The 8-bit scene is then created with dtype OM_U8 and these (lo, step)
+ * per source.
+ */
+int om_feature_range(const float* x, int64_t n, float* minmax, void* stream);
+int om_quant_params(const float* minmax_host, float* lo, float* step);
+int om_quantize_u8(const float* x, int64_t n, const float* lo, const float* step, uint8_t* out, void* stream);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* om_last_error(void);

@@ -23,7 +23,7 @@ from typing import Dict, Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import OM_BF16, OM_F32, OM_MAX_SAMPLES, OmerfError
+from ._lib import OM_BF16, OM_F32, OM_MAX_SAMPLES, OM_U8, OmerfError
 
 DELTA = 0.25 / 512  # lattice step: box height / 512 (2^-11)
 MLP_NPARAMS = 499  # N = 10 inputs (no direction encoding)
@@ -38,7 +38,8 @@ def mlp_nparams(dir_freqs: int = 0) -> int:
 _FREQS_OF = {mlp_nparams(0): 0, mlp_nparams(4): 4}
 
 __all__ = ["Scene", "place_samples", "render", "render_backward", "RenderFn", "SmoothFn", "smooth_loss",
-           "l2_loss_fp64", "l2_loss_grad", "occ_interval_loss", "mlp_nparams", "DELTA", "OmerfError",
+           "l2_loss_fp64", "l2_loss_grad", "occ_interval_loss", "mlp_nparams", "feature_range", "quant_params",
+           "quantize_u8", "quantize_features", "DELTA", "OmerfError",
            "OM_MAX_SAMPLES", "to_bf16"]
 
 
@@ -64,22 +65,27 @@ class Scene:
     """Library handle over borrowed device tensors.
 
     grid [Lz,Ly,Lx,8], plane_xy [Ny,Nx,8], plane_xz [Nz,Nx,8], plane_yz
-    [Nz,Ny,8] (all float32 or all bfloat16), occ float32 [My,Mx,2],
-    mlp float32 [499] (MLP input [F, d]) or [883] (input [F, d, sin/cos of
-    2^k d for k = 0..3], Sec. 4.2); the width selects the encoding.  The tensors are referenced (kept alive) by the
+    [Nz,Ny,8] (all float32, all bfloat16, or all uint8 codes with
+    quant=(lo, step), [4, 8] each, from quantize_features: render only),
+    occ float32 [My,Mx,2], mlp float32 [499] (MLP input [F, d]) or [883]
+    (input [F, d, sin/cos of 2^k d for k = 0..3], Sec. 4.2); the width
+    selects the encoding.  The tensors are referenced (kept alive) by the
     Scene, never copied."""
 
     def __init__(self, grid, plane_xy, plane_xz, plane_yz, occ, mlp,
-                 box_lo: Sequence[float] = (-1.0, -1.0, 0.0), box_hi: Sequence[float] = (1.0, 1.0, 0.25)):
+                 box_lo: Sequence[float] = (-1.0, -1.0, 0.0), box_hi: Sequence[float] = (1.0, 1.0, 0.25),
+                 quant=None):
         self._handle = ctypes.c_void_p()
         self.mips, self.mip_levels = None, 0
-        self._set(grid, plane_xy, plane_xz, plane_yz, occ, mlp, box_lo, box_hi)
+        self._set(grid, plane_xy, plane_xz, plane_yz, occ, mlp, box_lo, box_hi, quant)
         _lib.check("om_scene_create", _lib.lib().om_scene_create(ctypes.byref(self._desc), ctypes.byref(self._handle)))
 
-    def _set(self, grid, plane_xy, plane_xz, plane_yz, occ, mlp, box_lo, box_hi):
+    def _set(self, grid, plane_xy, plane_xz, plane_yz, occ, mlp, box_lo, box_hi, quant=None):
         dt = grid.dtype
-        if dt not in (torch.float32, torch.bfloat16):
-            raise TypeError("grid/planes must be float32 or bfloat16")
+        if dt not in (torch.float32, torch.bfloat16, torch.uint8):
+            raise TypeError("grid/planes must be float32, bfloat16 or uint8")
+        if (dt == torch.uint8) != (quant is not None):
+            raise ValueError("uint8 features need quant=(lo, step), [4, 8] each; other dtypes take none")
         lz, ly, lx, ch = grid.shape
         if ch != 8:
             raise ValueError("8 channels expected")
@@ -100,7 +106,13 @@ class Scene:
         d.grid_dims[:] = [lx, ly, lz]
         d.plane_dims[:] = [nx, ny, nz]
         d.occ_dims[:] = [mx, my]
-        d.dtype = OM_BF16 if dt == torch.bfloat16 else OM_F32
+        d.dtype = {torch.bfloat16: OM_BF16, torch.uint8: OM_U8}.get(dt, OM_F32)
+        if quant is not None:
+            lo, step = (torch.as_tensor(q, dtype=torch.float32).reshape(4, 8).tolist() for q in quant)
+            for i in range(4):
+                d.quant_lo[i][:] = lo[i]
+                d.quant_step[i][:] = step[i]
+        self.quant = quant
         d.grid, d.plane_xy, d.plane_xz, d.plane_yz = grid.data_ptr(), plane_xy.data_ptr(), plane_xz.data_ptr(), \
             plane_yz.data_ptr()
         d.occ, d.mlp = occ.data_ptr(), mlp.data_ptr()
@@ -113,14 +125,17 @@ class Scene:
 
     def update(self, **tensors) -> None:
         """Re-point the handle at new tensors (same keys as the constructor)."""
+        quant = tensors.pop("quant", self.quant)
         t = dict(self.tensors)
         t.update(tensors)
-        old = (self._desc, self.tensors, self.dtype)
+        if t["grid"].dtype != torch.uint8:
+            quant = None
+        old = (self._desc, self.tensors, self.dtype, self.quant, self.dir_freqs)
         self._set(t["grid"], t["plane_xy"], t["plane_xz"], t["plane_yz"], t["occ"], t["mlp"],
-                  tuple(self._desc.box_lo), tuple(self._desc.box_hi))
+                  tuple(self._desc.box_lo), tuple(self._desc.box_hi), quant)
         rc = _lib.lib().om_scene_update(self._handle, ctypes.byref(self._desc))
         if rc != 0:
-            self._desc, self.tensors, self.dtype = old
+            self._desc, self.tensors, self.dtype, self.quant, self.dir_freqs = old
             _lib.check("om_scene_update", rc)
         self.mips = None  # the library detached the pyramid; build it again if wanted
         self.mip_levels = 0
@@ -401,6 +416,54 @@ class SmoothFn(torch.autograd.Function):
         gF, gW = ctx.saved_tensors
         s = g.to(torch.float32)
         return None, gF * s, None, None, None, gW * s
+
+
+def feature_range(x: torch.Tensor) -> torch.Tensor:
+    """Per-channel (min, max) of float32 features [..., 8] (om_feature_range),
+    as a device float32 [8, 2] tensor."""
+    _need(x, "x", torch.float32)
+    if x.shape[-1] != 8:
+        raise ValueError("features must end in 8 channels")
+    out = torch.empty((8, 2), dtype=torch.float32, device=x.device)
+    _lib.check("om_feature_range", _lib.lib().om_feature_range(x.data_ptr(), x.numel() // 8, out.data_ptr(),
+                                                               _lib.stream_of(x)))
+    return out
+
+
+def quant_params(minmax) -> tuple:
+    """(lo, step) float32 [8] lists from a channel range [8, 2]
+    (om_quant_params: lo = min, step = (max - min) / 255 in binary32)."""
+    mm = (ctypes.c_float * 16)(*[float(v) for v in torch.as_tensor(minmax).reshape(-1).tolist()])
+    lo, step = (ctypes.c_float * 8)(), (ctypes.c_float * 8)()
+    _lib.check("om_quant_params", _lib.lib().om_quant_params(mm, lo, step))
+    return list(lo), list(step)
+
+
+def quantize_u8(x: torch.Tensor, lo, step, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """8-bit codes of float32 features [..., 8] (om_quantize_u8)."""
+    _need(x, "x", torch.float32)
+    if x.shape[-1] != 8:
+        raise ValueError("features must end in 8 channels")
+    if out is None:
+        out = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    _need(out, "out", torch.uint8, x.shape)
+    lo_c, st_c = (ctypes.c_float * 8)(*[float(v) for v in lo]), (ctypes.c_float * 8)(*[float(v) for v in step])
+    _lib.check("om_quantize_u8", _lib.lib().om_quantize_u8(x.data_ptr(), x.numel() // 8, lo_c, st_c, out.data_ptr(),
+                                                           _lib.stream_of(x)))
+    return out
+
+
+def quantize_features(tensors: Dict[str, torch.Tensor]):
+    """Bake float32 grid and planes to 8-bit storage (Sec. 4.4): per source,
+    its channel ranges, (lo, step) and codes.  Returns ({source: uint8
+    tensor}, (lo, step) as float32 [4, 8] lists for Scene(..., quant=...))."""
+    codes, los, steps = {}, [], []
+    for key in ("grid", "plane_xy", "plane_xz", "plane_yz"):
+        lo, step = quant_params(feature_range(tensors[key]).cpu())
+        codes[key] = quantize_u8(tensors[key], lo, step)
+        los.append(lo)
+        steps.append(step)
+    return codes, (los, steps)
 
 
 def l2_loss_fp64(C, target) -> torch.Tensor:

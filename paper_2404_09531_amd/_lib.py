@@ -16,13 +16,14 @@ import torch
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libomerf.so")
 
 OM_OK, OM_ERR_INVALID, OM_ERR_UNSUPPORTED, OM_ERR_HIP = 0, -1, -2, -3
-OM_F32, OM_BF16 = 0, 1
+OM_F32, OM_BF16, OM_U8 = 0, 1, 2
 OM_MAX_SAMPLES = 1024
 EXPORTS = ("om_scene_create", "om_scene_update", "om_scene_destroy", "om_occupancy_mips_size",
            "om_build_occupancy_mips", "om_place_samples", "om_march",
            "om_deferred_mlp", "om_render",
            "om_render_backward", "om_render_backward_ex", "om_smooth_loss", "om_render_fwd_bwd_l2", "om_render_fwd_bwd_l2_workspace_size",
-           "om_occ_interval_loss", "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str",
+           "om_occ_interval_loss", "om_feature_range", "om_quant_params", "om_quantize_u8",
+           "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str",
            "om_version")
 
 
@@ -30,7 +31,8 @@ class OmSceneDesc(ctypes.Structure):
     _fields_ = [("box_lo", c_float * 3), ("box_hi", c_float * 3), ("grid_dims", c_int32 * 3),
                 ("plane_dims", c_int32 * 3), ("occ_dims", c_int32 * 2), ("dtype", c_int32),
                 ("grid", c_void_p), ("plane_xy", c_void_p), ("plane_xz", c_void_p), ("plane_yz", c_void_p),
-                ("occ", c_void_p), ("mlp", c_void_p), ("dir_freqs", c_int32)]
+                ("occ", c_void_p), ("mlp", c_void_p), ("dir_freqs", c_int32),
+                ("quant_lo", (c_float * 8) * 4), ("quant_step", (c_float * 8) * 4)]
 
 
 class OmParams(ctypes.Structure):
@@ -78,6 +80,9 @@ def lib() -> ctypes.CDLL:
                                             POINTER(OmFwdOut), c_void_p, c_void_p, POINTER(OmGrads), c_void_p]
         L.om_smooth_loss.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int32, c_float, c_void_p,
                                      c_void_p, c_void_p, c_void_p]
+        L.om_feature_range.argtypes = [c_void_p, c_int64, c_void_p, c_void_p]
+        L.om_quant_params.argtypes = [POINTER(c_float), POINTER(c_float), POINTER(c_float)]
+        L.om_quantize_u8.argtypes = [c_void_p, c_int64, POINTER(c_float), POINTER(c_float), c_void_p, c_void_p]
         L.om_l2_loss_fp64.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
         L.om_l2_loss_grad.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
         L.om_render_fwd_bwd_l2.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(OmParams), c_void_p,

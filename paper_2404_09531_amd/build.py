@@ -13,7 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "march.hip", "mlp.hip"]
+SOURCES = ["api.hip", "march.hip", "mlp.hip", "bake.hip"]
 LIB = os.path.join(HERE, "libomerf.so")
 ARCH = "gfx950"
 

@@ -91,7 +91,15 @@ int validate_desc(const om_scene_desc* d, SceneDev* out) {
     }
     if ((int64_t)d->occ_dims[0] * d->occ_dims[1] >= (int64_t)1 << 31)
         return fail(OM_ERR_UNSUPPORTED, "occupancy plane too large");
-    if (d->dtype != OM_F32 && d->dtype != OM_BF16) return fail(OM_ERR_UNSUPPORTED, "dtype must be OM_F32 or OM_BF16");
+    if (d->dtype != OM_F32 && d->dtype != OM_BF16 && d->dtype != OM_U8)
+        return fail(OM_ERR_UNSUPPORTED, "dtype must be OM_F32, OM_BF16 or OM_U8");
+    if (d->dtype == OM_U8) {
+        for (int i = 0; i < 32; ++i) {
+            const float lo = (&d->quant_lo[0][0])[i], st = (&d->quant_step[0][0])[i];
+            if (!std::isfinite(lo) || !std::isfinite(st) || st < 0.0f)
+                return fail(OM_ERR_INVALID, "quant_lo / quant_step must be finite with quant_step >= 0");
+        }
+    }
     if (d->dir_freqs != 0 && d->dir_freqs != 4) return fail(OM_ERR_UNSUPPORTED, "dir_freqs must be 0 or 4");
     const void* ptrs[6] = {d->grid, d->plane_xy, d->plane_xz, d->plane_yz, d->occ, d->mlp};
     const char* names[6] = {"grid", "plane_xy", "plane_xz", "plane_yz", "occ", "mlp"};
@@ -109,6 +117,10 @@ int validate_desc(const om_scene_desc* d, SceneDev* out) {
     s.occ = reinterpret_cast<const float2*>(d->occ);
     s.mlp = d->mlp;
     s.mlp_in = 10 + 6 * d->dir_freqs;
+    for (int i = 0; i < 32; ++i) {
+        s.qlo[i] = d->dtype == OM_U8 ? (&d->quant_lo[0][0])[i] : 0.0f;
+        s.qstep[i] = d->dtype == OM_U8 ? (&d->quant_step[0][0])[i] : 0.0f;
+    }
     s.Lx = d->grid_dims[0];
     s.Ly = d->grid_dims[1];
     s.Lz = d->grid_dims[2];
@@ -265,6 +277,8 @@ int check_fwd(const om_scene* scene, const float* o, const float* d, int64_t n, 
         return fail(OM_ERR_INVALID, "required om_fwd_out buffers are NULL");
     if (out->batch_wv && ((uintptr_t)out->batch_wv & 3u))
         return fail(OM_ERR_INVALID, "batch_wv must be 4-byte aligned");
+    if (out->batch_wv && scene->desc.dtype == OM_U8)
+        return fail(OM_ERR_UNSUPPORTED, "8-bit scenes are render-only: batch_wv must be NULL");
     return OM_OK;
 }
 
@@ -281,8 +295,7 @@ int om_march(const om_scene* scene, const float* o, const float* d, int64_t n, c
     RayParams rp;
     int rc = check_fwd(scene, o, d, n, p, out, true, false, &rp);
     if (rc != OM_OK || n == 0) return rc == OM_OK ? ok() : rc;
-    const bool bf16 = scene->desc.dtype == OM_BF16;
-    return hip_status(launch_march_fwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_placed, out->n_eval,
+    return hip_status(launch_march_fwd(scene->dev, scene->desc.dtype, rp, o, d, n, out->F, out->T, out->n_placed, out->n_eval,
                                        out->batch_wv, (hipStream_t)stream), "om_march");
 }
 
@@ -300,10 +313,9 @@ int om_render(const om_scene* scene, const float* o, const float* d, int64_t n, 
     RayParams rp;
     int rc = check_fwd(scene, o, d, n, p, out, true, true, &rp);
     if (rc != OM_OK || n == 0) return rc == OM_OK ? ok() : rc;
-    const bool bf16 = scene->desc.dtype == OM_BF16;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_march_fwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_placed, out->n_eval,
-                                    out->batch_wv, s);
+    hipError_t e = launch_march_fwd(scene->dev, scene->desc.dtype, rp, o, d, n, out->F, out->T, out->n_placed,
+                                    out->n_eval, out->batch_wv, s);
     if (e != hipSuccess) return hip_status(e, "om_render (march)");
     e = launch_mlp(scene->dev.mlp, scene->dev.mlp_in, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval, out->C, s);
     return hip_status(e, "om_render (mlp)");
@@ -321,6 +333,7 @@ int om_render_backward_ex(const om_scene* scene, const float* o, const float* d,
     if (rc != OM_OK) return rc;
     RayParams rp;
     if ((rc = validate_params(p, &rp)) != OM_OK) return rc;
+    if (scene->desc.dtype == OM_U8) return fail(OM_ERR_UNSUPPORTED, "8-bit scenes are render-only");
     if (!saved || !g) return fail(OM_ERR_INVALID, "saved / grads struct is NULL");
     if (n == 0) return ok();
     if (!saved->F || !saved->T || !saved->n_eval) return fail(OM_ERR_INVALID, "saved F, T and n_eval are required");
@@ -354,6 +367,7 @@ int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, 
     RayParams rp;
     int rc = check_fwd(scene, o, d, n, p, out, true, true, &rp);
     if (rc != OM_OK) return rc;
+    if (scene->desc.dtype == OM_U8) return fail(OM_ERR_UNSUPPORTED, "8-bit scenes are render-only");
     if (n == 0) return ok();
     if (!target || !g) return fail(OM_ERR_INVALID, "target / grads is NULL");
     if (!g->grid || !g->plane_xy || !g->plane_xz || !g->plane_yz || !g->mlp)
@@ -367,7 +381,8 @@ int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, 
     float* bw = reinterpret_cast<float*>(static_cast<char*>(workspace) + (n * 3 * (int64_t)sizeof(float) + 255) / 256 * 256);
     const bool bf16 = scene->desc.dtype == OM_BF16;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_march_fwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_placed, out->n_eval, bw, s);
+    hipError_t e = launch_march_fwd(scene->dev, scene->desc.dtype, rp, o, d, n, out->F, out->T, out->n_placed,
+                                    out->n_eval, bw, s);
     if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2 (march)");
     e = launch_mlp(scene->dev.mlp, scene->dev.mlp_in, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval, out->C, s);
     if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2 (mlp)");
@@ -402,6 +417,50 @@ int om_occ_interval_loss(const float* occ, int64_t cells, float weight, double* 
                       "om_occ_interval_loss");
 }
 
+int om_feature_range(const float* x, int64_t n, float* minmax, void* stream) {
+    if (n <= 0) return fail(OM_ERR_INVALID, "n must be > 0");
+    if (!x || !minmax) return fail(OM_ERR_INVALID, "NULL pointer");
+    if (((uintptr_t)x & 15u) || ((uintptr_t)minmax & 3u))
+        return fail(OM_ERR_INVALID, "x must be 16-byte and minmax 4-byte aligned");
+    const char* xb = reinterpret_cast<const char*>(x);
+    const char* mb = reinterpret_cast<const char*>(minmax);
+    if (mb + 64 > xb && mb < xb + n * 32) return fail(OM_ERR_INVALID, "minmax must not alias x");
+    return hip_status(launch_range(x, n, minmax, reinterpret_cast<uint32_t*>(minmax), (hipStream_t)stream),
+                      "om_feature_range");
+}
+
+int om_quant_params(const float* minmax_host, float* lo, float* step) {
+    if (!minmax_host || !lo || !step) return fail(OM_ERR_INVALID, "NULL pointer");
+    for (int c = 0; c < 8; ++c) {
+        const float mn = minmax_host[2 * c], mx = minmax_host[2 * c + 1];
+        if (!std::isfinite(mn) || !std::isfinite(mx) || mx < mn)
+            return fail(OM_ERR_INVALID, "channel %d: need finite min <= max", c);
+    }
+    for (int c = 0; c < 8; ++c) {
+        const float mn = minmax_host[2 * c], mx = minmax_host[2 * c + 1];
+        const float span = mx - mn;  // binary32 arithmetic, as the codes are decided in it
+        lo[c] = mn;
+        step[c] = span / 255.0f;
+        if (!std::isfinite(step[c])) return fail(OM_ERR_UNSUPPORTED, "channel %d: range overflows float32", c);
+    }
+    return ok();
+}
+
+int om_quantize_u8(const float* x, int64_t n, const float* lo, const float* step, uint8_t* out, void* stream) {
+    if (n <= 0) return fail(OM_ERR_INVALID, "n must be > 0");
+    if (!x || !lo || !step || !out) return fail(OM_ERR_INVALID, "NULL pointer");
+    if (((uintptr_t)x & 15u) || ((uintptr_t)out & 7u))
+        return fail(OM_ERR_INVALID, "x must be 16-byte and out 8-byte aligned");
+    float inv[8];
+    for (int c = 0; c < 8; ++c) {
+        if (!std::isfinite(lo[c]) || !std::isfinite(step[c]) || step[c] < 0.0f)
+            return fail(OM_ERR_INVALID, "lo / step must be finite with step >= 0");
+        inv[c] = step[c] > 0.0f ? 1.0f / step[c] : 0.0f;
+        if (!std::isfinite(inv[c])) return fail(OM_ERR_UNSUPPORTED, "step %g too small to invert in float32", step[c]);
+    }
+    return hip_status(launch_quantize(x, n, lo, inv, out, (hipStream_t)stream), "om_quantize_u8");
+}
+
 int om_l2_loss_fp64(const float* C, const float* target, int64_t n, double* out, void* stream) {
     if (n <= 0) return fail(OM_ERR_INVALID, "n must be > 0");
     if (!C || !target || !out) return fail(OM_ERR_INVALID, "NULL pointer");
@@ -427,6 +486,6 @@ const char* om_status_str(int status) {
     }
 }
 
-int om_version(void) { return 105; }
+int om_version(void) { return 106; }
 
 }  // extern "C"

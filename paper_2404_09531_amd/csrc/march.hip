@@ -7,6 +7,7 @@
 //                recomputed features + scatter-add of feature gradients
 //
 // One ray per 16-lane group; see omerf_device.h for the decomposition.
+#include "../../include/omerf.h"
 #include "omerf_device.h"
 #include "omerf_launch.h"
 
@@ -211,6 +212,83 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
             for (int c = 0; c < 7; ++c) store_group_total(bacc[c], gl, dst + c);
         }
         ++batch;
+        return stop;
+    });
+    float f[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) f[c] = g_sum(acc[c]);
+    if (gl == 0) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) F[ray * 7 + c] = f[c];
+        T[ray] = __expf(-carry);
+        n_placed[ray] = placed;
+        n_eval[ray] = evals;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward march for 8-bit features (render only): one lane per sample.  An
+// 8-byte corner needs no split across lanes, so lane s of the group shades
+// sample s of the batch with 20 corner loads, and the batch of 16 samples is
+// composited with one 16-lane scan.
+// ---------------------------------------------------------------------------
+template <bool kSoft>
+__global__ __launch_bounds__(kBlock) void k_march_fwd_u8(SceneDev sc, RayParams rp, const float* __restrict__ o_,
+                                                         const float* __restrict__ d_, int64_t n,
+                                                         float* __restrict__ F, float* __restrict__ T,
+                                                         int32_t* __restrict__ n_placed,
+                                                         int32_t* __restrict__ n_eval) {
+    __shared__ int qs[kGroupsPerBlock][kQueue];
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (kGroup - 1);
+    const int gid = threadIdx.x / kGroup;
+    const int64_t ray = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kGroupsPerBlock + gid;
+    if (ray >= n) return;
+    const float3 o = load3(o_, ray), d = load3(d_, ray);
+    float acc[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) acc[c] = 0.0f;
+    float carry = 0.0f;
+    int evals = 0;
+    const int placed = march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
+        const bool act = gl < nb;
+        float t[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) t[c] = 0.0f;
+        float msoft = 0.0f;
+        if (act) {
+            const float3 p = lattice_point(kq, o, d, rp.delta);
+            gather_u8(sc, corners_of(sc, p), t);
+            if (kSoft) msoft = occ_value(sc, p, rp.occ_inv_eps).m;
+        }
+        float a = 0.0f;
+        float v[7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] = 0.0f;
+        if (act) {
+            a = __expf(t[0]) * rp.delta;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) v[c] = sigmoidf_fast(t[c + 1]);
+        }
+        const float incl = g_scan_incl(a, gl);
+        const float excl = g_shift_up1(incl);
+        float w = __expf(-(carry + excl)) * (-expm1f(-a));
+        int nb_eff = nb;
+        bool stop = false;
+        if (rp.t_term > 0.0f) {
+            const float Tnext = __expf(-(carry + incl));
+            const uint32_t m = g_ballot(act && Tnext < rp.t_term, lane);
+            if (m) {
+                nb_eff = __ffs(m);
+                stop = true;
+            }
+        }
+        if (kSoft) w *= msoft;  // Eq. 8: the weight, not T
+        if (gl >= nb_eff) w = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) acc[c] += w * v[c];
+        carry += __shfl(incl, nb_eff - 1, kGroup);
+        evals += nb_eff;
         return stop;
     });
     float f[7];
@@ -771,11 +849,13 @@ hipError_t launch_place(const SceneDev& sc, const RayParams& rp, const float* o,
 }
 
 template <bool kSoft>
-static void launch_fwd_soft(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
+static void launch_fwd_soft(const SceneDev& sc, int dtype, const RayParams& rp, const float* o, const float* d,
                             int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, float* batch_wv,
                             hipStream_t s) {
     const dim3 grid(blocks_for(n)), block(kBlock);
-    if (bf16) {
+    if (dtype == OM_U8) {  // render only: no per-batch sums
+        hipLaunchKernelGGL((k_march_fwd_u8<kSoft>), grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed, n_eval);
+    } else if (dtype == OM_BF16) {
         if (batch_wv)
             hipLaunchKernelGGL((k_march_fwd<BF16Store, true, kSoft>), grid, block, 0, s, sc, rp, o, d, n, F, T,
                                n_placed, n_eval, batch_wv);
@@ -792,15 +872,15 @@ static void launch_fwd_soft(const SceneDev& sc, bool bf16, const RayParams& rp, 
     }
 }
 
-hipError_t launch_march_fwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
+hipError_t launch_march_fwd(const SceneDev& sc, int dtype, const RayParams& rp, const float* o, const float* d,
                             int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, float* batch_wv,
                             hipStream_t s) {
     // The per-batch sums and the soft occupancy are separate
     // specialisations, so the plain render path carries neither.
     if (rp.occ_inv_eps > 0.0f)
-        launch_fwd_soft<true>(sc, bf16, rp, o, d, n, F, T, n_placed, n_eval, batch_wv, s);
+        launch_fwd_soft<true>(sc, dtype, rp, o, d, n, F, T, n_placed, n_eval, batch_wv, s);
     else
-        launch_fwd_soft<false>(sc, bf16, rp, o, d, n, F, T, n_placed, n_eval, batch_wv, s);
+        launch_fwd_soft<false>(sc, dtype, rp, o, d, n, F, T, n_placed, n_eval, batch_wv, s);
     return hipGetLastError();
 }
 

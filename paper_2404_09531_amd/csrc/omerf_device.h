@@ -48,6 +48,9 @@ struct SceneDev {
     const float2* mips;
     int mip_levels;
     int mlp_in;  // deferred-MLP input width: 10 or 34
+    // 8-bit storage: channel c of source s (grid, XY, XZ, YZ) decodes as
+    // qlo[8 s + c] + q qstep[8 s + c]; indexed with constants only.
+    float qlo[32], qstep[32];
 };
 
 struct RayParams {
@@ -264,6 +267,26 @@ struct BF16Store {
     static __device__ __forceinline__ void acc(const Row& v, float w, float* t) {
         t[0] += w * lo16(v.x); t[1] += w * hi16(v.x); t[2] += w * lo16(v.y); t[3] += w * hi16(v.y);
         t[4] += w * lo16(v.z); t[5] += w * hi16(v.z); t[6] += w * lo16(v.w); t[7] += w * hi16(v.w);
+    }
+};
+
+// 8-bit storage (Sec. 4.4): one vertex or texel is 8 bytes, channel c in
+// byte c.  Interpolation weights of one source sum to one, so a source adds
+// lo + step * sum_corners w q per channel; acc accumulates sum w q.
+struct U8Store {
+    typedef uint2 Row;
+    static __device__ __forceinline__ Row load(const void* base, uint32_t idx) {
+        return reinterpret_cast<const uint2*>(base)[idx];
+    }
+    static __device__ __forceinline__ void acc(const Row& v, float w, float* a) {
+        a[0] += w * (float)(v.x & 0xffu);
+        a[1] += w * (float)((v.x >> 8) & 0xffu);
+        a[2] += w * (float)((v.x >> 16) & 0xffu);
+        a[3] += w * (float)(v.x >> 24);
+        a[4] += w * (float)(v.y & 0xffu);
+        a[5] += w * (float)((v.y >> 8) & 0xffu);
+        a[6] += w * (float)((v.y >> 16) & 0xffu);
+        a[7] += w * (float)(v.y >> 24);
     }
 };
 
@@ -592,6 +615,64 @@ __device__ __forceinline__ void gather_half(const SceneDev& sc, const Corners& c
     S::acc(r[7], wa * e1, t);
     S::acc(r[8], wb * e0, t);
     S::acc(r[9], wb * e1, t);
+}
+
+// Eq. 2 for 8-bit storage, one lane per sample: the 20 corners are loaded
+// first (8 bytes each), then each source's weighted code sums are decoded
+// with that source's per-channel (lo, step).
+__device__ __forceinline__ void decode_add(const SceneDev& sc, int src, const float* a, float* t) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) t[c] += fmaf(sc.qstep[8 * src + c], a[c], sc.qlo[8 * src + c]);
+}
+
+__device__ __forceinline__ void gather_u8(const SceneDev& sc, const Corners& c, float* t) {
+    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
+    const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
+    uint2 r[20];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const uint32_t base = c.g + ((p & 1) ? sy : 0u) + ((p >> 1) ? sz : 0u);
+        r[2 * p] = U8Store::load(sc.grid, base);
+        r[2 * p + 1] = U8Store::load(sc.grid, base + 1);
+    }
+    r[8] = U8Store::load(sc.pxy, c.xy);
+    r[9] = U8Store::load(sc.pxy, c.xy + 1);
+    r[10] = U8Store::load(sc.pxy, c.xy + nx);
+    r[11] = U8Store::load(sc.pxy, c.xy + nx + 1);
+    r[12] = U8Store::load(sc.pxz, c.xz);
+    r[13] = U8Store::load(sc.pxz, c.xz + 1);
+    r[14] = U8Store::load(sc.pxz, c.xz + nx);
+    r[15] = U8Store::load(sc.pxz, c.xz + nx + 1);
+    r[16] = U8Store::load(sc.pyz, c.yz);
+    r[17] = U8Store::load(sc.pyz, c.yz + 1);
+    r[18] = U8Store::load(sc.pyz, c.yz + ny);
+    r[19] = U8Store::load(sc.pyz, c.yz + ny + 1);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = 0.0f;
+    float a[8];
+    const float x0 = 1.0f - c.fx, x1 = c.fx, y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[i] = 0.0f;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const float wyz = ((p & 1) ? y1 : y0) * ((p >> 1) ? z1 : z0);
+        U8Store::acc(r[2 * p], x0 * wyz, a);
+        U8Store::acc(r[2 * p + 1], x1 * wyz, a);
+    }
+    decode_add(sc, 0, a, t);
+    const float u0 = 1.0f - c.ux, u1 = c.ux, v0 = 1.0f - c.uy, v1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
+    const float wa[3][2] = {{u0, u1}, {u0, u1}, {v0, v1}};  // first axis: x, x, y
+    const float wb[3][2] = {{v0, v1}, {e0, e1}, {e0, e1}};  // second axis: y, z, z
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = 0.0f;
+        U8Store::acc(r[8 + 4 * q], wa[q][0] * wb[q][0], a);
+        U8Store::acc(r[9 + 4 * q], wa[q][1] * wb[q][0], a);
+        U8Store::acc(r[10 + 4 * q], wa[q][0] * wb[q][1], a);
+        U8Store::acc(r[11 + 4 * q], wa[q][1] * wb[q][1], a);
+        decode_add(sc, 1 + q, a, t);
+    }
 }
 
 // Block index -> virtual block index such that the blocks the hardware

@@ -10,7 +10,7 @@ namespace omerf {
 
 hipError_t launch_place(const SceneDev& sc, const RayParams& rp, const float* o, const float* d, int64_t n,
                         int32_t* k_out, int32_t* n_placed, hipStream_t s);
-hipError_t launch_march_fwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
+hipError_t launch_march_fwd(const SceneDev& sc, int dtype, const RayParams& rp, const float* o, const float* d,
                             int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, float* batch_wv,
                             hipStream_t s);
 hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
@@ -23,6 +23,8 @@ hipError_t launch_mlp(const float* W, int mlp_in, bool bf16, const RayParams& rp
                       const float* T, const int32_t* n_eval, float* C, hipStream_t s);
 hipError_t launch_occ_pyramid(const float2* occ, int Mx, int My, float2* mips, int levels, hipStream_t s);
 hipError_t launch_occ_loss(const float* occ, int64_t cells, float weight, double* loss, float* grad, hipStream_t s);
+hipError_t launch_range(const float* x, int64_t n, float* minmax, uint32_t* keys, hipStream_t s);
+hipError_t launch_quantize(const float* x, int64_t n, const float* lo, const float* inv, uint8_t* out, hipStream_t s);
 hipError_t launch_l2(const float* C, const float* tgt, int64_t n, float* dC, double* loss, hipStream_t s);
 
 }  // namespace omerf

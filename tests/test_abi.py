@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol(L):
     assert names == set(_lib.EXPORTS)
     for n in names:
         assert hasattr(L, n), n
-    assert L.om_version() == 105
+    assert L.om_version() == 106
     assert L.om_status_str(-2) == b"unsupported shape or dtype"
 
 
@@ -184,8 +184,34 @@ def test_struct_layouts_match_header():
                       ("om_grads", _lib.OmGrads)):
         body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), hdr, re.S).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-        fields = re.findall(r"(\w+)(?:\[\d+\])?;", body)
+        fields = re.findall(r"(\w+)(?:\[\d+\])*;", body)
         assert fields == [f for f, _ in cls._fields_], name
+
+
+def test_struct_offsets_match_a_c_compiler(tmp_path):
+    """Sizes and field offsets of the ABI structs as gcc lays them out."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    structs = {"om_scene_desc": _lib.OmSceneDesc, "om_params": _lib.OmParams, "om_fwd_out": _lib.OmFwdOut,
+               "om_grads": _lib.OmGrads}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "omerf.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
 
 
 def test_fwd_out_layout_matches_header():
@@ -233,3 +259,57 @@ def test_smooth_loss_validation(L):
     assert L.om_smooth_loss(h, f, f, 16, f, 4, 1.0, None, None, None, None) == 0
     assert L.om_smooth_loss(h, None, None, 0, None, 4, 1.0, None, f, f, None) == 0
     L.om_scene_destroy(h)
+
+
+def test_u8_scene_validation(L):
+    rc, h = _create(L, _desc(dtype=_lib.OM_U8))
+    assert rc == 0 and h.value
+    L.om_scene_destroy(h)
+    d = _desc(dtype=_lib.OM_U8)
+    d.quant_step[2][3] = -0.5
+    rc, h = _create(L, d)
+    assert rc == _lib.OM_ERR_INVALID and not h.value
+    d = _desc(dtype=_lib.OM_U8)
+    d.quant_lo[0][0] = math.inf
+    assert _create(L, d)[0] == _lib.OM_ERR_INVALID
+    d = _desc(dtype=_lib.OM_F32)
+    d.quant_step[0][0] = -1.0  # ignored for float scenes
+    rc, h = _create(L, d)
+    assert rc == 0
+    L.om_scene_destroy(h)
+
+
+def test_quant_params_host_matches_oracle(L):
+    """om_quant_params runs on the host: lo = min, step = fl32((max - min)/255)."""
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(5)
+    mm = np.sort(rng.standard_normal((8, 2)).astype(np.float32), axis=1)
+    mm[3] = [0.25, 0.25]  # constant channel
+    lo, step = (ctypes.c_float * 8)(), (ctypes.c_float * 8)()
+    assert L.om_quant_params((ctypes.c_float * 16)(*mm.reshape(-1).tolist()), lo, step) == 0
+    want_lo, want_step = oracle.quant_params(mm)
+    assert np.array_equal(np.array(list(lo), np.float32), want_lo)
+    assert np.array_equal(np.array(list(step), np.float32), want_step)
+    bad = mm.copy()
+    bad[1] = [1.0, 0.0]  # max < min
+    assert L.om_quant_params((ctypes.c_float * 16)(*bad.reshape(-1).tolist()), lo, step) == _lib.OM_ERR_INVALID
+    bad[1] = [0.0, math.nan]
+    assert L.om_quant_params((ctypes.c_float * 16)(*bad.reshape(-1).tolist()), lo, step) == _lib.OM_ERR_INVALID
+
+
+def test_bake_calls_validate_before_device_work(L):
+    f = ctypes.c_void_p(FAKE)
+    lo = (ctypes.c_float * 8)(*[0.0] * 8)
+    step = (ctypes.c_float * 8)(*[0.1] * 8)
+    assert L.om_feature_range(f, 0, ctypes.c_void_p(FAKE * 4), None) == _lib.OM_ERR_INVALID
+    assert L.om_feature_range(None, 10, ctypes.c_void_p(FAKE * 4), None) == _lib.OM_ERR_INVALID
+    assert L.om_feature_range(f, 10, ctypes.c_void_p(FAKE + 64), None) == _lib.OM_ERR_INVALID  # aliases x
+    assert L.om_feature_range(ctypes.c_void_p(FAKE + 4), 10, ctypes.c_void_p(FAKE * 4), None) == _lib.OM_ERR_INVALID
+    assert L.om_quantize_u8(f, -1, lo, step, ctypes.c_void_p(FAKE * 4), None) == _lib.OM_ERR_INVALID
+    neg = (ctypes.c_float * 8)(*([0.1] * 7 + [-0.1]))
+    assert L.om_quantize_u8(f, 10, lo, neg, ctypes.c_void_p(FAKE * 4), None) == _lib.OM_ERR_INVALID
+    tiny = (ctypes.c_float * 8)(*([0.1] * 7 + [1e-40]))
+    assert L.om_quantize_u8(f, 10, lo, tiny, ctypes.c_void_p(FAKE * 4), None) == _lib.OM_ERR_UNSUPPORTED
+    assert L.om_quantize_u8(f, 10, lo, step, ctypes.c_void_p(FAKE * 4 + 1), None) == _lib.OM_ERR_INVALID

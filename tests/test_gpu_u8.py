@@ -1,0 +1,170 @@
+"""GPU: 8-bit feature storage (Sec. 4.4) through the C ABI.
+
+Baking (channel ranges, quantisation parameters, codes) is compared bit for
+bit with the oracle, which takes the code decisions in the same binary32
+arithmetic.  The render of an 8-bit scene is compared with the float64
+oracle render of the decoded scene at the forward bars (placement and
+sample counts exact; C, T and F within 1e-5 with the float32 MLP), on the
+tiny scene and on a sample of the full oblique 1920x1080 frame; the
+bfloat16 MFMA MLP keeps its bf16-rounding bars.  8-bit scenes are render
+only: the backward refuses them.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2404_09531_amd as om
+import scenegen
+from tests.gpu_util import DEV, log, rays_to
+
+pytestmark = pytest.mark.gpu
+
+BG = (0.25, 0.5, 0.75)
+TOL = 1e-5
+SOURCES = ("grid", "plane_xy", "plane_xz", "plane_yz")
+
+
+def _bake(sc):
+    """GPU bake of a float32 scene dict -> (Scene, codes, (lo, step), device tensors)."""
+    t = {k: torch.from_numpy(np.ascontiguousarray(sc[k], np.float32)).to(DEV) for k in (*SOURCES, "occ", "mlp")}
+    codes, quant = om.quantize_features(t)
+    scene = om.Scene(codes["grid"], codes["plane_xy"], codes["plane_xz"], codes["plane_yz"], t["occ"], t["mlp"],
+                     box_lo=tuple(float(v) for v in sc["box_lo"]), box_hi=tuple(float(v) for v in sc["box_hi"]),
+                     quant=quant)
+    return scene, codes, quant, t
+
+
+def _compare(res, ref, rows=None, tol=TOL):
+    rows = slice(None) if rows is None else rows
+    assert np.array_equal(res["n_placed"].cpu().numpy()[rows], ref["n_placed"])
+    assert np.array_equal(res["n_eval"].cpu().numpy()[rows], ref["n_eval"])
+    for key in ("C", "T", "F"):
+        err = np.abs(res[key].double().cpu().numpy()[rows] - ref[key]).max(initial=0.0)
+        log(f"  max |{key} - oracle| = {err:.3e}")
+        assert err <= tol, key
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    sc = scenegen.make_scene(scenegen.TINY)
+    o, d = scenegen.oblique_rays(2000, seed=21)  # 125 groups of 16
+    return sc, o, d
+
+
+def test_feature_range_exact():
+    log("test_feature_range_exact")
+    rng = np.random.default_rng(4)
+    for n in (1, 37, 5000, 300001):
+        x = (rng.standard_normal((n, 8)) * rng.uniform(0.1, 3.0, 8)).astype(np.float32)
+        x[rng.integers(0, n)] = -0.0
+        got = om.feature_range(torch.from_numpy(x).to(DEV)).cpu().numpy()
+        assert np.array_equal(got, oracle.feature_range(x)), n
+
+
+def test_quantize_codes_bit_exact(tiny):
+    log("test_quantize_codes_bit_exact")
+    sc, _, _ = tiny
+    for src in SOURCES:
+        x = sc[src]
+        lo, step = oracle.quant_params(oracle.feature_range(x))
+        got = om.quantize_u8(torch.from_numpy(np.ascontiguousarray(x)).to(DEV), lo.tolist(), step.tolist())
+        assert np.array_equal(got.cpu().numpy(), oracle.quantize_u8(x, lo, step)), src
+    # special values: ties, clamping, NaN, infinities (lo = -1, step = 0.5)
+    lo, step = [-1.0] * 8, [0.5] * 8
+    vals = np.array([-1.0, -0.75, -0.25, 0.0, 126.5, 126.25, 200.0, -5.0, np.nan, np.inf, -np.inf, 0.25,
+                     -1.0 + 2.0 ** -20, 126.75, 3.0, 3.25], np.float32)
+    x = np.tile(vals[:, None], (1, 8))
+    got = om.quantize_u8(torch.from_numpy(x).to(DEV), lo, step).cpu().numpy()
+    assert np.array_equal(got, oracle.quantize_u8(x, np.float32(lo), np.float32(step)))
+    # a zero step encodes everything as 0
+    got = om.quantize_u8(torch.from_numpy(x).to(DEV), lo, [0.0] * 8).cpu().numpy()
+    assert not got.any()
+
+
+def test_bake_matches_oracle_scene(tiny):
+    log("test_bake_matches_oracle_scene")
+    sc, _, _ = tiny
+    scene, codes, (lo, step), _ = _bake(sc)
+    ref = oracle.quantize_scene(sc)
+    assert np.array_equal(np.array(lo, np.float32), ref["quant_lo"])
+    assert np.array_equal(np.array(step, np.float32), ref["quant_step"])
+    for src in SOURCES:
+        assert np.array_equal(codes[src].cpu().numpy(), ref[src]), src
+
+
+@pytest.mark.parametrize("t_term,occ_eps", [(0.0, 0.0), (1e-3, 0.0), (0.0, 0.01)])
+def test_u8_render_vs_oracle(tiny, t_term, occ_eps):
+    log(f"test_u8_render_vs_oracle: t_term={t_term} occ_eps={occ_eps}")
+    sc, o, d = tiny
+    scene, _, _, _ = _bake(sc)
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG, t_term=t_term, occ_eps=occ_eps)
+    dec = oracle.dequantize_scene(oracle.quantize_scene(sc))
+    ref = oracle.oracle_render(dec, o, d, oracle.RenderParams(n_max=64, c_bg=BG, t_term=t_term, occ_eps=occ_eps),
+                               keep_k=False)
+    if t_term > 0:  # the float64 termination decision may differ by one sample near the threshold
+        same = res["n_eval"].cpu().numpy() == ref["n_eval"]
+        assert same.mean() > 0.99
+        for key in ("C", "F"):
+            err = np.abs(res[key].double().cpu().numpy()[same] - ref[key][same]).max()
+            assert err <= TOL, key
+        return
+    _compare(res, ref)
+    assert (ref["n_placed"] > 0).sum() > 1000
+
+
+def test_u8_render_bf16_mlp(tiny):
+    log("test_u8_render_bf16_mlp")
+    sc, o, d = tiny
+    scene, _, _, _ = _bake(sc)
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG, mlp_bf16=1)
+    dec = oracle.dequantize_scene(oracle.quantize_scene(sc))
+    ref = oracle.oracle_render(dec, o, d, oracle.RenderParams(n_max=64, c_bg=BG), keep_k=False)
+    err = np.abs(res["C"].double().cpu().numpy() - ref["C"])
+    assert err.max() < 2e-2 and err.mean() < 3e-3, (err.max(), err.mean())
+    np.testing.assert_allclose(res["F"].double().cpu().numpy(), ref["F"], atol=TOL, rtol=0)
+
+
+def test_u8_scene_is_render_only(tiny):
+    log("test_u8_scene_is_render_only")
+    sc, o, d = tiny
+    scene, _, _, t = _bake(sc)
+    og, dg = rays_to(o[:64], d[:64])
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG)
+    grads = {k: torch.zeros(t[k].shape, device=DEV) for k in (*SOURCES, "mlp")}
+    with pytest.raises(om.OmerfError):
+        om.render_backward(scene, og, dg, res, torch.zeros_like(res["C"]), grads, n_max=64, c_bg=BG)
+    with pytest.raises(om.OmerfError):
+        om.render(scene, og, dg, n_max=64, c_bg=BG, batch_wv=True)
+
+
+def test_u8_oblique_1080p_sampled_parity():
+    """The bench's 8-bit form: the 1920x1080 oblique frame in its launch
+    configuration, a sample of rays checked against the oracle."""
+    log("test_u8_oblique_1080p_sampled_parity: building the oblique scene")
+    cfg, recipe = scenegen.workload("oblique-1080p")
+    sc = scenegen.make_scene(cfg)
+    o, d = scenegen.make_rays(recipe)
+    scene, codes, (lo, step), _ = _bake(sc)
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=256, c_bg=BG)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    rows = np.unique(np.concatenate([rng.choice(o.shape[0], 600, replace=False), np.arange(16),
+                                     np.arange(o.shape[0] - 21, o.shape[0])]))
+    for i, src in enumerate(SOURCES):  # quantisation parameters from the oracle's ranges
+        want_lo, want_step = oracle.quant_params(oracle.feature_range(sc[src]))
+        assert np.array_equal(np.array(lo[i], np.float32), want_lo), src
+        assert np.array_equal(np.array(step[i], np.float32), want_step), src
+    dec = dict(sc)
+    for i, src in enumerate(SOURCES):
+        dec[src] = oracle.dequantize(codes[src].cpu().numpy(), np.float32(lo[i]), np.float32(step[i]))
+    ref = oracle.oracle_render(dec, o[rows], d[rows], oracle.RenderParams(n_max=256, c_bg=BG), keep_k=False)
+    _compare(res, ref, rows)
+    # codes of a sample of grid vertices against the oracle's encoder
+    flat = sc["grid"].reshape(-1, 8)
+    pick = rng.choice(flat.shape[0], 20000, replace=False)
+    want = oracle.quantize_u8(flat[pick], np.float32(lo[0]), np.float32(step[0]))
+    assert np.array_equal(codes["grid"].reshape(-1, 8)[torch.from_numpy(pick).to(DEV)].cpu().numpy(), want)
