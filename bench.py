@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--t-term", type=float, default=0.0)
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and fwd+bwd forms")
-    ap.add_argument("--forms", default="bf16_render,fp32_fwd_bwd,fp32_fwd_bwd_soft_occ,fp32_fwd_bwd_enc_smooth,"
+    ap.add_argument("--forms", default="bf16_render,u8_render,fp32_fwd_bwd,fp32_fwd_bwd_soft_occ,fp32_fwd_bwd_enc_smooth,"
                                        "bf16_render_4k_x8,"
                                        "high_altitude_mips,towers_bf16_fwd_bwd",
                     help="comma-separated subset of forms to run")
@@ -119,7 +119,31 @@ def form_bf16_render(om, torch, t, og, dg, out, kw, samples, n, a):
     return {"Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
             "march_ms": round(mb_ms, 4), "mlp_ms": round(lb_ms, 4),
             "roofline_frac_algorithmic": round((sb * 320 + n * 64) / (mb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "psnr_vs_fp32_render_db": round(10.0 * np.log10(
+                1.0 / max(float(((outb["C"].double() - out["C"].double()) ** 2).mean().item()), 1e-30)), 2),
             "max_abs_vs_fp32_render": float((outb["C"] - out["C"]).abs().max().item())}
+
+
+def form_u8_render(om, torch, t, og, dg, out, kw, n, a):
+    """8-bit features (Sec. 4.4: the baked, deployed precision) baked on the
+    GPU from the float32 scene, float32 MLP, the same 1080p frame; quality
+    as PSNR against the float32 render."""
+    codes, quant = om.quantize_features(t)
+    scene_q = om.Scene(codes["grid"], codes["plane_xy"], codes["plane_xz"], codes["plane_yz"], t["occ"], t["mlp"],
+                       quant=quant)
+    outq = {k: torch.empty_like(v) for k, v in out.items()}
+    mq = lambda: om.render_into(scene_q, og, dg, outq, stage="march", **kw)  # noqa: E731
+    lq = lambda: om.render_into(scene_q, og, dg, outq, stage="mlp", **kw)  # noqa: E731
+    tot, (mq_ms, lq_ms) = time_stages([mq, lq], a.steps, a.warmup, torch)
+    ms = tot / a.steps
+    sq = int(outq["n_eval"].sum().item())
+    mse = float(((outq["C"].double() - out["C"].double()) ** 2).mean().item())
+    return {"Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
+            "march_ms": round(mq_ms, 4), "mlp_ms": round(lq_ms, 4),
+            "roofline_frac_algorithmic": round((sq * 160 + n * 64) / (mq_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "psnr_vs_fp32_render_db": round(10.0 * np.log10(1.0 / max(mse, 1e-30)), 2),
+            "max_abs_vs_fp32_render": float((outq["C"] - out["C"]).abs().max().item()),
+            "feature_bytes": int(sum(c.numel() for c in codes.values()))}
 
 
 def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a, occ_eps=0.0):
@@ -351,6 +375,8 @@ def main():
     want = set() if a.no_forms else set(a.forms.split(","))
     if "bf16_render" in want:
         forms["bf16_render"] = form_bf16_render(om, torch, t, og, dg, out, kw, samples, n, a)
+    if "u8_render" in want:
+        forms["u8_render"] = form_u8_render(om, torch, t, og, dg, out, kw, n, a)
     if "fp32_fwd_bwd" in want:
         forms["fp32_fwd_bwd"] = form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a)
     if "fp32_fwd_bwd_soft_occ" in want:

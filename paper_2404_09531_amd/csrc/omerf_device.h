@@ -617,9 +617,9 @@ __device__ __forceinline__ void gather_half(const SceneDev& sc, const Corners& c
     S::acc(r[9], wb * e1, t);
 }
 
-// Eq. 2 for 8-bit storage, one lane per sample: the 20 corners are loaded
-// first (8 bytes each), then each source's weighted code sums are decoded
-// with that source's per-channel (lo, step).
+// Eq. 2 for 8-bit storage, one lane per sample: the 10 corner pairs are
+// loaded first (16 bytes each), then each source's weighted code sums are
+// decoded with that source's per-channel (lo, step).
 __device__ __forceinline__ void decode_add(const SceneDev& sc, int src, const float* a, float* t) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) t[c] += fmaf(sc.qstep[8 * src + c], a[c], sc.qlo[8 * src + c]);
@@ -628,25 +628,23 @@ __device__ __forceinline__ void decode_add(const SceneDev& sc, int src, const fl
 __device__ __forceinline__ void gather_u8(const SceneDev& sc, const Corners& c, float* t) {
     const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
     const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
-    uint2 r[20];
+    // Each row's corner pair (i0, i0 + 1) is 16 contiguous bytes: one load
+    // (8-byte aligned; the hardware serves unaligned global loads).
+    uint4 r[10];
+    const uint8_t* G = static_cast<const uint8_t*>(sc.grid);
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const uint32_t base = c.g + ((p & 1) ? sy : 0u) + ((p >> 1) ? sz : 0u);
-        r[2 * p] = U8Store::load(sc.grid, base);
-        r[2 * p + 1] = U8Store::load(sc.grid, base + 1);
+        __builtin_memcpy(&r[p], G + (size_t)base * 8, 16);
     }
-    r[8] = U8Store::load(sc.pxy, c.xy);
-    r[9] = U8Store::load(sc.pxy, c.xy + 1);
-    r[10] = U8Store::load(sc.pxy, c.xy + nx);
-    r[11] = U8Store::load(sc.pxy, c.xy + nx + 1);
-    r[12] = U8Store::load(sc.pxz, c.xz);
-    r[13] = U8Store::load(sc.pxz, c.xz + 1);
-    r[14] = U8Store::load(sc.pxz, c.xz + nx);
-    r[15] = U8Store::load(sc.pxz, c.xz + nx + 1);
-    r[16] = U8Store::load(sc.pyz, c.yz);
-    r[17] = U8Store::load(sc.pyz, c.yz + 1);
-    r[18] = U8Store::load(sc.pyz, c.yz + ny);
-    r[19] = U8Store::load(sc.pyz, c.yz + ny + 1);
+    const uint8_t* P[3] = {static_cast<const uint8_t*>(sc.pxy), static_cast<const uint8_t*>(sc.pxz),
+                           static_cast<const uint8_t*>(sc.pyz)};
+    const uint32_t pb[3] = {c.xy, c.xz, c.yz}, ps[3] = {nx, nx, ny};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        __builtin_memcpy(&r[4 + 2 * q], P[q] + (size_t)pb[q] * 8, 16);
+        __builtin_memcpy(&r[5 + 2 * q], P[q] + (size_t)(pb[q] + ps[q]) * 8, 16);
+    }
 #pragma unroll
     for (int i = 0; i < 8; ++i) t[i] = 0.0f;
     float a[8];
@@ -656,8 +654,8 @@ __device__ __forceinline__ void gather_u8(const SceneDev& sc, const Corners& c, 
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const float wyz = ((p & 1) ? y1 : y0) * ((p >> 1) ? z1 : z0);
-        U8Store::acc(r[2 * p], x0 * wyz, a);
-        U8Store::acc(r[2 * p + 1], x1 * wyz, a);
+        U8Store::acc(make_uint2(r[p].x, r[p].y), x0 * wyz, a);
+        U8Store::acc(make_uint2(r[p].z, r[p].w), x1 * wyz, a);
     }
     decode_add(sc, 0, a, t);
     const float u0 = 1.0f - c.ux, u1 = c.ux, v0 = 1.0f - c.uy, v1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
@@ -667,10 +665,11 @@ __device__ __forceinline__ void gather_u8(const SceneDev& sc, const Corners& c, 
     for (int q = 0; q < 3; ++q) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) a[i] = 0.0f;
-        U8Store::acc(r[8 + 4 * q], wa[q][0] * wb[q][0], a);
-        U8Store::acc(r[9 + 4 * q], wa[q][1] * wb[q][0], a);
-        U8Store::acc(r[10 + 4 * q], wa[q][0] * wb[q][1], a);
-        U8Store::acc(r[11 + 4 * q], wa[q][1] * wb[q][1], a);
+        const uint4 lo = r[4 + 2 * q], hi = r[5 + 2 * q];
+        U8Store::acc(make_uint2(lo.x, lo.y), wa[q][0] * wb[q][0], a);
+        U8Store::acc(make_uint2(lo.z, lo.w), wa[q][1] * wb[q][0], a);
+        U8Store::acc(make_uint2(hi.x, hi.y), wa[q][0] * wb[q][1], a);
+        U8Store::acc(make_uint2(hi.z, hi.w), wa[q][1] * wb[q][1], a);
         decode_add(sc, 1 + q, a, t);
     }
 }
