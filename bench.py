@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--t-term", type=float, default=0.0)
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and fwd+bwd forms")
-    ap.add_argument("--forms", default="bf16_render,u8_render,fp32_fwd_bwd,fp32_fwd_bwd_soft_occ,fp32_fwd_bwd_enc_smooth,"
+    ap.add_argument("--forms", default="fp32_render_ert,bf16_render,u8_render,fp32_fwd_bwd,fp32_fwd_bwd_soft_occ,fp32_fwd_bwd_enc_smooth,"
                                        "bf16_render_4k_x8,"
                                        "high_altitude_mips,towers_bf16_fwd_bwd",
                     help="comma-separated subset of forms to run")
@@ -122,6 +122,21 @@ def form_bf16_render(om, torch, t, og, dg, out, kw, samples, n, a):
             "psnr_vs_fp32_render_db": round(10.0 * np.log10(
                 1.0 / max(float(((outb["C"].double() - out["C"].double()) ** 2).mean().item()), 1e-30)), 2),
             "max_abs_vs_fp32_render": float((outb["C"] - out["C"]).abs().max().item())}
+
+
+def form_fp32_render_ert(om, torch, scene, og, dg, out, kw, n, a, t_term=1e-4):
+    """The headline float32 frame with early ray termination at T < 1e-4
+    (not in the paper; reported beside the t_term = 0 value)."""
+    kw = dict(kw, t_term=t_term)
+    oute = {k: torch.empty_like(v) for k, v in out.items()}
+    me = lambda: om.render_into(scene, og, dg, oute, stage="march", **kw)  # noqa: E731
+    le = lambda: om.render_into(scene, og, dg, oute, stage="mlp", **kw)  # noqa: E731
+    tot, (me_ms, le_ms) = time_stages([me, le], a.steps, a.warmup, torch)
+    ms = tot / a.steps
+    se = int(oute["n_eval"].sum().item())
+    return {"t_term": t_term, "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
+            "march_ms": round(me_ms, 4), "mlp_ms": round(le_ms, 4), "samples_per_ray": round(se / n, 2),
+            "max_abs_vs_t_term_0": float((oute["C"] - out["C"]).abs().max().item())}
 
 
 def form_u8_render(om, torch, t, og, dg, out, kw, n, a):
@@ -375,6 +390,8 @@ def main():
     want = set() if a.no_forms else set(a.forms.split(","))
     if "bf16_render" in want:
         forms["bf16_render"] = form_bf16_render(om, torch, t, og, dg, out, kw, samples, n, a)
+    if "fp32_render_ert" in want:
+        forms["fp32_render_ert"] = form_fp32_render_ert(om, torch, scene, og, dg, out, kw, n, a)
     if "u8_render" in want:
         forms["u8_render"] = form_u8_render(om, torch, t, og, dg, out, kw, n, a)
     if "fp32_fwd_bwd" in want:
