@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--t-term", type=float, default=0.0)
     ap.add_argument("--no-forms", action="store_true", help="skip the bf16 and fwd+bwd forms")
-    ap.add_argument("--forms", default="fp32_render_ert,bf16_render,u8_render,fp32_fwd_bwd,fp32_fwd_bwd_soft_occ,fp32_fwd_bwd_enc_smooth,"
+    ap.add_argument("--forms", default="fp32_render_ert,bf16_render,u8_render,sparse_render,fp32_fwd_bwd,fp32_fwd_bwd_soft_occ,fp32_fwd_bwd_enc_smooth,"
                                        "bf16_render_4k_x8,"
                                        "high_altitude_mips,towers_bf16_fwd_bwd",
                     help="comma-separated subset of forms to run")
@@ -137,6 +137,37 @@ def form_fp32_render_ert(om, torch, scene, og, dg, out, kw, n, a, t_term=1e-4):
     return {"t_term": t_term, "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
             "march_ms": round(me_ms, 4), "mlp_ms": round(le_ms, 4), "samples_per_ray": round(se / n, 2),
             "max_abs_vs_t_term_0": float((oute["C"] - out["C"]).abs().max().item())}
+
+
+def form_sparse_render(om, torch, t, scene, og, dg, out, kw, n, a, shift=3):
+    """Sparse voxel blocks of 2^shift cells (Sec. 4.4: the baked grid kept as
+    sparse blocks chosen from the occupancy plane) on the same 1080p frame,
+    float32 and 8-bit; the renders equal the dense ones bit for bit."""
+    res = {}
+    codes, quant = om.quantize_features(t)
+    scene_q = om.Scene(codes["grid"], codes["plane_xy"], codes["plane_xz"], codes["plane_yz"], t["occ"], t["mlp"],
+                       quant=quant)
+    for name, sc_d, q, ref_out in (("f32", scene, None, out), ("u8", scene_q, quant, None)):
+        atlas, sg = om.sparse_grid(sc_d, shift)
+        src = sc_d.tensors
+        sp = om.Scene(atlas, src["plane_xy"], src["plane_xz"], src["plane_yz"], t["occ"], t["mlp"], quant=q,
+                      sparse=sg)
+        if ref_out is None:
+            ref_out = {k: torch.empty_like(v) for k, v in out.items()}
+            om.render_into(sc_d, og, dg, ref_out, **kw)
+        outs = {k: torch.empty_like(v) for k, v in out.items()}
+        ms_ = lambda: om.render_into(sp, og, dg, outs, stage="march", **kw)  # noqa: E731
+        ls_ = lambda: om.render_into(sp, og, dg, outs, stage="mlp", **kw)  # noqa: E731
+        tot, (m_ms, l_ms) = time_stages([ms_, ls_], a.steps, a.warmup, torch)
+        ms = tot / a.steps
+        res[name] = {"Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
+                     "march_ms": round(m_ms, 4), "blocks_kept": sg.n_blocks, "blocks_total": sg.blocks.numel(),
+                     "grid_bytes_sparse": atlas.numel() * atlas.element_size(),
+                     "grid_bytes_dense": src["grid"].numel() * src["grid"].element_size(),
+                     "equal_to_dense": bool(all(torch.equal(outs[k], ref_out[k]) for k in ("C", "T", "F")))}
+        del atlas, sp
+    res["block_cells"] = 1 << shift
+    return res
 
 
 def form_u8_render(om, torch, t, og, dg, out, kw, n, a):
@@ -392,6 +423,8 @@ def main():
         forms["bf16_render"] = form_bf16_render(om, torch, t, og, dg, out, kw, samples, n, a)
     if "fp32_render_ert" in want:
         forms["fp32_render_ert"] = form_fp32_render_ert(om, torch, scene, og, dg, out, kw, n, a)
+    if "sparse_render" in want:
+        forms["sparse_render"] = form_sparse_render(om, torch, t, scene, og, dg, out, kw, n, a)
     if "u8_render" in want:
         forms["u8_render"] = form_u8_render(om, torch, t, og, dg, out, kw, n, a)
     if "fp32_fwd_bwd" in want:

@@ -112,6 +112,19 @@ typedef struct om_scene_desc {
      * as 8-bit images).  Copied when the handle is created or updated. */
     float quant_lo[4][8];
     float quant_step[4][8];
+    /* Sparse voxel blocks of the grid (Sec. 4.4: the baked grid is kept as
+     * sparse blocks).  block_shift = 0: grid is the dense array above.
+     * block_shift = s in 1..5: B = 2^s cells per block edge; grid is an
+     * atlas of n_blocks + 1 blocks of (B + 1)^3 vertices ([z][y][x][8] of
+     * dtype each, one vertex of overlap with the next block), block 0 all
+     * zero; grid_blocks (device int32 [ceil((Lz-1)/B)][ceil((Ly-1)/B)]
+     * [ceil((Lx-1)/B)]) names the atlas block of each B^3 region of cells
+     * (0 for regions no sample can reach).  Ids above n_blocks read block
+     * n_blocks.  Built by om_sparse_grid_index / om_sparse_grid_fill.
+     * Render only.  (n_blocks + 1) (B + 1)^3 must be below 2^31. */
+    const int32_t* grid_blocks;
+    int32_t block_shift;
+    int32_t n_blocks;
 } om_scene_desc;
 
 /* Packed MLP parameters for an N -> 16 -> 16 -> 3 network: W1 [16][N], b1,
@@ -254,8 +267,8 @@ int om_deferred_mlp(const om_scene* scene, const float* d, int64_t n, const om_p
  * ADDED with float32 atomics into g (grid, planes, MLP; no ray gradient);
  * per-sample features are recomputed, not stored.  Summation order of the
  * atomics is not deterministic.  The MLP part is differentiated in float32
- * regardless of p->mlp_bf16.  OM_U8 scenes are render-only: the
- * backward and the fused step return OM_ERR_UNSUPPORTED for them.
+ * regardless of p->mlp_bf16.  OM_U8 and sparse-block scenes are render
+ * only: the backward and the fused step return OM_ERR_UNSUPPORTED for them.
  */
 int om_render_backward(const om_scene* scene, const float* o, const float* d, int64_t n,
                        const om_params* p, const om_fwd_out* saved, const float* dL_dC,
@@ -360,6 +373,27 @@ int om_occ_interval_loss(const float* occ, int64_t cells, float weight, double* 
 int om_feature_range(const float* x, int64_t n, float* minmax, void* stream);
 int om_quant_params(const float* minmax_host, float* lo, float* step);
 int om_quantize_u8(const float* x, int64_t n, const float* lo, const float* step, uint8_t* out, void* stream);
+
+/*
+ * Sparse voxel blocks for a dense scene handle (its grid, occupancy plane and
+ * dtype), block edge B = 2^block_shift cells (1 <= block_shift <= 5):
+ *  - om_sparse_grid_index: writes the block index grid_blocks (device int32
+ *    [ceil((Lz-1)/B)][ceil((Ly-1)/B)][ceil((Lx-1)/B)], idx_len entries) and
+ *    returns the number of kept blocks (>= 0), or -1 with om_last_error
+ *    set.  A block is kept if an occupancy column overlapping its xy extent
+ *    (one column of padding) has an interval meeting its z extent (one cell
+ *    of padding), so every block holding a placeable sample is kept.  Ids
+ *    are 1.. in index order.  Synchronous: it waits for `stream`.
+ *  - om_sparse_grid_fill: copies the kept blocks into the caller's atlas
+ *    (device, (n_blocks + 1) (B + 1)^3 vertices of the scene dtype, 16-byte
+ *    aligned) and zeroes block 0.
+ * The sparse scene is then created with the atlas as grid and grid_blocks,
+ * block_shift and n_blocks set; it renders exactly like the dense one.
+ */
+int64_t om_sparse_grid_index(const om_scene* scene, int block_shift, int32_t* grid_blocks, int64_t idx_len,
+                             void* stream);
+int om_sparse_grid_fill(const om_scene* scene, int block_shift, const int32_t* grid_blocks, int64_t n_blocks,
+                        void* atlas, void* stream);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* om_last_error(void);

@@ -39,7 +39,7 @@ _FREQS_OF = {mlp_nparams(0): 0, mlp_nparams(4): 4}
 
 __all__ = ["Scene", "place_samples", "render", "render_backward", "RenderFn", "SmoothFn", "smooth_loss",
            "l2_loss_fp64", "l2_loss_grad", "occ_interval_loss", "mlp_nparams", "feature_range", "quant_params",
-           "quantize_u8", "quantize_features", "DELTA", "OmerfError",
+           "quantize_u8", "quantize_features", "sparse_grid", "SparseGrid", "DELTA", "OmerfError",
            "OM_MAX_SAMPLES", "to_bf16"]
 
 
@@ -74,19 +74,27 @@ class Scene:
 
     def __init__(self, grid, plane_xy, plane_xz, plane_yz, occ, mlp,
                  box_lo: Sequence[float] = (-1.0, -1.0, 0.0), box_hi: Sequence[float] = (1.0, 1.0, 0.25),
-                 quant=None):
+                 quant=None, sparse=None):
         self._handle = ctypes.c_void_p()
         self.mips, self.mip_levels = None, 0
-        self._set(grid, plane_xy, plane_xz, plane_yz, occ, mlp, box_lo, box_hi, quant)
+        self._set(grid, plane_xy, plane_xz, plane_yz, occ, mlp, box_lo, box_hi, quant, sparse)
         _lib.check("om_scene_create", _lib.lib().om_scene_create(ctypes.byref(self._desc), ctypes.byref(self._handle)))
 
-    def _set(self, grid, plane_xy, plane_xz, plane_yz, occ, mlp, box_lo, box_hi, quant=None):
+    def _set(self, grid, plane_xy, plane_xz, plane_yz, occ, mlp, box_lo, box_hi, quant=None, sparse=None):
         dt = grid.dtype
         if dt not in (torch.float32, torch.bfloat16, torch.uint8):
             raise TypeError("grid/planes must be float32, bfloat16 or uint8")
         if (dt == torch.uint8) != (quant is not None):
             raise ValueError("uint8 features need quant=(lo, step), [4, 8] each; other dtypes take none")
-        lz, ly, lx, ch = grid.shape
+        if sparse is None:
+            lz, ly, lx, ch = grid.shape
+        else:  # atlas [n_blocks + 1, B + 1, B + 1, B + 1, 8] over a logical (Lx, Ly, Lz) grid
+            lx, ly, lz = sparse.dims
+            e = (1 << sparse.shift) + 1
+            ch = grid.shape[-1]
+            if tuple(grid.shape) != (sparse.n_blocks + 1, e, e, e, 8):
+                raise ValueError(f"sparse grid atlas must be [{sparse.n_blocks + 1}, {e}, {e}, {e}, 8]")
+            _need(sparse.blocks, "grid_blocks", torch.int32, sparse.index_shape())
         if ch != 8:
             raise ValueError("8 channels expected")
         ny, nx = plane_xy.shape[:2]
@@ -118,6 +126,9 @@ class Scene:
         d.occ, d.mlp = occ.data_ptr(), mlp.data_ptr()
         d.dir_freqs = _FREQS_OF[mlp.numel()]
         self.dir_freqs = d.dir_freqs
+        if sparse is not None:
+            d.grid_blocks, d.block_shift, d.n_blocks = sparse.blocks.data_ptr(), sparse.shift, sparse.n_blocks
+        self.sparse = sparse
         self._desc = d
         self.tensors = dict(grid=grid, plane_xy=plane_xy, plane_xz=plane_xz, plane_yz=plane_yz, occ=occ, mlp=mlp)
         self.dtype = dt
@@ -126,16 +137,17 @@ class Scene:
     def update(self, **tensors) -> None:
         """Re-point the handle at new tensors (same keys as the constructor)."""
         quant = tensors.pop("quant", self.quant)
+        sparse = tensors.pop("sparse", self.sparse)
         t = dict(self.tensors)
         t.update(tensors)
         if t["grid"].dtype != torch.uint8:
             quant = None
-        old = (self._desc, self.tensors, self.dtype, self.quant, self.dir_freqs)
+        old = (self._desc, self.tensors, self.dtype, self.quant, self.dir_freqs, self.sparse)
         self._set(t["grid"], t["plane_xy"], t["plane_xz"], t["plane_yz"], t["occ"], t["mlp"],
-                  tuple(self._desc.box_lo), tuple(self._desc.box_hi), quant)
+                  tuple(self._desc.box_lo), tuple(self._desc.box_hi), quant, sparse)
         rc = _lib.lib().om_scene_update(self._handle, ctypes.byref(self._desc))
         if rc != 0:
-            self._desc, self.tensors, self.dtype, self.quant, self.dir_freqs = old
+            self._desc, self.tensors, self.dtype, self.quant, self.dir_freqs, self.sparse = old
             _lib.check("om_scene_update", rc)
         self.mips = None  # the library detached the pyramid; build it again if wanted
         self.mip_levels = 0
@@ -416,6 +428,44 @@ class SmoothFn(torch.autograd.Function):
         gF, gW = ctx.saved_tensors
         s = g.to(torch.float32)
         return None, gF * s, None, None, None, gW * s
+
+
+class SparseGrid:
+    """Sparse voxel-block layout of a grid (Sec. 4.4): blocks of 2^shift
+    cells per edge over a logical (Lx, Ly, Lz) grid; `blocks` is the int32
+    block index, the atlas (the Scene's grid tensor) holds n_blocks + 1
+    blocks of (B + 1)^3 vertices, block 0 all zero."""
+
+    def __init__(self, blocks: torch.Tensor, shift: int, n_blocks: int, dims):
+        self.blocks, self.shift, self.n_blocks, self.dims = blocks, int(shift), int(n_blocks), tuple(dims)
+
+    def index_shape(self):
+        b = 1 << self.shift
+        lx, ly, lz = self.dims
+        return ((lz - 2) // b + 1, (ly - 2) // b + 1, (lx - 2) // b + 1)
+
+
+def sparse_grid(scene: "Scene", shift: int = 3):
+    """Bake the dense grid of `scene` into sparse voxel blocks of 2^shift
+    cells per edge (om_sparse_grid_index, om_sparse_grid_fill).  Returns
+    (atlas tensor of the scene's dtype, SparseGrid) for
+    Scene(atlas, ..., sparse=SparseGrid) (with quant= for 8-bit scenes)."""
+    if scene.sparse is not None:
+        raise ValueError("the scene's grid is already sparse")
+    lz, ly, lx, _ = scene.tensors["grid"].shape
+    sg = SparseGrid(None, shift, 0, (lx, ly, lz))
+    blocks = torch.empty(sg.index_shape(), dtype=torch.int32, device=scene.device)
+    L = _lib.lib()
+    n = L.om_sparse_grid_index(scene.handle, shift, blocks.data_ptr(), blocks.numel(),
+                               _lib.stream_of(scene.tensors["grid"]))
+    if n < 0:
+        raise _lib.OmerfError("om_sparse_grid_index", _lib.OM_ERR_INVALID, L.om_last_error().decode())
+    e = (1 << shift) + 1
+    atlas = torch.empty((n + 1, e, e, e, 8), dtype=scene.dtype, device=scene.device)
+    _lib.check("om_sparse_grid_fill", L.om_sparse_grid_fill(scene.handle, shift, blocks.data_ptr(), n,
+                                                            atlas.data_ptr(), _lib.stream_of(atlas)))
+    sg.blocks, sg.n_blocks = blocks, n
+    return atlas, sg
 
 
 def feature_range(x: torch.Tensor) -> torch.Tensor:

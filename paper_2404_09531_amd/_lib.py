@@ -23,6 +23,7 @@ EXPORTS = ("om_scene_create", "om_scene_update", "om_scene_destroy", "om_occupan
            "om_deferred_mlp", "om_render",
            "om_render_backward", "om_render_backward_ex", "om_smooth_loss", "om_render_fwd_bwd_l2", "om_render_fwd_bwd_l2_workspace_size",
            "om_occ_interval_loss", "om_feature_range", "om_quant_params", "om_quantize_u8",
+           "om_sparse_grid_index", "om_sparse_grid_fill",
            "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str",
            "om_version")
 
@@ -32,7 +33,8 @@ class OmSceneDesc(ctypes.Structure):
                 ("plane_dims", c_int32 * 3), ("occ_dims", c_int32 * 2), ("dtype", c_int32),
                 ("grid", c_void_p), ("plane_xy", c_void_p), ("plane_xz", c_void_p), ("plane_yz", c_void_p),
                 ("occ", c_void_p), ("mlp", c_void_p), ("dir_freqs", c_int32),
-                ("quant_lo", (c_float * 8) * 4), ("quant_step", (c_float * 8) * 4)]
+                ("quant_lo", (c_float * 8) * 4), ("quant_step", (c_float * 8) * 4),
+                ("grid_blocks", c_void_p), ("block_shift", c_int32), ("n_blocks", c_int32)]
 
 
 class OmParams(ctypes.Structure):
@@ -83,6 +85,8 @@ def lib() -> ctypes.CDLL:
         L.om_feature_range.argtypes = [c_void_p, c_int64, c_void_p, c_void_p]
         L.om_quant_params.argtypes = [POINTER(c_float), POINTER(c_float), POINTER(c_float)]
         L.om_quantize_u8.argtypes = [c_void_p, c_int64, POINTER(c_float), POINTER(c_float), c_void_p, c_void_p]
+        L.om_sparse_grid_index.argtypes = [c_void_p, c_int, c_void_p, c_int64, c_void_p]
+        L.om_sparse_grid_fill.argtypes = [c_void_p, c_int, c_void_p, c_int64, c_void_p, c_void_p]
         L.om_l2_loss_fp64.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
         L.om_l2_loss_grad.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
         L.om_render_fwd_bwd_l2.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(OmParams), c_void_p,
@@ -101,6 +105,7 @@ def lib() -> ctypes.CDLL:
                 getattr(L, name).restype = c_int
         L.om_render_fwd_bwd_l2_workspace_size.restype = c_int64
         L.om_occupancy_mips_size.restype = c_int64
+        L.om_sparse_grid_index.restype = c_int64
         _lib = L
     return _lib
 

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/omerf.h"
 #include "omerf_device.h"
@@ -101,6 +102,14 @@ int validate_desc(const om_scene_desc* d, SceneDev* out) {
         }
     }
     if (d->dir_freqs != 0 && d->dir_freqs != 4) return fail(OM_ERR_UNSUPPORTED, "dir_freqs must be 0 or 4");
+    if (d->block_shift < 0 || d->block_shift > 5) return fail(OM_ERR_INVALID, "block_shift must be in 0 .. 5");
+    if (d->block_shift > 0) {
+        const int64_t E = ((int64_t)1 << d->block_shift) + 1;
+        if (!d->grid_blocks || ((uintptr_t)d->grid_blocks & 3u))
+            return fail(OM_ERR_INVALID, "grid_blocks must be a 4-byte aligned device pointer");
+        if (d->n_blocks < 0 || ((int64_t)d->n_blocks + 1) * E * E * E >= ((int64_t)1 << 31))
+            return fail(OM_ERR_UNSUPPORTED, "n_blocks must be >= 0 with (n_blocks + 1) (B + 1)^3 < 2^31");
+    }
     const void* ptrs[6] = {d->grid, d->plane_xy, d->plane_xz, d->plane_yz, d->occ, d->mlp};
     const char* names[6] = {"grid", "plane_xy", "plane_xz", "plane_yz", "occ", "mlp"};
     for (int i = 0; i < 6; ++i) {
@@ -117,6 +126,24 @@ int validate_desc(const om_scene_desc* d, SceneDev* out) {
     s.occ = reinterpret_cast<const float2*>(d->occ);
     s.mlp = d->mlp;
     s.mlp_in = 10 + 6 * d->dir_freqs;
+    s.gsy = (uint32_t)d->grid_dims[0];
+    s.gsz = (uint32_t)d->grid_dims[0] * (uint32_t)d->grid_dims[1];
+    s.blk_idx = nullptr;
+    s.blk_shift = 0;
+    s.bnx = s.bny = 0;
+    s.blk_verts = 0;
+    s.n_blocks = 0;
+    if (d->block_shift > 0) {
+        const int B = 1 << d->block_shift;
+        s.blk_shift = d->block_shift;
+        s.blk_idx = d->grid_blocks;
+        s.bnx = (d->grid_dims[0] - 2) / B + 1;  // ceil((L - 1) / B)
+        s.bny = (d->grid_dims[1] - 2) / B + 1;
+        s.gsy = (uint32_t)(B + 1);
+        s.gsz = (uint32_t)((B + 1) * (B + 1));
+        s.blk_verts = (uint32_t)((B + 1) * (B + 1) * (B + 1));
+        s.n_blocks = (uint32_t)d->n_blocks;
+    }
     for (int i = 0; i < 32; ++i) {
         s.qlo[i] = d->dtype == OM_U8 ? (&d->quant_lo[0][0])[i] : 0.0f;
         s.qstep[i] = d->dtype == OM_U8 ? (&d->quant_step[0][0])[i] : 0.0f;
@@ -277,8 +304,8 @@ int check_fwd(const om_scene* scene, const float* o, const float* d, int64_t n, 
         return fail(OM_ERR_INVALID, "required om_fwd_out buffers are NULL");
     if (out->batch_wv && ((uintptr_t)out->batch_wv & 3u))
         return fail(OM_ERR_INVALID, "batch_wv must be 4-byte aligned");
-    if (out->batch_wv && scene->desc.dtype == OM_U8)
-        return fail(OM_ERR_UNSUPPORTED, "8-bit scenes are render-only: batch_wv must be NULL");
+    if (out->batch_wv && (scene->desc.dtype == OM_U8 || scene->desc.block_shift > 0))
+        return fail(OM_ERR_UNSUPPORTED, "8-bit and sparse-block scenes are render-only: batch_wv must be NULL");
     return OM_OK;
 }
 
@@ -333,7 +360,8 @@ int om_render_backward_ex(const om_scene* scene, const float* o, const float* d,
     if (rc != OM_OK) return rc;
     RayParams rp;
     if ((rc = validate_params(p, &rp)) != OM_OK) return rc;
-    if (scene->desc.dtype == OM_U8) return fail(OM_ERR_UNSUPPORTED, "8-bit scenes are render-only");
+    if (scene->desc.dtype == OM_U8 || scene->desc.block_shift > 0)
+        return fail(OM_ERR_UNSUPPORTED, "8-bit and sparse-block scenes are render-only");
     if (!saved || !g) return fail(OM_ERR_INVALID, "saved / grads struct is NULL");
     if (n == 0) return ok();
     if (!saved->F || !saved->T || !saved->n_eval) return fail(OM_ERR_INVALID, "saved F, T and n_eval are required");
@@ -367,7 +395,8 @@ int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, 
     RayParams rp;
     int rc = check_fwd(scene, o, d, n, p, out, true, true, &rp);
     if (rc != OM_OK) return rc;
-    if (scene->desc.dtype == OM_U8) return fail(OM_ERR_UNSUPPORTED, "8-bit scenes are render-only");
+    if (scene->desc.dtype == OM_U8 || scene->desc.block_shift > 0)
+        return fail(OM_ERR_UNSUPPORTED, "8-bit and sparse-block scenes are render-only");
     if (n == 0) return ok();
     if (!target || !g) return fail(OM_ERR_INVALID, "target / grads is NULL");
     if (!g->grid || !g->plane_xy || !g->plane_xz || !g->plane_yz || !g->mlp)
@@ -461,6 +490,63 @@ int om_quantize_u8(const float* x, int64_t n, const float* lo, const float* step
     return hip_status(launch_quantize(x, n, lo, inv, out, (hipStream_t)stream), "om_quantize_u8");
 }
 
+namespace {
+int sparse_dims(const om_scene* scene, int block_shift, int* bn) {
+    if (!scene) return fail(OM_ERR_INVALID, "scene is NULL");
+    if (block_shift < 1 || block_shift > 5) return fail(OM_ERR_INVALID, "block_shift must be in 1 .. 5");
+    if (scene->desc.block_shift > 0) return fail(OM_ERR_INVALID, "the scene's grid is already sparse");
+    const int B = 1 << block_shift;
+    for (int a = 0; a < 3; ++a) bn[a] = (scene->desc.grid_dims[a] - 2) / B + 1;
+    return OM_OK;
+}
+}  // namespace
+
+int64_t om_sparse_grid_index(const om_scene* scene, int block_shift, int32_t* grid_blocks, int64_t idx_len,
+                             void* stream) {
+    int bn[3];
+    if (sparse_dims(scene, block_shift, bn) != OM_OK) return -1;
+    const int64_t n = (int64_t)bn[0] * bn[1] * bn[2];
+    if (!grid_blocks || idx_len != n) {
+        fail(OM_ERR_INVALID, "grid_blocks must hold %lld entries", (long long)n);
+        return -1;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_blocks_mark(scene->dev, block_shift, bn[0], bn[1], bn[2], grid_blocks, s);
+    std::vector<int32_t> mark((size_t)n);
+    if (e == hipSuccess) e = hipMemcpyAsync(mark.data(), grid_blocks, (size_t)n * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        hip_status(e, "om_sparse_grid_index");
+        return -1;
+    }
+    int64_t kept = 0;
+    for (int64_t i = 0; i < n; ++i) mark[(size_t)i] = mark[(size_t)i] ? (int32_t)(++kept) : 0;
+    e = hipMemcpyAsync(grid_blocks, mark.data(), (size_t)n * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        hip_status(e, "om_sparse_grid_index");
+        return -1;
+    }
+    ok();
+    return kept;
+}
+
+int om_sparse_grid_fill(const om_scene* scene, int block_shift, const int32_t* grid_blocks, int64_t n_blocks,
+                        void* atlas, void* stream) {
+    int bn[3];
+    int rc = sparse_dims(scene, block_shift, bn);
+    if (rc != OM_OK) return rc;
+    if (!grid_blocks || !atlas || ((uintptr_t)atlas & 15u))
+        return fail(OM_ERR_INVALID, "grid_blocks and a 16-byte aligned atlas are required");
+    const int64_t E = ((int64_t)1 << block_shift) + 1;
+    if (n_blocks < 0 || (n_blocks + 1) * E * E * E >= ((int64_t)1 << 31))
+        return fail(OM_ERR_UNSUPPORTED, "n_blocks must be >= 0 with (n_blocks + 1) (B + 1)^3 < 2^31");
+    const int units = scene->desc.dtype == OM_F32 ? 4 : scene->desc.dtype == OM_BF16 ? 2 : 1;
+    return hip_status(launch_blocks_fill(scene->dev, block_shift, bn[0], bn[1], bn[2], grid_blocks, n_blocks, units,
+                                         atlas, (hipStream_t)stream),
+                      "om_sparse_grid_fill");
+}
+
 int om_l2_loss_fp64(const float* C, const float* target, int64_t n, double* out, void* stream) {
     if (n <= 0) return fail(OM_ERR_INVALID, "n must be > 0");
     if (!C || !target || !out) return fail(OM_ERR_INVALID, "NULL pointer");
@@ -486,6 +572,6 @@ const char* om_status_str(int status) {
     }
 }
 
-int om_version(void) { return 106; }
+int om_version(void) { return 107; }
 
 }  // extern "C"

@@ -8,6 +8,8 @@
 //              on the order-preserving integer image of the values.
 // k_quantize : q = clamp(rint(fl32(fl32(x - lo) * inv)), 0, 255), the code
 //              decision taken in binary32 (NaN -> 0).
+// k_blocks_* : sparse voxel-block storage of the grid (which blocks to
+//              keep, and the copy into the block atlas).
 #include "../../include/omerf.h"
 #include "omerf_device.h"
 #include "omerf_launch.h"
@@ -97,6 +99,85 @@ hipError_t launch_quantize(const float* x, int64_t n, const float* lo, const flo
     }
     const int64_t blocks = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_quantize, dim3((unsigned)blocks), dim3(kBlock), 0, s, x, n, qp, reinterpret_cast<uint2*>(out));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sparse voxel blocks of the grid (Sec. 4.4: the baked grid is stored as
+// sparse blocks, chosen from the occupancy plane).  A block covers B^3
+// cells; it is kept if some occupancy column overlapping its xy extent (one
+// column of padding) has an interval meeting its z extent (one cell of
+// padding), which holds for every block that contains a placed sample.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_blocks_mark(SceneDev sc, int shift, int bnx, int bny, int bnz,
+                                                        int32_t* __restrict__ mark) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= (int64_t)bnx * bny * bnz) return;
+    const int bx = (int)(i % bnx), by = (int)((i / bnx) % bny), bz = (int)(i / ((int64_t)bnx * bny));
+    const int B = 1 << shift;
+    // vertex ranges of the block's cells
+    const int x0 = bx * B, x1 = min(x0 + B, sc.Lx - 1);
+    const int y0 = by * B, y1 = min(y0 + B, sc.Ly - 1);
+    const int z0 = bz * B, z1 = min(z0 + B, sc.Lz - 1);
+    const float hx = (sc.hi0 - sc.lo0) / (float)(sc.Lx - 1), hy = (sc.hi1 - sc.lo1) / (float)(sc.Ly - 1);
+    const float hz = (sc.hi2 - sc.lo2) / (float)(sc.Lz - 1);
+    const float za = sc.lo2 + (float)(z0 - 1) * hz, zb = sc.lo2 + (float)(z1 + 1) * hz;
+    const int cx0 = max(0, (int)floorf((float)x0 * hx * sc.occ_sx) - 1);
+    const int cx1 = min(sc.Mx - 1, (int)floorf((float)x1 * hx * sc.occ_sx) + 1);
+    const int cy0 = max(0, (int)floorf((float)y0 * hy * sc.occ_sy) - 1);
+    const int cy1 = min(sc.My - 1, (int)floorf((float)y1 * hy * sc.occ_sy) + 1);
+    int keep = 0;
+    for (int cy = cy0; cy <= cy1 && !keep; ++cy)
+        for (int cx = cx0; cx <= cx1; ++cx) {
+            const float2 z = sc.occ[(size_t)cy * sc.Mx + cx];
+            if (z.x <= z.y && z.x <= zb && z.y >= za) {
+                keep = 1;
+                break;
+            }
+        }
+    mark[i] = keep;
+}
+
+hipError_t launch_blocks_mark(const SceneDev& sc, int shift, int bnx, int bny, int bnz, int32_t* mark, hipStream_t s) {
+    const int64_t n = (int64_t)bnx * bny * bnz;
+    hipLaunchKernelGGL(k_blocks_mark, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, sc, shift, bnx,
+                       bny, bnz, mark);
+    return hipGetLastError();
+}
+
+// One workgroup per block-index entry: copies the (B + 1)^3 vertices of a
+// kept block (vertices past the grid's last one are zero) into its atlas
+// slot; workgroup 0 of the first launch also zeroes atlas block 0.
+__global__ __launch_bounds__(kBlock) void k_blocks_fill(SceneDev sc, int shift, int bnx, int bny,
+                                                        const int32_t* __restrict__ idx, int64_t n_blocks, int units,
+                                                        uint2* __restrict__ atlas) {
+    const int64_t e = blockIdx.x;
+    const int B = 1 << shift, E = B + 1;
+    const int64_t per = (int64_t)E * E * E * units;  // 8-byte units per block
+    if (e == 0) {
+        for (int64_t u = threadIdx.x; u < per; u += kBlock) atlas[u] = make_uint2(0u, 0u);
+    }
+    const int32_t id = idx[e];
+    if (id <= 0 || id > n_blocks) return;  // ids past the atlas are not written
+    const int bx = (int)(e % bnx), by = (int)((e / bnx) % bny), bz = (int)(e / ((int64_t)bnx * bny));
+    const uint2* src = reinterpret_cast<const uint2*>(sc.grid);
+    uint2* dst = atlas + (int64_t)id * per;
+    for (int64_t u = threadIdx.x; u < per; u += kBlock) {
+        const int v = (int)(u / units), w = (int)(u - (int64_t)v * units);
+        const int lx = v % E, ly = (v / E) % E, lz = v / (E * E);
+        const int x = bx * B + lx, y = by * B + ly, z = bz * B + lz;
+        uint2 val = make_uint2(0u, 0u);
+        if (x < sc.Lx && y < sc.Ly && z < sc.Lz)
+            val = src[(((int64_t)z * sc.Ly + y) * sc.Lx + x) * units + w];
+        dst[u] = val;
+    }
+}
+
+hipError_t launch_blocks_fill(const SceneDev& sc, int shift, int bnx, int bny, int bnz, const int32_t* idx,
+                              int64_t n_blocks, int units, void* atlas, hipStream_t s) {
+    const int64_t n = (int64_t)bnx * bny * bnz;
+    hipLaunchKernelGGL(k_blocks_fill, dim3((unsigned)n), dim3(kBlock), 0, s, sc, shift, bnx, bny, idx, n_blocks, units,
+                       reinterpret_cast<uint2*>(atlas));
     return hipGetLastError();
 }
 

@@ -128,7 +128,7 @@ __device__ __forceinline__ void store_group_total(float x, int gl, float* dst) {
     if (gl == kGroup - 1) *dst = x;
 }
 
-template <class S, bool kBW, bool kSoft>
+template <class S, bool kBW, bool kSoft, bool kSparse>
 __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                            const float* __restrict__ d_, int64_t n,
                                                            float* __restrict__ F, float* __restrict__ T,
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
                 float msoft = 0.0f;
                 if (act) {
                     const float3 p = lattice_point(ks, o, d, rp.delta);
-                    gather_half<S>(sc, corners_of(sc, p), half, t);
+                    gather_half<S>(sc, corners_of<kSparse>(sc, p), half, t);
                     if (kSoft) msoft = occ_value(sc, p, rp.occ_inv_eps).m;
                 }
 #pragma unroll
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
 // sample s of the batch with 20 corner loads, and the batch of 16 samples is
 // composited with one 16-lane scan.
 // ---------------------------------------------------------------------------
-template <bool kSoft>
+template <bool kSoft, bool kSparse>
 __global__ __launch_bounds__(kBlock) void k_march_fwd_u8(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                          const float* __restrict__ d_, int64_t n,
                                                          float* __restrict__ F, float* __restrict__ T,
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_u8(SceneDev sc, RayParams 
         float msoft = 0.0f;
         if (act) {
             const float3 p = lattice_point(kq, o, d, rp.delta);
-            gather_u8(sc, corners_of(sc, p), t);
+            gather_u8(sc, corners_of<kSparse>(sc, p), t);
             if (kSoft) msoft = occ_value(sc, p, rp.occ_inv_eps).m;
         }
         float a = 0.0f;
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_u8(SceneDev sc, RayParams 
 // are gathered before the batch is composited, so their loads overlap.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void quad_gather(const SceneDev& sc, const Corners& c, int h, int ch, float* t) {
-    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
+    const uint32_t sy = sc.gsy, sz = sc.gsz;
     const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
     const uint32_t hh = (uint32_t)h;
     const float4* G = reinterpret_cast<const float4*>(sc.grid) + ch;
@@ -353,7 +353,7 @@ __device__ __forceinline__ void quad_gather(const SceneDev& sc, const Corners& c
     }
 }
 
-template <bool kBW, bool kSoft>
+template <bool kBW, bool kSoft, bool kSparse>
 __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                            const float* __restrict__ d_, int64_t n,
                                                            float* __restrict__ F, float* __restrict__ T,
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParam
             msoft[j] = 0.0f;
             if (i < nb) {
                 const float3 p = lattice_point(ks, o, d, rp.delta);
-                quad_gather(sc, corners_of(sc, p), h, ch, t);
+                quad_gather(sc, corners_of<kSparse>(sc, p), h, ch, t);
                 if (kSoft) msoft[j] = occ_value(sc, p, rp.occ_inv_eps).m;
             }
 #pragma unroll
@@ -848,27 +848,28 @@ hipError_t launch_place(const SceneDev& sc, const RayParams& rp, const float* o,
     return hipGetLastError();
 }
 
-template <bool kSoft>
+template <bool kSoft, bool kSparse>
 static void launch_fwd_soft(const SceneDev& sc, int dtype, const RayParams& rp, const float* o, const float* d,
                             int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, float* batch_wv,
                             hipStream_t s) {
     const dim3 grid(blocks_for(n)), block(kBlock);
     if (dtype == OM_U8) {  // render only: no per-batch sums
-        hipLaunchKernelGGL((k_march_fwd_u8<kSoft>), grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed, n_eval);
+        hipLaunchKernelGGL((k_march_fwd_u8<kSoft, kSparse>), grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed,
+                           n_eval);
     } else if (dtype == OM_BF16) {
         if (batch_wv)
-            hipLaunchKernelGGL((k_march_fwd<BF16Store, true, kSoft>), grid, block, 0, s, sc, rp, o, d, n, F, T,
-                               n_placed, n_eval, batch_wv);
+            hipLaunchKernelGGL((k_march_fwd<BF16Store, true, kSoft, kSparse>), grid, block, 0, s, sc, rp, o, d, n, F,
+                               T, n_placed, n_eval, batch_wv);
         else
-            hipLaunchKernelGGL((k_march_fwd<BF16Store, false, kSoft>), grid, block, 0, s, sc, rp, o, d, n, F, T,
-                               n_placed, n_eval, batch_wv);
+            hipLaunchKernelGGL((k_march_fwd<BF16Store, false, kSoft, kSparse>), grid, block, 0, s, sc, rp, o, d, n, F,
+                               T, n_placed, n_eval, batch_wv);
     } else {
         if (batch_wv)
-            hipLaunchKernelGGL((k_march_fwd_f32q<true, kSoft>), grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed,
-                               n_eval, batch_wv);
+            hipLaunchKernelGGL((k_march_fwd_f32q<true, kSoft, kSparse>), grid, block, 0, s, sc, rp, o, d, n, F, T,
+                               n_placed, n_eval, batch_wv);
         else
-            hipLaunchKernelGGL((k_march_fwd_f32q<false, kSoft>), grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed,
-                               n_eval, batch_wv);
+            hipLaunchKernelGGL((k_march_fwd_f32q<false, kSoft, kSparse>), grid, block, 0, s, sc, rp, o, d, n, F, T,
+                               n_placed, n_eval, batch_wv);
     }
 }
 
@@ -877,10 +878,18 @@ hipError_t launch_march_fwd(const SceneDev& sc, int dtype, const RayParams& rp, 
                             hipStream_t s) {
     // The per-batch sums and the soft occupancy are separate
     // specialisations, so the plain render path carries neither.
-    if (rp.occ_inv_eps > 0.0f)
-        launch_fwd_soft<true>(sc, dtype, rp, o, d, n, F, T, n_placed, n_eval, batch_wv, s);
-    else
-        launch_fwd_soft<false>(sc, dtype, rp, o, d, n, F, T, n_placed, n_eval, batch_wv, s);
+    // Sparse blocks are render only (the API refuses per-batch sums for them).
+    const bool soft = rp.occ_inv_eps > 0.0f;
+    if (sc.blk_shift > 0) {
+        if (soft)
+            launch_fwd_soft<true, true>(sc, dtype, rp, o, d, n, F, T, n_placed, n_eval, nullptr, s);
+        else
+            launch_fwd_soft<false, true>(sc, dtype, rp, o, d, n, F, T, n_placed, n_eval, nullptr, s);
+    } else if (soft) {
+        launch_fwd_soft<true, false>(sc, dtype, rp, o, d, n, F, T, n_placed, n_eval, batch_wv, s);
+    } else {
+        launch_fwd_soft<false, false>(sc, dtype, rp, o, d, n, F, T, n_placed, n_eval, batch_wv, s);
+    }
     return hipGetLastError();
 }
 

@@ -51,6 +51,16 @@ struct SceneDev {
     // 8-bit storage: channel c of source s (grid, XY, XZ, YZ) decodes as
     // qlo[8 s + c] + q qstep[8 s + c]; indexed with constants only.
     float qlo[32], qstep[32];
+    // Grid row strides in vertices: (Lx, Lx Ly) for the dense grid,
+    // (B + 1, (B + 1)^2) inside a sparse block.
+    uint32_t gsy, gsz;
+    // Sparse voxel blocks (blk_shift > 0): the grid is an atlas of
+    // (B + 1)^3-vertex blocks (B = 2^blk_shift cells per edge, one vertex
+    // of overlap so a cell never straddles blocks); blk_idx[bz][by][bx]
+    // names the block of each B^3 cell region, 0 being an all-zero block.
+    const int32_t* blk_idx;
+    int blk_shift, bnx, bny;
+    uint32_t blk_verts, n_blocks;
 };
 
 struct RayParams {
@@ -299,6 +309,9 @@ struct Corners {
     float ux, uy, uz;        // plane fractions
 };
 
+// kSparse: the grid is the atlas of sparse voxel blocks (a separate
+// specialisation, so the dense kernels carry no block lookup).
+template <bool kSparse = false>
 __device__ __forceinline__ Corners corners_of(const SceneDev& sc, float3 p) {
     Corners c;
     axis_coord(p.x, sc.gx, c.ix, c.fx);
@@ -307,7 +320,15 @@ __device__ __forceinline__ Corners corners_of(const SceneDev& sc, float3 p) {
     axis_coord(p.x, sc.px, c.jx, c.ux);
     axis_coord(p.y, sc.py, c.jy, c.uy);
     axis_coord(p.z, sc.pz, c.jz, c.uz);
-    c.g = ((uint32_t)c.iz * (uint32_t)sc.Ly + (uint32_t)c.iy) * (uint32_t)sc.Lx + (uint32_t)c.ix;
+    if (kSparse) {
+        const int m = (1 << sc.blk_shift) - 1;
+        const int32_t id = sc.blk_idx[((c.iz >> sc.blk_shift) * sc.bny + (c.iy >> sc.blk_shift)) * sc.bnx +
+                                      (c.ix >> sc.blk_shift)];
+        const uint32_t b = min((uint32_t)id, sc.n_blocks);  // a stray id reads a stored block, never past the atlas
+        c.g = b * sc.blk_verts + ((uint32_t)(c.iz & m) * sc.gsy + (uint32_t)(c.iy & m)) * sc.gsy + (uint32_t)(c.ix & m);
+    } else {
+        c.g = ((uint32_t)c.iz * (uint32_t)sc.Ly + (uint32_t)c.iy) * (uint32_t)sc.Lx + (uint32_t)c.ix;
+    }
     c.xy = (uint32_t)c.jy * (uint32_t)sc.Nx + (uint32_t)c.jx;
     c.xz = (uint32_t)c.jz * (uint32_t)sc.Nx + (uint32_t)c.jx;
     c.yz = (uint32_t)c.jz * (uint32_t)sc.Ny + (uint32_t)c.jy;
@@ -320,7 +341,7 @@ template <class S>
 __device__ __forceinline__ void gather_features(const SceneDev& sc, const Corners& c, float* t) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) t[i] = 0.0f;
-    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
+    const uint32_t sy = sc.gsy, sz = sc.gsz;
     const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
     typename S::Row r[20];
     r[0] = S::load(sc.grid, c.g);
@@ -373,7 +394,7 @@ template <class S>
 __device__ __forceinline__ void gather_features_split(const SceneDev& sc, const Corners& c, float* t) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) t[i] = 0.0f;
-    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
+    const uint32_t sy = sc.gsy, sz = sc.gsz;
     const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
     // two rows (one pair adjacent along the row axis) in flight for 32-byte
     // rows, four for 16-byte rows
@@ -586,7 +607,7 @@ template <class S>
 __device__ __forceinline__ void gather_half(const SceneDev& sc, const Corners& c, int h, float* t) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) t[i] = 0.0f;
-    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
+    const uint32_t sy = sc.gsy, sz = sc.gsz;
     const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
     const uint32_t hh = (uint32_t)h;
     typename S::Row r[10];
@@ -626,7 +647,7 @@ __device__ __forceinline__ void decode_add(const SceneDev& sc, int src, const fl
 }
 
 __device__ __forceinline__ void gather_u8(const SceneDev& sc, const Corners& c, float* t) {
-    const uint32_t sy = (uint32_t)sc.Lx, sz = (uint32_t)sc.Lx * (uint32_t)sc.Ly;
+    const uint32_t sy = sc.gsy, sz = sc.gsz;
     const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
     // Each row's corner pair (i0, i0 + 1) is 16 contiguous bytes: one load
     // (8-byte aligned; the hardware serves unaligned global loads).

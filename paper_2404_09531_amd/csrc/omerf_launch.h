@@ -25,6 +25,9 @@ hipError_t launch_occ_pyramid(const float2* occ, int Mx, int My, float2* mips, i
 hipError_t launch_occ_loss(const float* occ, int64_t cells, float weight, double* loss, float* grad, hipStream_t s);
 hipError_t launch_range(const float* x, int64_t n, float* minmax, uint32_t* keys, hipStream_t s);
 hipError_t launch_quantize(const float* x, int64_t n, const float* lo, const float* inv, uint8_t* out, hipStream_t s);
+hipError_t launch_blocks_mark(const SceneDev& sc, int shift, int bnx, int bny, int bnz, int32_t* mark, hipStream_t s);
+hipError_t launch_blocks_fill(const SceneDev& sc, int shift, int bnx, int bny, int bnz, const int32_t* idx,
+                              int64_t n_blocks, int units, void* atlas, hipStream_t s);
 hipError_t launch_l2(const float* C, const float* tgt, int64_t n, float* dC, double* loss, hipStream_t s);
 
 }  // namespace omerf

@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol(L):
     assert names == set(_lib.EXPORTS)
     for n in names:
         assert hasattr(L, n), n
-    assert L.om_version() == 106
+    assert L.om_version() == 107
     assert L.om_status_str(-2) == b"unsupported shape or dtype"
 
 
@@ -313,3 +313,26 @@ def test_bake_calls_validate_before_device_work(L):
     tiny = (ctypes.c_float * 8)(*([0.1] * 7 + [1e-40]))
     assert L.om_quantize_u8(f, 10, lo, tiny, ctypes.c_void_p(FAKE * 4), None) == _lib.OM_ERR_UNSUPPORTED
     assert L.om_quantize_u8(f, 10, lo, step, ctypes.c_void_p(FAKE * 4 + 1), None) == _lib.OM_ERR_INVALID
+
+
+def test_sparse_grid_validation(L):
+    d = _desc(block_shift=6, grid_blocks=FAKE)
+    assert _create(L, d)[0] == _lib.OM_ERR_INVALID
+    d = _desc(block_shift=3)  # no block index
+    assert _create(L, d)[0] == _lib.OM_ERR_INVALID
+    d = _desc(block_shift=3, grid_blocks=FAKE, n_blocks=1 << 22)  # (n + 1) 9^3 >= 2^31
+    assert _create(L, d)[0] == _lib.OM_ERR_UNSUPPORTED
+    rc, h = _create(L, _desc(block_shift=3, grid_blocks=FAKE, n_blocks=100))
+    assert rc == 0
+    # a sparse scene cannot be sparsified again; bad shifts and lengths fail before device work
+    assert L.om_sparse_grid_index(h, 3, ctypes.c_void_p(FAKE), 8 * 8 * 2, None) == -1
+    L.om_scene_destroy(h)
+    rc, h = _create(L, _desc())  # grid 64 x 64 x 16 -> 8 x 8 x 2 blocks of 8 cells
+    assert L.om_sparse_grid_index(h, 0, ctypes.c_void_p(FAKE), 128, None) == -1
+    assert L.om_sparse_grid_index(h, 3, ctypes.c_void_p(FAKE), 127, None) == -1
+    assert L.om_sparse_grid_index(h, 3, None, 128, None) == -1
+    assert L.om_sparse_grid_fill(h, 3, ctypes.c_void_p(FAKE), -1, ctypes.c_void_p(FAKE), None) == \
+        _lib.OM_ERR_UNSUPPORTED
+    assert L.om_sparse_grid_fill(h, 3, ctypes.c_void_p(FAKE), 10, ctypes.c_void_p(FAKE + 8), None) == \
+        _lib.OM_ERR_INVALID
+    L.om_scene_destroy(h)
