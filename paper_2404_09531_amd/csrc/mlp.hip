@@ -305,13 +305,15 @@ hipError_t launch_occ_loss(const float* occ, int64_t cells, float weight, double
 // View-smoothness loss (Sec. 4.2, Eq. 9-10):
 // L = weight sum_r sum_p S(d_r, s_rp) ||G(F_r, s_rp) - G(F_r, d_r)||^2,
 // s_rp = d_r + delta_rp (the caller draws delta ~ N(0, Sigma)), S the
-// cosine similarity.  One ray per 16-lane group, one hidden unit per lane:
-// G at d and at the P perturbed directions, then the backward of each
-// evaluation into LDS-reduced MLP gradients and dL/dF (added to dF).
+// cosine similarity.  One (ray, perturbation) pair per 16-lane group, one
+// hidden unit per lane: G at d and at s, and the backward of both
+// evaluations (dL/dG = +g at s, -g at d; the MLP backward is linear in
+// dL/dG) into LDS-reduced MLP gradients; dL/dF is added to dF with float32
+// atomics (the P pairs of a ray land in different groups).
 // ---------------------------------------------------------------------------
 template <int NIN>
 __global__ __launch_bounds__(kBlock) void k_smooth(const float* __restrict__ W, const float* __restrict__ F,
-                                                   const float* __restrict__ d_, int64_t n, int64_t chunk,
+                                                   const float* __restrict__ d_, int64_t items, int64_t chunk,
                                                    const float* __restrict__ perturb, int P, float weight,
                                                    double* __restrict__ loss, float* __restrict__ dF,
                                                    float* __restrict__ gmlp) {
@@ -322,49 +324,53 @@ __global__ __launch_bounds__(kBlock) void k_smooth(const float* __restrict__ W, 
     const int gl = lane & (kGroup - 1);
     const int gid = threadIdx.x / kGroup;
     const int64_t start = (int64_t)xcd_block(blockIdx.x, gridDim.x) * chunk;
-    const int64_t stop_r = min(n, start + chunk);
+    const int64_t stop = min(items, start + chunk);
     double acc = 0.0;
-    for (int64_t ray = start + gid; ray < stop_r; ray += kGroupsPerBlock) {
+    for (int64_t it = start + gid; it < stop; it += kGroupsPerBlock) {
+        const int64_t ray = it / P;
         float f7[7];
 #pragma unroll
         for (int c = 0; c < 7; ++c) f7[c] = F[ray * 7 + c];
         const float3 d = make_float3(d_[ray * 3 + 0], d_[ray * 3 + 1], d_[ray * 3 + 2]);
+        const float* dp = perturb + (size_t)it * 3;
+        const float3 sv = make_float3(d.x + dp[0], d.y + dp[1], d.z + dp[2]);
         const float dn = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
-        MlpAct ad;
-        {
-            float xd[NIN];
-            mlp_input<NIN>(f7, d, xd);
-            ad = group_mlp_fwd<NIN>(W, xd, gl);
-        }
-        float gd[3] = {0.0f, 0.0f, 0.0f};  // dL/dG at d
+        const float sn = sqrtf(sv.x * sv.x + sv.y * sv.y + sv.z * sv.z);
+        const float cosv = (d.x * sv.x + d.y * sv.y + d.z * sv.z) / (dn * sn);
         float g7[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        for (int p = 0; p < P; ++p) {
-            const float* dp = perturb + ((size_t)ray * P + p) * 3;
-            const float3 sv = make_float3(d.x + dp[0], d.y + dp[1], d.z + dp[2]);
-            float xs[NIN];
-            mlp_input<NIN>(f7, sv, xs);
-            const MlpAct as = group_mlp_fwd<NIN>(W, xs, gl);
-            const float sn = sqrtf(sv.x * sv.x + sv.y * sv.y + sv.z * sv.z);
-            const float cosv = (d.x * sv.x + d.y * sv.y + d.z * sv.z) / (dn * sn);
-            float e2 = 0.0f, gs[3];
+        MlpAct ad, as;
+        float gs[3], gd[3];
+        {
+            float x[NIN];
+            mlp_input<NIN>(f7, d, x);
+            ad = group_mlp_fwd<NIN>(W, x, gl);
+        }
+        {
+            float x[NIN];
+            mlp_input<NIN>(f7, sv, x);
+            as = group_mlp_fwd<NIN>(W, x, gl);
+            float e2 = 0.0f;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const float diff = as.g[c] - ad.g[c];
                 e2 += diff * diff;
                 gs[c] = 2.0f * weight * cosv * diff;
-                gd[c] -= gs[c];
+                gd[c] = -gs[c];
             }
             acc += (double)weight * (double)cosv * (double)e2;
-            group_mlp_bwd<NIN>(W, xs, gl, as, gs, sW, g7);
+            group_mlp_bwd<NIN>(W, x, gl, as, gs, sW, g7);
         }
         {
-            float xd[NIN];  // recomputed: not held live across the perturbation loop
-            mlp_input<NIN>(f7, d, xd);
-            group_mlp_bwd<NIN>(W, xd, gl, ad, gd, sW, g7);
+            float x[NIN];
+            mlp_input<NIN>(f7, d, x);
+            group_mlp_bwd<NIN>(W, x, gl, ad, gd, sW, g7);
         }
-        if (dF && gl == 0) {
+        if (dF && gl < 7) {
+            float v = g7[0];
 #pragma unroll
-            for (int c = 0; c < 7; ++c) dF[ray * 7 + c] += g7[c];
+            for (int c = 1; c < 7; ++c)
+                if (gl == c) v = g7[c];
+            unsafeAtomicAdd(dF + ray * 7 + gl, v);
         }
     }
     if (loss && gl == 0 && acc != 0.0) atomicAdd(loss, acc);
@@ -381,18 +387,19 @@ hipError_t launch_smooth(const float* W, int mlp_in, const float* F, const float
                          int P, float weight, double* loss, float* dF, float* gmlp, hipStream_t s) {
     if (loss) hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, loss);
     if (n == 0) return hipGetLastError();
+    const int64_t items = n * P;
     const int64_t max_blocks = 4096;
-    int64_t nb = (n + kGroupsPerBlock - 1) / kGroupsPerBlock;
+    int64_t nb = (items + kGroupsPerBlock - 1) / kGroupsPerBlock;
     if (nb > max_blocks) nb = max_blocks;
-    int64_t chunk = (n + nb - 1) / nb;
+    int64_t chunk = (items + nb - 1) / nb;
     chunk = (chunk + kGroupsPerBlock - 1) / kGroupsPerBlock * kGroupsPerBlock;
-    nb = (n + chunk - 1) / chunk;
+    nb = (items + chunk - 1) / chunk;
     if (mlp_in == 34)
-        hipLaunchKernelGGL(k_smooth<34>, dim3((unsigned)nb), dim3(kBlock), 0, s, W, F, d, n, chunk, perturb, P, weight,
-                           loss, dF, gmlp);
+        hipLaunchKernelGGL(k_smooth<34>, dim3((unsigned)nb), dim3(kBlock), 0, s, W, F, d, items, chunk, perturb, P,
+                           weight, loss, dF, gmlp);
     else
-        hipLaunchKernelGGL(k_smooth<10>, dim3((unsigned)nb), dim3(kBlock), 0, s, W, F, d, n, chunk, perturb, P, weight,
-                           loss, dF, gmlp);
+        hipLaunchKernelGGL(k_smooth<10>, dim3((unsigned)nb), dim3(kBlock), 0, s, W, F, d, items, chunk, perturb, P,
+                           weight, loss, dF, gmlp);
     return hipGetLastError();
 }
 
