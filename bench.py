@@ -221,7 +221,9 @@ def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, out, kw, a, occ_eps=0.0):
                                                                              if occ_eps > 0 else ""), "rays": n2,
             "Mrays_per_s": round(n2 / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4),
             "fwd_ms": round(f_ms, 4), "loss_ms": round(l_ms, 4), "bwd_ms": round(b_ms, 4),
-            "samples_per_ray": round(s2 / n2, 1), "targets": "forward colours + N(0, 0.05), seeded"}
+            "samples_per_ray": round(s2 / n2, 1), "targets": "forward colours + N(0, 0.05), seeded",
+            # backward per evaluated sample: 640 B re-gathered + 160 float32 gradient adds (640 B)
+            "bwd_roofline_frac_algorithmic": round(s2 * 1280 / (b_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 SMOOTH_RAYS = 1 << 10  # directions per step in the view-smoothness loss
@@ -327,6 +329,9 @@ def form_towers(om, scenegen, torch, a):
     return {"workload": "towers: occupancy 512^2, 10% towers, 2^20 rays of 64 cameras, n_max 512", "rays": n,
             "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 3),
             "fwd_ms": round(f_ms, 3), "bwd_ms": round(b_ms, 3),
+            # bf16 backward per evaluated sample: 320 B re-gathered + 640 B of float32 gradient adds
+            "bwd_roofline_frac_algorithmic": round(int(out["n_eval"].sum().item()) * 960 / (b_ms * 1e-3) / 1e9
+                                                   / HBM_PEAK_GBS, 4),
             "samples_per_ray": round(float(npl.mean()), 1), "max_samples": int(npl.max()),
             "n_placed_hist_bins32": hist.tolist()}
 

@@ -195,3 +195,27 @@ def test_l2_plus_smooth_gradients_vs_oracle(freqs):
     loss.backward()
     torch.cuda.synchronize()
     _check_grads({k: m.grad.double().cpu().numpy() for k, m in zip((*SOURCES, "mlp"), masters)}, ref_grads)
+
+
+def test_backward_encoded_bf16_storage_vs_oracle(enc_scene):
+    """bfloat16 storage with the 34-input MLP: float32 arithmetic and master
+    gradients must match the float64 oracle on the bfloat16-rounded scene."""
+    sc, _, _, o, d = enc_scene
+    o, d = o[:256], d[:256]
+    log("test_backward_encoded_bf16_storage_vs_oracle: 256 rays")
+    rsc = dict(sc)
+    for k in SOURCES:
+        rsc[k] = torch.from_numpy(sc[k]).to(torch.bfloat16).float().numpy()
+    scene, t = upload_scene(sc, dtype=torch.bfloat16)
+    target = _target(sc, o, d).astype(np.float32)
+    og, dg = rays_to(o, d)
+    tg = torch.from_numpy(target).to(og.device)
+    _, _, ref = oracle.oracle_loss_and_grads(rsc, o, d, oracle.RenderParams(n_max=64, c_bg=BG),
+                                             target.astype(np.float64))
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG, mlp_bf16=0, batch_wv=True)
+    dC, _ = om.l2_loss_grad(res["C"], tg)
+    grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in SOURCES}
+    grads["mlp"] = torch.zeros_like(t["mlp"])
+    om.render_backward(scene, og, dg, res, dC, grads, n_max=64, c_bg=BG)
+    torch.cuda.synchronize()
+    _check_grads({k: v.double().cpu().numpy() for k, v in grads.items()}, ref)

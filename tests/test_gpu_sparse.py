@@ -46,7 +46,7 @@ def tiny():
     return sc, scene, t, o, d
 
 
-@pytest.mark.parametrize("shift", [1, 2, 3, 4])
+@pytest.mark.parametrize("shift", [1, 2, 3, 4, 5])
 def test_index_and_atlas(tiny, shift):
     log(f"test_index_and_atlas: B = {1 << shift}")
     sc, scene, t, o, d = tiny
@@ -139,3 +139,17 @@ def test_sparse_oblique_1080p_equals_dense():
         f"vs dense {t['grid'].numel() * 4 / 2**30:.2f} GiB")
     assert sg.n_blocks < sg.blocks.numel()
     _equal(om.render(sp, og, dg, n_max=256, c_bg=BG), dense)
+
+
+def test_sparse_u8_with_pyramid_equals_dense(tiny):
+    """8-bit sparse blocks with the occupancy pyramid attached: the same
+    render as the dense 8-bit scene without it."""
+    log("test_sparse_u8_with_pyramid_equals_dense")
+    sc, scene, t, o, d = tiny
+    codes, quant = om.quantize_features(t)
+    dense = om.Scene(codes["grid"], codes["plane_xy"], codes["plane_xz"], codes["plane_yz"], t["occ"], t["mlp"],
+                     quant=quant)
+    sp, _, _ = _sparse_scene(dense, t, 3, quant)
+    sp.build_occupancy_mips(3)
+    og, dg = rays_to(o, d)
+    _equal(om.render(sp, og, dg, n_max=64, c_bg=BG), om.render(dense, og, dg, n_max=64, c_bg=BG))
