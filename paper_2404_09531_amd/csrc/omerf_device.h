@@ -335,61 +335,9 @@ __device__ __forceinline__ Corners corners_of(const SceneDev& sc, float3 p) {
     return c;
 }
 
-// Eq. 2: t = trilinear(V) + bilinear(P_xy) + bilinear(P_xz) + bilinear(P_yz).
-// All 20 corner loads are issued before the first one is consumed.
-template <class S>
-__device__ __forceinline__ void gather_features(const SceneDev& sc, const Corners& c, float* t) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) t[i] = 0.0f;
-    const uint32_t sy = sc.gsy, sz = sc.gsz;
-    const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
-    typename S::Row r[20];
-    r[0] = S::load(sc.grid, c.g);
-    r[1] = S::load(sc.grid, c.g + 1);
-    r[2] = S::load(sc.grid, c.g + sy);
-    r[3] = S::load(sc.grid, c.g + sy + 1);
-    r[4] = S::load(sc.grid, c.g + sz);
-    r[5] = S::load(sc.grid, c.g + sz + 1);
-    r[6] = S::load(sc.grid, c.g + sz + sy);
-    r[7] = S::load(sc.grid, c.g + sz + sy + 1);
-    r[8] = S::load(sc.pxy, c.xy);
-    r[9] = S::load(sc.pxy, c.xy + 1);
-    r[10] = S::load(sc.pxy, c.xy + nx);
-    r[11] = S::load(sc.pxy, c.xy + nx + 1);
-    r[12] = S::load(sc.pxz, c.xz);
-    r[13] = S::load(sc.pxz, c.xz + 1);
-    r[14] = S::load(sc.pxz, c.xz + nx);
-    r[15] = S::load(sc.pxz, c.xz + nx + 1);
-    r[16] = S::load(sc.pyz, c.yz);
-    r[17] = S::load(sc.pyz, c.yz + 1);
-    r[18] = S::load(sc.pyz, c.yz + ny);
-    r[19] = S::load(sc.pyz, c.yz + ny + 1);
-    const float x0 = 1.0f - c.fx, x1 = c.fx, y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
-    const float a0 = 1.0f - c.ux, a1 = c.ux, b0 = 1.0f - c.uy, b1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
-    S::acc(r[0], x0 * y0 * z0, t);
-    S::acc(r[1], x1 * y0 * z0, t);
-    S::acc(r[2], x0 * y1 * z0, t);
-    S::acc(r[3], x1 * y1 * z0, t);
-    S::acc(r[4], x0 * y0 * z1, t);
-    S::acc(r[5], x1 * y0 * z1, t);
-    S::acc(r[6], x0 * y1 * z1, t);
-    S::acc(r[7], x1 * y1 * z1, t);
-    S::acc(r[8], a0 * b0, t);
-    S::acc(r[9], a1 * b0, t);
-    S::acc(r[10], a0 * b1, t);
-    S::acc(r[11], a1 * b1, t);
-    S::acc(r[12], a0 * e0, t);
-    S::acc(r[13], a1 * e0, t);
-    S::acc(r[14], a0 * e1, t);
-    S::acc(r[15], a1 * e1, t);
-    S::acc(r[16], b0 * e0, t);
-    S::acc(r[17], b1 * e0, t);
-    S::acc(r[18], b0 * e1, t);
-    S::acc(r[19], b1 * e1, t);
-}
-
-// Same sum with at most 12 corners in flight (grid first, then planes), for
-// kernels that carry more live state than the forward march.
+// Eq. 2: t = trilinear(V) + bilinear(P_xy) + bilinear(P_xz) + bilinear(P_yz),
+// one lane per sample, with at most 12 corners in flight (grid first, then
+// planes), for kernels that carry more live state than the forward march.
 template <class S>
 __device__ __forceinline__ void gather_features_split(const SceneDev& sc, const Corners& c, float* t) {
 #pragma unroll
