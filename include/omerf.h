@@ -26,9 +26,13 @@
  *   plane_xy [Ny][Nx][8], plane_xz [Nz][Nx][8], plane_yz [Nz][Ny][8];
  *   channel 0 = density pre-activation, 1..3 = diffuse colour,
  *   4..7 = specular features (Eq. 3).  Occupancy plane float32 [My][Mx][2]
- *   holding (z_min, z_max).  MLP float32[499] packed as
- *   W1[16][10], b1[16], W2[16][16], b2[16], W3[3][16], b3[3]
- *   (row-major (out, in)); input order [sum w c^d (3), sum w f (4), d (3)].
+ *   holding (z_min, z_max).  MLP float32[OM_MLP_NPARAMS(dir_freqs)] packed
+ *   as W1[16][N], b1[16], W2[16][16], b2[16], W3[3][16], b3[3] (row-major
+ *   (out, in)); input order [sum w c^d (3), sum w f (4), enc(d)] with
+ *   enc(d) = d (N = 10) or d and its four sine/cosine frequencies (N = 34).
+ * - Storage: float32, bfloat16 or 8-bit features (OM_U8, with per-source
+ *   decoding); the grid dense or as sparse voxel blocks.  8-bit and sparse
+ *   scenes are render only.
  *
  * Sample lattice and placement (Sec. 4.1 Eq. 6-7, Sec. 4.4)
  * ---------------------------------------------------------
@@ -67,7 +71,6 @@ extern "C" {
 #define OM_BF16 1
 #define OM_U8 2 /* 8-bit codes, decoded per source and channel (quant_lo, quant_step) */
 
-#define OM_MLP_NPARAMS 499
 #define OM_CHANNELS 8
 #define OM_MAX_SAMPLES 1024       /* largest n_max the kernels accept   */
 
@@ -130,6 +133,7 @@ typedef struct om_scene_desc {
 /* Packed MLP parameters for an N -> 16 -> 16 -> 3 network: W1 [16][N], b1,
  * W2 [16][16], b2, W3 [3][16], b3, N = 10 + 6 dir_freqs (499 or 883). */
 #define OM_MLP_NPARAMS(dir_freqs) (16 * (10 + 6 * (dir_freqs)) + 16 + 256 + 16 + 48 + 3)
+#define OM_MLP_NPARAMS_RAW_DIR OM_MLP_NPARAMS(0) /* 499: input [F, d] */
 
 /* Per-call render parameters. */
 typedef struct om_params {
@@ -177,7 +181,8 @@ typedef struct om_fwd_out {
 
 /* Gradient buffers (device, float32, caller-zeroed or holding a running
  * sum: the backward pass ACCUMULATES into them).  Shapes match the scene:
- * grid [Lz][Ly][Lx][8], planes as the scene, mlp [OM_MLP_NPARAMS]. */
+ * grid [Lz][Ly][Lx][8] (sparse scenes are render only), planes as the
+ * scene, mlp [OM_MLP_NPARAMS(dir_freqs)]. */
 typedef struct om_grads {
     float* grid;
     float* plane_xy;
@@ -297,7 +302,7 @@ int om_render_backward_ex(const om_scene* scene, const float* o, const float* d,
  * loss_fp64: optional device double[1] (overwritten); dL_dF: optional
  * device float32 [n][7] into which dL/dF is ADDED (pass it to
  * om_render_backward_ex); grad_mlp: optional device float32
- * [OM_MLP_NPARAMS] into which dL/dW is ADDED (float32 atomics, order not
+ * [OM_MLP_NPARAMS(dir_freqs)] into which dL/dW is ADDED (float32 atomics, order not
  * deterministic).  Evaluated in float32 regardless of the scene dtype.
  */
 int om_smooth_loss(const om_scene* scene, const float* F, const float* d, int64_t n,

@@ -336,3 +336,23 @@ def test_sparse_grid_validation(L):
     assert L.om_sparse_grid_fill(h, 3, ctypes.c_void_p(FAKE), 10, ctypes.c_void_p(FAKE + 8), None) == \
         _lib.OM_ERR_INVALID
     L.om_scene_destroy(h)
+
+
+def test_header_compiles_cleanly_in_c_and_cpp(tmp_path):
+    """include/omerf.h compiles warning-free as C11 and C++17, and its
+    parameter-count macro agrees with the library's MLP sizes."""
+    import shutil
+    import subprocess
+    src = tmp_path / "h.c"
+    src.write_text('#include "omerf.h"\n'
+                   '#ifdef __cplusplus\n#define SA static_assert\n#else\n#define SA _Static_assert\n#endif\n'
+                   'SA(OM_MLP_NPARAMS(0) == 499, "10 inputs");\n'
+                   'SA(OM_MLP_NPARAMS(4) == 883, "34 inputs");\n'
+                   'SA(OM_BATCH_SLOTS(17) == 2, "slots");\n'
+                   'int main(void) { return 0; }\n')
+    for cc, extra in (("gcc", ["-std=c11", "-x", "c"]), ("g++", ["-std=c++17", "-x", "c++"])):
+        if shutil.which(cc) is None:
+            pytest.skip(f"no {cc}")
+        r = subprocess.run([cc, *extra, "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"),
+                            "-fsyntax-only", str(src)], capture_output=True, text=True)
+        assert r.returncode == 0, (cc, r.stderr)
