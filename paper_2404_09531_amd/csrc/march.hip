@@ -1,8 +1,10 @@
 // march.hip -- occupancy-plane ray marching kernels for gfx950.
 //
 // k_place      : sample placement only (k-lists), Sec. 4.1 Eq. 6-7 / Sec. 4.4
-// k_march_fwd  : placement + feature gather (Eq. 2) + activations (Eq. 3) +
-//                compositing (Eq. 1) -> F, T, counts per ray
+// k_march_fwd_f32q / k_march_fwd_lane : placement + feature gather (Eq. 2)
+//                + activations (Eq. 3) + compositing (Eq. 1) -> F, T, counts
+//                per ray (float32 lane quads; bfloat16 and 8-bit one lane
+//                per sample)
 // k_march_bwd  : deferred-MLP backward (Eq. 4) + replay of the samples with
 //                recomputed features + scatter-add of feature gradients
 //
@@ -112,14 +114,8 @@ __global__ __launch_bounds__(kBlock) void k_place(SceneDev sc, RayParams rp, con
 }
 
 // ---------------------------------------------------------------------------
-// Forward march: writes F [n][7], T [n], n_placed [n], n_eval [n].
-// Lane-pair shading: each queued batch of up to 16 samples is
-// shaded as two halves of 8 samples; sample s of a half is owned by lanes
-// 2s and 2s+1, which fetch the x-offset-0 and x-offset-1 corners (the two
-// 32-byte halves of one contiguous 64-byte pair) and add their partial sums
-// with a lane swap.  Each gather instruction then covers 32 samples with two
-// adjacent corners per sample.  Transmittance comes from a 16-lane scan with
-// the optical depth on the even lanes only.
+// Forward marches: write F [n][7], T [n], n_placed [n], n_eval [n] (and, with
+// kBW, the per-batch sums of w v).
 // ---------------------------------------------------------------------------
 // Group total of x (inclusive DPP scan; the row's last lane holds it) stored
 // by that lane at dst, for the optional per-batch sums of w v.
@@ -128,18 +124,31 @@ __device__ __forceinline__ void store_group_total(float x, int gl, float* dst) {
     if (gl == kGroup - 1) *dst = x;
 }
 
-template <class S, bool kBW, bool kSoft, bool kSparse>
-__global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
+// ---------------------------------------------------------------------------
+// Forward march with one lane per sample, for 8-bit and bfloat16 features.
+// A corner pair is 16 (8-bit) or 32 (bfloat16) contiguous bytes, so lane s
+// of the group shades sample s of the batch on its own (10 or 20 loads),
+// and the batch of 16 samples is composited with one 16-lane scan.
+// ---------------------------------------------------------------------------
+struct GatherU8 {
+    static __device__ __forceinline__ void run(const SceneDev& sc, const Corners& c, float* t) { gather_u8(sc, c, t); }
+};
+struct GatherBF16 {
+    static __device__ __forceinline__ void run(const SceneDev& sc, const Corners& c, float* t) {
+        gather_features_split<BF16Store>(sc, c, t);
+    }
+};
+
+template <class Gather, bool kBW, bool kSoft, bool kSparse>
+__global__ __launch_bounds__(kBlock) void k_march_fwd_lane(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                            const float* __restrict__ d_, int64_t n,
                                                            float* __restrict__ F, float* __restrict__ T,
                                                            int32_t* __restrict__ n_placed,
-                                                           int32_t* __restrict__ n_eval,
-                                                           float* __restrict__ BW) {
+                                                           int32_t* __restrict__ n_eval, float* __restrict__ BW) {
     __shared__ int qs[kGroupsPerBlock][kQueue];
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kGroup - 1);
     const int gid = threadIdx.x / kGroup;
-    const int half = gl & 1;
     const int64_t ray = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kGroupsPerBlock + gid;
     if (ray >= n) return;
     const float3 o = load3(o_, ray), d = load3(d_, ray);
@@ -150,107 +159,6 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd(SceneDev sc, RayParams rp,
     int evals = 0, batch = 0;
     const int slots = (rp.n_max + kGroup - 1) / kGroup;
     const int placed = march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
-        bool stop = false;
-        float bacc[7];
-#pragma unroll
-        for (int c = 0; c < 7; ++c) bacc[c] = 0.0f;
-#pragma unroll
-        for (int sub = 0; sub < 2; ++sub) {
-            const int nsub = min(max(nb - sub * 8, 0), 8);  // samples in this half (group-uniform)
-            if (nsub > 0 && !stop) {
-                const int s = gl >> 1;
-                const bool act = s < nsub;
-                const int ks = __shfl(kq, sub * 8 + s, kGroup);
-                float t[8];
-#pragma unroll
-                for (int c = 0; c < 8; ++c) t[c] = 0.0f;
-                float msoft = 0.0f;
-                if (act) {
-                    const float3 p = lattice_point(ks, o, d, rp.delta);
-                    gather_half<S>(sc, corners_of<kSparse>(sc, p), half, t);
-                    if (kSoft) msoft = occ_value(sc, p, rp.occ_inv_eps).m;
-                }
-#pragma unroll
-                for (int c = 0; c < 8; ++c) t[c] += pair_swap(t[c]);
-                float a = 0.0f;
-                float v[7];
-#pragma unroll
-                for (int c = 0; c < 7; ++c) v[c] = 0.0f;
-                if (act) {
-                    a = __expf(t[0]) * rp.delta;
-#pragma unroll
-                    for (int c = 0; c < 7; ++c) v[c] = sigmoidf_fast(t[c + 1]);
-                }
-                const float ae = half ? 0.0f : a;             // depth on the even lane of each pair
-                const float incl = g_scan_incl(ae, gl);         // lane 2s: sum_{j<=s} a_j
-                const float excl_e = g_shift_up1(incl);         // even lanes: sum_{j<s} a_j (from lane 2s-1)
-                const float excl = half ? pair_swap(excl_e) : excl_e;
-                const float Ti = __expf(-(carry + excl));
-                float w = Ti * (-expm1f(-a));
-                int nb_eff = nsub;
-                if (rp.t_term > 0.0f) {
-                    const float Tnext = __expf(-(carry + incl));
-                    const uint32_t m = g_ballot(act && !half && Tnext < rp.t_term, lane);
-                    if (m) {
-                        nb_eff = ((__ffs(m) - 1) >> 1) + 1;
-                        stop = true;
-                    }
-                }
-                if (kSoft) w *= msoft;              // Eq. 8: the weight, not T
-                if (s >= nb_eff || half) w = 0.0f;  // accumulate once per sample (even lane)
-#pragma unroll
-                for (int c = 0; c < 7; ++c) bacc[c] += w * v[c];
-                carry += __shfl(incl, 2 * (nb_eff - 1), kGroup);
-                evals += nb_eff;
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 7; ++c) acc[c] += bacc[c];
-        if (kBW) {
-            float* dst = BW + ((size_t)ray * slots + batch) * 7;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) store_group_total(bacc[c], gl, dst + c);
-        }
-        ++batch;
-        return stop;
-    });
-    float f[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) f[c] = g_sum(acc[c]);
-    if (gl == 0) {
-#pragma unroll
-        for (int c = 0; c < 7; ++c) F[ray * 7 + c] = f[c];
-        T[ray] = __expf(-carry);
-        n_placed[ray] = placed;
-        n_eval[ray] = evals;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Forward march for 8-bit features (render only): one lane per sample.  An
-// 8-byte corner needs no split across lanes, so lane s of the group shades
-// sample s of the batch with 20 corner loads, and the batch of 16 samples is
-// composited with one 16-lane scan.
-// ---------------------------------------------------------------------------
-template <bool kSoft, bool kSparse>
-__global__ __launch_bounds__(kBlock) void k_march_fwd_u8(SceneDev sc, RayParams rp, const float* __restrict__ o_,
-                                                         const float* __restrict__ d_, int64_t n,
-                                                         float* __restrict__ F, float* __restrict__ T,
-                                                         int32_t* __restrict__ n_placed,
-                                                         int32_t* __restrict__ n_eval) {
-    __shared__ int qs[kGroupsPerBlock][kQueue];
-    const int lane = threadIdx.x & 63;
-    const int gl = lane & (kGroup - 1);
-    const int gid = threadIdx.x / kGroup;
-    const int64_t ray = (int64_t)xcd_block(blockIdx.x, gridDim.x) * kGroupsPerBlock + gid;
-    if (ray >= n) return;
-    const float3 o = load3(o_, ray), d = load3(d_, ray);
-    float acc[7];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) acc[c] = 0.0f;
-    float carry = 0.0f;
-    int evals = 0;
-    const int placed = march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
         const bool act = gl < nb;
         float t[8];
 #pragma unroll
@@ -258,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_u8(SceneDev sc, RayParams 
         float msoft = 0.0f;
         if (act) {
             const float3 p = lattice_point(kq, o, d, rp.delta);
-            gather_u8(sc, corners_of<kSparse>(sc, p), t);
+            Gather::run(sc, corners_of<kSparse>(sc, p), t);
             if (kSoft) msoft = occ_value(sc, p, rp.occ_inv_eps).m;
         }
         float a = 0.0f;
@@ -287,8 +195,14 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_u8(SceneDev sc, RayParams 
         if (gl >= nb_eff) w = 0.0f;
 #pragma unroll
         for (int c = 0; c < 7; ++c) acc[c] += w * v[c];
+        if (kBW) {
+            float* dst = BW + ((size_t)ray * slots + batch) * 7;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) store_group_total(w * v[c], gl, dst + c);
+        }
         carry += __shfl(incl, nb_eff - 1, kGroup);
         evals += nb_eff;
+        ++batch;
         return stop;
     });
     float f[7];
@@ -854,15 +768,15 @@ static void launch_fwd_soft(const SceneDev& sc, int dtype, const RayParams& rp, 
                             hipStream_t s) {
     const dim3 grid(blocks_for(n)), block(kBlock);
     if (dtype == OM_U8) {  // render only: no per-batch sums
-        hipLaunchKernelGGL((k_march_fwd_u8<kSoft, kSparse>), grid, block, 0, s, sc, rp, o, d, n, F, T, n_placed,
-                           n_eval);
+        hipLaunchKernelGGL((k_march_fwd_lane<GatherU8, false, kSoft, kSparse>), grid, block, 0, s, sc, rp, o, d, n, F,
+                           T, n_placed, n_eval, nullptr);
     } else if (dtype == OM_BF16) {
         if (batch_wv)
-            hipLaunchKernelGGL((k_march_fwd<BF16Store, true, kSoft, kSparse>), grid, block, 0, s, sc, rp, o, d, n, F,
-                               T, n_placed, n_eval, batch_wv);
+            hipLaunchKernelGGL((k_march_fwd_lane<GatherBF16, true, kSoft, kSparse>), grid, block, 0, s, sc, rp, o, d,
+                               n, F, T, n_placed, n_eval, batch_wv);
         else
-            hipLaunchKernelGGL((k_march_fwd<BF16Store, false, kSoft, kSparse>), grid, block, 0, s, sc, rp, o, d, n, F,
-                               T, n_placed, n_eval, batch_wv);
+            hipLaunchKernelGGL((k_march_fwd_lane<GatherBF16, false, kSoft, kSparse>), grid, block, 0, s, sc, rp, o, d,
+                               n, F, T, n_placed, n_eval, batch_wv);
     } else {
         if (batch_wv)
             hipLaunchKernelGGL((k_march_fwd_f32q<true, kSoft, kSparse>), grid, block, 0, s, sc, rp, o, d, n, F, T,

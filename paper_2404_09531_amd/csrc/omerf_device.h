@@ -547,45 +547,6 @@ __device__ __forceinline__ void wave_order() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Half of Eq. 2 for lane-pair shading: the lane with x-offset h (0 or 1)
-// sums the corners whose first interpolation axis index is i0 + h (grid: x;
-// XY and XZ planes: x; YZ plane: y).  The two lanes' partial sums add up to
-// the full feature vector.
-template <class S>
-__device__ __forceinline__ void gather_half(const SceneDev& sc, const Corners& c, int h, float* t) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) t[i] = 0.0f;
-    const uint32_t sy = sc.gsy, sz = sc.gsz;
-    const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
-    const uint32_t hh = (uint32_t)h;
-    typename S::Row r[10];
-    r[0] = S::load(sc.grid, c.g + hh);
-    r[1] = S::load(sc.grid, c.g + sy + hh);
-    r[2] = S::load(sc.grid, c.g + sz + hh);
-    r[3] = S::load(sc.grid, c.g + sz + sy + hh);
-    r[4] = S::load(sc.pxy, c.xy + hh);
-    r[5] = S::load(sc.pxy, c.xy + nx + hh);
-    r[6] = S::load(sc.pxz, c.xz + hh);
-    r[7] = S::load(sc.pxz, c.xz + nx + hh);
-    r[8] = S::load(sc.pyz, c.yz + hh);
-    r[9] = S::load(sc.pyz, c.yz + ny + hh);
-    const float wx = h ? c.fx : 1.0f - c.fx;
-    const float y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
-    const float wa = h ? c.ux : 1.0f - c.ux;  // x for XY / XZ
-    const float wb = h ? c.uy : 1.0f - c.uy;  // y for YZ
-    const float b0 = 1.0f - c.uy, b1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
-    S::acc(r[0], wx * y0 * z0, t);
-    S::acc(r[1], wx * y1 * z0, t);
-    S::acc(r[2], wx * y0 * z1, t);
-    S::acc(r[3], wx * y1 * z1, t);
-    S::acc(r[4], wa * b0, t);
-    S::acc(r[5], wa * b1, t);
-    S::acc(r[6], wa * e0, t);
-    S::acc(r[7], wa * e1, t);
-    S::acc(r[8], wb * e0, t);
-    S::acc(r[9], wb * e1, t);
-}
-
 // Eq. 2 for 8-bit storage, one lane per sample: the 10 corner pairs are
 // loaded first (16 bytes each), then each source's weighted code sums are
 // decoded with that source's per-channel (lo, step).
