@@ -136,3 +136,36 @@ def test_u8_psnr_gate_and_fidelity(oblique_crop):
     log(f"  vs perturbed-scene target: FP32 {g32:.3f} dB, 8-bit {g8:.3f} dB, loss {g32 - g8:.4f} dB")
     assert e8 < 5e-2 and p8 > 40.0
     assert g32 - g8 <= 0.1
+
+
+def test_bf16_4k_image0_crop_fidelity():
+    """The 8 x 3840x2160 bfloat16 form, image 0 (the bench's first camera):
+    on its centre 256x256 crop the float32 render matches the float64 oracle
+    to 1e-5; bfloat16 storage with the float32 MLP matches the oracle run on
+    the bfloat16-rounded scene to 1e-5 (the compute error alone); the full
+    bfloat16 form (MFMA MLP) is reported and bounded against the oracle."""
+    log("test_bf16_4k_image0_crop_fidelity: building the oblique scene")
+    sc = scenegen.make_scene(scenegen.OBLIQUE)
+    pitch, yaw, aim = scenegen.random_cameras(8, seed=3)[0]
+    w, h, c = 3840, 2160, 256
+    pix = np.array([(h // 2 - c // 2 + j) * w + (w // 2 - c // 2 + i) for j in range(c) for i in range(c)])
+    o, d = scenegen.camera_rays(w, h, pitch, yaw, aim, pixels=pix)
+    prm = oracle.RenderParams(n_max=256, c_bg=BG)
+    log("  oracle renders of the crop (scene, bf16-rounded scene)")
+    ref = oracle.oracle_render(sc, o, d, prm, keep_k=False)
+    ref16 = oracle.oracle_render(_rounded(sc), o, d, prm, keep_k=False)
+    og, dg = rays_to(o, d)
+    s32, _ = upload_scene(sc)
+    r32 = om.render(s32, og, dg, n_max=256, c_bg=BG)
+    e32 = np.abs(r32["C"].double().cpu().numpy() - ref["C"]).max()
+    del s32, r32
+    torch.cuda.empty_cache()
+    s16, _ = upload_scene(sc, dtype=torch.bfloat16)
+    r16 = om.render(s16, og, dg, n_max=256, c_bg=BG, mlp_bf16=0)
+    e16s = np.abs(r16["C"].double().cpu().numpy() - ref16["C"]).max()
+    full = om.render(s16, og, dg, n_max=256, c_bg=BG)["C"].double().cpu().numpy()
+    e16, p16 = np.abs(full - ref["C"]).max(), psnr(full, ref["C"])
+    log(f"  FP32 max-abs {e32:.2e}; bf16 storage vs rounded-scene oracle {e16s:.2e}; "
+        f"full BF16 max-abs {e16:.2e} PSNR {p16:.1f} dB; {int((ref['n_placed'] > 0).sum())} rays hit")
+    assert e32 <= 1e-5 and e16s <= 1e-5
+    assert e16 < 5e-2 and p16 > 40.0
