@@ -325,7 +325,9 @@ def form_towers(om, scenegen, torch, a):
     tot, (f_ms, l_ms, b_ms) = time_stages([fwd, lossg, bwd], steps, 1, torch)
     ms = tot / steps
     npl = out["n_placed"].cpu().numpy()
-    hist = np.histogram(npl, bins=np.arange(0, 513 + 32, 32))[0]
+    bins = np.arange(0, 513 + 32, 32)
+    hist = np.histogram(npl, bins=bins)[0]
+    hist_eval = np.histogram(out["n_eval"].cpu().numpy(), bins=bins)[0]  # equal to n_placed at t_term = 0
     return {"workload": "towers: occupancy 512^2, 10% towers, 2^20 rays of 64 cameras, n_max 512", "rays": n,
             "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 3),
             "fwd_ms": round(f_ms, 3), "bwd_ms": round(b_ms, 3),
@@ -333,7 +335,7 @@ def form_towers(om, scenegen, torch, a):
             "bwd_roofline_frac_algorithmic": round(int(out["n_eval"].sum().item()) * 960 / (b_ms * 1e-3) / 1e9
                                                    / HBM_PEAK_GBS, 4),
             "samples_per_ray": round(float(npl.mean()), 1), "max_samples": int(npl.max()),
-            "n_placed_hist_bins32": hist.tolist()}
+            "n_placed_hist_bins32": hist.tolist(), "n_eval_hist_bins32": hist_eval.tolist()}
 
 
 def form_high_altitude(om, scenegen, torch, t, a):
