@@ -207,3 +207,32 @@ def test_oblique_placement_sampled(oblique):
     kr, nr, _ = oracle.place_samples(o[rows], d[rows], sc["occ"], sc["box_lo"], sc["box_hi"], om.DELTA, 256)
     assert np.array_equal(cnt.cpu().numpy(), nr)
     assert np.array_equal(k.cpu().numpy(), kr)
+
+
+def test_oblique_1080p_ert_sampled(oblique):
+    """The benchmark's early-termination form (t_term = 1e-4) on the full
+    frame: sampled rays follow the termination rule against the oracle, and
+    their colours match where the evaluated counts agree."""
+    sc, scene, t, o, d = oblique
+    t_term = 1e-4
+    log("test_oblique_1080p_ert_sampled: 2073600 rays, n_max=256, t_term=1e-4")
+    og, dg = rays_to(o, d)
+    res = om.render(scene, og, dg, n_max=256, c_bg=BG, t_term=t_term)
+    torch.cuda.synchronize()
+    rows = _sample_rows(o.shape[0], 1000, 17)
+    ref = oracle.oracle_render(sc, o[rows], d[rows], oracle.RenderParams(n_max=256, c_bg=BG, t_term=t_term),
+                               keep_k=False)
+    nev = res["n_eval"].cpu().numpy()[rows]
+    same = nev == ref["n_eval"]
+    log(f"  n_eval equal on {same.mean():.4f} of {rows.size} rays; mean n_eval {nev.mean():.1f}")
+    assert same.mean() > 0.99
+    if (~same).any():
+        assert np.all(np.abs(nev[~same] - ref["n_eval"][~same]) == 1)
+        tg = res["T"].double().cpu().numpy()[rows][~same]
+        near = np.minimum(np.abs(tg - t_term), np.abs(ref["T"][~same] - t_term)) / t_term
+        assert np.all(near <= 1e-4), near
+    for key in ("C", "F"):
+        err = np.abs(res[key].double().cpu().numpy()[rows][same] - ref[key][same]).max()
+        log(f"  max |{key} - oracle| = {err:.3e}")
+        assert err <= TOL, key
+    assert nev.mean() < 0.5 * 200  # termination cuts the ~200 samples per ray of this frame
