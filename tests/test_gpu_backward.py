@@ -330,6 +330,73 @@ def test_oblique_backward_vs_oracle_256(oblique_train):
         _check_against_oracle(sc, grads, ref)
 
 
+def test_oblique_soft_occ_backward_vs_oracle_256(oblique_train):
+    """The soft-occupancy training form (eps = 0.01) on the full oblique
+    scene: loss and gradients into features, MLP and the occupancy bounds for
+    256 of its rays against the oracle."""
+    sc, scene, t, o, d, target, n_max = oblique_train
+    eps = 0.01
+    log("test_oblique_soft_occ_backward_vs_oracle_256: eps=0.01")
+    o256, d256, t256 = o[:256].copy(), d[:256].copy(), target[:256].copy()
+    og, dg = rays_to(o256, d256)
+    tg = torch.from_numpy(t256).to(og.device)
+    ref_loss, _, ref = oracle.oracle_loss_and_grads(sc, o256, d256,
+                                                   oracle.RenderParams(n_max=n_max, c_bg=BG, occ_eps=eps),
+                                                   t256.astype(np.float64))
+    res = om.render(scene, og, dg, n_max=n_max, c_bg=BG, occ_eps=eps, batch_wv=True)
+    dC, loss = om.l2_loss_grad(res["C"], tg)
+    grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp", "occ")}
+    om.render_backward(scene, og, dg, res, dC, grads, n_max=n_max, c_bg=BG, occ_eps=eps)
+    torch.cuda.synchronize()
+    g = {k: v.double().cpu().numpy() for k, v in grads.items()}
+    assert abs(loss.item() - ref_loss) <= 1e-3 * ref_loss
+    _check_against_oracle(sc, g, ref)
+    cells, rows = ref["occ"]
+    go = g["occ"].reshape(-1, 2)
+    scale = np.abs(rows).max()
+    assert scale > 0
+    excess = np.abs(go[cells] - rows) - (1e-3 * np.abs(rows) + 2e-6 * scale)
+    log(f"  occupancy gradient: {len(cells)} cells, worst excess {excess.max() / scale:.2e}")
+    assert excess.max() <= 0
+    mask = np.ones(go.shape[0], bool)
+    mask[cells] = False
+    assert np.all(go[mask] == 0)
+
+
+def test_oblique_enc_smooth_gradients_vs_oracle_256(oblique_train):
+    """The encoded-direction training form on the full oblique scene: the
+    34-input MLP, L2 + view-smoothness loss (4 perturbations per ray,
+    weight 0.1) over 256 of its rays, loss and gradients against the
+    oracle."""
+    sc, scene, t, o, d, target, n_max = oblique_train
+    log("test_oblique_enc_smooth_gradients_vs_oracle_256: dir_freqs=4, P=4")
+    mlp = scenegen.mlp_params(4, seed=7)
+    sc4 = dict(sc, mlp=mlp, dir_freqs=4)
+    dev = t["grid"].device
+    scene4 = om.Scene(t["grid"], t["plane_xy"], t["plane_xz"], t["plane_yz"], t["occ"], torch.from_numpy(mlp).to(dev),
+                      box_lo=tuple(float(v) for v in sc["box_lo"]), box_hi=tuple(float(v) for v in sc["box_hi"]))
+    assert scene4.dir_freqs == 4
+    o256, d256, t256 = o[:256].copy(), d[:256].copy(), target[:256].copy()
+    pert = scenegen.view_perturbations(256, 4, seed=4)
+    w = float(np.float32(0.1))
+    ref_loss, _, ref = oracle.oracle_loss_and_grads(sc4, o256, d256, oracle.RenderParams(n_max=n_max, c_bg=BG),
+                                                   t256.astype(np.float64), smooth=dict(perturb=pert, weight=w))
+    og, dg = rays_to(o256, d256)
+    tg = torch.from_numpy(t256).to(dev)
+    pg = torch.from_numpy(pert).to(dev)
+    res = om.render(scene4, og, dg, n_max=n_max, c_bg=BG, mlp_bf16=0, batch_wv=True)
+    dC, l2 = om.l2_loss_grad(res["C"], tg)
+    grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=dev) for k in SOURCES}
+    grads["mlp"] = torch.zeros(mlp.shape, dtype=torch.float32, device=dev)
+    dF = torch.zeros_like(res["F"])
+    ls = om.smooth_loss(scene4, res["F"], dg, pg, w, dL_dF=dF, grad_mlp=grads["mlp"])
+    om.render_backward(scene4, og, dg, res, dC, grads, n_max=n_max, c_bg=BG, dL_dF=dF)
+    torch.cuda.synchronize()
+    log(f"  loss {l2.item() + ls.item():.6e} vs oracle {ref_loss:.6e}")
+    assert abs(l2.item() + ls.item() - ref_loss) <= 1e-3 * ref_loss
+    _check_against_oracle(sc4, {k: v.double().cpu().numpy() for k, v in grads.items()}, ref)
+
+
 def test_oblique_finite_differences_2e18(oblique_train):
     """Central FD (eps = 1e-3) of the float64 GPU loss over all 2^18 rays,
     L2 against oracle renders of the perturbed scene."""
