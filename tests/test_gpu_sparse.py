@@ -125,7 +125,8 @@ def test_sparse_scene_is_render_only(tiny):
 
 
 def test_sparse_oblique_1080p_equals_dense():
-    """The bench's sparse form: the full 1920x1080 oblique frame, every ray."""
+    """The bench's sparse forms: the full 1920x1080 oblique frame, every ray,
+    float32 and 8-bit."""
     log("test_sparse_oblique_1080p_equals_dense: building the oblique scene")
     cfg, recipe = scenegen.workload("oblique-1080p")
     sc = scenegen.make_scene(cfg)
@@ -139,6 +140,14 @@ def test_sparse_oblique_1080p_equals_dense():
         f"vs dense {t['grid'].numel() * 4 / 2**30:.2f} GiB")
     assert sg.n_blocks < sg.blocks.numel()
     _equal(om.render(sp, og, dg, n_max=256, c_bg=BG), dense)
+    del sp, atlas, dense
+    # the bench's 8-bit sparse form: 8-bit codes baked on the GPU, in blocks
+    codes, quant = om.quantize_features(t)
+    dense8 = om.Scene(codes["grid"], codes["plane_xy"], codes["plane_xz"], codes["plane_yz"], t["occ"], t["mlp"],
+                      box_lo=tuple(scene._desc.box_lo), box_hi=tuple(scene._desc.box_hi), quant=quant)
+    sp8, _, sg8 = _sparse_scene(dense8, t, 3, quant)
+    log(f"  8-bit: kept {sg8.n_blocks} blocks")
+    _equal(om.render(sp8, og, dg, n_max=256, c_bg=BG), om.render(dense8, og, dg, n_max=256, c_bg=BG))
 
 
 def test_sparse_u8_with_pyramid_equals_dense(tiny):
