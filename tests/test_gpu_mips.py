@@ -108,3 +108,31 @@ def test_pyramid_detached_by_update():
     assert scene.mip_levels == 3
     scene.update(occ=t["occ"].clone())
     assert scene.mip_levels == 0 and scene.occupancy_mips() == []
+
+
+def test_high_altitude_1080p_form():
+    """The bench's high-altitude form: the oblique scene's tensors over a
+    [0, 1] z box, one 1920x1080 camera at pitch 45 deg from z = 1.5 in Morton
+    order.  The 4-level pyramid leaves placement and render unchanged, and
+    sampled rays match the oracle."""
+    log("test_high_altitude_1080p_form: 1080p, 4 levels (oracle on 700 rays)")
+    cfg, _ = scenegen.workload("oblique-1080p")
+    sc = dict(scenegen.make_scene(cfg))
+    sc["box_hi"] = np.array([1.0, 1.0, 1.0])
+    o, d = scenegen.camera_rays(1920, 1080, 45.0, 90.0, origin_z=1.5,
+                                pixels=scenegen.pixel_order(1920, 1080, "morton"))
+    rows = np.unique(np.concatenate([np.random.default_rng(12).choice(o.shape[0], 700, replace=False),
+                                     np.arange(16), np.arange(o.shape[0] - 21, o.shape[0])]))
+    _placement_with_and_without(sc, o, d, 256, 4, rows)
+    scene, t = upload_scene(sc)
+    tall = om.Scene(t["grid"], t["plane_xy"], t["plane_xz"], t["plane_yz"], t["occ"], t["mlp"],
+                    box_lo=tuple(sc["box_lo"]), box_hi=(1.0, 1.0, 1.0))
+    tall.build_occupancy_mips(4)
+    og, dg = rays_to(o, d)
+    res = om.render(tall, og, dg, n_max=256, c_bg=BG)
+    ref = oracle.oracle_render(sc, o[rows], d[rows], oracle.RenderParams(n_max=256, c_bg=BG), keep_k=False)
+    assert np.array_equal(res["n_eval"].cpu().numpy()[rows], ref["n_eval"])
+    for key in ("C", "T", "F"):
+        err = np.abs(res[key].double().cpu().numpy()[rows] - ref[key]).max()
+        log(f"  max |{key} - oracle| = {err:.2e}")
+        assert err <= 1e-5, key
