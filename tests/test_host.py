@@ -45,3 +45,27 @@ def test_towers_scene_has_uneven_intervals():
     thick = sc["occ"][..., 1] - sc["occ"][..., 0]
     assert (thick > 0.019).mean() >= 0.1
     assert thick.max() <= 0.25 + 1e-6
+
+
+def test_traffic_figure_only_for_the_profiled_kernel_source(tmp_path, monkeypatch):
+    """The bench reports the committed HBM traffic only while the hashed
+    kernel sources are the ones the counters were taken on."""
+    import shutil
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    csrc = tmp_path / "paper_2404_09531_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    for f in ("omerf_device.h", "march.hip"):
+        shutil.copy(os.path.join(ROOT, "paper_2404_09531_amd", "csrc", f), csrc / f)
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("k", "w") is None  # no record file
+    rec = {"k": {"w": {"source_hash": bench.kernel_source_hash(), "hbm_bytes_per_launch": 1234}}}
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    assert bench.measured_traffic("k", "w") == 1234
+    assert bench.measured_traffic("k", "other") is None
+    with open(csrc / "march.hip", "a") as fh:
+        fh.write("\n// edited\n")
+    assert bench.measured_traffic("k", "w") is None
