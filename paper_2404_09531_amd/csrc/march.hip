@@ -594,6 +594,9 @@ __device__ __forceinline__ void scatter_occ(float* gocc, bool act, const OccValu
     }
 }
 
+// Longest chunk of rays a backward block sorts by length (LDS: 6 KB).
+constexpr int kSortMax = 1024;
+
 template <class S, bool kSoft, int NIN>
 __global__ __launch_bounds__(kBlock, NIN == 10 ? 4 : 1) void k_march_bwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                       const float* __restrict__ d_, int64_t n, int64_t chunk,
@@ -608,6 +611,8 @@ __global__ __launch_bounds__(kBlock, NIN == 10 ? 4 : 1) void k_march_bwd(SceneDe
     __shared__ int qs[kGroupsPerBlock][kQueue];
     __shared__ float sW[kMlpMaxSize];
     __shared__ __attribute__((aligned(16))) Stage stages[kGroupsPerBlock];
+    __shared__ int s_key[kSortMax];
+    __shared__ uint16_t s_ord[kSortMax];
     for (int i = threadIdx.x; i < kMlpMaxSize; i += kBlock) sW[i] = 0.0f;
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -617,8 +622,28 @@ __global__ __launch_bounds__(kBlock, NIN == 10 ? 4 : 1) void k_march_bwd(SceneDe
     Stage& stage = stages[gid];
     const float* W = sc.mlp;
     const int64_t start = (int64_t)xcd_block(blockIdx.x, gridDim.x) * chunk;
-    const int64_t stop_r = min(n, start + chunk);
-    for (int64_t ray = start + gid; ray < stop_r; ray += kGroupsPerBlock) {
+    const int cnt = (int)(min(n, start + chunk) - start);
+    // A wave's four groups walk their rays in step, so a wave waits for its
+    // longest ray.  The chunk is therefore walked longest-first (a stable
+    // rank sort of n_eval in LDS), which hands each wave rays of similar
+    // length; chunks longer than kSortMax keep their order.
+    const bool by_len = cnt <= kSortMax;
+    if (by_len) {
+        for (int i = threadIdx.x; i < cnt; i += kBlock) s_key[i] = n_eval[start + i];
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += kBlock) {
+            const int ki = s_key[i];
+            int r = 0;
+            for (int j = 0; j < cnt; ++j) {
+                const int kj = s_key[j];
+                r += (kj > ki) || (kj == ki && j < i);
+            }
+            s_ord[r] = (uint16_t)i;
+        }
+        __syncthreads();
+    }
+    for (int it = gid; it < cnt; it += kGroupsPerBlock) {
+        const int64_t ray = start + (by_len ? (int)s_ord[it] : it);
         const float3 o = load3(o_, ray), d = load3(d_, ray);
         const int ne = n_eval[ray];
         const float Tn = Ts[ray];
