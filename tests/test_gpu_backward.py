@@ -413,3 +413,40 @@ def test_oblique_finite_differences_2e18(oblique_train):
     _, fd4, an4, err4 = _fd_check(scene, t, og, dg, tg, n_max, grads, eps=1e-4, picks=mlp_sel)
     log(f"  FD eps=1e-4 mlp      : max rel err {err4.max():.2e}, median {np.median(err4):.2e}")
     assert err.max() <= 1e-3, [(p, f, a) for p, f, a, e in zip(picks, fd, an, err) if e > 1e-3]
+
+
+def test_backward_long_chunks_keep_caller_order():
+    """Above 4096 x 1024 rays a backward block's chunk is longer than the
+    1024 rays it can sort by length and is walked in the caller's order.
+    That path and the length-sorted one must give the same gradients: the
+    whole batch in one call against its two halves in two calls (the
+    backward adds into the gradient buffers), with the same dL/dC."""
+    n = 4096 * 1024 + 4096 * 16 + 5  # chunks of 1040 rays, ragged tail
+    log(f"test_backward_long_chunks_keep_caller_order: {n} rays")
+    sc = scenegen.make_scene(scenegen.TINY)
+    scene, t = upload_scene(sc)
+    o, d = scenegen.oblique_rays(n, seed=23)
+    og, dg = rays_to(o, d)
+    kw = dict(n_max=64, c_bg=BG)
+    res = om.render(scene, og, dg, batch_wv=True, **kw)
+    gen = torch.Generator(device=og.device)
+    gen.manual_seed(3)
+    dC = (torch.randn(res["C"].shape, device=og.device, generator=gen) * 1e-6).contiguous()
+    zero = lambda: {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp")}  # noqa: E731
+    whole = zero()
+    om.render_backward(scene, og, dg, res, dC, whole, **kw)
+    halves = zero()
+    h = n // 2
+    for sl in (slice(0, h), slice(h, n)):
+        part = {k: v[sl].contiguous() for k, v in res.items()}
+        om.render_backward(scene, og[sl].contiguous(), dg[sl].contiguous(), part, dC[sl].contiguous(), halves, **kw)
+    torch.cuda.synchronize()
+    # float32 atomics add millions of cancelling terms in a different order
+    # in the two runs (8e-6 of the largest entry measured); a skipped or
+    # repeated ray moves entries by far more than the 5e-5 floor
+    for k in (*SOURCES, "mlp"):
+        scale = float(whole[k].abs().max())
+        diff = (whole[k] - halves[k]).abs()
+        log(f"  {k}: max |g| {scale:.3e}, max |whole - halves| / max |g| {float(diff.max()) / scale:.2e}")
+        assert scale > 0
+        assert float((diff - (1e-3 * halves[k].abs() + 5e-5 * scale)).max()) <= 0, k
