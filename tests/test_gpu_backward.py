@@ -442,8 +442,8 @@ def test_backward_long_chunks_keep_caller_order():
         om.render_backward(scene, og[sl].contiguous(), dg[sl].contiguous(), part, dC[sl].contiguous(), halves, **kw)
     torch.cuda.synchronize()
     # float32 atomics add millions of cancelling terms in a different order
-    # in the two runs (8e-6 of the largest entry measured); a skipped or
-    # repeated ray moves entries by far more than the 5e-5 floor
+    # in the two runs (up to 8.5e-6 of the largest entry measured), hence
+    # the 5e-5 floor
     for k in (*SOURCES, "mlp"):
         scale = float(whole[k].abs().max())
         diff = (whole[k] - halves[k]).abs()
