@@ -243,6 +243,24 @@ int om_place_samples(const om_scene* scene, const float* o, const float* d, int6
                      const om_params* p, int32_t* k_out, int32_t* n_placed, void* stream);
 
 /*
+ * Feature rows a render reads (Eq. 2 over the samples of Sec. 4.1 / 4.4):
+ * for every evaluated sample -- the first n_eval[r] placed samples of ray r
+ * (n_eval: device int32 [n] from om_render with the same parameters), or
+ * every placed sample when n_eval is NULL -- stores the byte 1 at its 8 grid
+ * vertices and 12 plane texels.  grid_flags: device uint8 with one byte per
+ * grid row ([Lz][Ly][Lx] for a dense grid, the atlas's
+ * (n_blocks + 1) (B + 1)^3 vertices for sparse blocks); xy_flags [Ny][Nx],
+ * xz_flags [Nz][Nx], yz_flags [Nz][Ny].  Flags are only set, never cleared:
+ * the caller zeroes them (or accumulates several calls).  The marked rows are
+ * the rows whose gradient a backward can touch, and their bytes the least
+ * HBM traffic a render must move (each row read once).  p->t_term and
+ * p->c_bg are ignored.
+ */
+int om_mark_rows(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                 const int32_t* n_eval, uint8_t* grid_flags, uint8_t* xy_flags, uint8_t* xz_flags,
+                 uint8_t* yz_flags, void* stream);
+
+/*
  * Forward render of n rays (Sec. 3 Eq. 1-4 with the occupancy-plane
  * sampling of Sec. 4.1 / 4.4).  o, d: device float32 [n][3]; out: see
  * om_fwd_out.  Deterministic: no atomics, identical results run to run.
@@ -399,6 +417,18 @@ int64_t om_sparse_grid_index(const om_scene* scene, int block_shift, int32_t* gr
                              void* stream);
 int om_sparse_grid_fill(const om_scene* scene, int block_shift, const int32_t* grid_blocks, int64_t n_blocks,
                         void* atlas, void* stream);
+
+/*
+ * bfloat16 shadow of float32 parameters (the storage form of Sec. 4.4 kept
+ * in 16 bits; the re-cast after each optimiser step of a bfloat16 scene
+ * trained through float32 master copies): dst[i] = the upper 16 bits of
+ * src[i] rounded to nearest, ties to even.  Finite values beyond the largest
+ * bfloat16 become infinities of their sign; NaN stays NaN (quiet, same
+ * sign); infinities and signed zeros are kept.  src: device float32 [n];
+ * dst: device uint16 [n] (bfloat16 bit patterns), not overlapping src; both
+ * 16-byte aligned.  n = 0 is a no-op.  Asynchronous on `stream`.
+ */
+int om_cast_bf16(const float* src, int64_t n, uint16_t* dst, void* stream);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char* om_last_error(void);

@@ -252,7 +252,10 @@ def _render_chunk(scene, o, d, prm: RenderParams, grad: bool, mlp_leaf=None):
     C = cd_acc + g + T[:, None] * bg[None, :]
     F = torch.cat([cd_acc, f_acc], dim=1)
     return dict(C=C, T=T, F=F, n_placed=n_placed, n_eval=n_eval.numpy().astype(np.int32),
-                k_list=k_list, tables=tables, occ_leaf=occ_leaf, occ_uniq=occ_uniq)
+                k_list=k_list, tables=tables, occ_leaf=occ_leaf, occ_uniq=occ_uniq,
+                # per-sample intermediates, for the float32 error scale of the gradient
+                samples=dict(rows=rows, slots=slots, p=p64, terms=terms, tau=tau_s, cd=cd_s, f=f_s,
+                             mask=None if mask is None else m_s), x=x, g=g)
 
 
 def oracle_render(scene: Dict[str, np.ndarray], o: np.ndarray, d: np.ndarray, prm: RenderParams,
@@ -282,11 +285,15 @@ def oracle_render(scene: Dict[str, np.ndarray], o: np.ndarray, d: np.ndarray, pr
     return out
 
 
-def oracle_loss_and_grads(scene, o, d, prm: RenderParams, target: np.ndarray, smooth: Optional[dict] = None):
+def oracle_loss_and_grads(scene, o, d, prm: RenderParams, target: Optional[np.ndarray] = None,
+                          smooth: Optional[dict] = None, upstream: Optional[np.ndarray] = None):
     """L2 loss (mean over rays x 3) and its float64 gradient.  With
     smooth = dict(perturb=[n, P, 3], weight=w) the loss also holds the
     view-smoothness term of Eq. 9-10 on the rays' composited features F
     (the training objective of Eq. 10 without its other regularisers).
+    With upstream = [n, 3] instead of target, the colour term is the linear
+    functional sum(upstream * C), whose gradient is the vector-Jacobian
+    product of the render with that fixed dL/dC (the backward's input).
 
     Returns (loss, C, grads) where grads[src] = (flat row indices, [U, 8]
     gradient rows) for the four feature sources and grads['mlp'] is the
@@ -297,8 +304,12 @@ def oracle_loss_and_grads(scene, o, d, prm: RenderParams, target: np.ndarray, sm
     mlp_leaf = torch.from_numpy(np.asarray(scene["mlp"], dtype=np.float64).copy()).requires_grad_(True)
     res = _render_chunk(scene, o, d, prm, grad=True, mlp_leaf=mlp_leaf)
     C = res["C"]
-    tgt = torch.from_numpy(np.asarray(target, dtype=np.float64))
-    loss = torch.mean((C - tgt) ** 2)
+    if (target is None) == (upstream is None):
+        raise ValueError("pass exactly one of target and upstream")
+    if upstream is not None:
+        loss = torch.sum(torch.from_numpy(np.asarray(upstream, dtype=np.float64)) * C)
+    else:
+        loss = torch.mean((C - torch.from_numpy(np.asarray(target, dtype=np.float64))) ** 2)
     if smooth is not None:
         loss = loss + _smooth_term(res["F"], d, smooth["perturb"], mlp_leaf, int(scene.get("dir_freqs", 0)),
                                    float(smooth["weight"]))

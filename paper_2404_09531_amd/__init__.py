@@ -40,7 +40,7 @@ _FREQS_OF = {mlp_nparams(0): 0, mlp_nparams(4): 4}
 __all__ = ["Scene", "place_samples", "render", "render_backward", "RenderFn", "SmoothFn", "smooth_loss",
            "l2_loss_fp64", "l2_loss_grad", "occ_interval_loss", "mlp_nparams", "feature_range", "quant_params",
            "quantize_u8", "quantize_features", "sparse_grid", "SparseGrid", "DELTA", "OmerfError",
-           "OM_MAX_SAMPLES", "to_bf16"]
+           "OM_MAX_SAMPLES", "to_bf16", "mark_rows"]
 
 
 def _need(t: torch.Tensor, name: str, dtype, shape=None) -> None:
@@ -56,9 +56,17 @@ def _need(t: torch.Tensor, name: str, dtype, shape=None) -> None:
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
 
 
-def to_bf16(t: torch.Tensor) -> torch.Tensor:
-    """bfloat16 shadow of a float32 tensor (round to nearest even)."""
-    return t.to(torch.bfloat16).contiguous()
+def to_bf16(t: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """bfloat16 shadow of a float32 tensor, rounded to nearest even by the
+    library (om_cast_bf16), into `out` (bfloat16, same shape; allocated if
+    None) -- the re-cast of a bfloat16 scene after an optimiser step on its
+    float32 master copy."""
+    _need(t, "src", torch.float32)
+    if out is None:
+        out = torch.empty(t.shape, dtype=torch.bfloat16, device=t.device)
+    _need(out, "out", torch.bfloat16, t.shape)
+    _lib.check("om_cast_bf16", _lib.lib().om_cast_bf16(t.data_ptr(), t.numel(), out.data_ptr(), _lib.stream_of(t)))
+    return out
 
 
 class Scene:
@@ -225,6 +233,28 @@ def place_samples(scene: Scene, o, d, n_max: int, delta: float = DELTA):
                                                                  ctypes.byref(p), k.data_ptr(), cnt.data_ptr(),
                                                                  _lib.stream_of(o)))
     return k, cnt
+
+
+def mark_rows(scene: Scene, o, d, n_max: int, n_eval: Optional[torch.Tensor] = None, delta: float = DELTA,
+              flags: Optional[Dict[str, torch.Tensor]] = None) -> Dict[str, torch.Tensor]:
+    """uint8 flags per feature row (keys grid, plane_xy, plane_xz, plane_yz;
+    one byte per vertex / texel, 1 where some evaluated sample of the rays
+    reads it: the first n_eval placed samples, or all placed samples).
+    `flags` (optional, zeroed by the caller) accumulates instead."""
+    n = _rays(scene, o, d)
+    if n_eval is not None:
+        _need(n_eval, "n_eval", torch.int32, (n,))
+    src = scene.tensors
+    if flags is None:
+        flags = {k: torch.zeros(src[k].shape[:-1], dtype=torch.uint8, device=o.device)
+                 for k in ("grid", "plane_xy", "plane_xz", "plane_yz")}
+    for k in ("grid", "plane_xy", "plane_xz", "plane_yz"):
+        _need(flags[k], f"flags[{k}]", torch.uint8, src[k].shape[:-1])
+    p = _params(n_max, delta, 0.0, (0, 0, 0), -1)
+    _lib.check("om_mark_rows", _lib.lib().om_mark_rows(
+        scene.handle, o.data_ptr(), d.data_ptr(), n, ctypes.byref(p), _lib.ptr(n_eval), flags["grid"].data_ptr(),
+        flags["plane_xy"].data_ptr(), flags["plane_xz"].data_ptr(), flags["plane_yz"].data_ptr(), _lib.stream_of(o)))
+    return flags
 
 
 BATCH = 16  # samples per batch of the per-batch w v sums (OM_BATCH)

@@ -24,7 +24,7 @@ EXPORTS = ("om_scene_create", "om_scene_update", "om_scene_destroy", "om_occupan
            "om_render_backward", "om_render_backward_ex", "om_smooth_loss", "om_render_fwd_bwd_l2", "om_render_fwd_bwd_l2_workspace_size",
            "om_occ_interval_loss", "om_feature_range", "om_quant_params", "om_quantize_u8",
            "om_sparse_grid_index", "om_sparse_grid_fill",
-           "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str",
+           "om_cast_bf16", "om_mark_rows", "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str",
            "om_version")
 
 
@@ -87,6 +87,9 @@ def lib() -> ctypes.CDLL:
         L.om_quantize_u8.argtypes = [c_void_p, c_int64, POINTER(c_float), POINTER(c_float), c_void_p, c_void_p]
         L.om_sparse_grid_index.argtypes = [c_void_p, c_int, c_void_p, c_int64, c_void_p]
         L.om_sparse_grid_fill.argtypes = [c_void_p, c_int, c_void_p, c_int64, c_void_p, c_void_p]
+        L.om_cast_bf16.argtypes = [c_void_p, c_int64, c_void_p, c_void_p]
+        L.om_mark_rows.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(OmParams), c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p, c_void_p]
         L.om_l2_loss_fp64.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
         L.om_l2_loss_grad.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
         L.om_render_fwd_bwd_l2.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(OmParams), c_void_p,

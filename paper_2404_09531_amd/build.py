@@ -13,8 +13,11 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "march.hip", "mlp.hip", "bake.hip"]
+SOURCES = ["api.hip", "march_fwd.hip", "march_bwd.hip", "mlp.hip", "bake.hip"]
 LIB = os.path.join(HERE, "libomerf.so")
+# measurement-only calibration kernels (not part of the C ABI)
+CALIB_SOURCES = ["calib.hip"]
+CALIB_LIB = os.path.join(HERE, "libomcalib.so")
 ARCH = "gfx950"
 
 FLAGS = [
@@ -76,16 +79,22 @@ def build(asm_dir: str | None = None, verbose: bool = False, out: str | None = N
             print(res.stderr, file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+    with ThreadPoolExecutor(len(SOURCES) + len(CALIB_SOURCES)) as ex:
+        objs = list(ex.map(compile_one, SOURCES + CALIB_SOURCES))
+
+    def link(objects, lib):
+        os.makedirs(os.path.dirname(lib), exist_ok=True)
+        tmp = lib + ".tmp"
+        cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objects, "-o", tmp]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"link failed:\n{res.stderr}")
+        os.replace(tmp, lib)
+
     lib = out or LIB
-    os.makedirs(os.path.dirname(lib), exist_ok=True)
-    tmp = lib + ".tmp"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError(f"link failed:\n{res.stderr}")
-    os.replace(tmp, lib)
+    link(objs[:len(SOURCES)], lib)
+    if out is None:
+        link(objs[len(SOURCES):], CALIB_LIB)
     return lib
 
 

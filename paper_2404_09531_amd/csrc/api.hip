@@ -289,6 +289,20 @@ int om_place_samples(const om_scene* scene, const float* o, const float* d, int6
     return hip_status(launch_place(scene->dev, rp, o, d, n, k_out, n_placed, (hipStream_t)stream), "om_place_samples");
 }
 
+int om_mark_rows(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                 const int32_t* n_eval, uint8_t* grid_flags, uint8_t* xy_flags, uint8_t* xz_flags,
+                 uint8_t* yz_flags, void* stream) {
+    int rc = check_rays(scene, o, d, n);
+    if (rc != OM_OK) return rc;
+    RayParams rp;
+    if ((rc = validate_params(p, &rp)) != OM_OK) return rc;
+    if (n == 0) return ok();
+    if (!grid_flags || !xy_flags || !xz_flags || !yz_flags) return fail(OM_ERR_INVALID, "flag buffers are NULL");
+    return hip_status(launch_mark(scene->dev, rp, o, d, n, n_eval, grid_flags, xy_flags, xz_flags, yz_flags,
+                                  (hipStream_t)stream),
+                      "om_mark_rows");
+}
+
 }  // extern "C"
 
 namespace {
@@ -545,6 +559,18 @@ int om_sparse_grid_fill(const om_scene* scene, int block_shift, const int32_t* g
     return hip_status(launch_blocks_fill(scene->dev, block_shift, bn[0], bn[1], bn[2], grid_blocks, n_blocks, units,
                                          atlas, (hipStream_t)stream),
                       "om_sparse_grid_fill");
+}
+
+int om_cast_bf16(const float* src, int64_t n, uint16_t* dst, void* stream) {
+    if (n < 0) return fail(OM_ERR_INVALID, "n must be >= 0");
+    if (n == 0) return ok();
+    if (!src || !dst) return fail(OM_ERR_INVALID, "NULL pointer");
+    if (((uintptr_t)src & 15u) || ((uintptr_t)dst & 15u))
+        return fail(OM_ERR_INVALID, "src and dst must be 16-byte aligned");
+    const char* sb = reinterpret_cast<const char*>(src);
+    const char* db = reinterpret_cast<const char*>(dst);
+    if (db < sb + n * 4 && sb < db + n * 2) return fail(OM_ERR_INVALID, "dst must not overlap src");
+    return hip_status(launch_cast_bf16(src, n, dst, (hipStream_t)stream), "om_cast_bf16");
 }
 
 int om_l2_loss_fp64(const float* C, const float* target, int64_t n, double* out, void* stream) {

@@ -10,6 +10,9 @@
 //              decision taken in binary32 (NaN -> 0).
 // k_blocks_* : sparse voxel-block storage of the grid (which blocks to
 //              keep, and the copy into the block atlas).
+// k_cast_bf16: the bfloat16 shadow of a float32 tensor, rounded to nearest
+//              even (the re-cast after each optimiser step of a bfloat16
+//              scene with float32 master parameters).
 #include "../../include/omerf.h"
 #include "omerf_device.h"
 #include "omerf_launch.h"
@@ -178,6 +181,51 @@ hipError_t launch_blocks_fill(const SceneDev& sc, int shift, int bnx, int bny, i
     const int64_t n = (int64_t)bnx * bny * bnz;
     hipLaunchKernelGGL(k_blocks_fill, dim3((unsigned)n), dim3(kBlock), 0, s, sc, shift, bnx, bny, idx, n_blocks, units,
                        reinterpret_cast<uint2*>(atlas));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// float32 -> bfloat16 (the upper 16 bits of a binary32), rounded to nearest,
+// ties to even: add 0x7fff plus the kept part's lowest bit, then truncate.
+// Finite values beyond the largest bfloat16 round to infinity; NaN stays a
+// (quiet) NaN with its sign.  Eight values per thread: two 16-byte loads and
+// one 16-byte store; the tail of n mod 8 values is converted one per thread.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t bf16_rne(float x) {
+    const uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (u >> 16) | 0x40u;  // NaN: keep it quiet
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_bf16(const float4* __restrict__ src, uint4* __restrict__ dst,
+                                                      int64_t n8) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n8; i += stride) {
+        const float4 a = src[2 * i], b = src[2 * i + 1];
+        uint4 o;
+        o.x = bf16_rne(a.x) | (bf16_rne(a.y) << 16);
+        o.y = bf16_rne(a.z) | (bf16_rne(a.w) << 16);
+        o.z = bf16_rne(b.x) | (bf16_rne(b.y) << 16);
+        o.w = bf16_rne(b.z) | (bf16_rne(b.w) << 16);
+        dst[i] = o;
+    }
+}
+
+__global__ void k_cast_bf16_tail(const float* __restrict__ src, uint16_t* __restrict__ dst, int64_t first,
+                                 int64_t n) {
+    const int64_t i = first + threadIdx.x;
+    if (i < n) dst[i] = (uint16_t)bf16_rne(src[i]);
+}
+
+hipError_t launch_cast_bf16(const float* src, int64_t n, uint16_t* dst, hipStream_t s) {
+    const int64_t n8 = n / 8;
+    if (n8 > 0) {
+        int64_t blocks = (n8 + kBlock - 1) / kBlock;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(k_cast_bf16, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                           reinterpret_cast<const float4*>(src), reinterpret_cast<uint4*>(dst), n8);
+    }
+    if (n8 * 8 < n) hipLaunchKernelGGL(k_cast_bf16_tail, dim3(1), dim3(8), 0, s, src, dst, n8 * 8, n);
     return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@
 //                  holds rows 4(l/16)..+3 of column l%16) is exactly the B
 //                  operand layout of the next, so no data moves between
 //                  layers.  Biases enter as the accumulator's initial value.
-#include "omerf_device.h"
+#include "bwd_device.h"
 #include "omerf_launch.h"
 
 namespace omerf {

@@ -10,6 +10,8 @@ namespace omerf {
 
 hipError_t launch_place(const SceneDev& sc, const RayParams& rp, const float* o, const float* d, int64_t n,
                         int32_t* k_out, int32_t* n_placed, hipStream_t s);
+hipError_t launch_mark(const SceneDev& sc, const RayParams& rp, const float* o, const float* d, int64_t n,
+                       const int32_t* n_eval, uint8_t* fg, uint8_t* fxy, uint8_t* fxz, uint8_t* fyz, hipStream_t s);
 hipError_t launch_march_fwd(const SceneDev& sc, int dtype, const RayParams& rp, const float* o, const float* d,
                             int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, float* batch_wv,
                             hipStream_t s);
@@ -28,6 +30,7 @@ hipError_t launch_quantize(const float* x, int64_t n, const float* lo, const flo
 hipError_t launch_blocks_mark(const SceneDev& sc, int shift, int bnx, int bny, int bnz, int32_t* mark, hipStream_t s);
 hipError_t launch_blocks_fill(const SceneDev& sc, int shift, int bnx, int bny, int bnz, const int32_t* idx,
                               int64_t n_blocks, int units, void* atlas, hipStream_t s);
+hipError_t launch_cast_bf16(const float* src, int64_t n, uint16_t* dst, hipStream_t s);
 hipError_t launch_l2(const float* C, const float* tgt, int64_t n, float* dC, double* loss, hipStream_t s);
 
 }  // namespace omerf

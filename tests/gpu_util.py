@@ -12,7 +12,7 @@ def upload_scene(sc, dtype=torch.float32, device=DEV):
     t = {}
     for k in ("grid", "plane_xy", "plane_xz", "plane_yz"):
         x = torch.from_numpy(np.ascontiguousarray(sc[k], dtype=np.float32)).to(device)
-        t[k] = x.to(dtype).contiguous() if dtype != torch.float32 else x
+        t[k] = om.to_bf16(x) if dtype == torch.bfloat16 else x
     t["occ"] = torch.from_numpy(np.ascontiguousarray(sc["occ"], dtype=np.float32)).to(device)
     t["mlp"] = torch.from_numpy(np.ascontiguousarray(sc["mlp"], dtype=np.float32)).to(device)
     scene = om.Scene(t["grid"], t["plane_xy"], t["plane_xz"], t["plane_yz"], t["occ"], t["mlp"],

@@ -202,3 +202,54 @@ def test_bf16_oblique_1080p_sampled_parity():
     err = np.abs(full["C"].double().cpu().numpy()[rows] - ref["C"])
     log(f"  full bf16 form: max |C - oracle(rounded)| = {err.max():.2e}, mean {err.mean():.2e}")
     assert err.max() < 2e-2 and err.mean() < 3e-3
+
+
+def _bits_f32(u):
+    return np.asarray(u, dtype=np.uint32).view(np.float32)
+
+
+def test_cast_bf16_bit_exact():
+    """om_cast_bf16 (the bfloat16 shadow refresh) rounds to nearest even
+    exactly as the CPU conversion does: ties to even at both parities, the
+    round-up into infinity above the largest bfloat16, subnormals, signed
+    zeros and infinities; NaN stays NaN.  Random values over the whole
+    exponent range, with a ragged tail (n mod 8 = 3)."""
+    log("test_cast_bf16_bit_exact")
+    special = _bits_f32([0x00000000, 0x80000000, 0x3f800000, 0xbf800000, 0x3f808000, 0x3f818000, 0x3f80ffff,
+                         0x3f817fff, 0x7f7f0000, 0x7f7f7fff, 0x7f7f8000, 0x7f7fffff, 0xff7f8000, 0x7f800000,
+                         0xff800000, 0x00000001, 0x00008000, 0x00018000, 0x807fffff, 0x00800000, 0x7fc00000,
+                         0x7f800001, 0xffc00001])
+    rng = np.random.default_rng(12)
+    rand = rng.integers(0, 2 ** 32, size=1_000_003, dtype=np.uint64).astype(np.uint32).view(np.float32)
+    for x in (special, rand):
+        xg = torch.from_numpy(x.copy()).cuda()
+        got = om.to_bf16(xg).view(torch.int16).cpu().numpy().view(np.uint16)
+        want = torch.from_numpy(x.copy()).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+        nan = np.isnan(x)
+        back = got.astype(np.uint32) << 16
+        assert np.all(np.isnan(back.view(np.float32)[nan]))
+        mism = np.nonzero(got[~nan] != want[~nan])[0]
+        log(f"  {x.size} values, {int(nan.sum())} NaN, {mism.size} mismatches")
+        assert mism.size == 0, [(hex(x[~nan].view(np.uint32)[i]), hex(got[~nan][i]), hex(want[~nan][i]))
+                                for i in mism[:5]]
+
+
+def test_cast_bf16_shadow_refresh_and_errors():
+    """The re-cast after an optimiser step writes into the existing shadow
+    (no new tensor), and the call rejects misaligned or overlapping buffers;
+    n = 0 is a no-op."""
+    log("test_cast_bf16_shadow_refresh_and_errors")
+    master = torch.randn(4096, 8, device="cuda")
+    shadow = om.to_bf16(master)
+    ptr = shadow.data_ptr()
+    master -= 0.01 * torch.randn_like(master)  # an optimiser step
+    om.to_bf16(master, out=shadow)
+    assert shadow.data_ptr() == ptr
+    assert torch.equal(shadow.cpu(), master.cpu().to(torch.bfloat16))
+    L = om._lib.lib()
+    base = torch.zeros(64, device="cuda")
+    out = torch.zeros(64, dtype=torch.bfloat16, device="cuda")
+    assert L.om_cast_bf16(base.data_ptr() + 4, 8, out.data_ptr(), None) == om._lib.OM_ERR_INVALID
+    assert L.om_cast_bf16(base.data_ptr(), 8, base.data_ptr() + 16, None) == om._lib.OM_ERR_INVALID
+    assert L.om_cast_bf16(base.data_ptr(), 0, out.data_ptr(), None) == om._lib.OM_OK
+    assert L.om_cast_bf16(0, 8, out.data_ptr(), None) == om._lib.OM_ERR_INVALID

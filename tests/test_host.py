@@ -57,7 +57,7 @@ def test_traffic_figure_only_for_the_profiled_kernel_source(tmp_path, monkeypatc
 
     csrc = tmp_path / "paper_2404_09531_amd" / "csrc"
     csrc.mkdir(parents=True)
-    for f in ("omerf_device.h", "march.hip"):
+    for f in bench.KERNEL_SOURCES["fwd"]:
         shutil.copy(os.path.join(ROOT, "paper_2404_09531_amd", "csrc", f), csrc / f)
     (tmp_path / "profiles").mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
@@ -66,6 +66,29 @@ def test_traffic_figure_only_for_the_profiled_kernel_source(tmp_path, monkeypatc
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
     assert bench.measured_traffic("k", "w") == 1234
     assert bench.measured_traffic("k", "other") is None
-    with open(csrc / "march.hip", "a") as fh:
+    with open(csrc / "march_fwd.hip", "a") as fh:
         fh.write("\n// edited\n")
     assert bench.measured_traffic("k", "w") is None
+
+
+def test_oracle_pool_equals_serial_oracle():
+    """render_parallel splits the rays over worker processes and returns what
+    oracle_render returns; the k-list check flags exactly the altered rays."""
+    import numpy as np
+
+    import oracle
+    import scenegen
+    from oracle.parallel import render_parallel
+
+    sc = scenegen.make_scene(scenegen.TINY)
+    o, d = scenegen.oblique_rays(300, seed=5)
+    prm = oracle.RenderParams(n_max=64, c_bg=(0.25, 0.5, 0.75))
+    ref = oracle.oracle_render(sc, o, d, prm)
+    k = ref["k_list"].copy()
+    k[7, 0] += 1
+    k[250, 3] = -5
+    par = render_parallel(sc, o, d, prm, workers=2, chunk=64, k_list=k)
+    for key in ("C", "T", "F", "n_placed", "n_eval"):
+        assert np.array_equal(par[key], ref[key]), key
+    assert par["k_mismatch_rays"].tolist() == [7, 250]
+    assert par["workers"] == 2

@@ -725,3 +725,95 @@ def test_u8_scene_render_is_render_of_decoded_scene():
     a = oracle.oracle_render(dec, o, d, prm, keep_k=False)
     b = oracle.oracle_render(sc, o, d, prm, keep_k=False)
     assert np.array_equal(a["C"], b["C"]) and (a["n_placed"] > 0).sum() > 10
+
+
+# ---------------------------------------------------------------------------
+# Upstream-gradient form and the float32 error scale of the gradient
+# ---------------------------------------------------------------------------
+
+def test_upstream_form_is_the_l2_gradient():
+    """With upstream = dL/dC of the L2 loss, 2 (C - C*)/(3n), the linear
+    functional sum(upstream * C) has the L2 loss's gradient."""
+    sc, o, d, tgt = _grad_problem(seed=2)
+    prm = oracle.RenderParams(n_max=256, c_bg=(0.2, 0.4, 0.6))
+    _, C, g_l2 = oracle.oracle_loss_and_grads(sc, o, d, prm, tgt)
+    up = 2.0 * (C - tgt) / (3.0 * o.shape[0])
+    _, _, g_up = oracle.oracle_loss_and_grads(sc, o, d, prm, upstream=up)
+    for src in ("grid", "plane_xy", "plane_xz", "plane_yz"):
+        assert np.array_equal(g_l2[src][0], g_up[src][0])
+        np.testing.assert_allclose(g_up[src][1], g_l2[src][1], rtol=1e-12, atol=1e-18)
+    np.testing.assert_allclose(g_up["mlp"], g_l2["mlp"], rtol=1e-12, atol=1e-18)
+    with pytest.raises(ValueError):
+        oracle.oracle_loss_and_grads(sc, o, d, prm, tgt, upstream=up)
+
+
+def _bound_problem(eps=0.0, freqs=0, t_term=0.0, seed=5):
+    import scenegen
+    sc = micro_scene(grid=(6, 5, 4), planes=(9, 8, 6), m=4, zmin=0.02, zmax=0.2, seed=seed, std=0.7)
+    sc["grid"][..., 0] += 3.0
+    if freqs:
+        sc["mlp"] = (np.random.default_rng(seed).standard_normal(883) * 0.3).astype(np.float32)
+        sc["dir_freqs"] = freqs
+    o, d = scenegen.oblique_rays(32, seed=seed + 10, origin_z=0.6)
+    up = np.random.default_rng(seed + 1).standard_normal((32, 3)) * 1e-2
+    prm = oracle.RenderParams(n_max=256, c_bg=(0.25, -0.5, 0.75), occ_eps=eps, t_term=t_term)
+    return sc, o, d, up, prm
+
+
+@pytest.mark.parametrize("eps,freqs", [(0.0, 0), (0.02, 0), (0.0, 4)])
+def test_error_scale_bounds_every_entry(eps, freqs):
+    """Triangle inequality: the sum of absolute terms A_e is at least the
+    magnitude of the entry, for every entry of every tensor (soft occupancy,
+    smoothness term and a c_bg with a negative channel included); B >= 64 A
+    (every term carries at least 64 roundings)."""
+    from oracle.fp32_bound import gradient_error_scale
+    sc, o, d, up, prm = _bound_problem(eps, freqs)
+    smooth = None
+    if freqs:
+        import scenegen
+        smooth = dict(perturb=scenegen.view_perturbations(o.shape[0], 3, seed=9), weight=0.1)
+    _, _, g = oracle.oracle_loss_and_grads(sc, o, d, prm, upstream=up, smooth=smooth)
+    es = gradient_error_scale(sc, o, d, prm, up, smooth=smooth)
+    keys = ["grid", "plane_xy", "plane_xz", "plane_yz"] + (["occ"] if eps > 0 else [])
+    for k in keys:
+        u, rows = g[k]
+        u2, A, B, N = es[k]
+        assert np.array_equal(u, u2), k
+        assert np.all(np.abs(rows) <= A * (1 + 1e-12) + 1e-300), k
+        assert np.all(B >= 64 * A * (1 - 1e-12)), k
+        assert np.all(N >= 1), k
+    A, B, N = es["mlp"]
+    assert np.all(np.abs(g["mlp"]) <= A * (1 + 1e-12) + 1e-300)
+    assert N == (o.shape[0] + (2 * o.shape[0] * 3 if freqs else 0))
+
+
+def test_error_scale_keeps_cancelled_terms():
+    """Constant density and colour, zero-weight MLP and c_bg equal to the
+    diffuse colour: dL/da_i = T_{i+1} gv - sum_{k>i} w_k gv - T_n gT
+    = T_n (gv - gT) = 0, so the channel-0 gradient cancels exactly, while
+    its terms (and A) do not vanish."""
+    from oracle.fp32_bound import gradient_error_scale
+    c = 0.3
+    sc = _constant_density_scene(60.0, c, [0.1, 0.2, 0.3])
+    s = 1 / (1 + math.exp(-float(np.float32(c))))
+    prm = oracle.RenderParams(n_max=1024, c_bg=(s, s, s))
+    o = _f32([[0.1, 0.1, 1.0], [-0.5, 0.6, 1.0]])
+    d = np.tile(_f32([0, 0, -1]), (2, 1))
+    up = np.array([[0.3, -0.2, 0.5], [0.1, 0.4, -0.7]])
+    _, _, g = oracle.oracle_loss_and_grads(sc, o, d, prm, upstream=up)
+    _, A, _, _ = gradient_error_scale(sc, o, d, prm, up)["grid"]
+    g0 = g["grid"][1][:, 0]
+    assert A[:, 0].min() > 0
+    assert np.abs(g0).max() <= 1e-9 * A[:, 0].max()
+
+
+def test_error_scale_counts_evaluated_incidences():
+    """N_e sums to (evaluated samples) x (corners per sample) per source; with
+    early termination the placed-but-unevaluated samples do not count."""
+    from oracle.fp32_bound import gradient_error_scale
+    sc, o, d, up, prm = _bound_problem(t_term=0.05)
+    r = oracle.oracle_render(sc, o, d, prm, keep_k=False)
+    assert r["n_eval"].sum() < r["n_placed"].sum()
+    es = gradient_error_scale(sc, o, d, prm, up)
+    for k, corners in (("grid", 8), ("plane_xy", 4), ("plane_xz", 4), ("plane_yz", 4)):
+        assert es[k][3].sum() == corners * r["n_eval"].sum(), k
