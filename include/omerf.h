@@ -317,20 +317,23 @@ int om_render_backward_ex(const om_scene* scene, const float* o, const float* d,
  * of Eq. 9 are drawn by the caller.  F: device float32 [n][7] (the
  * composited features of om_render); d: [n][3]; perturb: [n][P][3],
  * 1 <= P <= 64; no direction or d + perturb may be the zero vector.
- * loss_fp64: optional device double[1] (overwritten); dL_dF: optional
+ * loss: optional device float[1] (overwritten; a float32 sum whose order
+ * of float32 atomics is not deterministic); dL_dF: optional
  * device float32 [n][7] into which dL/dF is ADDED (pass it to
  * om_render_backward_ex); grad_mlp: optional device float32
  * [OM_MLP_NPARAMS(dir_freqs)] into which dL/dW is ADDED (float32 atomics, order not
  * deterministic).  Evaluated in float32 regardless of the scene dtype.
  */
 int om_smooth_loss(const om_scene* scene, const float* F, const float* d, int64_t n,
-                   const float* perturb, int32_t P, float weight, double* loss_fp64,
+                   const float* perturb, int32_t P, float weight, float* loss,
                    float* dL_dF, float* grad_mlp, void* stream);
 
 /*
  * L2 loss in float64, for finite-difference gradient checks:
  * *out = sum over n rays and 3 channels of (C - target)^2 / (3 n).
  * C, target: device float32 [n][3]; out: device double[1] (overwritten).
+ * Summed by one workgroup in a fixed order: the same colours always give
+ * the same bits.  This is the library's only float64 arithmetic.
  */
 int om_l2_loss_fp64(const float* C, const float* target, int64_t n, double* out, void* stream);
 
@@ -338,11 +341,11 @@ int om_l2_loss_fp64(const float* C, const float* target, int64_t n, double* out,
  * Gradient of the same L2 loss with respect to C, for a training step that
  * stays inside the library: dL_dC[r][c] = 2 (C[r][c] - target[r][c]) / (3 n).
  * C, target, dL_dC: device float32 [n][3] (dL_dC may alias neither input).
- * loss_out: optional device double[1] that receives the float64 loss
- * (overwritten), or NULL.
+ * loss_out: optional device float[1] that receives the loss as a float32
+ * sum in a fixed order (overwritten), or NULL.
  */
 int om_l2_loss_grad(const float* C, const float* target, int64_t n, float* dL_dC,
-                    double* loss_out, void* stream);
+                    float* loss_out, void* stream);
 
 /*
  * Fused training step for an L2 photometric loss, everything on `stream`:
@@ -354,13 +357,14 @@ int om_l2_loss_grad(const float* C, const float* target, int64_t n, float* dL_dC
  * [n][3].  workspace: caller-owned device memory of at least
  * om_render_fwd_bwd_l2_workspace_size(n, p) bytes, 256-byte aligned; it
  * holds dL/dC and the per-batch sums (out->batch_wv is ignored).
- * loss_fp64: optional device double[1] receiving the float64 loss
- * (overwritten), or NULL.  Equivalent to om_render + om_l2_loss_grad +
- * om_render_backward.  Cites: Eq. 1-4 (forward) and their derivative.
+ * loss: optional device float[1] receiving the loss as om_l2_loss_grad
+ * computes it (overwritten), or NULL.  Equivalent to om_render +
+ * om_l2_loss_grad + om_render_backward.  Cites: Eq. 1-4 (forward) and
+ * their derivative.
  */
 int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, int64_t n,
                          const om_params* p, const float* target, const om_fwd_out* out,
-                         void* workspace, int64_t workspace_bytes, double* loss_fp64,
+                         void* workspace, int64_t workspace_bytes, float* loss,
                          const om_grads* g, void* stream);
 
 /* Workspace bytes om_render_fwd_bwd_l2 needs for n rays and p->n_max, or
@@ -370,11 +374,12 @@ int64_t om_render_fwd_bwd_l2_workspace_size(int64_t n, const om_params* p);
 /*
  * Interval-span regulariser of Sec. 4.1, Eq. 5, scaled by `weight` (the
  * schedule's lambda): L = weight * sum over the My x Mx grid points of
- * (z_max - z_min)^2.  occ: device float32 [cells][2].  loss_fp64: optional
- * device double[1] receiving L (overwritten); grad_occ: optional device
- * float32 [cells][2] into which dL/d(z_min, z_max) is ADDED.
+ * (z_max - z_min)^2.  occ: device float32 [cells][2].  loss: optional
+ * device float[1] receiving L, a float32 sum in a fixed order
+ * (overwritten); grad_occ: optional device float32 [cells][2] into which
+ * dL/d(z_min, z_max) = 2 weight (z_max - z_min) (-1, +1) is ADDED.
  */
-int om_occ_interval_loss(const float* occ, int64_t cells, float weight, double* loss_fp64, float* grad_occ,
+int om_occ_interval_loss(const float* occ, int64_t cells, float weight, float* loss, float* grad_occ,
                          void* stream);
 
 /*

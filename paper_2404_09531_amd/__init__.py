@@ -363,7 +363,7 @@ def render_fwd_bwd_l2(scene: Scene, o, d, target, out: Dict[str, torch.Tensor], 
                       mlp_bf16: int = -1, workspace: Optional[torch.Tensor] = None,
                       loss: Optional[torch.Tensor] = None, occ_eps: float = 0.0) -> Optional[torch.Tensor]:
     """One fused L2 training step (om_render_fwd_bwd_l2): forward into `out`
-    (keys as render()), dL/dC, float64 loss into `loss` (a device float64 [1]
+    (keys as render()), dL/dC, the loss into `loss` (a device float32 [1]
     tensor, or None to skip), and the backward ADDED into float32 `grads`.
     `workspace` is a device uint8 tensor of fwd_bwd_l2_workspace_size bytes
     (allocated here if None)."""
@@ -375,7 +375,7 @@ def render_fwd_bwd_l2(scene: Scene, o, d, target, out: Dict[str, torch.Tensor], 
     if workspace is None:
         workspace = torch.empty((max(nbytes, 1),), dtype=torch.uint8, device=o.device)
     if loss is not None:
-        _need(loss, "loss", torch.float64, (1,))
+        _need(loss, "loss", torch.float32, (1,))
     fo = _lib.OmFwdOut(out["C"].data_ptr(), out["T"].data_ptr(), out["F"].data_ptr(), out["n_placed"].data_ptr(),
                        out["n_eval"].data_ptr(), 0)
     g = _grads(scene, grads)
@@ -399,14 +399,14 @@ def _grads(scene: Scene, grads: Dict[str, torch.Tensor]) -> _lib.OmGrads:
 def occ_interval_loss(occ, weight: float = 1.0, grad: Optional[torch.Tensor] = None,
                       with_loss: bool = True) -> Optional[torch.Tensor]:
     """Interval-span regulariser of Eq. 5: weight * sum (z_max - z_min)^2 as a
-    device float64 [1] tensor (if with_loss), and its gradient ADDED into
+    device float32 [1] tensor (if with_loss), and its gradient ADDED into
     `grad` (float32, shape of occ) when given."""
     _need(occ, "occ", torch.float32)
     if occ.shape[-1] != 2:
         raise ValueError("occ must end in (z_min, z_max)")
     if grad is not None:
         _need(grad, "grad", torch.float32, occ.shape)
-    loss = torch.empty((1,), dtype=torch.float64, device=occ.device) if with_loss else None
+    loss = torch.empty((1,), dtype=torch.float32, device=occ.device) if with_loss else None
     _lib.check("om_occ_interval_loss", _lib.lib().om_occ_interval_loss(
         occ.data_ptr(), occ.numel() // 2, float(weight), _lib.ptr(loss), _lib.ptr(grad), _lib.stream_of(occ)))
     return loss
@@ -418,7 +418,7 @@ def smooth_loss(scene: Scene, F, d, perturb, weight: float = 1.0, dL_dF: Optiona
     (om_smooth_loss): weight * sum_r sum_p cos(d_r, s_rp) ||G(F_r, s_rp) -
     G(F_r, d_r)||^2 with s_rp = d_r + perturb[r, p].  F float32 [n, 7], d
     [n, 3], perturb [n, P, 3] (the caller's Gaussian draws).  Returns the
-    float64 loss as a device [1] tensor (if with_loss); dL/dF and dL/dmlp
+    float32 loss as a device [1] tensor (if with_loss); dL/dF and dL/dmlp
     are ADDED into dL_dF / grad_mlp when given."""
     n = F.shape[0]
     _need(F, "F", torch.float32, (n, 7))
@@ -430,7 +430,7 @@ def smooth_loss(scene: Scene, F, d, perturb, weight: float = 1.0, dL_dF: Optiona
         _need(dL_dF, "dL_dF", torch.float32, (n, 7))
     if grad_mlp is not None:
         _need(grad_mlp, "grad_mlp", torch.float32, scene.tensors["mlp"].shape)
-    loss = torch.empty((1,), dtype=torch.float64, device=F.device) if with_loss else None
+    loss = torch.empty((1,), dtype=torch.float32, device=F.device) if with_loss else None
     _lib.check("om_smooth_loss", _lib.lib().om_smooth_loss(
         scene.handle, F.data_ptr(), d.data_ptr(), n, perturb.data_ptr(), perturb.shape[1], float(weight),
         _lib.ptr(loss), _lib.ptr(dL_dF), _lib.ptr(grad_mlp), _lib.stream_of(F)))
@@ -438,7 +438,7 @@ def smooth_loss(scene: Scene, F, d, perturb, weight: float = 1.0, dL_dF: Optiona
 
 
 class SmoothFn(torch.autograd.Function):
-    """L_smooth = smooth_loss(scene, F, d, perturb, weight) as a float64
+    """L_smooth = smooth_loss(scene, F, d, perturb, weight) as a float32
     scalar, differentiable in F and in the float32 MLP master passed last.
     ``SmoothFn.apply(scene, F, d, perturb, weight, mlp)``.  The loss and both
     gradients come out of one kernel call in the forward; the backward scales
@@ -558,13 +558,14 @@ def l2_loss_fp64(C, target) -> torch.Tensor:
 
 
 def l2_loss_grad(C, target, dL_dC: Optional[torch.Tensor] = None, with_loss: bool = True):
-    """dL/dC of the mean L2 loss (and the float64 loss if with_loss)."""
+    """dL/dC of the mean L2 loss (and the loss, a float32 sum in a fixed
+    order, if with_loss)."""
     n = C.shape[0]
     _need(C, "C", torch.float32, (n, 3))
     _need(target, "target", torch.float32, (n, 3))
     if dL_dC is None:
         dL_dC = torch.empty_like(C)
-    loss = torch.empty((1,), dtype=torch.float64, device=C.device) if with_loss else None
+    loss = torch.empty((1,), dtype=torch.float32, device=C.device) if with_loss else None
     _lib.check("om_l2_loss_grad", _lib.lib().om_l2_loss_grad(C.data_ptr(), target.data_ptr(), n, dL_dC.data_ptr(),
                                                                _lib.ptr(loss), _lib.stream_of(C)))
     return dL_dC, loss

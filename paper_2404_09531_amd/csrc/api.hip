@@ -403,60 +403,82 @@ int64_t om_render_fwd_bwd_l2_workspace_size(int64_t n, const om_params* p) {
     return dc + n * slots * 7 * (int64_t)sizeof(float);
 }
 
-int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
-                         const float* target, const om_fwd_out* out, void* workspace, int64_t workspace_bytes,
-                         double* loss_fp64, const om_grads* g, void* stream) {
-    RayParams rp;
-    int rc = check_fwd(scene, o, d, n, p, out, true, true, &rp);
+namespace {
+
+// Validation of the fused L2 step.
+int check_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                     const float* target, const om_fwd_out* out, const om_grads* g, RayParams* rp) {
+    int rc = check_fwd(scene, o, d, n, p, out, true, true, rp);
     if (rc != OM_OK) return rc;
     if (scene->desc.dtype == OM_U8 || scene->desc.block_shift > 0)
         return fail(OM_ERR_UNSUPPORTED, "8-bit and sparse-block scenes are render-only");
-    if (n == 0) return ok();
+    if (n == 0) return OM_OK;
     if (!target || !g) return fail(OM_ERR_INVALID, "target / grads is NULL");
     if (!g->grid || !g->plane_xy || !g->plane_xz || !g->plane_yz || !g->mlp)
         return fail(OM_ERR_INVALID, "all gradient buffers are required");
+    return OM_OK;
+}
+
+// The step itself over a workspace laid out as [dL/dC, 256-byte aligned |
+// per-batch sums of w v]: forward with per-batch sums, loss gradient,
+// backward.
+int fwd_bwd_l2_launch(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                      const RayParams& rp, const float* target, const om_fwd_out* out, void* workspace, float* loss,
+                      const om_grads* g, hipStream_t s, const char* who) {
+    float* dC = static_cast<float*>(workspace);
+    float* bw = reinterpret_cast<float*>(static_cast<char*>(workspace) + (n * 3 * (int64_t)sizeof(float) + 255) / 256 * 256);
+    const bool bf16 = scene->desc.dtype == OM_BF16;
+    hipError_t e = launch_march_fwd(scene->dev, scene->desc.dtype, rp, o, d, n, out->F, out->T, out->n_placed,
+                                    out->n_eval, bw, s);
+    if (e != hipSuccess) return hip_status(e, who);
+    e = launch_mlp(scene->dev.mlp, scene->dev.mlp_in, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval, out->C, s);
+    if (e != hipSuccess) return hip_status(e, who);
+    e = launch_l2(out->C, target, n, dC, loss, s);
+    if (e != hipSuccess) return hip_status(e, who);
+    e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_eval, bw, dC, nullptr, g->grid, g->plane_xy,
+                         g->plane_xz, g->plane_yz, g->mlp, g->occ, s);
+    return hip_status(e, who);
+}
+
+}  // namespace
+
+int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                         const float* target, const om_fwd_out* out, void* workspace, int64_t workspace_bytes,
+                         float* loss, const om_grads* g, void* stream) {
+    RayParams rp;
+    int rc = check_fwd_bwd_l2(scene, o, d, n, p, target, out, g, &rp);
+    if (rc != OM_OK) return rc;
+    if (n == 0) return ok();
     const int64_t need = om_render_fwd_bwd_l2_workspace_size(n, p);
     if (!workspace || ((uintptr_t)workspace & 255u)) return fail(OM_ERR_INVALID, "workspace must be 256-byte aligned");
     if (workspace_bytes < need)
         return fail(OM_ERR_INVALID, "workspace holds %lld bytes, %lld needed", (long long)workspace_bytes,
                     (long long)need);
-    float* dC = static_cast<float*>(workspace);
-    float* bw = reinterpret_cast<float*>(static_cast<char*>(workspace) + (n * 3 * (int64_t)sizeof(float) + 255) / 256 * 256);
-    const bool bf16 = scene->desc.dtype == OM_BF16;
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_march_fwd(scene->dev, scene->desc.dtype, rp, o, d, n, out->F, out->T, out->n_placed,
-                                    out->n_eval, bw, s);
-    if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2 (march)");
-    e = launch_mlp(scene->dev.mlp, scene->dev.mlp_in, mlp_in_bf16(scene, p), rp, d, n, out->F, out->T, out->n_eval, out->C, s);
-    if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2 (mlp)");
-    e = launch_l2(out->C, target, n, dC, loss_fp64, s);
-    if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2 (loss)");
-    e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_eval, bw, dC, nullptr, g->grid, g->plane_xy,
-                         g->plane_xz, g->plane_yz, g->mlp, g->occ, s);
-    return hip_status(e, "om_render_fwd_bwd_l2 (backward)");
+    return fwd_bwd_l2_launch(scene, o, d, n, p, rp, target, out, workspace, loss, g, (hipStream_t)stream,
+                             "om_render_fwd_bwd_l2");
 }
 
 int om_smooth_loss(const om_scene* scene, const float* F, const float* d, int64_t n, const float* perturb, int32_t P,
-                   float weight, double* loss_fp64, float* dL_dF, float* grad_mlp, void* stream) {
+                   float weight, float* loss, float* dL_dF, float* grad_mlp, void* stream) {
     if (!scene) return fail(OM_ERR_INVALID, "scene is NULL");
     if (n < 0) return fail(OM_ERR_INVALID, "n must be >= 0");
     if (P < 1 || P > 64) return fail(OM_ERR_INVALID, "P must be in 1 .. 64");
     if (!std::isfinite(weight)) return fail(OM_ERR_INVALID, "weight must be finite");
     if (n > 0 && (!F || !d || !perturb)) return fail(OM_ERR_INVALID, "F, d and perturb are required");
-    if (!loss_fp64 && !dL_dF && !grad_mlp) return ok();
-    if (n == 0 && !loss_fp64) return ok();
-    return hip_status(launch_smooth(scene->dev.mlp, scene->dev.mlp_in, F, d, n, perturb, P, weight, loss_fp64, dL_dF,
+    if (!loss && !dL_dF && !grad_mlp) return ok();
+    if (n == 0 && !loss) return ok();
+    return hip_status(launch_smooth(scene->dev.mlp, scene->dev.mlp_in, F, d, n, perturb, P, weight, loss, dL_dF,
                                     grad_mlp, (hipStream_t)stream),
                       "om_smooth_loss");
 }
 
-int om_occ_interval_loss(const float* occ, int64_t cells, float weight, double* loss_fp64, float* grad_occ,
+int om_occ_interval_loss(const float* occ, int64_t cells, float weight, float* loss, float* grad_occ,
                          void* stream) {
     if (cells <= 0) return fail(OM_ERR_INVALID, "cells must be > 0");
     if (!occ) return fail(OM_ERR_INVALID, "occ is NULL");
     if (!std::isfinite(weight)) return fail(OM_ERR_INVALID, "weight must be finite");
-    if (!loss_fp64 && !grad_occ) return ok();
-    return hip_status(launch_occ_loss(occ, cells, weight, loss_fp64, grad_occ, (hipStream_t)stream),
+    if (!loss && !grad_occ) return ok();
+    return hip_status(launch_occ_loss(occ, cells, weight, loss, grad_occ, (hipStream_t)stream),
                       "om_occ_interval_loss");
 }
 
@@ -576,10 +598,10 @@ int om_cast_bf16(const float* src, int64_t n, uint16_t* dst, void* stream) {
 int om_l2_loss_fp64(const float* C, const float* target, int64_t n, double* out, void* stream) {
     if (n <= 0) return fail(OM_ERR_INVALID, "n must be > 0");
     if (!C || !target || !out) return fail(OM_ERR_INVALID, "NULL pointer");
-    return hip_status(launch_l2(C, target, n, nullptr, out, (hipStream_t)stream), "om_l2_loss_fp64");
+    return hip_status(launch_l2_fp64(C, target, n, out, (hipStream_t)stream), "om_l2_loss_fp64");
 }
 
-int om_l2_loss_grad(const float* C, const float* target, int64_t n, float* dL_dC, double* loss_out, void* stream) {
+int om_l2_loss_grad(const float* C, const float* target, int64_t n, float* dL_dC, float* loss_out, void* stream) {
     if (n <= 0) return fail(OM_ERR_INVALID, "n must be > 0");
     if (!C || !target || !dL_dC) return fail(OM_ERR_INVALID, "NULL pointer");
     if (dL_dC == C || dL_dC == target) return fail(OM_ERR_INVALID, "dL_dC must not alias C or target");

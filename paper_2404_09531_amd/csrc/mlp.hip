@@ -169,31 +169,40 @@ __global__ __launch_bounds__(kBlock) void k_mlp_bf16(const float* __restrict__ W
 }
 
 // ---------------------------------------------------------------------------
-// L2 loss in float64 (finite-difference checks) and its gradient.
+// L2 loss and its gradient.  dL/dC is elementwise float32 over the whole
+// grid.  The loss value is summed by ONE workgroup in a fixed order -- each
+// lane a fixed strided subset, then a fixed butterfly over the wave and a
+// fixed sum over the waves -- so two calls on the same colours return the
+// same bits (a cross-block atomic sum would not).  It is accumulated in
+// float64 only for the finite-difference checks (om_l2_loss_fp64) and in
+// float32 for the optional loss of a training step.
 // ---------------------------------------------------------------------------
-__global__ void k_zero_f64(double* p) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0;
+constexpr int kLossBlock = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_l2_grad(const float* __restrict__ C, const float* __restrict__ tgt,
+                                                    int64_t n, float scale2, float* __restrict__ dC) {
+    const int64_t m = n * 3;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock)
+        dC[i] = scale2 * (C[i] - tgt[i]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_l2(const float* __restrict__ C, const float* __restrict__ tgt, int64_t n,
-                                               float* __restrict__ dC, double* __restrict__ loss) {
-    __shared__ double part[kBlock / 64];
+template <class Acc>
+__global__ __launch_bounds__(kLossBlock) void k_l2_loss(const float* __restrict__ C, const float* __restrict__ tgt,
+                                                       int64_t n, Acc* __restrict__ loss) {
+    __shared__ Acc part[kLossBlock / 64];
     const int64_t m = n * 3;
-    const double scale = 1.0 / (3.0 * (double)n);
-    double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += (int64_t)gridDim.x * kBlock) {
-        const float e = C[i] - tgt[i];
-        if (dC) dC[i] = (float)(2.0 * scale) * e;
-        s += (double)e * (double)e;
+    Acc s = 0;
+    for (int64_t i = threadIdx.x; i < m; i += kLossBlock) {
+        const Acc e = (Acc)C[i] - (Acc)tgt[i];
+        s += e * e;
     }
-    if (!loss) return;
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) t += part[w];
-        unsafeAtomicAdd(loss, t * scale);
+        Acc t = 0;
+        for (int w = 0; w < kLossBlock / 64; ++w) t += part[w];
+        *loss = t / (Acc)3 / (Acc)n;
     }
 }
 
@@ -220,12 +229,19 @@ hipError_t launch_mlp(const float* W, int mlp_in, bool bf16, const RayParams& rp
     return hipGetLastError();
 }
 
-hipError_t launch_l2(const float* C, const float* tgt, int64_t n, float* dC, double* loss, hipStream_t s) {
-    if (loss) hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, loss);
-    int64_t blocks = (n * 3 + kBlock - 1) / kBlock;
-    if (blocks > 2048) blocks = 2048;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_l2, dim3((unsigned)blocks), dim3(kBlock), 0, s, C, tgt, n, dC, loss);
+hipError_t launch_l2(const float* C, const float* tgt, int64_t n, float* dC, float* loss, hipStream_t s) {
+    if (dC) {
+        int64_t blocks = (n * 3 + kBlock - 1) / kBlock;
+        if (blocks > 2048) blocks = 2048;
+        const float scale2 = (float)(2.0 / (3.0 * (double)n));  // 2 / (3 n), rounded once on the host
+        hipLaunchKernelGGL(k_l2_grad, dim3((unsigned)blocks), dim3(kBlock), 0, s, C, tgt, n, scale2, dC);
+    }
+    if (loss) hipLaunchKernelGGL(k_l2_loss<float>, dim3(1), dim3(kLossBlock), 0, s, C, tgt, n, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_l2_fp64(const float* C, const float* tgt, int64_t n, double* loss, hipStream_t s) {
+    hipLaunchKernelGGL(k_l2_loss<double>, dim3(1), dim3(kLossBlock), 0, s, C, tgt, n, loss);
     return hipGetLastError();
 }
 
@@ -268,36 +284,50 @@ hipError_t launch_occ_pyramid(const float2* occ, int Mx, int My, float2* mips, i
 }
 
 // ---------------------------------------------------------------------------
-// Interval-span regulariser (Eq. 5): weight * sum (z_max - z_min)^2 in
-// float64, and its gradient added to grad_occ.
+// Interval-span regulariser (Eq. 5): weight * sum (z_max - z_min)^2 and its
+// gradient 2 weight (z_max - z_min) (-1, +1) added to grad_occ, in float32.
+// The loss is summed by one workgroup in a fixed order (see k_l2_loss).
 // ---------------------------------------------------------------------------
-__global__ void k_occ_loss(const float2* __restrict__ occ, int64_t cells, float weight, double* __restrict__ loss,
-                           float2* __restrict__ grad) {
-    double acc = 0.0;
+__global__ void k_occ_grad(const float2* __restrict__ occ, int64_t cells, float weight, float2* __restrict__ grad) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells; i += (int64_t)gridDim.x * blockDim.x) {
         const float2 z = occ[i];
-        const double span = (double)z.y - (double)z.x;
-        acc += span * span;
-        if (grad) {
-            const float g = (float)(2.0 * (double)weight * span);
-            float2 cur = grad[i];
-            cur.x -= g;
-            cur.y += g;
-            grad[i] = cur;
-        }
-    }
-    if (loss) {
-        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if ((threadIdx.x & 63) == 0 && acc != 0.0) atomicAdd(loss, acc * (double)weight);
+        const float g = 2.0f * weight * (z.y - z.x);
+        float2 cur = grad[i];
+        cur.x -= g;
+        cur.y += g;
+        grad[i] = cur;
     }
 }
 
-hipError_t launch_occ_loss(const float* occ, int64_t cells, float weight, double* loss, float* grad, hipStream_t s) {
-    if (loss) hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, loss);
-    int64_t blocks = (cells + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_occ_loss, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const float2*>(occ),
-                       cells, weight, loss, reinterpret_cast<float2*>(grad));
+__global__ __launch_bounds__(kLossBlock) void k_occ_loss(const float2* __restrict__ occ, int64_t cells, float weight,
+                                                        float* __restrict__ loss) {
+    __shared__ float part[kLossBlock / 64];
+    float s = 0.0f;
+    for (int64_t i = threadIdx.x; i < cells; i += kLossBlock) {
+        const float2 z = occ[i];
+        const float span = z.y - z.x;
+        s += span * span;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < kLossBlock / 64; ++w) t += part[w];
+        *loss = weight * t;
+    }
+}
+
+hipError_t launch_occ_loss(const float* occ, int64_t cells, float weight, float* loss, float* grad, hipStream_t s) {
+    if (grad) {
+        int64_t blocks = (cells + 255) / 256;
+        if (blocks > 1024) blocks = 1024;
+        hipLaunchKernelGGL(k_occ_grad, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const float2*>(occ),
+                           cells, weight, reinterpret_cast<float2*>(grad));
+    }
+    if (loss)
+        hipLaunchKernelGGL(k_occ_loss, dim3(1), dim3(kLossBlock), 0, s, reinterpret_cast<const float2*>(occ), cells,
+                           weight, loss);
     return hipGetLastError();
 }
 
@@ -309,13 +339,18 @@ hipError_t launch_occ_loss(const float* occ, int64_t cells, float weight, double
 // hidden unit per lane: G at d and at s, and the backward of both
 // evaluations (dL/dG = +g at s, -g at d; the MLP backward is linear in
 // dL/dG) into LDS-reduced MLP gradients; dL/dF is added to dF with float32
-// atomics (the P pairs of a ray land in different groups).
+// atomics (the P pairs of a ray land in different groups).  The loss value
+// is a float32 sum (per group, then one float32 atomic per group).
 // ---------------------------------------------------------------------------
+__global__ void k_zero_f32(float* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0f;
+}
+
 template <int NIN>
 __global__ __launch_bounds__(kBlock) void k_smooth(const float* __restrict__ W, const float* __restrict__ F,
                                                    const float* __restrict__ d_, int64_t items, int64_t chunk,
                                                    const float* __restrict__ perturb, int P, float weight,
-                                                   double* __restrict__ loss, float* __restrict__ dF,
+                                                   float* __restrict__ loss, float* __restrict__ dF,
                                                    float* __restrict__ gmlp) {
     __shared__ float sW[kMlpMaxSize];
     for (int i = threadIdx.x; i < kMlpMaxSize; i += kBlock) sW[i] = 0.0f;
@@ -325,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(const float* __restrict__ W, 
     const int gid = threadIdx.x / kGroup;
     const int64_t start = (int64_t)xcd_block(blockIdx.x, gridDim.x) * chunk;
     const int64_t stop = min(items, start + chunk);
-    double acc = 0.0;
+    float acc = 0.0f;
     for (int64_t it = start + gid; it < stop; it += kGroupsPerBlock) {
         const int64_t ray = it / P;
         float f7[7];
@@ -357,7 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(const float* __restrict__ W, 
                 gs[c] = 2.0f * weight * cosv * diff;
                 gd[c] = -gs[c];
             }
-            acc += (double)weight * (double)cosv * (double)e2;
+            acc += weight * cosv * e2;
             group_mlp_bwd<NIN>(W, x, gl, as, gs, sW, g7);
         }
         {
@@ -373,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(const float* __restrict__ W, 
             unsafeAtomicAdd(dF + ray * 7 + gl, v);
         }
     }
-    if (loss && gl == 0 && acc != 0.0) atomicAdd(loss, acc);
+    if (loss && gl == 0 && acc != 0.0f) unsafeAtomicAdd(loss, acc);
     __syncthreads();
     if (gmlp) {
         for (int i = threadIdx.x; i < MlpLayout<NIN>::SIZE; i += kBlock) {
@@ -384,8 +419,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth(const float* __restrict__ W, 
 }
 
 hipError_t launch_smooth(const float* W, int mlp_in, const float* F, const float* d, int64_t n, const float* perturb,
-                         int P, float weight, double* loss, float* dF, float* gmlp, hipStream_t s) {
-    if (loss) hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, loss);
+                         int P, float weight, float* loss, float* dF, float* gmlp, hipStream_t s) {
+    if (loss) hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, loss);
     if (n == 0) return hipGetLastError();
     const int64_t items = n * P;
     const int64_t max_blocks = 4096;

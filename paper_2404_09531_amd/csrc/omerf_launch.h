@@ -20,17 +20,18 @@ hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, 
                             const float* dC, const float* dF, float* gV, float* gxy, float* gxz, float* gyz,
                             float* gmlp, float* gocc, hipStream_t s);
 hipError_t launch_smooth(const float* W, int mlp_in, const float* F, const float* d, int64_t n, const float* perturb,
-                         int P, float weight, double* loss, float* dF, float* gmlp, hipStream_t s);
+                         int P, float weight, float* loss, float* dF, float* gmlp, hipStream_t s);
 hipError_t launch_mlp(const float* W, int mlp_in, bool bf16, const RayParams& rp, const float* d, int64_t n, const float* F,
                       const float* T, const int32_t* n_eval, float* C, hipStream_t s);
 hipError_t launch_occ_pyramid(const float2* occ, int Mx, int My, float2* mips, int levels, hipStream_t s);
-hipError_t launch_occ_loss(const float* occ, int64_t cells, float weight, double* loss, float* grad, hipStream_t s);
+hipError_t launch_occ_loss(const float* occ, int64_t cells, float weight, float* loss, float* grad, hipStream_t s);
 hipError_t launch_range(const float* x, int64_t n, float* minmax, uint32_t* keys, hipStream_t s);
 hipError_t launch_quantize(const float* x, int64_t n, const float* lo, const float* inv, uint8_t* out, hipStream_t s);
 hipError_t launch_blocks_mark(const SceneDev& sc, int shift, int bnx, int bny, int bnz, int32_t* mark, hipStream_t s);
 hipError_t launch_blocks_fill(const SceneDev& sc, int shift, int bnx, int bny, int bnz, const int32_t* idx,
                               int64_t n_blocks, int units, void* atlas, hipStream_t s);
 hipError_t launch_cast_bf16(const float* src, int64_t n, uint16_t* dst, hipStream_t s);
-hipError_t launch_l2(const float* C, const float* tgt, int64_t n, float* dC, double* loss, hipStream_t s);
+hipError_t launch_l2(const float* C, const float* tgt, int64_t n, float* dC, float* loss, hipStream_t s);
+hipError_t launch_l2_fp64(const float* C, const float* tgt, int64_t n, double* loss, hipStream_t s);
 
 }  // namespace omerf

@@ -17,10 +17,12 @@ the worst |err| / bar, the worst |err| / (u A), and for the entries with
 |g| >= 1e-3 max |g| of their tensor: how many of them the float32 floor
 resolves to 1e-3 and the worst relative error over those.
 """
+import os
+
 import numpy as np
 
 import oracle
-from oracle.fp32_bound import compare, gradient_error_scale
+from oracle.fp32_bound import U32, compare, floor, gradient_error_scale
 from tests.gpu_util import log
 
 SOURCES = ("grid", "plane_xy", "plane_xz", "plane_yz")
@@ -55,4 +57,36 @@ def check(grads, ref, scale, tag="", keys=None):
             f"(all of them {s['worst_rel_big']:.2e})")
         if not s["ok"]:
             bad.append((k, s["worst"], s["untouched_zero"]))
+            _report_worst(grads[k], ref[k], scale[k], f"{tag} {k}")
     assert not bad, bad
+
+
+def _report_worst(got, ref, scale, tag, k=5):
+    """Log the k entries furthest beyond their bar (row, channel, GPU value,
+    oracle value, A, B, N); with OM_GRADCHECK_DUMP set to a directory, also
+    save them there as an .npz for analysis on the host."""
+    if isinstance(ref, tuple):
+        idx, rows = ref
+        g = np.asarray(got, dtype=np.float64).reshape(-1, rows.shape[-1])[idx]
+        row_ids = np.broadcast_to(np.asarray(idx)[:, None], rows.shape)
+    else:
+        rows = np.asarray(ref, dtype=np.float64)
+        g = np.asarray(got, dtype=np.float64)
+        row_ids = np.arange(rows.size)
+    A, B, N = scale[-3], scale[-2], np.asarray(scale[-1], dtype=np.float64)
+    Nb = np.broadcast_to(N[:, None], A.shape) if A.ndim == 2 else np.broadcast_to(N, A.shape)
+    bar = 1e-3 * np.abs(rows) + floor(scale)
+    ratio = (np.abs(g - rows) / np.maximum(bar, 1e-300)).reshape(-1)
+    order = np.argsort(-ratio)[:k]
+    chan = np.broadcast_to(np.arange(rows.shape[-1]) if rows.ndim == 2 else np.zeros(1, int), rows.shape).reshape(-1)
+    for i in order:
+        log(f"    {tag}: row {int(row_ids.reshape(-1)[i])} ch {int(chan[i])}: gpu {g.reshape(-1)[i]:.6e} "
+            f"oracle {rows.reshape(-1)[i]:.6e} A {A.reshape(-1)[i]:.3e} B/A {B.reshape(-1)[i] / max(A.reshape(-1)[i], 1e-300):.1f} "
+            f"N {int(Nb.reshape(-1)[i])} err/bar {ratio[i]:.2f}")
+    out = os.environ.get("OM_GRADCHECK_DUMP")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        name = "".join(ch if ch.isalnum() else "_" for ch in tag)
+        np.savez(os.path.join(out, f"{name}.npz"), row=row_ids.reshape(-1)[order], chan=chan[order],
+                 gpu=g.reshape(-1)[order], oracle=rows.reshape(-1)[order], A=A.reshape(-1)[order],
+                 B=B.reshape(-1)[order], N=Nb.reshape(-1)[order], u=U32)

@@ -6,8 +6,9 @@ a whole training step in a graph (torch.cuda.CUDAGraph records the kernels
 that the library enqueues on the capturing stream) and replay it.  Each
 replay here runs with eager work and synchronisations in between, and is
 checked against the eager result: the forward bit for bit (it is
-deterministic), the float64 loss to 1e-12 relative and the gradients (float
-atomics in a varying order) to 1e-5 of the largest entry.
+deterministic), the loss bit for bit (a float32 sum in a fixed order) and
+the gradients (float atomics in a varying order) to 1e-5 of the largest
+entry.
 """
 import numpy as np
 import pytest
@@ -87,7 +88,7 @@ def test_training_step_graph_replays_match_eager(tiny):
     def fresh():
         out = {k: torch.empty_like(v) for k, v in first.items()}
         grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in SOURCES}
-        loss = torch.zeros((1,), dtype=torch.float64, device=og.device)
+        loss = torch.zeros((1,), dtype=torch.float32, device=og.device)
         return out, grads, loss
 
     out_e, grads_e, loss_e = fresh()
@@ -117,7 +118,7 @@ def test_training_step_graph_replays_match_eager(tiny):
         torch.cuda.synchronize()
         for k in KEYS:
             assert torch.equal(out[k], out_e[k]), (rep, k)
-        assert abs(loss.item() - loss_e.item()) <= 1e-12 * abs(loss_e.item()), rep
+        assert loss.item() == loss_e.item(), rep  # a float32 sum in a fixed order
         for k in SOURCES:
             err = float((grads[k] - grads_e[k]).abs().max())
             assert err <= 1e-5 * scale[k], (rep, k, err / scale[k])

@@ -16,6 +16,7 @@ import torch
 
 import oracle
 import oracle.field as field
+import oracle.fp32_bound as fp32_bound
 import oracle.placement as placement
 import oracle.quant as quant
 import oracle.render as render
@@ -41,6 +42,10 @@ PIN_TESTS = [
     pins.test_quantize_u8_hand_values,
     pins.test_quant_params_span_the_range,
     pins.test_u8_scene_render_is_render_of_decoded_scene,
+    pins.test_error_scale_covers_float32_underflow,
+    pins.test_error_scale_input_errors_bound_a_perturbed_mlp,
+    pins.test_error_scale_weight_error_bounds_perturbed_fractions,
+    pins.test_error_scale_fraction_slopes_bound_a_perturbed_field,
 ]
 
 
@@ -213,6 +218,41 @@ def _both(mp, name, new):
         mp.setattr(render, name, new)
 
 
+def _input_err_unscaled(x, raw_err, freqs):
+    """The encoded direction's error without the 2^k of d/dd sin(2^k d)."""
+    e = np.zeros_like(x)
+    e[:, 7:10] = raw_err
+    for k in range(freqs):
+        e[:, 10 + 6 * k:16 + 6 * k] = np.concatenate([raw_err, raw_err], 1) + fp32_bound.SINCOS_ERR
+    return e
+
+
+def _omega_is_weight(orig):
+    """The weight term taken relative to the corner weight (omega = w)."""
+    def f(p, scene):
+        from oracle.field import feature_terms
+        dims_g = scene["grid"].shape[:3][::-1]
+        dims_p = (scene["plane_xy"].shape[1], scene["plane_xy"].shape[0], scene["plane_xz"].shape[0])
+        terms = feature_terms(p, scene["box_lo"], scene["box_hi"], dims_g, dims_p)
+        return {k: terms[k][1] for k in terms}
+    return f
+
+
+def _slopes_one_axis(orig):
+    """Fraction slopes of the first axis only (the others forgotten)."""
+    def f(p, scene, idx_of):
+        q = p.copy()
+        for a in (1, 2):  # put the other axes on vertices: their slopes no longer count
+            lo, hi = float(scene["box_lo"][a]), float(scene["box_hi"][a])
+            q[:, a] = lo
+        return orig(q, scene, idx_of)
+    return f
+
+
+def _input_err_dropped(fw, e_x):
+    return np.zeros(e_x.shape[0]), np.zeros((e_x.shape[0], 3))
+
+
 MUTANTS = {
     "drop plane_yz": lambda mp: _both(mp, "feature_terms", _drop_plane_yz(field.feature_terms)),
     "transposed XZ plane": lambda mp: _both(mp, "feature_terms", _transpose_xz(field.feature_terms)),
@@ -239,6 +279,15 @@ MUTANTS = {
                                               mp.setattr(oracle, "quant_params", _params_256)),
     "8-bit code wraps instead of clamping": lambda mp: (mp.setattr(quant, "quantize_u8", _quantize_wrap),
                                                         mp.setattr(oracle, "quantize_u8", _quantize_wrap)),
+    "error scale without the float32 underflow allowance": lambda mp: mp.setattr(fp32_bound, "TINY_TERM", 0.0),
+    "error scale: encoding error not scaled by 2^k": lambda mp: mp.setattr(fp32_bound, "_input_abs_err",
+                                                                           _input_err_unscaled),
+    "error scale: MLP input errors dropped": lambda mp: mp.setattr(fp32_bound, "_input_err_coeffs",
+                                                                   _input_err_dropped),
+    "error scale: weight error relative to the weight": lambda mp: mp.setattr(
+        fp32_bound, "_other_axis_weights", _omega_is_weight(fp32_bound._other_axis_weights)),
+    "error scale: fraction slopes of one axis only": lambda mp: mp.setattr(
+        fp32_bound, "_fraction_slopes", _slopes_one_axis(fp32_bound._fraction_slopes)),
     "interval loss not squared": lambda mp: (mp.setattr(render, "occ_interval_loss", _span_not_squared),
                                              mp.setattr(oracle, "occupancy_value", render.occupancy_value),
                                              mp.setattr(oracle, "occ_interval_loss", _span_not_squared)),

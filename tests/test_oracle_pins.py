@@ -817,3 +817,160 @@ def test_error_scale_counts_evaluated_incidences():
     es = gradient_error_scale(sc, o, d, prm, up)
     for k, corners in (("grid", 8), ("plane_xy", 4), ("plane_xz", 4), ("plane_yz", 4)):
         assert es[k][3].sum() == corners * r["n_eval"].sum(), k
+
+
+def test_error_scale_covers_float32_underflow():
+    """Far behind a dense medium the transmittance falls below the binary32
+    range: with a = 9 per sample (tau = 9 / delta) T_s = exp(-9 s) is below
+    2^-100 from the 8th sample on.  A grid of 32 cells in z (16 samples per
+    cell) has vertices that only such samples reach; their float64 gradient
+    is nonzero but made of terms below 2^-80, which a float32 backward may
+    flush to zero.  The floor u (B + N A) must cover those entries whole,
+    and must not add the underflow allowance to entries of ordinary size."""
+    import oracle.fp32_bound as fb
+    from oracle.fp32_bound import U32, gradient_error_scale
+    sc = micro_scene(grid=(4, 4, 33), planes=(6, 6, 5), zmin=0.0, zmax=0.25, seed=11, std=0.2)
+    sc["grid"][..., 0] = np.float32(math.log(9.0 / DELTA))
+    prm = oracle.RenderParams(n_max=1024, c_bg=(0.25, 0.5, 0.75))
+    o, d = _f32([[0.13, -0.21, 1.0], [-0.4, 0.35, 1.0]]), np.tile(_f32([0, 0, -1]), (2, 1))
+    up = np.array([[0.3, -0.2, 0.5], [0.1, 0.4, -0.7]])
+    _, _, g = oracle.oracle_loss_and_grads(sc, o, d, prm, upstream=up)
+    idx, A, B, N = gradient_error_scale(sc, o, d, prm, up)["grid"]
+    rows = g["grid"][1]
+    tiny = (A > 0) & (A < 2.0 ** -80)
+    big = A > 2.0 ** -60
+    assert tiny.sum() >= 8 and big.sum() >= 8
+    fl = U32 * (B + N[:, None] * A)
+    assert np.all(fl[tiny] >= np.abs(rows[tiny]))
+    keep = fb.TINY_TERM
+    try:
+        fb.TINY_TERM = 0.0
+        _, _, B0, _ = gradient_error_scale(sc, o, d, prm, up)["grid"]
+    finally:
+        fb.TINY_TERM = keep
+    # the allowance adds at most 2^-80 / u per term, nothing of note to an ordinary entry
+    Nc = np.broadcast_to(N[:, None], B.shape)
+    assert np.all(B[big] - B0[big] <= Nc[big] * 2.0 ** -80 / U32)
+    assert np.all(B[tiny] > B0[tiny])
+
+
+def test_error_scale_input_errors_bound_a_perturbed_mlp():
+    """The MLP-input error model against brute force in float64: (1) the
+    encoded direction of s = fl32(d + delta) differs from that of the exact
+    d + delta by at most the modelled input error less the sincos allowance;
+    (2) moving every input by its modelled error, with random signs, moves
+    z3 = W3 relu(W2 relu(W1 x + b1) + b2) + b3 by at most the propagated
+    bound e_z3 (rows whose ReLU pattern does not change)."""
+    from oracle.fp32_bound import SINCOS_ERR, U32, _input_abs_err, _input_err_coeffs, _mlp_abs
+    from oracle.render import encode_dir, unpack_mlp
+    rng = np.random.default_rng(21)
+    n, freqs = 512, 4
+    d = rng.standard_normal((n, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    pert = (rng.standard_normal((n, 3)) * 0.3).astype(np.float32)
+    s32 = (d + pert).astype(np.float64)  # float32 addition, as on the GPU
+    s64 = d.astype(np.float64) + pert.astype(np.float64)
+    raw = U32 * np.abs(s32)
+    F = rng.uniform(0.0, 1.0, (n, 7))
+    x64 = np.concatenate([F, encode_dir(torch.from_numpy(s64), freqs).numpy()], 1)
+    x32 = np.concatenate([F, encode_dir(torch.from_numpy(s32), freqs).numpy()], 1)
+    e_x = _input_abs_err(x32, raw, freqs)
+    assert np.all(np.abs(x32 - x64)[:, 7:] <= (e_x - np.where(np.arange(34) >= 10, SINCOS_ERR, 0.0))[:, 7:] * (1 + 1e-9))
+    mlp = (rng.standard_normal(883) * 0.4).astype(np.float64)
+    fw = _mlp_abs(mlp, x32)
+    _, ez3 = _input_err_coeffs(fw, e_x)
+    w1, b1, w2, b2, w3, b3 = [t.numpy() for t in unpack_mlp(torch.from_numpy(mlp))]
+
+    def fwd(x):
+        z1 = x @ w1.T + b1
+        z2 = np.maximum(z1, 0.0) @ w2.T + b2
+        return np.maximum(z2, 0.0) @ w3.T + b3, np.concatenate([z1 > 0, z2 > 0], 1)
+
+    z0, pat0 = fwd(x32)
+    checked = 0
+    for _ in range(32):
+        sign = rng.choice([-1.0, 1.0], size=x32.shape)
+        z, pat = fwd(x32 + sign * e_x)
+        keep = np.all(pat == pat0, axis=1)
+        checked += int(keep.sum())
+        assert np.all(np.abs(z - z0)[keep] <= U32 * ez3[keep] * (1 + 1e-9) + 1e-300)
+    assert checked >= 32 * n * 0.9
+
+
+def test_error_scale_weight_error_bounds_perturbed_fractions():
+    """The interpolation-weight term against brute force: moving every 1-D
+    factor (f and 1 - f of each axis) by +-FRAC_ERR u with random signs
+    changes each corner's weight (the product of its factors, Eq. 2) by at
+    most FRAC_ERR u omega_c (first order; the products of two or three
+    perturbations add at most 4 (FRAC_ERR u)^2), for the trilinear grid and
+    the three planes."""
+    from oracle.field import feature_terms
+    from oracle.fp32_bound import FRAC_ERR, U32, _other_axis_weights
+    rng = np.random.default_rng(31)
+    sc = micro_scene(grid=(9, 7, 5), planes=(13, 11, 6))
+    p = np.stack([rng.uniform(-1, 1, 4000), rng.uniform(-1, 1, 4000), rng.uniform(0, 0.25, 4000)], 1)
+    p[:50, 0] = -1.0 + 2.0 * 3 / 12 + rng.uniform(-1e-7, 1e-7, 50)  # samples next to a vertex plane
+    dims_g = (9, 7, 5)
+    dims_p = (13, 11, 6)
+    om = _other_axis_weights(p, sc)
+    terms = feature_terms(p, BOX_LO, BOX_HI, dims_g, dims_p)
+    e = FRAC_ERR * U32
+    for _ in range(16):
+        sg = rng.choice([-1.0, 1.0], size=(p.shape[0], 3, 2))  # axis, (1 - f, f)
+
+        def fac(axis, n, side):
+            u = (p[:, axis] - BOX_LO[axis]) / (BOX_HI[axis] - BOX_LO[axis]) * (n - 1)
+            f = u - np.clip(np.floor(u), 0, n - 2)
+            return (f if side else 1.0 - f) + sg[:, axis, side] * e
+
+        for c in range(8):
+            dx, dy, dz = c & 1, (c >> 1) & 1, (c >> 2) & 1
+            w = fac(0, 9, dx) * fac(1, 7, dy) * fac(2, 5, dz)
+            assert np.all(np.abs(w - terms["grid"][1][:, c]) <= e * om["grid"][:, c] * (1 + 1e-9) + 4 * e * e)
+        for src, (a0, n0), (a1, n1) in (("plane_xy", (0, 13), (1, 11)), ("plane_xz", (0, 13), (2, 6)),
+                                         ("plane_yz", (1, 11), (2, 6))):
+            for c in range(4):
+                w = fac(a0, n0, c & 1) * fac(a1, n1, (c >> 1) & 1)
+                assert np.all(np.abs(w - terms[src][1][:, c]) <= e * om[src][:, c] * (1 + 1e-9) + 4 * e * e)
+
+
+def test_error_scale_fraction_slopes_bound_a_perturbed_field():
+    """The interpolated t of Eq. 2 against brute force: moving every 1-D
+    factor by +-FRAC_ERR u (random signs) moves t by at most FRAC_ERR u
+    times the modelled slope sum_axes |dt/df_a| per channel (first order,
+    plus the products of two perturbations)."""
+    from oracle.field import feature_terms
+    from oracle.fp32_bound import FRAC_ERR, U32, _fraction_slopes
+    rng = np.random.default_rng(41)
+    sc = micro_scene(grid=(9, 7, 5), planes=(13, 11, 6), seed=41, std=0.7)
+    p = np.stack([rng.uniform(-1, 1, 3000), rng.uniform(-1, 1, 3000), rng.uniform(0, 0.25, 3000)], 1)
+    dims = {"grid": (9, 7, 5), "plane_xy": (13, 11), "plane_xz": (13, 6), "plane_yz": (11, 6)}
+    axes = {"grid": (0, 1, 2), "plane_xy": (0, 1), "plane_xz": (0, 2), "plane_yz": (1, 2)}
+    terms = feature_terms(p, BOX_LO, BOX_HI, (9, 7, 5), (13, 11, 6))
+    slopes = _fraction_slopes(p, sc, {k: terms[k][0] for k in terms})
+    e = FRAC_ERR * U32
+
+    def t_of(sign):
+        t = np.zeros((p.shape[0], 8))
+        for src, ax in axes.items():
+            tab = np.asarray(sc[src], dtype=np.float64).reshape(-1, 8)
+            idx = terms[src][0]
+            fac = []
+            for j, a in enumerate(ax):
+                n = dims[src][j]
+                u = (p[:, a] - BOX_LO[a]) / (BOX_HI[a] - BOX_LO[a]) * (n - 1)
+                f = u - np.clip(np.floor(u), 0, n - 2)
+                s_ = sign[:, a]
+                fac.append((1.0 - f - s_ * e, f + s_ * e))
+            for c in range(1 << len(ax)):
+                w = np.ones(p.shape[0])
+                for j in range(len(ax)):
+                    w = w * fac[j][(c >> j) & 1]
+                t += w[:, None] * tab[idx[:, c]]
+        return t
+
+    t0 = t_of(np.zeros((p.shape[0], 3)))
+    tab_max = max(np.abs(np.asarray(sc[k])).max() for k in axes)
+    for _ in range(16):
+        dt = np.abs(t_of(rng.choice([-1.0, 1.0], size=(p.shape[0], 3))) - t0)
+        assert np.all(dt <= e * slopes * (1 + 1e-9) + 64 * e * e * tab_max)
