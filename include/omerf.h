@@ -372,6 +372,29 @@ int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, 
 int64_t om_render_fwd_bwd_l2_workspace_size(int64_t n, const om_params* p);
 
 /*
+ * om_render_fwd_bwd_l2 for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving or training loops, harnesses that
+ * forbid hipMalloc.  Same arguments and results as om_render_fwd_bwd_l2
+ * minus the workspace: the workspace (dL/dC and the per-batch sums) lives
+ * in a fixed array of om_render_fwd_bwd_l2_noalloc_max_bytes() bytes
+ * (64 MiB) inside the library, one per GPU, held until the process ends.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  Limit: om_render_fwd_bwd_l2_workspace_size(n, p) must not
+ * exceed that size (e.g. 145,000 rays at n_max 256, 540,000 at n_max 64),
+ * else OM_ERR_UNSUPPORTED with om_last_error naming the sizes.  Every
+ * call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (each call overwrites what it reads before reading it): calls
+ * that overlap on one GPU (concurrent streams, threads) race and must be
+ * serialised by the caller.
+ */
+int om_render_fwd_bwd_l2_noalloc(const om_scene* scene, const float* o, const float* d, int64_t n,
+                                 const om_params* p, const float* target, const om_fwd_out* out,
+                                 float* loss, const om_grads* g, void* stream);
+
+/* Size in bytes of the fixed workspace of om_render_fwd_bwd_l2_noalloc. */
+int64_t om_render_fwd_bwd_l2_noalloc_max_bytes(void);
+
+/*
  * Interval-span regulariser of Sec. 4.1, Eq. 5, scaled by `weight` (the
  * schedule's lambda): L = weight * sum over the My x Mx grid points of
  * (z_max - z_min)^2.  occ: device float32 [cells][2].  loss: optional

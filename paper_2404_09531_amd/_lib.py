@@ -22,6 +22,7 @@ EXPORTS = ("om_scene_create", "om_scene_update", "om_scene_destroy", "om_occupan
            "om_build_occupancy_mips", "om_place_samples", "om_march",
            "om_deferred_mlp", "om_render",
            "om_render_backward", "om_render_backward_ex", "om_smooth_loss", "om_render_fwd_bwd_l2", "om_render_fwd_bwd_l2_workspace_size",
+           "om_render_fwd_bwd_l2_noalloc", "om_render_fwd_bwd_l2_noalloc_max_bytes",
            "om_occ_interval_loss", "om_feature_range", "om_quant_params", "om_quantize_u8",
            "om_sparse_grid_index", "om_sparse_grid_fill",
            "om_cast_bf16", "om_mark_rows", "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str",
@@ -96,6 +97,9 @@ def lib() -> ctypes.CDLL:
                                            POINTER(OmFwdOut), c_void_p, c_int64, c_void_p, POINTER(OmGrads),
                                            c_void_p]
         L.om_render_fwd_bwd_l2_workspace_size.argtypes = [c_int64, POINTER(OmParams)]
+        L.om_render_fwd_bwd_l2_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(OmParams),
+                                                   c_void_p, POINTER(OmFwdOut), c_void_p, POINTER(OmGrads), c_void_p]
+        L.om_render_fwd_bwd_l2_noalloc_max_bytes.argtypes = []
         L.om_occupancy_mips_size.argtypes = [c_void_p, c_int]
         L.om_occ_interval_loss.argtypes = [c_void_p, c_int64, c_float, c_void_p, c_void_p, c_void_p]
         L.om_build_occupancy_mips.argtypes = [c_void_p, c_void_p, c_int64, c_int, c_void_p]
@@ -104,9 +108,10 @@ def lib() -> ctypes.CDLL:
         L.om_status_str.argtypes = [c_int]
         for name in EXPORTS:
             if name not in ("om_last_error", "om_status_str", "om_render_fwd_bwd_l2_workspace_size",
-                            "om_occupancy_mips_size"):
+                            "om_render_fwd_bwd_l2_noalloc_max_bytes", "om_occupancy_mips_size"):
                 getattr(L, name).restype = c_int
         L.om_render_fwd_bwd_l2_workspace_size.restype = c_int64
+        L.om_render_fwd_bwd_l2_noalloc_max_bytes.restype = c_int64
         L.om_occupancy_mips_size.restype = c_int64
         L.om_sparse_grid_index.restype = c_int64
         _lib = L

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -403,9 +404,17 @@ int64_t om_render_fwd_bwd_l2_workspace_size(int64_t n, const om_params* p) {
     return dc + n * slots * 7 * (int64_t)sizeof(float);
 }
 
+// Workspace of om_render_fwd_bwd_l2_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device
+// address); it uses the address hipGetSymbolAddress returns for the current
+// device, looked up once per device on the entry point's first call there.
+constexpr int64_t kNoAllocScratchBytes = 64ll << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
-// Validation of the fused L2 step.
+// Validation shared by the fused L2 step and its no-alloc variant.
 int check_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
                      const float* target, const om_fwd_out* out, const om_grads* g, RayParams* rp) {
     int rc = check_fwd(scene, o, d, n, p, out, true, true, rp);
@@ -440,6 +449,27 @@ int fwd_bwd_l2_launch(const om_scene* scene, const float* o, const float* d, int
     return hip_status(e, who);
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for_current_device(void** ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2_noalloc (hipGetDevice)");
+    if (dev < 0 || dev >= kMaxDevices) return fail(OM_ERR_UNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_status(e, "om_render_fwd_bwd_l2_noalloc (hipGetSymbolAddress)");
+        if (!p) return fail(OM_ERR_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return OM_OK;
+}
+
 }  // namespace
 
 int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
@@ -456,6 +486,28 @@ int om_render_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, 
                     (long long)need);
     return fwd_bwd_l2_launch(scene, o, d, n, p, rp, target, out, workspace, loss, g, (hipStream_t)stream,
                              "om_render_fwd_bwd_l2");
+}
+
+int64_t om_render_fwd_bwd_l2_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+int om_render_fwd_bwd_l2_noalloc(const om_scene* scene, const float* o, const float* d, int64_t n,
+                                 const om_params* p, const float* target, const om_fwd_out* out, float* loss,
+                                 const om_grads* g, void* stream) {
+    RayParams rp;
+    int rc = check_fwd_bwd_l2(scene, o, d, n, p, target, out, g, &rp);
+    if (rc != OM_OK) return rc;
+    if (n == 0) return ok();
+    const int64_t need = om_render_fwd_bwd_l2_workspace_size(n, p);
+    if (need > kNoAllocScratchBytes)
+        return fail(OM_ERR_UNSUPPORTED,
+                    "om_render_fwd_bwd_l2_noalloc: %lld rays at n_max %d need %lld bytes of workspace, above the "
+                    "library's fixed %lld; use om_render_fwd_bwd_l2 with a caller workspace",
+                    (long long)n, p->n_max, (long long)need, (long long)kNoAllocScratchBytes);
+    void* ws = nullptr;
+    rc = scratch_for_current_device(&ws);
+    if (rc != OM_OK) return rc;
+    return fwd_bwd_l2_launch(scene, o, d, n, p, rp, target, out, ws, loss, g, (hipStream_t)stream,
+                             "om_render_fwd_bwd_l2_noalloc");
 }
 
 int om_smooth_loss(const om_scene* scene, const float* F, const float* d, int64_t n, const float* perturb, int32_t P,
