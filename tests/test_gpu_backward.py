@@ -358,8 +358,10 @@ def test_towers_bf16_storage_gradient_vs_oracle(towers):
 
 def test_towers_full_bf16_gradient_error(towers):
     """Full BF16 form (bf16 storage + bf16 MFMA MLP forward) against the
-    float64 oracle gradient of the float32 scene: reported, and the
-    gradient direction must agree (cosine > 0.999)."""
+    float64 oracle gradient of the float32 scene: the gradient's direction
+    (cosine), its relative L2 error and the median per-entry relative error
+    over the entries above 1e-2 max|g|, each within about 3x its measured
+    value."""
     sc, o, d, target, n_max = towers
     log("test_towers_full_bf16_gradient_error")
     scene, t = upload_scene(sc, dtype=torch.bfloat16)
@@ -382,9 +384,16 @@ def test_towers_full_bf16_gradient_error(towers):
     cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
     big = np.abs(b) >= 1e-2 * np.abs(b).max()
     rel = np.abs(a - b)[big] / np.abs(b)[big]
-    log(f"  BF16 form vs FP64 oracle gradient: cosine {cos:.6f}, max rel err (|g| >= 1e-2 max) {rel.max():.3e}, "
-        f"median {np.median(rel):.3e}")
-    assert cos > 0.999
+    l2 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    log(f"  BF16 form vs FP64 oracle gradient: cosine {cos:.6f}, relative L2 error {l2:.3e}, "
+        f"rel err on |g| >= 1e-2 max: median {np.median(rel):.3e}, 99th percentile {np.percentile(rel, 99):.3e}, "
+        f"max {rel.max():.3e}")
+    # about 3x the measured 1 - cos = 1.08e-4, 1.52e-2 and 1.8e-2: the bfloat16
+    # rounding of the stored features and of the MLP's operands moves every
+    # per-sample term by ~2^-9 relative, so individual entries that sum
+    # cancelling terms can be off by far more (99th percentile 0.2)
+    assert 1.0 - cos < 3.3e-4
+    assert l2 < 4.5e-2 and np.median(rel) < 5.5e-2
 
 
 @pytest.fixture(scope="module")

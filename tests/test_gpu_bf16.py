@@ -52,8 +52,9 @@ def test_bf16_march_matches_oracle_on_rounded_scene():
     # full BF16 form (MFMA MLP): bounded by bfloat16 rounding of the MLP
     res2 = om.render(scene, og, dg, n_max=64, c_bg=BG)
     err2 = np.abs(res2["C"].double().cpu().numpy() - ref["C"]).max()
-    log(f"  bf16 storage + bf16 MFMA MLP: max |C - oracle(rounded)| = {err2:.2e}")
-    assert err2 < 2e-2
+    err2m = np.abs(res2["C"].double().cpu().numpy() - ref["C"]).mean()
+    log(f"  bf16 storage + bf16 MFMA MLP: max |C - oracle(rounded)| = {err2:.2e}, mean {err2m:.2e}")
+    assert err2 < 4e-3 and err2m < 7e-4  # about 3x the measured 1.24e-3 / 2.2e-4
 
 
 def test_bf16_ert_rule():
@@ -112,8 +113,9 @@ def test_bf16_psnr_gate_and_fidelity(oblique_crop):
     log(f"  fidelity vs FP64 oracle: FP32 max-abs {e32:.2e} PSNR {p32:.1f} dB; "
         f"BF16 max-abs {e16:.2e} PSNR {p16:.1f} dB")
     log(f"  vs perturbed-scene target: FP32 {g32:.3f} dB, BF16 {g16:.3f} dB, loss {g32 - g16:.4f} dB")
+    # about 3x the measured 2.65e-3 / 70.2 dB (one MI355X)
     assert e32 <= 1e-5
-    assert e16 < 5e-2 and p16 > 40.0
+    assert e16 < 8e-3 and p16 > 61.0
     assert g32 - g16 <= 0.1
 
 
@@ -134,7 +136,8 @@ def test_u8_psnr_gate_and_fidelity(oblique_crop):
     g32, g8 = psnr(c32, gt), psnr(c8, gt)
     log(f"  fidelity vs FP64 oracle: 8-bit max-abs {e8:.2e} PSNR {p8:.1f} dB")
     log(f"  vs perturbed-scene target: FP32 {g32:.3f} dB, 8-bit {g8:.3f} dB, loss {g32 - g8:.4f} dB")
-    assert e8 < 5e-2 and p8 > 40.0
+    # about 3x the measured 5.3e-3 / 64.3 dB
+    assert e8 < 1.6e-2 and p8 > 55.0
     assert g32 - g8 <= 0.1
 
 
@@ -168,7 +171,7 @@ def test_bf16_4k_image0_crop_fidelity():
     log(f"  FP32 max-abs {e32:.2e}; bf16 storage vs rounded-scene oracle {e16s:.2e}; "
         f"full BF16 max-abs {e16:.2e} PSNR {p16:.1f} dB; {int((ref['n_placed'] > 0).sum())} rays hit")
     assert e32 <= 1e-5 and e16s <= 1e-5
-    assert e16 < 5e-2 and p16 > 40.0
+    assert e16 < 1.05e-2 and p16 > 60.0  # about 3x the measured 3.5e-3 / 69.2 dB
 
 
 def test_bf16_oblique_1080p_sampled_parity():
@@ -201,7 +204,7 @@ def test_bf16_oblique_1080p_sampled_parity():
         assert err <= 1e-5, key
     err = np.abs(full["C"].double().cpu().numpy()[rows] - ref["C"])
     log(f"  full bf16 form: max |C - oracle(rounded)| = {err.max():.2e}, mean {err.mean():.2e}")
-    assert err.max() < 2e-2 and err.mean() < 3e-3
+    assert err.max() < 3e-3 and err.mean() < 6e-4  # about 3x the measured 1.0e-3 / 2.0e-4
 
 
 def _bits_f32(u):

@@ -163,7 +163,9 @@ def test_mlp_bf16_mfma_close_to_oracle(tiny):
     res = om.render(scene, og, dg, n_max=64, c_bg=BG, mlp_bf16=1)
     ref = oracle.oracle_render(sc, o, d, oracle.RenderParams(n_max=64, c_bg=BG), keep_k=False)
     err = np.abs(res["C"].double().cpu().numpy() - ref["C"])
-    assert err.max() < 2e-2 and err.mean() < 3e-3, (err.max(), err.mean())
+    log(f"  bf16 MFMA MLP: max |C - oracle| = {err.max():.2e}, mean {err.mean():.2e}")
+    # about 3x the measured 1.31e-3 / 2.2e-4
+    assert err.max() < 4e-3 and err.mean() < 7e-4, (err.max(), err.mean())
     # the march outputs are unaffected by the MLP precision
     np.testing.assert_allclose(res["F"].double().cpu().numpy(), ref["F"], atol=TOL, rtol=0)
 

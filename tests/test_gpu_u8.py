@@ -123,7 +123,9 @@ def test_u8_render_bf16_mlp(tiny):
     dec = oracle.dequantize_scene(oracle.quantize_scene(sc))
     ref = oracle.oracle_render(dec, o, d, oracle.RenderParams(n_max=64, c_bg=BG), keep_k=False)
     err = np.abs(res["C"].double().cpu().numpy() - ref["C"])
-    assert err.max() < 2e-2 and err.mean() < 3e-3, (err.max(), err.mean())
+    log(f"  8-bit + bf16 MFMA MLP: max |C - oracle(decoded)| = {err.max():.2e}, mean {err.mean():.2e}")
+    # about 3x the measured 1.14e-3 / 2.1e-4
+    assert err.max() < 4e-3 and err.mean() < 7e-4, (err.max(), err.mean())
     np.testing.assert_allclose(res["F"].double().cpu().numpy(), ref["F"], atol=TOL, rtol=0)
 
 
