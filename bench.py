@@ -62,7 +62,7 @@ def parse():
 KERNEL_SOURCES = {
     "fwd": ("omerf_device.h", "march_fwd.hip"),
     "bwd": ("omerf_device.h", "bwd_device.h", "march_bwd.hip"),
-    "mlp": ("omerf_device.h", "bwd_device.h", "mlp.hip"),
+    "mlp": ("omerf_device.h", "mlp.hip"),
 }
 
 

@@ -37,7 +37,7 @@ def mlp_nparams(dir_freqs: int = 0) -> int:
 
 _FREQS_OF = {mlp_nparams(0): 0, mlp_nparams(4): 4}
 
-__all__ = ["Scene", "place_samples", "render", "render_backward", "RenderFn", "SmoothFn", "smooth_loss",
+__all__ = ["Scene", "place_samples", "render", "render_backward", "backward_workspace_size", "RenderFn", "SmoothFn", "smooth_loss",
            "l2_loss_fp64", "l2_loss_grad", "occ_interval_loss", "mlp_nparams", "feature_range", "quant_params",
            "quantize_u8", "quantize_features", "sparse_grid", "SparseGrid", "DELTA", "OmerfError",
            "OM_MAX_SAMPLES", "to_bf16", "mark_rows"]
@@ -326,13 +326,16 @@ def render_into(scene: Scene, o, d, out: Dict[str, torch.Tensor], n_max: int, de
 
 def render_backward(scene: Scene, o, d, saved: Dict[str, torch.Tensor], dL_dC, grads: Dict[str, torch.Tensor],
                     n_max: int, delta: float = DELTA, t_term: float = 0.0, c_bg=(0.0, 0.0, 0.0),
-                    occ_eps: float = 0.0, dL_dF: Optional[torch.Tensor] = None) -> None:
+                    occ_eps: float = 0.0, dL_dF: Optional[torch.Tensor] = None,
+                    workspace: Optional[torch.Tensor] = None) -> None:
     """Accumulate dL/d(grid, planes, mlp) into float32 `grads` (keys grid,
     plane_xy, plane_xz, plane_yz, mlp) given dL/dC and the forward's outputs
     (with "batch_wv" among them when the forward wrote it).  With
     occ_eps > 0 an optional grads["occ"] [My, Mx, 2] receives dL/d(z_min, z_max).
     dL_dF (float32 [n, 7], optional) is an extra upstream gradient on the
-    composited features, e.g. from smooth_loss."""
+    composited features, e.g. from smooth_loss.  `workspace`: optional
+    device uint8 tensor of at least backward_workspace_size(n) bytes
+    (om_render_backward_ws); allocated here when None."""
     n = _rays(scene, o, d)
     _need(dL_dC, "dL_dC", torch.float32, (n, 3))
     if dL_dF is not None:
@@ -343,9 +346,22 @@ def render_backward(scene: Scene, o, d, saved: Dict[str, torch.Tensor], dL_dC, g
                        saved["n_placed"].data_ptr(), saved["n_eval"].data_ptr(), _batch_wv(saved, n, n_max))
     g = _grads(scene, grads)
     p = _params(n_max, delta, t_term, c_bg, -1, occ_eps)
-    _lib.check("om_render_backward_ex", _lib.lib().om_render_backward_ex(
+    nbytes = backward_workspace_size(n)
+    if workspace is None:
+        workspace = torch.empty((max(nbytes, 1),), dtype=torch.uint8, device=o.device)
+    _need_workspace(workspace, nbytes, o.device)
+    _lib.check("om_render_backward_ws", _lib.lib().om_render_backward_ws(
         scene.handle, o.data_ptr(), d.data_ptr(), n, ctypes.byref(p), ctypes.byref(fo), dL_dC.data_ptr(),
-        _lib.ptr(dL_dF), ctypes.byref(g), _lib.stream_of(o)))
+        _lib.ptr(dL_dF), workspace.data_ptr(), workspace.numel(), ctypes.byref(g), _lib.stream_of(o)))
+
+
+def backward_workspace_size(n: int) -> int:
+    """Bytes of workspace render_backward needs (om_render_backward_workspace_size)."""
+    nb = _lib.lib().om_render_backward_workspace_size(n)
+    if nb < 0:
+        raise _lib.OmerfError("om_render_backward_workspace_size", _lib.OM_ERR_INVALID,
+                              _lib.lib().om_last_error().decode())
+    return int(nb)
 
 
 def fwd_bwd_l2_workspace_size(n: int, n_max: int, delta: float = DELTA) -> int:
@@ -374,6 +390,7 @@ def render_fwd_bwd_l2(scene: Scene, o, d, target, out: Dict[str, torch.Tensor], 
     nbytes = fwd_bwd_l2_workspace_size(n, n_max, delta)
     if workspace is None:
         workspace = torch.empty((max(nbytes, 1),), dtype=torch.uint8, device=o.device)
+    _need_workspace(workspace, nbytes, o.device)
     if loss is not None:
         _need(loss, "loss", torch.float32, (1,))
     fo = _lib.OmFwdOut(out["C"].data_ptr(), out["T"].data_ptr(), out["F"].data_ptr(), out["n_placed"].data_ptr(),
@@ -384,6 +401,15 @@ def render_fwd_bwd_l2(scene: Scene, o, d, target, out: Dict[str, torch.Tensor], 
         scene.handle, o.data_ptr(), d.data_ptr(), n, ctypes.byref(p), target.data_ptr(), ctypes.byref(fo),
         workspace.data_ptr(), workspace.numel(), _lib.ptr(loss), ctypes.byref(g), _lib.stream_of(o)))
     return loss
+
+
+def _need_workspace(ws: torch.Tensor, nbytes: int, device) -> None:
+    """A caller workspace: contiguous device uint8 of at least nbytes (the
+    library checks its 256-byte alignment)."""
+    if ws.dtype != torch.uint8 or not ws.is_contiguous() or ws.device != device:
+        raise ValueError(f"workspace must be a contiguous uint8 tensor on {device}")
+    if ws.numel() < nbytes:
+        raise ValueError(f"workspace holds {ws.numel()} bytes, {nbytes} needed")
 
 
 def _grads(scene: Scene, grads: Dict[str, torch.Tensor]) -> _lib.OmGrads:

@@ -368,28 +368,78 @@ int om_render_backward(const om_scene* scene, const float* o, const float* d, in
     return om_render_backward_ex(scene, o, d, n, p, saved, dL_dC, nullptr, g, stream);
 }
 
-int om_render_backward_ex(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
-                          const om_fwd_out* saved, const float* dL_dC, const float* dL_dF, const om_grads* g,
-                          void* stream) {
+int64_t om_render_backward_workspace_size(int64_t n) {
+    if (n < 0) {
+        fail(OM_ERR_INVALID, "n must be >= 0");
+        return -1;
+    }
+    return (n * 8 * (int64_t)sizeof(float) + 255) / 256 * 256;
+}
+
+namespace {
+
+int check_backward(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                   const om_fwd_out* saved, const float* dL_dC, const om_grads* g, RayParams* rp) {
     int rc = check_rays(scene, o, d, n);
     if (rc != OM_OK) return rc;
-    RayParams rp;
-    if ((rc = validate_params(p, &rp)) != OM_OK) return rc;
+    if ((rc = validate_params(p, rp)) != OM_OK) return rc;
     if (scene->desc.dtype == OM_U8 || scene->desc.block_shift > 0)
         return fail(OM_ERR_UNSUPPORTED, "8-bit and sparse-block scenes are render-only");
     if (!saved || !g) return fail(OM_ERR_INVALID, "saved / grads struct is NULL");
-    if (n == 0) return ok();
+    if (n == 0) return OM_OK;
     if (!saved->F || !saved->T || !saved->n_eval) return fail(OM_ERR_INVALID, "saved F, T and n_eval are required");
     if (saved->batch_wv && ((uintptr_t)saved->batch_wv & 3u))
         return fail(OM_ERR_INVALID, "batch_wv must be 4-byte aligned");
     if (!dL_dC) return fail(OM_ERR_INVALID, "dL_dC is NULL");
     if (!g->grid || !g->plane_xy || !g->plane_xz || !g->plane_yz || !g->mlp)
         return fail(OM_ERR_INVALID, "all gradient buffers are required");
-    const bool bf16 = scene->desc.dtype == OM_BF16;
-    hipError_t e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, saved->F, saved->T, saved->n_eval, saved->batch_wv,
-                                    dL_dC, dL_dF, g->grid, g->plane_xy, g->plane_xz, g->plane_yz, g->mlp, g->occ,
-                                    (hipStream_t)stream);
-    return hip_status(e, "om_render_backward");
+    return OM_OK;
+}
+
+// MLP backward into G8 (per-ray dL/dF and background term), then the march
+// backward that reads it.
+hipError_t backward_launch(const om_scene* scene, const RayParams& rp, const float* o, const float* d, int64_t n,
+                           const float* F, const float* T, const int32_t* n_eval, const float* batch_wv,
+                           const float* dC, const float* dF, float* G8, const om_grads* g, hipStream_t s) {
+    hipError_t e = launch_mlp_bwd(scene->dev.mlp, scene->dev.mlp_in, rp, F, d, n_eval, dC, dF, n, G8, g->mlp, s);
+    if (e != hipSuccess) return e;
+    return launch_march_bwd(scene->dev, scene->desc.dtype == OM_BF16, rp, o, d, n, T, n_eval, batch_wv, G8, g->grid,
+                            g->plane_xy, g->plane_xz, g->plane_yz, g->occ, s);
+}
+
+}  // namespace
+
+int om_render_backward_ws(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                          const om_fwd_out* saved, const float* dL_dC, const float* dL_dF, void* workspace,
+                          int64_t workspace_bytes, const om_grads* g, void* stream) {
+    RayParams rp;
+    int rc = check_backward(scene, o, d, n, p, saved, dL_dC, g, &rp);
+    if (rc != OM_OK || n == 0) return rc == OM_OK ? ok() : rc;
+    const int64_t need = om_render_backward_workspace_size(n);
+    if (!workspace || ((uintptr_t)workspace & 255u)) return fail(OM_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (workspace_bytes < need)
+        return fail(OM_ERR_INVALID, "workspace holds %lld bytes, %lld needed", (long long)workspace_bytes,
+                    (long long)need);
+    const hipError_t e = backward_launch(scene, rp, o, d, n, saved->F, saved->T, saved->n_eval, saved->batch_wv, dL_dC,
+                                         dL_dF, static_cast<float*>(workspace), g, (hipStream_t)stream);
+    return hip_status(e, "om_render_backward_ws");
+}
+
+int om_render_backward_ex(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                          const om_fwd_out* saved, const float* dL_dC, const float* dL_dF, const om_grads* g,
+                          void* stream) {
+    RayParams rp;
+    int rc = check_backward(scene, o, d, n, p, saved, dL_dC, g, &rp);
+    if (rc != OM_OK || n == 0) return rc == OM_OK ? ok() : rc;
+    const hipStream_t s = (hipStream_t)stream;
+    void* ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, (size_t)om_render_backward_workspace_size(n), s);
+    if (e != hipSuccess) return hip_status(e, "om_render_backward (hipMallocAsync)");
+    e = backward_launch(scene, rp, o, d, n, saved->F, saved->T, saved->n_eval, saved->batch_wv, dL_dC, dL_dF,
+                        static_cast<float*>(ws), g, s);
+    const hipError_t ef = hipFreeAsync(ws, s);
+    if (e != hipSuccess) return hip_status(e, "om_render_backward");
+    return hip_status(ef, "om_render_backward (hipFreeAsync)");
 }
 
 int64_t om_render_fwd_bwd_l2_workspace_size(int64_t n, const om_params* p) {
@@ -401,7 +451,7 @@ int64_t om_render_fwd_bwd_l2_workspace_size(int64_t n, const om_params* p) {
     if (validate_params(p, &rp) != OM_OK) return -1;
     const int64_t slots = (p->n_max + kGroup - 1) / kGroup;
     const int64_t dc = (n * 3 * (int64_t)sizeof(float) + 255) / 256 * 256;
-    return dc + n * slots * 7 * (int64_t)sizeof(float);
+    return dc + om_render_backward_workspace_size(n) + n * slots * 7 * (int64_t)sizeof(float);
 }
 
 // Workspace of om_render_fwd_bwd_l2_noalloc: a file-scope device array, one
@@ -429,14 +479,16 @@ int check_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, int6
 }
 
 // The step itself over a workspace laid out as [dL/dC, 256-byte aligned |
+// per-ray dL/dF and background term (om_render_backward_workspace_size) |
 // per-batch sums of w v]: forward with per-batch sums, loss gradient,
-// backward.
+// MLP backward, march backward.
 int fwd_bwd_l2_launch(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
                       const RayParams& rp, const float* target, const om_fwd_out* out, void* workspace, float* loss,
                       const om_grads* g, hipStream_t s, const char* who) {
-    float* dC = static_cast<float*>(workspace);
-    float* bw = reinterpret_cast<float*>(static_cast<char*>(workspace) + (n * 3 * (int64_t)sizeof(float) + 255) / 256 * 256);
-    const bool bf16 = scene->desc.dtype == OM_BF16;
+    char* base = static_cast<char*>(workspace);
+    float* dC = reinterpret_cast<float*>(base);
+    float* G8 = reinterpret_cast<float*>(base + (n * 3 * (int64_t)sizeof(float) + 255) / 256 * 256);
+    float* bw = reinterpret_cast<float*>(reinterpret_cast<char*>(G8) + om_render_backward_workspace_size(n));
     hipError_t e = launch_march_fwd(scene->dev, scene->desc.dtype, rp, o, d, n, out->F, out->T, out->n_placed,
                                     out->n_eval, bw, s);
     if (e != hipSuccess) return hip_status(e, who);
@@ -444,8 +496,7 @@ int fwd_bwd_l2_launch(const om_scene* scene, const float* o, const float* d, int
     if (e != hipSuccess) return hip_status(e, who);
     e = launch_l2(out->C, target, n, dC, loss, s);
     if (e != hipSuccess) return hip_status(e, who);
-    e = launch_march_bwd(scene->dev, bf16, rp, o, d, n, out->F, out->T, out->n_eval, bw, dC, nullptr, g->grid, g->plane_xy,
-                         g->plane_xz, g->plane_yz, g->mlp, g->occ, s);
+    e = backward_launch(scene, rp, o, d, n, out->F, out->T, out->n_eval, bw, dC, nullptr, G8, g, s);
     return hip_status(e, who);
 }
 

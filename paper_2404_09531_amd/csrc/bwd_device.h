@@ -1,8 +1,6 @@
-// bwd_device.h -- device-side building blocks of the backward pass and of the
-// group-cooperative deferred MLP (one hidden unit per lane of a 16-lane
-// group): run detection and segmented sums over the lanes of a group, and
-// the MLP forward/backward shared by the backward march and the
-// view-smoothness loss.
+// bwd_device.h -- device-side building blocks of the backward march: run
+// detection, segmented sums and reverse scans over the lanes of a 16-lane
+// group.
 #pragma once
 
 #include "omerf_device.h"
@@ -86,58 +84,6 @@ __device__ __forceinline__ float g_rscan_incl(float x, int /*gl*/) {
     x += dpp_row<kRowShl | 4>(x);
     x += dpp_row<kRowShl | 8>(x);
     return x;
-}
-
-struct MlpAct {
-    float z1, h1, z2, h2;  // this lane's hidden unit, both layers
-    float g[3];            // G (after the sigmoid), the same on every lane
-};
-
-template <int NIN>
-__device__ __forceinline__ MlpAct group_mlp_fwd(const float* W, const float* x, int h) {
-    using L = MlpLayout<NIN>;
-    MlpAct a;
-    a.z1 = W[L::B1 + h];
-#pragma unroll
-    for (int c = 0; c < NIN; ++c) a.z1 += W[L::W1 + h * NIN + c] * x[c];
-    a.h1 = fmaxf(a.z1, 0.0f);
-    a.z2 = W[L::B2 + h];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) a.z2 += W[L::W2 + h * 16 + j] * __shfl(a.h1, j, kGroup);
-    a.h2 = fmaxf(a.z2, 0.0f);
-#pragma unroll
-    for (int r = 0; r < 3; ++r) a.g[r] = sigmoidf_fast(W[L::B3 + r] + g_sum(W[L::W3 + r * 16 + h] * a.h2));
-    return a;
-}
-
-// Backward of group_mlp_fwd for dL/dG = dG (the same on every lane): adds
-// the parameter gradients into the LDS array sW (distinct addresses per
-// lane) and dL/dx[0..6] into dx7 (the same on every lane).
-template <int NIN>
-__device__ __forceinline__ void group_mlp_bwd(const float* W, const float* x, int h, const MlpAct& a,
-                                              const float* dG, float* sW, float* dx7) {
-    using L = MlpLayout<NIN>;
-    float dz3[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) dz3[r] = dG[r] * a.g[r] * (1.0f - a.g[r]);
-    const float dh2 = W[L::W3 + h] * dz3[0] + W[L::W3 + 16 + h] * dz3[1] + W[L::W3 + 32 + h] * dz3[2];
-    const float dz2 = a.z2 > 0.0f ? dh2 : 0.0f;
-    float dh1 = 0.0f;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        dh1 += W[L::W2 + j * 16 + h] * __shfl(dz2, j, kGroup);
-        atomicAdd(&sW[L::W2 + h * 16 + j], dz2 * __shfl(a.h1, j, kGroup));
-    }
-    const float dz1 = a.z1 > 0.0f ? dh1 : 0.0f;
-#pragma unroll
-    for (int c = 0; c < 7; ++c) dx7[c] += g_sum(W[L::W1 + h * NIN + c] * dz1);
-#pragma unroll
-    for (int c = 0; c < NIN; ++c) atomicAdd(&sW[L::W1 + h * NIN + c], dz1 * x[c]);
-    atomicAdd(&sW[L::B1 + h], dz1);
-    atomicAdd(&sW[L::B2 + h], dz2);
-#pragma unroll
-    for (int r = 0; r < 3; ++r) atomicAdd(&sW[L::W3 + r * 16 + h], dz3[r] * a.h2);
-    if (h < 3) atomicAdd(&sW[L::B3 + h], h == 0 ? dz3[0] : h == 1 ? dz3[1] : dz3[2]);
 }
 
 }  // namespace omerf

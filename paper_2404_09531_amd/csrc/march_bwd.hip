@@ -1,6 +1,7 @@
 // march_bwd.hip -- backward of the occupancy-plane ray march for gfx950:
-// deferred-MLP backward (Eq. 4) + replay of the samples with recomputed
-// features + scatter-add of the feature gradients (derivative of Eq. 1-3).
+// replay of the samples with recomputed features + scatter-add of the
+// feature gradients (derivative of Eq. 1-3), given dL/dF from the deferred
+// MLP's backward (k_mlp_bwd, Eq. 4).
 //
 // One ray per 16-lane group; see omerf_device.h for the decomposition.
 #include "../../include/omerf.h"
@@ -10,9 +11,9 @@
 namespace omerf {
 
 // ---------------------------------------------------------------------------
-// Backward.  Per ray: the deferred MLP backward runs across the 16 lanes of
-// the group (lane h owns hidden unit h of both hidden layers), giving
-// g7 = dL/dF (+ dL/dC on the diffuse part).  The samples are then replayed
+// Backward.  Per ray, g7 = dL/dF (dL/dC on the diffuse part + the deferred
+// MLP's backward + losses on F) and dL/dC . c_bg come precomputed from
+// k_mlp_bwd, so the march holds no MLP state.  The samples are replayed
 // twice in the forward's order with recomputed features:
 //
 //   pass 1 records, per 16-sample batch, B_b = sum_{i in b} w_i (g7 . v_i);
@@ -223,30 +224,23 @@ __device__ __forceinline__ void scatter_occ(float* gocc, bool act, const OccValu
 // Longest chunk of rays a backward block sorts by length (LDS: 6 KB).
 constexpr int kSortMax = 1024;
 
-template <class S, bool kSoft, int NIN>
-__global__ __launch_bounds__(kBlock, NIN == 10 ? 4 : 1) void k_march_bwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
-                                                      const float* __restrict__ d_, int64_t n, int64_t chunk,
-                                                      const float* __restrict__ Fs, const float* __restrict__ Ts,
-                                                      const int32_t* __restrict__ n_eval,
-                                                      const float* __restrict__ BW,
-                                                      const float* __restrict__ dC,
-                                                      const float* __restrict__ dF, float* __restrict__ gV,
-                                                      float* __restrict__ gxy, float* __restrict__ gxz,
-                                                      float* __restrict__ gyz, float* __restrict__ gmlp,
-                                                      float* __restrict__ gocc) {
+template <class S, bool kSoft>
+__global__ __launch_bounds__(kBlock, 4) void k_march_bwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
+                                                       const float* __restrict__ d_, int64_t n, int64_t chunk,
+                                                       const float* __restrict__ Ts,
+                                                       const int32_t* __restrict__ n_eval,
+                                                       const float* __restrict__ BW, const float* __restrict__ G8,
+                                                       float* __restrict__ gV, float* __restrict__ gxy,
+                                                       float* __restrict__ gxz, float* __restrict__ gyz,
+                                                       float* __restrict__ gocc) {
     __shared__ int qs[kGroupsPerBlock][kQueue];
-    __shared__ float sW[kMlpMaxSize];
     __shared__ __attribute__((aligned(16))) Stage stages[kGroupsPerBlock];
     __shared__ int s_key[kSortMax];
     __shared__ uint16_t s_ord[kSortMax];
-    for (int i = threadIdx.x; i < kMlpMaxSize; i += kBlock) sW[i] = 0.0f;
-    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kGroup - 1);
     const int gid = threadIdx.x / kGroup;
-    const int h = gl;
     Stage& stage = stages[gid];
-    const float* W = sc.mlp;
     const int64_t start = (int64_t)xcd_block(blockIdx.x, gridDim.x) * chunk;
     const int cnt = (int)(min(n, start + chunk) - start);
     // A wave's four groups walk their rays in step, so a wave waits for its
@@ -273,28 +267,11 @@ __global__ __launch_bounds__(kBlock, NIN == 10 ? 4 : 1) void k_march_bwd(SceneDe
         const float3 o = load3(o_, ray), d = load3(d_, ray);
         const int ne = n_eval[ray];
         const float Tn = Ts[ray];
-        const float dc0 = dC[ray * 3 + 0], dc1 = dC[ray * 3 + 1], dc2 = dC[ray * 3 + 2];
         if (ne <= 0) continue;  // no sample: C = c_bg, no parameter gradient
-        // g7 = dL/dF: the diffuse part of dL/dC, the deferred MLP G (Eq. 4)
-        // backward (hidden unit h per lane) and an optional dL/dF from
-        // losses on F itself.
-        float g7[7];
-        {
-            float x[NIN];
-            mlp_input<NIN>(Fs + ray * 7, d, x);
-            const MlpAct act = group_mlp_fwd<NIN>(W, x, h);
-            const float dG[3] = {dc0, dc1, dc2};
-            g7[0] = dc0;
-            g7[1] = dc1;
-            g7[2] = dc2;
-            g7[3] = g7[4] = g7[5] = g7[6] = 0.0f;
-            group_mlp_bwd<NIN>(W, x, h, act, dG, sW, g7);
-            if (dF) {
-#pragma unroll
-                for (int c = 0; c < 7; ++c) g7[c] += dF[ray * 7 + c];
-            }
-        }
-        const float gT = dc0 * rp.bg0 + dc1 * rp.bg1 + dc2 * rp.bg2;
+        const float4 ga = *reinterpret_cast<const float4*>(G8 + ray * 8);
+        const float4 gb = *reinterpret_cast<const float4*>(G8 + ray * 8 + 4);
+        const float g7[7] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z};
+        const float gT = gb.w;
 
         // Pass 1: per-batch totals of w (g7 . v); batch b lives in lane b % 16
         // of register slot b / 16.
@@ -395,55 +372,35 @@ __global__ __launch_bounds__(kBlock, NIN == 10 ? 4 : 1) void k_march_bwd(SceneDe
             return done >= ne;
         });
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < MlpLayout<NIN>::SIZE; i += kBlock) {
-        const float v = sW[i];
-        if (v != 0.0f) unsafeAtomicAdd(gmlp + i, v);
-    }
-}
-
-template <class S, bool kSoft>
-static void launch_bwd_nin(const SceneDev& sc, const RayParams& rp, const float* o, const float* d, int64_t n,
-                           int64_t chunk, dim3 grid, const float* F, const float* T, const int32_t* n_eval,
-                           const float* batch_wv, const float* dC, const float* dF, float* gV, float* gxy, float* gxz,
-                           float* gyz, float* gmlp, float* gocc, hipStream_t s) {
-    if (sc.mlp_in == 34)
-        hipLaunchKernelGGL((k_march_bwd<S, kSoft, 34>), grid, dim3(kBlock), 0, s, sc, rp, o, d, n, chunk, F, T, n_eval,
-                           batch_wv, dC, dF, gV, gxy, gxz, gyz, gmlp, gocc);
-    else
-        hipLaunchKernelGGL((k_march_bwd<S, kSoft, 10>), grid, dim3(kBlock), 0, s, sc, rp, o, d, n, chunk, F, T, n_eval,
-                           batch_wv, dC, dF, gV, gxy, gxz, gyz, gmlp, gocc);
 }
 
 hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
-                            int64_t n, const float* F, const float* T, const int32_t* n_eval, const float* batch_wv,
-                            const float* dC, const float* dF, float* gV, float* gxy, float* gxz, float* gyz,
-                            float* gmlp, float* gocc, hipStream_t s) {
-    // Persistent blocks, each owning a contiguous chunk of rays, so the MLP
-    // weight gradients are reduced in LDS over many rays before one set of
-    // global atomics per block.
+                            int64_t n, const float* T, const int32_t* n_eval, const float* batch_wv, const float* G8,
+                            float* gV, float* gxy, float* gxz, float* gyz, float* gocc, hipStream_t s) {
+    // Persistent blocks, each owning a contiguous chunk of rays that it walks
+    // longest-first.
     const int64_t max_blocks = 4096;
     int64_t nb = (n + kGroupsPerBlock - 1) / kGroupsPerBlock;
     if (nb > max_blocks) nb = max_blocks;
     int64_t chunk = (n + nb - 1) / nb;
     chunk = (chunk + kGroupsPerBlock - 1) / kGroupsPerBlock * kGroupsPerBlock;
     nb = (n + chunk - 1) / chunk;
-    const dim3 grid((unsigned)nb);
+    const dim3 grid((unsigned)nb), block(kBlock);
     const bool soft = rp.occ_inv_eps > 0.0f;
     if (bf16) {
         if (soft)
-            launch_bwd_nin<BF16Store, true>(sc, rp, o, d, n, chunk, grid, F, T, n_eval, batch_wv, dC, dF, gV, gxy, gxz,
-                                            gyz, gmlp, gocc, s);
+            hipLaunchKernelGGL((k_march_bwd<BF16Store, true>), grid, block, 0, s, sc, rp, o, d, n, chunk, T, n_eval,
+                               batch_wv, G8, gV, gxy, gxz, gyz, gocc);
         else
-            launch_bwd_nin<BF16Store, false>(sc, rp, o, d, n, chunk, grid, F, T, n_eval, batch_wv, dC, dF, gV, gxy, gxz,
-                                             gyz, gmlp, gocc, s);
+            hipLaunchKernelGGL((k_march_bwd<BF16Store, false>), grid, block, 0, s, sc, rp, o, d, n, chunk, T, n_eval,
+                               batch_wv, G8, gV, gxy, gxz, gyz, gocc);
     } else {
         if (soft)
-            launch_bwd_nin<F32Store, true>(sc, rp, o, d, n, chunk, grid, F, T, n_eval, batch_wv, dC, dF, gV, gxy, gxz,
-                                           gyz, gmlp, gocc, s);
+            hipLaunchKernelGGL((k_march_bwd<F32Store, true>), grid, block, 0, s, sc, rp, o, d, n, chunk, T, n_eval,
+                               batch_wv, G8, gV, gxy, gxz, gyz, gocc);
         else
-            launch_bwd_nin<F32Store, false>(sc, rp, o, d, n, chunk, grid, F, T, n_eval, batch_wv, dC, dF, gV, gxy, gxz,
-                                            gyz, gmlp, gocc, s);
+            hipLaunchKernelGGL((k_march_bwd<F32Store, false>), grid, block, 0, s, sc, rp, o, d, n, chunk, T, n_eval,
+                               batch_wv, G8, gV, gxy, gxz, gyz, gocc);
     }
     return hipGetLastError();
 }

@@ -13,7 +13,6 @@
 //                  holds rows 4(l/16)..+3 of column l%16) is exactly the B
 //                  operand layout of the next, so no data moves between
 //                  layers.  Biases enter as the accumulator's initial value.
-#include "bwd_device.h"
 #include "omerf_launch.h"
 
 namespace omerf {
@@ -166,6 +165,232 @@ __global__ __launch_bounds__(kBlock) void k_mlp_bf16(const float* __restrict__ W
             C[r * 3 + 2] = f7[2] + (gate ? sigmoidf_fast(h[2]) : 0.0f) + t * rp.bg2;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Group-cooperative MLP (one ray per 16-lane group, hidden unit h of both
+// hidden layers in lane h) and its backward, used by the render's MLP
+// backward and by the view-smoothness loss.
+// ---------------------------------------------------------------------------
+struct MlpAct {
+    float z1, h1, z2, h2;  // this lane's hidden unit, both layers
+    float g[3];            // G (after the sigmoid), the same on every lane
+};
+
+template <int NIN>
+__device__ __forceinline__ MlpAct group_mlp_fwd(const float* W, const float* x, int h) {
+    using L = MlpLayout<NIN>;
+    MlpAct a;
+    a.z1 = W[L::B1 + h];
+#pragma unroll
+    for (int c = 0; c < NIN; ++c) a.z1 += W[L::W1 + h * NIN + c] * x[c];
+    a.h1 = fmaxf(a.z1, 0.0f);
+    a.z2 = W[L::B2 + h];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) a.z2 += W[L::W2 + h * 16 + j] * __shfl(a.h1, j, kGroup);
+    a.h2 = fmaxf(a.z2, 0.0f);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) a.g[r] = sigmoidf_fast(W[L::B3 + r] + g_sum(W[L::W3 + r * 16 + h] * a.h2));
+    return a;
+}
+
+// MLP parameter gradients accumulated over the rays a wave visits.  The
+// weight matrices are reduced on MFMA (v_mfma_f32_16x16x4_f32, A 16x4,
+// B 4x16): with the wave's four rays in its four groups, a per-lane value
+// of layer-2 pre-activation gradient dz2 is the A operand entry
+// A[h][g] (lane 16 g + h) and a per-lane activation h1 the B operand entry
+// B[g][j] (lane 16 g + j), so one instruction adds sum_g dz2_g h1_g^T over
+// the four rays to a 16x16 accumulator, lane l holding rows
+// 4 (l / 16) .. +3 of column l % 16.  W1 is reduced against the input
+// extended by a constant 1, in column slices of 16 (its column NIN is the
+// b1 gradient); b2 and b3 are per-lane sums.
+template <int NIN>
+struct MlpGradAcc {
+    static constexpr int kSlices = (NIN + 1 + 15) / 16;
+    f32x4 w1[kSlices];
+    f32x4 w2, w3;
+    float b2, b3;
+    __device__ void zero() {
+#pragma unroll
+        for (int s = 0; s < kSlices; ++s) w1[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+        w2 = w3 = f32x4{0.f, 0.f, 0.f, 0.f};
+        b2 = b3 = 0.0f;
+    }
+};
+
+// Entry 16 s + h of [x, 1] (0 past it), the lane's B operand of W1 slice s.
+template <int NIN>
+__device__ __forceinline__ float mlp_x_slice(const float* F7, const float* d3, int s, int h) {
+    const int k = 16 * s + h;
+    return k < NIN ? mlp_x_at<NIN>(F7, d3, k) : (k == NIN ? 1.0f : 0.0f);
+}
+
+// Backward of group_mlp_fwd for dL/dG = dG (the same on every lane of the
+// group; zero for a group without a ray, whose activations must be finite):
+// adds dL/dx[0..6] to dx7 (the same on every lane) and the parameter
+// gradients to acc.  xs[s] = mlp_x_slice(..., s, h).  All 64 lanes of the
+// wave execute it (MFMA).
+template <int NIN>
+__device__ __forceinline__ void wave_mlp_bwd(const float* W, const float* xs, int h, const MlpAct& a,
+                                             const float* dG, MlpGradAcc<NIN>& acc, float* dx7) {
+    using L = MlpLayout<NIN>;
+    float dz3[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) dz3[r] = dG[r] * a.g[r] * (1.0f - a.g[r]);
+    const float dh2 = W[L::W3 + h] * dz3[0] + W[L::W3 + 16 + h] * dz3[1] + W[L::W3 + 32 + h] * dz3[2];
+    const float dz2 = a.z2 > 0.0f ? dh2 : 0.0f;
+    float dh1 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) dh1 += W[L::W2 + j * 16 + h] * __shfl(dz2, j, kGroup);
+    const float dz1 = a.z1 > 0.0f ? dh1 : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) dx7[c] += g_sum(W[L::W1 + h * NIN + c] * dz1);
+    const float d3 = h == 0 ? dz3[0] : h == 1 ? dz3[1] : h == 2 ? dz3[2] : 0.0f;
+    acc.w2 = __builtin_amdgcn_mfma_f32_16x16x4f32(dz2, a.h1, acc.w2, 0, 0, 0);
+    acc.w3 = __builtin_amdgcn_mfma_f32_16x16x4f32(d3, a.h2, acc.w3, 0, 0, 0);
+#pragma unroll
+    for (int s = 0; s < MlpGradAcc<NIN>::kSlices; ++s)
+        acc.w1[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(dz1, xs[s], acc.w1[s], 0, 0, 0);
+    acc.b2 += dz2;
+    acc.b3 += d3;
+}
+
+// Adds a wave's accumulators to the block's LDS copy of the gradient
+// (SIZE floats, MlpLayout order).
+template <int NIN>
+__device__ __forceinline__ void mlp_grad_to_lds(const MlpGradAcc<NIN>& acc, int lane, float* sW) {
+    using L = MlpLayout<NIN>;
+    const int col = lane & 15, row0 = (lane >> 4) * 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = row0 + r;
+        atomicAdd(&sW[L::W2 + row * 16 + col], acc.w2[r]);
+        if (row < 3) atomicAdd(&sW[L::W3 + row * 16 + col], acc.w3[r]);
+#pragma unroll
+        for (int s = 0; s < MlpGradAcc<NIN>::kSlices; ++s) {
+            const int c = 16 * s + col;
+            if (c < NIN)
+                atomicAdd(&sW[L::W1 + row * NIN + c], acc.w1[s][r]);
+            else if (c == NIN)
+                atomicAdd(&sW[L::B1 + row], acc.w1[s][r]);
+        }
+    }
+    atomicAdd(&sW[L::B2 + col], acc.b2);
+    if (col < 3) atomicAdd(&sW[L::B3 + col], acc.b3);
+}
+
+// Adds the block's LDS gradient to gmlp (one float atomic per nonzero entry).
+template <int NIN>
+__device__ __forceinline__ void mlp_grad_flush(const float* sW, float* gmlp) {
+    for (int i = threadIdx.x; i < MlpLayout<NIN>::SIZE; i += blockDim.x) {
+        const float v = sW[i];
+        if (v != 0.0f) unsafeAtomicAdd(gmlp + i, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward of the deferred MLP of the render (Eq. 4), ahead of the backward
+// march.  C = F[0:3] + [n_eval > 0] G(F, d) + T c_bg gives, per ray,
+//
+//   G8 = [dL/dF (7), dL/dC . c_bg],
+//   dL/dF = dL/dC on the diffuse part + [n_eval > 0] dL/dx[0..6] of G
+//           + dL/dF of losses on F itself (dF, optional),
+//
+// which is all the march needs of the MLP, and the MLP parameter gradients.
+// One ray per 16-lane group; a wave walks quads of consecutive rays so that
+// its four groups feed the MFMA reduction together.  Large blocks (1024
+// threads; 512 for the 34-input MLP, whose encoded input needs more than 128
+// registers), each over a contiguous range of quads, reduce in LDS before
+// one set of global atomics per block.
+// ---------------------------------------------------------------------------
+template <int NIN>
+constexpr int mlp_bwd_block() { return NIN == 10 ? 1024 : 512; }
+
+template <int NIN>
+__global__ __launch_bounds__(mlp_bwd_block<NIN>()) void k_mlp_bwd(const float* __restrict__ W, RayParams rp,
+                                                          const float* __restrict__ F, const float* __restrict__ d_,
+                                                          const int32_t* __restrict__ n_eval,
+                                                          const float* __restrict__ dC, const float* __restrict__ dF,
+                                                          int64_t n, int64_t quads_per_block, float* __restrict__ G8,
+                                                          float* __restrict__ gmlp) {
+    constexpr int kThreads = mlp_bwd_block<NIN>();
+    __shared__ float sW[MlpLayout<NIN>::SIZE];
+    for (int i = threadIdx.x; i < MlpLayout<NIN>::SIZE; i += kThreads) sW[i] = 0.0f;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, gl = lane & (kGroup - 1), g = lane >> 4;
+    const int64_t nq = (n + 3) / 4;
+    const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * quads_per_block;
+    const int64_t q1 = min(nq, q0 + quads_per_block);
+    MlpGradAcc<NIN> acc;
+    acc.zero();
+    for (int64_t q = q0 + (threadIdx.x >> 6); q < q1; q += kThreads / 64) {
+        const int64_t ray = q * 4 + g;
+        const bool in = ray < n;
+        const bool live = in && n_eval[ray] > 0;  // G gated off without samples
+        float f7[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, d3[3] = {0.f, 0.f, 0.f}, dc[3] = {0.f, 0.f, 0.f};
+        if (in) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dc[c] = dC[ray * 3 + c];
+        }
+        if (live) {
+#pragma unroll
+            for (int c = 0; c < 7; ++c) f7[c] = F[ray * 7 + c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) d3[c] = d_[ray * 3 + c];
+        }
+        // The weights are re-read (L1 hits) in every iteration instead of
+        // being hoisted into registers for the whole loop, which would
+        // leave too few registers for the large blocks.
+        const float* Wq = W;
+        asm volatile("" : "+s"(Wq));
+        float x[NIN];
+        mlp_input<NIN>(f7, make_float3(d3[0], d3[1], d3[2]), x);
+        const MlpAct a = group_mlp_fwd<NIN>(Wq, x, gl);
+        float xs[MlpGradAcc<NIN>::kSlices];
+#pragma unroll
+        for (int s = 0; s < MlpGradAcc<NIN>::kSlices; ++s) xs[s] = mlp_x_slice<NIN>(f7, d3, s, gl);
+        const float dG[3] = {live ? dc[0] : 0.0f, live ? dc[1] : 0.0f, live ? dc[2] : 0.0f};
+        float g8[8] = {dc[0], dc[1], dc[2], 0.f, 0.f, 0.f, 0.f, dc[0] * rp.bg0 + dc[1] * rp.bg1 + dc[2] * rp.bg2};
+        wave_mlp_bwd<NIN>(Wq, xs, gl, a, dG, acc, g8);
+        if (in && gl < 8) {
+            float v = g8[0];
+#pragma unroll
+            for (int c = 1; c < 8; ++c)
+                if (gl == c) v = g8[c];
+            if (dF && gl < 7) v += dF[ray * 7 + gl];
+            G8[ray * 8 + gl] = v;
+        }
+    }
+    mlp_grad_to_lds<NIN>(acc, lane, sW);
+    __syncthreads();
+    mlp_grad_flush<NIN>(sW, gmlp);
+}
+
+template <int NIN>
+static void launch_mlp_bwd_nin(const float* W, const RayParams& rp, const float* F, const float* d,
+                               const int32_t* n_eval, const float* dC, const float* dF, int64_t n, float* G8,
+                               float* gmlp, hipStream_t s) {
+    // At least 8 quads per wave; at most 512 blocks, whose LDS sums then
+    // cost at most 512 global atomics per MLP parameter.
+    const int64_t nq = (n + 3) / 4;
+    const int64_t waves = mlp_bwd_block<NIN>() / 64;
+    int64_t qpb = (nq + 511) / 512;
+    if (qpb < 8 * waves) qpb = 8 * waves;
+    qpb = (qpb + waves - 1) / waves * waves;
+    const int64_t nb = (nq + qpb - 1) / qpb;
+    hipLaunchKernelGGL(k_mlp_bwd<NIN>, dim3((unsigned)nb), dim3(mlp_bwd_block<NIN>()), 0, s, W, rp, F, d, n_eval, dC,
+                       dF, n, qpb, G8, gmlp);
+}
+
+hipError_t launch_mlp_bwd(const float* W, int mlp_in, const RayParams& rp, const float* F, const float* d,
+                          const int32_t* n_eval, const float* dC, const float* dF, int64_t n, float* G8, float* gmlp,
+                          hipStream_t s) {
+    if (n == 0) return hipGetLastError();
+    if (mlp_in == 34)
+        launch_mlp_bwd_nin<34>(W, rp, F, d, n_eval, dC, dF, n, G8, gmlp, s);
+    else
+        launch_mlp_bwd_nin<10>(W, rp, F, d, n_eval, dC, dF, n, G8, gmlp, s);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -338,9 +563,10 @@ hipError_t launch_occ_loss(const float* occ, int64_t cells, float weight, float*
 // cosine similarity.  One (ray, perturbation) pair per 16-lane group, one
 // hidden unit per lane: G at d and at s, and the backward of both
 // evaluations (dL/dG = +g at s, -g at d; the MLP backward is linear in
-// dL/dG) into LDS-reduced MLP gradients; dL/dF is added to dF with float32
-// atomics (the P pairs of a ray land in different groups).  The loss value
-// is a float32 sum (per group, then one float32 atomic per group).
+// dL/dG), whose parameter gradients are reduced on MFMA per wave and in LDS
+// per block (MlpGradAcc); dL/dF is added to dF with float32 atomics (the P
+// pairs of a ray land in different groups).  The loss value is a float32
+// sum (per group, then one float32 atomic per group).
 // ---------------------------------------------------------------------------
 __global__ void k_zero_f32(float* p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0.0f;
@@ -352,55 +578,65 @@ __global__ __launch_bounds__(kBlock) void k_smooth(const float* __restrict__ W, 
                                                    const float* __restrict__ perturb, int P, float weight,
                                                    float* __restrict__ loss, float* __restrict__ dF,
                                                    float* __restrict__ gmlp) {
-    __shared__ float sW[kMlpMaxSize];
-    for (int i = threadIdx.x; i < kMlpMaxSize; i += kBlock) sW[i] = 0.0f;
+    __shared__ float sW[MlpLayout<NIN>::SIZE];
+    for (int i = threadIdx.x; i < MlpLayout<NIN>::SIZE; i += kBlock) sW[i] = 0.0f;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kGroup - 1);
-    const int gid = threadIdx.x / kGroup;
+    const int g = lane >> 4;
+    // chunk is a multiple of 16 items, so a block's range is whole quads;
+    // each wave walks quads (4 items, one per group) in step.
     const int64_t start = (int64_t)xcd_block(blockIdx.x, gridDim.x) * chunk;
     const int64_t stop = min(items, start + chunk);
+    MlpGradAcc<NIN> macc;
+    macc.zero();
     float acc = 0.0f;
-    for (int64_t it = start + gid; it < stop; it += kGroupsPerBlock) {
-        const int64_t ray = it / P;
-        float f7[7];
+    for (int64_t it0 = start + 4 * (threadIdx.x >> 6); it0 < stop; it0 += kBlock / kGroup) {
+        const int64_t it = it0 + g;
+        const bool live = it < stop;
+        const int64_t ray = live ? it / P : 0;
+        float f7[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, d3[3] = {0.f, 0.f, 0.f}, s3[3] = {0.f, 0.f, 0.f};
+        if (live) {
 #pragma unroll
-        for (int c = 0; c < 7; ++c) f7[c] = F[ray * 7 + c];
-        const float3 d = make_float3(d_[ray * 3 + 0], d_[ray * 3 + 1], d_[ray * 3 + 2]);
-        const float* dp = perturb + (size_t)it * 3;
-        const float3 sv = make_float3(d.x + dp[0], d.y + dp[1], d.z + dp[2]);
-        const float dn = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
-        const float sn = sqrtf(sv.x * sv.x + sv.y * sv.y + sv.z * sv.z);
-        const float cosv = (d.x * sv.x + d.y * sv.y + d.z * sv.z) / (dn * sn);
+            for (int c = 0; c < 7; ++c) f7[c] = F[ray * 7 + c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                d3[c] = d_[ray * 3 + c];
+                s3[c] = d3[c] + perturb[it * 3 + c];
+            }
+        }
+        const float dn = sqrtf(d3[0] * d3[0] + d3[1] * d3[1] + d3[2] * d3[2]);
+        const float sn = sqrtf(s3[0] * s3[0] + s3[1] * s3[1] + s3[2] * s3[2]);
+        const float cosv = live ? (d3[0] * s3[0] + d3[1] * s3[1] + d3[2] * s3[2]) / (dn * sn) : 0.0f;
         float g7[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         MlpAct ad, as;
-        float gs[3], gd[3];
         {
             float x[NIN];
-            mlp_input<NIN>(f7, d, x);
+            mlp_input<NIN>(f7, make_float3(d3[0], d3[1], d3[2]), x);
             ad = group_mlp_fwd<NIN>(W, x, gl);
         }
         {
             float x[NIN];
-            mlp_input<NIN>(f7, sv, x);
+            mlp_input<NIN>(f7, make_float3(s3[0], s3[1], s3[2]), x);
             as = group_mlp_fwd<NIN>(W, x, gl);
-            float e2 = 0.0f;
+        }
+        float gs[3], gd[3], e2 = 0.0f;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float diff = as.g[c] - ad.g[c];
-                e2 += diff * diff;
-                gs[c] = 2.0f * weight * cosv * diff;
-                gd[c] = -gs[c];
-            }
-            acc += weight * cosv * e2;
-            group_mlp_bwd<NIN>(W, x, gl, as, gs, sW, g7);
+        for (int c = 0; c < 3; ++c) {
+            const float diff = as.g[c] - ad.g[c];
+            e2 += diff * diff;
+            gs[c] = 2.0f * weight * cosv * diff;
+            gd[c] = -gs[c];
         }
-        {
-            float x[NIN];
-            mlp_input<NIN>(f7, d, x);
-            group_mlp_bwd<NIN>(W, x, gl, ad, gd, sW, g7);
-        }
-        if (dF && gl < 7) {
+        acc += weight * cosv * e2;
+        float xs[MlpGradAcc<NIN>::kSlices];
+#pragma unroll
+        for (int s = 0; s < MlpGradAcc<NIN>::kSlices; ++s) xs[s] = mlp_x_slice<NIN>(f7, s3, s, gl);
+        wave_mlp_bwd<NIN>(W, xs, gl, as, gs, macc, g7);
+#pragma unroll
+        for (int s = 0; s < MlpGradAcc<NIN>::kSlices; ++s) xs[s] = mlp_x_slice<NIN>(f7, d3, s, gl);
+        wave_mlp_bwd<NIN>(W, xs, gl, ad, gd, macc, g7);
+        if (dF && live && gl < 7) {
             float v = g7[0];
 #pragma unroll
             for (int c = 1; c < 7; ++c)
@@ -409,12 +645,10 @@ __global__ __launch_bounds__(kBlock) void k_smooth(const float* __restrict__ W, 
         }
     }
     if (loss && gl == 0 && acc != 0.0f) unsafeAtomicAdd(loss, acc);
-    __syncthreads();
     if (gmlp) {
-        for (int i = threadIdx.x; i < MlpLayout<NIN>::SIZE; i += kBlock) {
-            const float v = sW[i];
-            if (v != 0.0f) unsafeAtomicAdd(gmlp + i, v);
-        }
+        mlp_grad_to_lds<NIN>(macc, lane, sW);
+        __syncthreads();
+        mlp_grad_flush<NIN>(sW, gmlp);
     }
 }
 

@@ -140,7 +140,8 @@ def test_fused_training_step_validation(L):
     p = _params()
     n = 1000
     ws = L.om_render_fwd_bwd_l2_workspace_size(n, ctypes.byref(p))
-    assert ws == (n * 12 + 255) // 256 * 256 + n * 4 * 7 * 4  # dL/dC, then 4 batch slots x 7 floats per ray
+    # dL/dC, the backward's per-ray hand-over (8 floats), then 4 batch slots x 7 floats per ray
+    assert ws == (n * 12 + 255) // 256 * 256 + (n * 32 + 255) // 256 * 256 + n * 4 * 7 * 4
     assert L.om_render_fwd_bwd_l2_workspace_size(-1, ctypes.byref(p)) == -1
     assert L.om_render_fwd_bwd_l2_workspace_size(n, ctypes.byref(_params(n_max=0))) == -1
     rc, h = _create(L, _desc())
@@ -153,6 +154,35 @@ def test_fused_training_step_validation(L):
     bad_g = _lib.OmGrads(FAKE, 0, FAKE, FAKE, FAKE, 0)
     assert step(FAKE, ctypes.byref(out), FAKE, ws, None, ctypes.byref(bad_g), None) == _lib.OM_ERR_INVALID
     assert "workspace" in L.om_last_error().decode() or "gradient" in L.om_last_error().decode()
+    L.om_scene_destroy(h)
+
+
+def test_backward_workspace_validation(L):
+    """Workspace query and argument checks of om_render_backward_ws (no
+    device work): 32 bytes per ray rounded up to 256; a workspace that is
+    too small or misaligned is refused before anything is launched."""
+    assert L.om_render_backward_workspace_size(0) == 0
+    assert L.om_render_backward_workspace_size(1) == 256
+    assert L.om_render_backward_workspace_size(1000) == 32000  # 125 x 256
+    assert L.om_render_backward_workspace_size(1001) == 32256
+    assert L.om_render_backward_workspace_size(-1) == -1
+    n = 1000
+    ws = L.om_render_backward_workspace_size(n)
+    rc, h = _create(L, _desc())
+    out = _lib.OmFwdOut(FAKE, FAKE, FAKE, FAKE, FAKE, 0)
+    g = _lib.OmGrads(FAKE, FAKE, FAKE, FAKE, FAKE, 0)
+    bwd = lambda *a: L.om_render_backward_ws(h, FAKE, FAKE, n, ctypes.byref(_params()), ctypes.byref(out),  # noqa: E731
+                                             FAKE, None, *a, ctypes.byref(g), None)
+    assert bwd(FAKE, ws - 1) == _lib.OM_ERR_INVALID
+    assert "workspace" in L.om_last_error().decode()
+    assert bwd(FAKE + 16, ws) == _lib.OM_ERR_INVALID
+    assert bwd(None, ws) == _lib.OM_ERR_INVALID
+    bad_g = _lib.OmGrads(FAKE, 0, FAKE, FAKE, FAKE, 0)
+    assert L.om_render_backward_ws(h, FAKE, FAKE, n, ctypes.byref(_params()), ctypes.byref(out), FAKE, None, FAKE,
+                                   ws, ctypes.byref(bad_g), None) == _lib.OM_ERR_INVALID
+    # n = 0 is a no-op that needs no workspace
+    assert L.om_render_backward_ws(h, None, None, 0, ctypes.byref(_params()), ctypes.byref(out), None, None, None, 0,
+                                   ctypes.byref(g), None) == 0
     L.om_scene_destroy(h)
 
 
