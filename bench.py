@@ -169,8 +169,13 @@ def hbm_roofline(kernel, workload, kernel_ms, min_bytes, l1_bytes=None, l1_peak=
     move at least) per launch time against the 8 TB/s peak, the measured
     DRAM bytes (rocprofv3, committed summary for this kernel source) beside
     it, and optionally the gather ceiling (algorithmic bytes returned to
-    registers against the calibrated cache-resident rate)."""
-    traffic = measured_traffic(kernel, workload)
+    registers against the calibrated cache-resident rate).  `kernel` may be
+    a tuple of kernels launched back to back by one timed call (the
+    backward's MLP stage and march): their DRAM bytes add up."""
+    kernels = kernel if isinstance(kernel, tuple) else (kernel,)
+    parts = [measured_traffic(k, workload) for k in kernels]
+    traffic = None if any(p is None for p in parts) else sum(parts)
+    kernel = " + ".join(kernels)
     s = kernel_ms * 1e-3
     r = {"bound": "hbm", "achieved": round(min_bytes / s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
          "frac": round(min_bytes / s / 1e9 / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
@@ -364,7 +369,8 @@ def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, kw, a, occ_eps=0.0):
     dC = torch.empty_like(out2["C"])
     fwd = lambda: om.render_into(scene, o2g, d2g, out2, **kw)  # noqa: E731
     lossg = lambda: om.l2_loss_grad(out2["C"], target, dL_dC=dC, with_loss=False)  # noqa: E731
-    bwd = lambda: om.render_backward(scene, o2g, d2g, out2, dC, grads, **kw)  # noqa: E731
+    ws = torch.empty((om.backward_workspace_size(n2),), dtype=torch.uint8, device=dev)
+    bwd = lambda: om.render_backward(scene, o2g, d2g, out2, dC, grads, workspace=ws, **kw)  # noqa: E731
     steps = max(3, a.steps // 2)
     tot, (f_ms, l_ms, b_ms) = time_stages([fwd, lossg, bwd], steps, a.warmup, torch)
     ms = tot / steps
@@ -377,7 +383,7 @@ def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, kw, a, occ_eps=0.0):
            "bwd_Msamples_per_s": round(s2 / (b_ms * 1e-3) / 1e6, 1)}
     if occ_eps == 0:
         res["roofline"] = _train_rooflines(om, scene, o2g, d2g, out2, kw, f_ms, b_ms, "k_march_fwd_f32q<true>",
-                                           "k_march_bwd<F32Store>", "train-2^18", 32)
+                                           ("k_mlp_bwd<10>", "k_march_bwd<F32Store>"), "train-2^18", 32)
     return res
 
 
@@ -412,7 +418,8 @@ def form_fp32_enc_smooth(om, scenegen, torch, t, kw, a):
     lossg = lambda: om.l2_loss_grad(out2["C"], target, dL_dC=dC, with_loss=False)  # noqa: E731
     smooth = lambda: om.smooth_loss(scene, Fs, ds, pert, w, dL_dF=dFs, grad_mlp=grads["mlp"],  # noqa: E731
                                     with_loss=False)
-    bwd = lambda: om.render_backward(scene, o2g, d2g, out2, dC, grads, dL_dF=dF, **kw)  # noqa: E731
+    ws = torch.empty((om.backward_workspace_size(n2),), dtype=torch.uint8, device=dev)
+    bwd = lambda: om.render_backward(scene, o2g, d2g, out2, dC, grads, dL_dF=dF, workspace=ws, **kw)  # noqa: E731
     steps = max(3, a.steps // 2)
     tot, (f_ms, l_ms, s_ms, b_ms) = time_stages([fwd, lossg, smooth, bwd], steps, a.warmup, torch)
     ms = tot / steps
@@ -490,7 +497,8 @@ def form_towers(om, scenegen, torch, a):
     dC = torch.empty_like(out["C"])
     fwd = lambda: om.render_into(scene_b, og, dg, out, **kw)  # noqa: E731
     lossg = lambda: om.l2_loss_grad(out["C"], target, dL_dC=dC, with_loss=False)  # noqa: E731
-    bwd = lambda: om.render_backward(scene_b, og, dg, out, dC, grads, **kw)  # noqa: E731
+    ws = torch.empty((om.backward_workspace_size(n),), dtype=torch.uint8, device=dev)
+    bwd = lambda: om.render_backward(scene_b, og, dg, out, dC, grads, workspace=ws, **kw)  # noqa: E731
     steps = max(3, a.steps // 4)
     tot, (f_ms, l_ms, b_ms) = time_stages([fwd, lossg, bwd], steps, 1, torch)
     ms = tot / steps
@@ -503,7 +511,7 @@ def form_towers(om, scenegen, torch, a):
             "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 3),
             "fwd_ms": round(f_ms, 3), "bwd_ms": round(b_ms, 3), "bwd_Msamples_per_s": round(se / (b_ms * 1e-3) / 1e6, 1),
             "roofline": _train_rooflines(om, scene_b, og, dg, out, kw, f_ms, b_ms,
-                                         "k_march_fwd_lane<GatherBF16,kBW>", "k_march_bwd<BF16Store>",
+                                         "k_march_fwd_lane<GatherBF16,kBW>", ("k_mlp_bwd<10>", "k_march_bwd<BF16Store>"),
                                          "towers-2^20", 16),
             "samples_per_ray": round(float(npl.mean()), 1), "max_samples": int(npl.max()),
             "n_placed_hist_bins32": hist.tolist(), "n_eval_hist_bins32": hist_eval.tolist()}

@@ -16,7 +16,7 @@ writes into
 Subcommands (``DIR`` = a rocprofv3 ``-d`` output directory, searched
 recursively for ``*_counter_collection.csv`` / ``*_kernel_stats.csv``):
 
-    python bench_counters.py traffic --fetch DIR --write DIR --workload W KEY=PATTERN ...
+    python bench_counters.py traffic --fetch DIR --write DIR --workload W [--slice A:B] KEY=PATTERN ...
     python bench_counters.py counters --dir DIR --workload W KEY=PATTERN ...
     python bench_counters.py stats --dir DIR
 
@@ -119,10 +119,13 @@ def cmd_traffic(a):
     print(f"calibration: 1 GiB copy FETCH_SIZE {cf[0]:.1f} KiB (x {fs:.4f}), WRITE_SIZE {cw[0]:.1f} KiB (x {ws:.4f})")
     print("| kernel | workload | dispatches | FETCH_SIZE KiB (median) | WRITE_SIZE KiB (median) | HBM bytes per launch |")
     print("|---|---|---|---|---|---|")
+    sl = slice(*[int(x) if x else None for x in a.slice.split(":")]) if a.slice else slice(None)
     for spec in a.kernels:
         key, pat = spec.split("=", 1)
         name, fv = _match(fetch, pat)
         _, wv = _match(write, pat)
+        fv = {"FETCH_SIZE": fv["FETCH_SIZE"][sl]}
+        wv = {"WRITE_SIZE": wv["WRITE_SIZE"][sl]}
         f, w = _median(fv["FETCH_SIZE"]), _median(wv["WRITE_SIZE"])
         hbm = int(round(f * 1024.0 * fs + w * 1024.0 * ws))
         fam = family_of(key)
@@ -177,6 +180,8 @@ def main():
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
     t.add_argument("--workload", required=True)
+    t.add_argument("--slice", default="", help="START:STOP of each kernel's dispatches (in dispatch order), "
+                                               "when one run holds several workloads of one kernel")
     t.add_argument("kernels", nargs="+")
     c = sub.add_parser("counters")
     c.add_argument("--dir", required=True)
