@@ -10,6 +10,8 @@ differences (float64 loss reduction on the GPU) within
 entries stratified over the five tensors and over magnitude, plus 4 entries
 with zero gradient.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -77,6 +79,50 @@ def test_backward_tiny_vs_oracle(tiny_train):
         res, grads = _gpu_vjp(scene, t, og, dg, up, 64, batch_wv=bw)
         _loss_check(res, tg, ref_loss, f"tiny batch_wv={bw}")
         check(grads, ref, scale, f"tiny batch_wv={bw}")
+
+
+def _backward_ex_direct(scene, t, og, dg, res, up32, n_max):
+    """om_render_backward_ex called through the C ABI: the entry point that
+    takes its per-ray hand-over from the stream-ordered allocator."""
+    from paper_2404_09531_amd import _lib
+    dC = torch.from_numpy(np.ascontiguousarray(up32, np.float32)).to(og.device)
+    grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp")}
+    fo = _lib.OmFwdOut(res["C"].data_ptr(), res["T"].data_ptr(), res["F"].data_ptr(), res["n_placed"].data_ptr(),
+                       res["n_eval"].data_ptr(), 0)
+    p = om._params(n_max, om.DELTA, 0.0, BG, -1, 0.0)
+    g = om._grads(scene, grads)
+    rc = _lib.lib().om_render_backward_ex(scene.handle, og.data_ptr(), dg.data_ptr(), og.shape[0], ctypes.byref(p),
+                                          ctypes.byref(fo), dC.data_ptr(), None, ctypes.byref(g),
+                                          _lib.stream_of(og))
+    assert rc == 0, _lib.lib().om_last_error().decode()
+    torch.cuda.synchronize()
+    return {k: v.double().cpu().numpy() for k, v in grads.items()}
+
+
+@pytest.mark.parametrize("n", [1, 3, 6, 1037])
+def test_backward_ragged_counts_vs_oracle(tiny_train, n):
+    """Ray counts that leave a partial quad of rays in the MLP backward's
+    last step, with every fourth ray turned upwards out of the box
+    (n_eval = 0: no sample and no MLP term): gradients against the oracle,
+    through the workspace entry point (the binding) and through
+    om_render_backward_ex, which allocates its own hand-over."""
+    sc, scene, t, _, _, _ = tiny_train
+    log(f"test_backward_ragged_counts_vs_oracle: {n} rays")
+    o, d = scenegen.oblique_rays(n, seed=11)
+    away = np.arange(n) % 4 == 1
+    d = d.copy()
+    d[away, 2] = -d[away, 2]  # from z = 1 upwards: never enters the box
+    g = np.random.Generator(np.random.PCG64(12))
+    target = g.uniform(0.0, 1.0, (n, 3)).astype(np.float32)
+    prm = oracle.RenderParams(n_max=64, c_bg=BG)
+    up, _ = oracle_upstream(sc, o, d, prm, target)
+    ref, scale = oracle_reference(sc, o, d, prm, up)
+    og, dg = rays_to(o, d)
+    res, grads = _gpu_vjp(scene, t, og, dg, up, 64)
+    ne = res["n_eval"].cpu().numpy()
+    assert (ne[away] == 0).all() and (ne[~away] > 0).any()
+    check(grads, ref, scale, f"ragged n={n}")
+    check(_backward_ex_direct(scene, t, og, dg, res, up, 64), ref, scale, f"ragged n={n}, allocating entry point")
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
