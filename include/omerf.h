@@ -286,16 +286,31 @@ int om_deferred_mlp(const om_scene* scene, const float* d, int64_t n, const om_p
 /*
  * Backward of om_render for a per-ray colour loss (derived from Eq. 1-4).
  * saved: the om_fwd_out written by om_render for the same scene, rays and
- * parameters (C is not read; batch_wv is used when non-NULL).  dL_dC: device float32 [n][3].  Gradients are
- * ADDED with float32 atomics into g (grid, planes, MLP; no ray gradient);
- * per-sample features are recomputed, not stored.  Summation order of the
- * atomics is not deterministic.  The MLP part is differentiated in float32
- * regardless of p->mlp_bf16.  OM_U8 and sparse-block scenes are render
- * only: the backward and the fused step return OM_ERR_UNSUPPORTED for them.
+ * parameters (C is not read; batch_wv is used when non-NULL).  dL_dC:
+ * device float32 [n][3].  Gradients are ADDED with float32 atomics into g
+ * (grid, planes, MLP; no ray gradient); per-sample features are
+ * recomputed, not stored.  Summation order of the atomics is not
+ * deterministic.  The MLP part is differentiated in float32 regardless of
+ * p->mlp_bf16.  OM_U8 and sparse-block scenes are render only: the
+ * backward and the fused step return OM_ERR_UNSUPPORTED for them.
+ *
+ * The backward runs in two stages: the deferred MLP's backward (derivative
+ * of Eq. 4) turns dL_dC (and dL_dF of om_render_backward_ex) into one total
+ * dL/dF per ray and the MLP parameter gradients; the march backward
+ * (derivative of Eq. 1-3) then distributes that dL/dF over the samples.
+ * The per-ray hand-over between them (8 floats: dL/dF and dL/dC . c_bg)
+ * lives in `workspace`: caller-owned device memory of at least
+ * om_render_backward_workspace_size(n) bytes, 256-byte aligned, overwritten
+ * (OM_ERR_INVALID if it is smaller or misaligned).  The call allocates
+ * nothing.
  */
 int om_render_backward(const om_scene* scene, const float* o, const float* d, int64_t n,
                        const om_params* p, const om_fwd_out* saved, const float* dL_dC,
-                       const om_grads* g, void* stream);
+                       void* workspace, int64_t workspace_bytes, const om_grads* g, void* stream);
+
+/* Workspace bytes om_render_backward(_ex) needs for n rays (32 n rounded up
+ * to a multiple of 256), or -1 (with om_last_error set) if n < 0. */
+int64_t om_render_backward_workspace_size(int64_t n);
 
 /*
  * om_render_backward with an extra upstream gradient on the composited
@@ -303,34 +318,13 @@ int om_render_backward(const om_scene* scene, const float* o, const float* d, in
  * of a loss term that reads F directly (the view-smoothness loss of
  * om_smooth_loss), added to what flows back from dL_dC before the march
  * backward distributes it over the samples.  om_render_backward(...) is
- * om_render_backward_ex(..., dL_dC, NULL, g, stream).
+ * om_render_backward_ex(..., dL_dC, NULL, workspace, workspace_bytes, g,
+ * stream).
  */
 int om_render_backward_ex(const om_scene* scene, const float* o, const float* d, int64_t n,
                           const om_params* p, const om_fwd_out* saved, const float* dL_dC,
-                          const float* dL_dF, const om_grads* g, void* stream);
-
-/*
- * om_render_backward_ex over caller-owned memory.  The backward runs in two
- * stages: the deferred MLP's backward (derivative of Eq. 4) first turns
- * dL_dC and dL_dF into one total dL/dF per ray and the MLP parameter
- * gradients, then the march backward (derivative of Eq. 1-3) distributes
- * that dL/dF over the samples.  The per-ray hand-over (8 floats: dL/dF and
- * dL/dC . c_bg) lives in `workspace`: device memory of at least
- * om_render_backward_workspace_size(n) bytes, 256-byte aligned,
- * overwritten; OM_ERR_INVALID if it is smaller or misaligned.
- * om_render_backward and om_render_backward_ex take the same memory from
- * HIP's stream-ordered allocator on `stream` (hipMallocAsync, then
- * hipFreeAsync after the launches) on every call.  Results are the same
- * as om_render_backward_ex's.
- */
-int om_render_backward_ws(const om_scene* scene, const float* o, const float* d, int64_t n,
-                          const om_params* p, const om_fwd_out* saved, const float* dL_dC,
                           const float* dL_dF, void* workspace, int64_t workspace_bytes,
                           const om_grads* g, void* stream);
-
-/* Workspace bytes om_render_backward_ws needs for n rays (32 n rounded up to
- * a multiple of 256), or -1 (with om_last_error set) if n < 0. */
-int64_t om_render_backward_workspace_size(int64_t n);
 
 /*
  * View-smoothness regulariser of Sec. 4.2 (Eq. 9-10) on the deferred MLP G
@@ -379,7 +373,7 @@ int om_l2_loss_grad(const float* C, const float* target, int64_t n, float* dL_dC
  * so that the backward replays the samples once.  target: device float32
  * [n][3].  workspace: caller-owned device memory of at least
  * om_render_fwd_bwd_l2_workspace_size(n, p) bytes, 256-byte aligned; it
- * holds dL/dC, the backward's per-ray hand-over (om_render_backward_ws)
+ * holds dL/dC, the backward's per-ray hand-over (om_render_backward)
  * and the per-batch sums (out->batch_wv is ignored).
  * loss: optional device float[1] receiving the loss as om_l2_loss_grad
  * computes it (overwritten), or NULL.  Equivalent to om_render +

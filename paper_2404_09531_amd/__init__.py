@@ -334,8 +334,9 @@ def render_backward(scene: Scene, o, d, saved: Dict[str, torch.Tensor], dL_dC, g
     occ_eps > 0 an optional grads["occ"] [My, Mx, 2] receives dL/d(z_min, z_max).
     dL_dF (float32 [n, 7], optional) is an extra upstream gradient on the
     composited features, e.g. from smooth_loss.  `workspace`: optional
-    device uint8 tensor of at least backward_workspace_size(n) bytes
-    (om_render_backward_ws); allocated here when None."""
+    device uint8 tensor of at least backward_workspace_size(n) bytes (the
+    per-ray hand-over between the MLP backward and the march backward);
+    allocated here when None."""
     n = _rays(scene, o, d)
     _need(dL_dC, "dL_dC", torch.float32, (n, 3))
     if dL_dF is not None:
@@ -350,7 +351,7 @@ def render_backward(scene: Scene, o, d, saved: Dict[str, torch.Tensor], dL_dC, g
     if workspace is None:
         workspace = torch.empty((max(nbytes, 1),), dtype=torch.uint8, device=o.device)
     _need_workspace(workspace, nbytes, o.device)
-    _lib.check("om_render_backward_ws", _lib.lib().om_render_backward_ws(
+    _lib.check("om_render_backward_ex", _lib.lib().om_render_backward_ex(
         scene.handle, o.data_ptr(), d.data_ptr(), n, ctypes.byref(p), ctypes.byref(fo), dL_dC.data_ptr(),
         _lib.ptr(dL_dF), workspace.data_ptr(), workspace.numel(), ctypes.byref(g), _lib.stream_of(o)))
 

@@ -21,8 +21,7 @@ OM_MAX_SAMPLES = 1024
 EXPORTS = ("om_scene_create", "om_scene_update", "om_scene_destroy", "om_occupancy_mips_size",
            "om_build_occupancy_mips", "om_place_samples", "om_march",
            "om_deferred_mlp", "om_render",
-           "om_render_backward", "om_render_backward_ex", "om_render_backward_ws",
-           "om_render_backward_workspace_size", "om_smooth_loss", "om_render_fwd_bwd_l2", "om_render_fwd_bwd_l2_workspace_size",
+           "om_render_backward", "om_render_backward_ex", "om_render_backward_workspace_size", "om_smooth_loss", "om_render_fwd_bwd_l2", "om_render_fwd_bwd_l2_workspace_size",
            "om_render_fwd_bwd_l2_noalloc", "om_render_fwd_bwd_l2_noalloc_max_bytes",
            "om_occ_interval_loss", "om_feature_range", "om_quant_params", "om_quantize_u8",
            "om_sparse_grid_index", "om_sparse_grid_fill",
@@ -79,10 +78,8 @@ def lib() -> ctypes.CDLL:
         L.om_march.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(OmParams), POINTER(OmFwdOut), c_void_p]
         L.om_deferred_mlp.argtypes = [c_void_p, c_void_p, c_int64, POINTER(OmParams), POINTER(OmFwdOut), c_void_p]
         L.om_render_backward.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(OmParams),
-                                         POINTER(OmFwdOut), c_void_p, POINTER(OmGrads), c_void_p]
+                                         POINTER(OmFwdOut), c_void_p, c_void_p, c_int64, POINTER(OmGrads), c_void_p]
         L.om_render_backward_ex.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(OmParams),
-                                            POINTER(OmFwdOut), c_void_p, c_void_p, POINTER(OmGrads), c_void_p]
-        L.om_render_backward_ws.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(OmParams),
                                             POINTER(OmFwdOut), c_void_p, c_void_p, c_void_p, c_int64,
                                             POINTER(OmGrads), c_void_p]
         L.om_render_backward_workspace_size.argtypes = [c_int64]

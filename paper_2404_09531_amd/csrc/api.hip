@@ -363,11 +363,6 @@ int om_render(const om_scene* scene, const float* o, const float* d, int64_t n, 
     return hip_status(e, "om_render (mlp)");
 }
 
-int om_render_backward(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
-                       const om_fwd_out* saved, const float* dL_dC, const om_grads* g, void* stream) {
-    return om_render_backward_ex(scene, o, d, n, p, saved, dL_dC, nullptr, g, stream);
-}
-
 int64_t om_render_backward_workspace_size(int64_t n) {
     if (n < 0) {
         fail(OM_ERR_INVALID, "n must be >= 0");
@@ -409,12 +404,19 @@ hipError_t backward_launch(const om_scene* scene, const RayParams& rp, const flo
 
 }  // namespace
 
-int om_render_backward_ws(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+int om_render_backward(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
+                       const om_fwd_out* saved, const float* dL_dC, void* workspace, int64_t workspace_bytes,
+                       const om_grads* g, void* stream) {
+    return om_render_backward_ex(scene, o, d, n, p, saved, dL_dC, nullptr, workspace, workspace_bytes, g, stream);
+}
+
+int om_render_backward_ex(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
                           const om_fwd_out* saved, const float* dL_dC, const float* dL_dF, void* workspace,
                           int64_t workspace_bytes, const om_grads* g, void* stream) {
     RayParams rp;
     int rc = check_backward(scene, o, d, n, p, saved, dL_dC, g, &rp);
-    if (rc != OM_OK || n == 0) return rc == OM_OK ? ok() : rc;
+    if (rc != OM_OK) return rc;
+    if (n == 0) return ok();
     const int64_t need = om_render_backward_workspace_size(n);
     if (!workspace || ((uintptr_t)workspace & 255u)) return fail(OM_ERR_INVALID, "workspace must be 256-byte aligned");
     if (workspace_bytes < need)
@@ -422,24 +424,7 @@ int om_render_backward_ws(const om_scene* scene, const float* o, const float* d,
                     (long long)need);
     const hipError_t e = backward_launch(scene, rp, o, d, n, saved->F, saved->T, saved->n_eval, saved->batch_wv, dL_dC,
                                          dL_dF, static_cast<float*>(workspace), g, (hipStream_t)stream);
-    return hip_status(e, "om_render_backward_ws");
-}
-
-int om_render_backward_ex(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
-                          const om_fwd_out* saved, const float* dL_dC, const float* dL_dF, const om_grads* g,
-                          void* stream) {
-    RayParams rp;
-    int rc = check_backward(scene, o, d, n, p, saved, dL_dC, g, &rp);
-    if (rc != OM_OK || n == 0) return rc == OM_OK ? ok() : rc;
-    const hipStream_t s = (hipStream_t)stream;
-    void* ws = nullptr;
-    hipError_t e = hipMallocAsync(&ws, (size_t)om_render_backward_workspace_size(n), s);
-    if (e != hipSuccess) return hip_status(e, "om_render_backward (hipMallocAsync)");
-    e = backward_launch(scene, rp, o, d, n, saved->F, saved->T, saved->n_eval, saved->batch_wv, dL_dC, dL_dF,
-                        static_cast<float*>(ws), g, s);
-    const hipError_t ef = hipFreeAsync(ws, s);
-    if (e != hipSuccess) return hip_status(e, "om_render_backward");
-    return hip_status(ef, "om_render_backward (hipFreeAsync)");
+    return hip_status(e, "om_render_backward");
 }
 
 int64_t om_render_fwd_bwd_l2_workspace_size(int64_t n, const om_params* p) {
@@ -723,6 +708,6 @@ const char* om_status_str(int status) {
     }
 }
 
-int om_version(void) { return 107; }
+int om_version(void) { return 108; }
 
 }  // extern "C"

@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol(L):
     assert names == set(_lib.EXPORTS)
     for n in names:
         assert hasattr(L, n), n
-    assert L.om_version() == 107
+    assert L.om_version() == 108
     assert L.om_status_str(-2) == b"unsupported shape or dtype"
 
 
@@ -120,15 +120,15 @@ def test_render_argument_errors(L):
     assert L.om_render(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(missing), None) == _lib.OM_ERR_INVALID
     assert L.om_render(None, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(out), None) == _lib.OM_ERR_INVALID
     g = _lib.OmGrads(FAKE, FAKE, FAKE, 0, FAKE, 0)
-    assert L.om_render_backward(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(out), FAKE,
+    assert L.om_render_backward(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(out), FAKE, FAKE, 1 << 20,
                                 ctypes.byref(g), None) == _lib.OM_ERR_INVALID
     # the optional per-batch sums must be float-aligned when given
     bad_bw = _lib.OmFwdOut(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE + 2)
     assert L.om_render(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(bad_bw), None) == _lib.OM_ERR_INVALID
     assert L.om_march(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(bad_bw), None) == _lib.OM_ERR_INVALID
     g_ok = _lib.OmGrads(FAKE, FAKE, FAKE, FAKE, FAKE, 0)
-    assert L.om_render_backward(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(bad_bw), FAKE,
-                                ctypes.byref(g_ok), None) == _lib.OM_ERR_INVALID
+    assert L.om_render_backward(h, FAKE, FAKE, 4, ctypes.byref(_params()), ctypes.byref(bad_bw), FAKE, FAKE,
+                                1 << 20, ctypes.byref(g_ok), None) == _lib.OM_ERR_INVALID
     assert L.om_place_samples(h, FAKE, FAKE, 4, ctypes.byref(_params()), 0, FAKE, None) == _lib.OM_ERR_INVALID
     assert L.om_l2_loss_fp64(FAKE, FAKE, 0, FAKE, None) == _lib.OM_ERR_INVALID
     assert L.om_l2_loss_grad(FAKE, FAKE, 3, FAKE, None, None) == _lib.OM_ERR_INVALID  # aliasing
@@ -158,9 +158,9 @@ def test_fused_training_step_validation(L):
 
 
 def test_backward_workspace_validation(L):
-    """Workspace query and argument checks of om_render_backward_ws (no
-    device work): 32 bytes per ray rounded up to 256; a workspace that is
-    too small or misaligned is refused before anything is launched."""
+    """Workspace query and argument checks of the two backward entry points
+    (no device work): 32 bytes per ray rounded up to 256; a workspace that
+    is too small or misaligned is refused before anything is launched."""
     assert L.om_render_backward_workspace_size(0) == 0
     assert L.om_render_backward_workspace_size(1) == 256
     assert L.om_render_backward_workspace_size(1000) == 32000  # 125 x 256
@@ -171,17 +171,19 @@ def test_backward_workspace_validation(L):
     rc, h = _create(L, _desc())
     out = _lib.OmFwdOut(FAKE, FAKE, FAKE, FAKE, FAKE, 0)
     g = _lib.OmGrads(FAKE, FAKE, FAKE, FAKE, FAKE, 0)
-    bwd = lambda *a: L.om_render_backward_ws(h, FAKE, FAKE, n, ctypes.byref(_params()), ctypes.byref(out),  # noqa: E731
-                                             FAKE, None, *a, ctypes.byref(g), None)
-    assert bwd(FAKE, ws - 1) == _lib.OM_ERR_INVALID
-    assert "workspace" in L.om_last_error().decode()
-    assert bwd(FAKE + 16, ws) == _lib.OM_ERR_INVALID
-    assert bwd(None, ws) == _lib.OM_ERR_INVALID
-    bad_g = _lib.OmGrads(FAKE, 0, FAKE, FAKE, FAKE, 0)
-    assert L.om_render_backward_ws(h, FAKE, FAKE, n, ctypes.byref(_params()), ctypes.byref(out), FAKE, None, FAKE,
-                                   ws, ctypes.byref(bad_g), None) == _lib.OM_ERR_INVALID
+    p = _params()
+    ex = lambda w, nb, gg=g: L.om_render_backward_ex(h, FAKE, FAKE, n, ctypes.byref(p), ctypes.byref(out),  # noqa: E731
+                                                     FAKE, None, w, nb, ctypes.byref(gg), None)
+    plain = lambda w, nb: L.om_render_backward(h, FAKE, FAKE, n, ctypes.byref(p), ctypes.byref(out),  # noqa: E731
+                                               FAKE, w, nb, ctypes.byref(g), None)
+    for call in (ex, plain):
+        assert call(FAKE, ws - 1) == _lib.OM_ERR_INVALID
+        assert "workspace" in L.om_last_error().decode()
+        assert call(FAKE + 16, ws) == _lib.OM_ERR_INVALID
+        assert call(None, ws) == _lib.OM_ERR_INVALID
+    assert ex(FAKE, ws, _lib.OmGrads(FAKE, 0, FAKE, FAKE, FAKE, 0)) == _lib.OM_ERR_INVALID
     # n = 0 is a no-op that needs no workspace
-    assert L.om_render_backward_ws(h, None, None, 0, ctypes.byref(_params()), ctypes.byref(out), None, None, None, 0,
+    assert L.om_render_backward_ex(h, None, None, 0, ctypes.byref(p), ctypes.byref(out), None, None, None, 0,
                                    ctypes.byref(g), None) == 0
     L.om_scene_destroy(h)
 

@@ -81,20 +81,23 @@ def test_backward_tiny_vs_oracle(tiny_train):
         check(grads, ref, scale, f"tiny batch_wv={bw}")
 
 
-def _backward_ex_direct(scene, t, og, dg, res, up32, n_max):
-    """om_render_backward_ex called through the C ABI: the entry point that
-    takes its per-ray hand-over from the stream-ordered allocator."""
+def _backward_plain_direct(scene, t, og, dg, res, up32, n_max):
+    """om_render_backward (no dL/dF) called through the C ABI, with a
+    workspace of exactly the queried size; the binding uses
+    om_render_backward_ex."""
     from paper_2404_09531_amd import _lib
+    L = _lib.lib()
+    n = og.shape[0]
     dC = torch.from_numpy(np.ascontiguousarray(up32, np.float32)).to(og.device)
     grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp")}
+    ws = torch.empty((L.om_render_backward_workspace_size(n),), dtype=torch.uint8, device=og.device)
     fo = _lib.OmFwdOut(res["C"].data_ptr(), res["T"].data_ptr(), res["F"].data_ptr(), res["n_placed"].data_ptr(),
                        res["n_eval"].data_ptr(), 0)
     p = om._params(n_max, om.DELTA, 0.0, BG, -1, 0.0)
     g = om._grads(scene, grads)
-    rc = _lib.lib().om_render_backward_ex(scene.handle, og.data_ptr(), dg.data_ptr(), og.shape[0], ctypes.byref(p),
-                                          ctypes.byref(fo), dC.data_ptr(), None, ctypes.byref(g),
-                                          _lib.stream_of(og))
-    assert rc == 0, _lib.lib().om_last_error().decode()
+    rc = L.om_render_backward(scene.handle, og.data_ptr(), dg.data_ptr(), n, ctypes.byref(p), ctypes.byref(fo),
+                              dC.data_ptr(), ws.data_ptr(), ws.numel(), ctypes.byref(g), _lib.stream_of(og))
+    assert rc == 0, L.om_last_error().decode()
     torch.cuda.synchronize()
     return {k: v.double().cpu().numpy() for k, v in grads.items()}
 
@@ -104,8 +107,7 @@ def test_backward_ragged_counts_vs_oracle(tiny_train, n):
     """Ray counts that leave a partial quad of rays in the MLP backward's
     last step, with every fourth ray turned upwards out of the box
     (n_eval = 0: no sample and no MLP term): gradients against the oracle,
-    through the workspace entry point (the binding) and through
-    om_render_backward_ex, which allocates its own hand-over."""
+    through om_render_backward_ex (the binding) and om_render_backward."""
     sc, scene, t, _, _, _ = tiny_train
     log(f"test_backward_ragged_counts_vs_oracle: {n} rays")
     o, d = scenegen.oblique_rays(n, seed=11)
@@ -122,7 +124,7 @@ def test_backward_ragged_counts_vs_oracle(tiny_train, n):
     ne = res["n_eval"].cpu().numpy()
     assert (ne[away] == 0).all() and (ne[~away] > 0).any()
     check(grads, ref, scale, f"ragged n={n}")
-    check(_backward_ex_direct(scene, t, og, dg, res, up, 64), ref, scale, f"ragged n={n}, allocating entry point")
+    check(_backward_plain_direct(scene, t, og, dg, res, up, 64), ref, scale, f"ragged n={n}, om_render_backward")
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
