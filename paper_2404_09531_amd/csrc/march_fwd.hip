@@ -11,6 +11,8 @@
 #include "omerf_device.h"
 #include "omerf_launch.h"
 
+#include <type_traits>
+
 namespace omerf {
 
 // ---------------------------------------------------------------------------
@@ -114,12 +116,17 @@ struct GatherBF16 {
     }
 };
 
+// Waves per SIMD the one-lane-per-sample forwards are compiled for: the
+// bfloat16 gather without the soft occupancy fits 6 (<= 80 VGPRs) without
+// spilling; the other forms keep the compiler's choice.
+template <class Gather, bool kSoft>
+constexpr int lane_min_waves() { return std::is_same<Gather, GatherBF16>::value && !kSoft ? 6 : 1; }
+
 template <class Gather, bool kBW, bool kSoft, bool kSparse>
-__global__ __launch_bounds__(kBlock) void k_march_fwd_lane(SceneDev sc, RayParams rp, const float* __restrict__ o_,
-                                                           const float* __restrict__ d_, int64_t n,
-                                                           float* __restrict__ F, float* __restrict__ T,
-                                                           int32_t* __restrict__ n_placed,
-                                                           int32_t* __restrict__ n_eval, float* __restrict__ BW) {
+__global__ __launch_bounds__(kBlock, (lane_min_waves<Gather, kSoft>())) void k_march_fwd_lane(
+    SceneDev sc, RayParams rp, const float* __restrict__ o_, const float* __restrict__ d_, int64_t n,
+    float* __restrict__ F, float* __restrict__ T, int32_t* __restrict__ n_placed, int32_t* __restrict__ n_eval,
+    float* __restrict__ BW) {
     __shared__ int qs[kGroupsPerBlock][kQueue];
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kGroup - 1);

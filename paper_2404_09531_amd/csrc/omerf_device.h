@@ -470,9 +470,11 @@ __device__ __forceinline__ void wave_order() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Eq. 2 for 8-bit storage, one lane per sample: the 10 corner pairs are
-// loaded first (16 bytes each), then each source's weighted code sums are
-// decoded with that source's per-channel (lo, step).
+// Eq. 2 for 8-bit storage, one lane per sample: the 4 grid corner pairs
+// (16 bytes each), then the 6 plane corner pairs, each group loaded before
+// its weighted code sums are decoded with the source's per-channel (lo,
+// step).  Two load groups instead of one keep the kernel at 86 VGPRs,
+// 5 waves per SIMD (one group of 10 needs 97: 4 waves).
 __device__ __forceinline__ void decode_add(const SceneDev& sc, int src, const float* a, float* t) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) t[c] += fmaf(sc.qstep[8 * src + c], a[c], sc.qlo[8 * src + c]);
@@ -481,36 +483,37 @@ __device__ __forceinline__ void decode_add(const SceneDev& sc, int src, const fl
 __device__ __forceinline__ void gather_u8(const SceneDev& sc, const Corners& c, float* t) {
     const uint32_t sy = sc.gsy, sz = sc.gsz;
     const uint32_t nx = (uint32_t)sc.Nx, ny = (uint32_t)sc.Ny;
-    // Each row's corner pair (i0, i0 + 1) is 16 contiguous bytes: one load
-    // (8-byte aligned; the hardware serves unaligned global loads).
-    uint4 r[10];
-    const uint8_t* G = static_cast<const uint8_t*>(sc.grid);
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const uint32_t base = c.g + ((p & 1) ? sy : 0u) + ((p >> 1) ? sz : 0u);
-        __builtin_memcpy(&r[p], G + (size_t)base * 8, 16);
+    for (int i = 0; i < 8; ++i) t[i] = 0.0f;
+    float a[8];
+    {
+        uint4 r[4];
+        const uint8_t* G = static_cast<const uint8_t*>(sc.grid);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const uint32_t base = c.g + ((p & 1) ? sy : 0u) + ((p >> 1) ? sz : 0u);
+            __builtin_memcpy(&r[p], G + (size_t)base * 8, 16);
+        }
+        const float x0 = 1.0f - c.fx, x1 = c.fx, y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = 0.0f;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const float wyz = ((p & 1) ? y1 : y0) * ((p >> 1) ? z1 : z0);
+            U8Store::acc(make_uint2(r[p].x, r[p].y), x0 * wyz, a);
+            U8Store::acc(make_uint2(r[p].z, r[p].w), x1 * wyz, a);
+        }
+        decode_add(sc, 0, a, t);
     }
+    uint4 r[6];
     const uint8_t* P[3] = {static_cast<const uint8_t*>(sc.pxy), static_cast<const uint8_t*>(sc.pxz),
                            static_cast<const uint8_t*>(sc.pyz)};
     const uint32_t pb[3] = {c.xy, c.xz, c.yz}, ps[3] = {nx, nx, ny};
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        __builtin_memcpy(&r[4 + 2 * q], P[q] + (size_t)pb[q] * 8, 16);
-        __builtin_memcpy(&r[5 + 2 * q], P[q] + (size_t)(pb[q] + ps[q]) * 8, 16);
+        __builtin_memcpy(&r[2 * q], P[q] + (size_t)pb[q] * 8, 16);
+        __builtin_memcpy(&r[1 + 2 * q], P[q] + (size_t)(pb[q] + ps[q]) * 8, 16);
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) t[i] = 0.0f;
-    float a[8];
-    const float x0 = 1.0f - c.fx, x1 = c.fx, y0 = 1.0f - c.fy, y1 = c.fy, z0 = 1.0f - c.fz, z1 = c.fz;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) a[i] = 0.0f;
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const float wyz = ((p & 1) ? y1 : y0) * ((p >> 1) ? z1 : z0);
-        U8Store::acc(make_uint2(r[p].x, r[p].y), x0 * wyz, a);
-        U8Store::acc(make_uint2(r[p].z, r[p].w), x1 * wyz, a);
-    }
-    decode_add(sc, 0, a, t);
     const float u0 = 1.0f - c.ux, u1 = c.ux, v0 = 1.0f - c.uy, v1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
     const float wa[3][2] = {{u0, u1}, {u0, u1}, {v0, v1}};  // first axis: x, x, y
     const float wb[3][2] = {{v0, v1}, {e0, e1}, {e0, e1}};  // second axis: y, z, z
@@ -518,7 +521,7 @@ __device__ __forceinline__ void gather_u8(const SceneDev& sc, const Corners& c, 
     for (int q = 0; q < 3; ++q) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) a[i] = 0.0f;
-        const uint4 lo = r[4 + 2 * q], hi = r[5 + 2 * q];
+        const uint4 lo = r[2 * q], hi = r[1 + 2 * q];
         U8Store::acc(make_uint2(lo.x, lo.y), wa[q][0] * wb[q][0], a);
         U8Store::acc(make_uint2(lo.z, lo.w), wa[q][1] * wb[q][0], a);
         U8Store::acc(make_uint2(hi.x, hi.y), wa[q][0] * wb[q][1], a);
