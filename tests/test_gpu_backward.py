@@ -546,7 +546,7 @@ def test_backward_long_chunks_keep_caller_order():
     That path and the length-sorted one must give the same gradients: the
     whole batch in one call against its two halves in two calls (the
     backward adds into the gradient buffers), with the same dL/dC."""
-    n = 4096 * 1024 + 4096 * 16 + 5  # chunks of 1040 rays, ragged tail
+    n = 4096 * 1024 + 4096 * 16 + 5  # 4034 chunks of 1056 rays (> 1024), the last one ragged
     log(f"test_backward_long_chunks_keep_caller_order: {n} rays")
     sc = scenegen.make_scene(scenegen.TINY)
     scene, t = upload_scene(sc)
