@@ -158,6 +158,49 @@ def l1_gather_peak(torch, span: int, blocks: int = 8192, iters: int = 64, reps: 
             "kernel": "omcalib_l1_gather (16 KiB buffer, 16-byte lane loads)"}
 
 
+_ATOMIC_PEAK = {}
+
+
+def atomic_segment_peak(torch, nbytes: int = 1 << 30, blocks: int = 8192, iters: int = 64, reps: int = 5) -> dict:
+    """Rate (G requests/s) at which the device performs float atomics of one
+    64-byte segment per 16-lane group, at random segments of a zeroed
+    `nbytes` buffer (calibration kernel in libomcalib.so; the backward's
+    segment flush has this shape).  Measured once per process."""
+    if nbytes in _ATOMIC_PEAK:
+        return _ATOMIC_PEAK[nbytes]
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2404_09531_amd", "libomcalib.so"))
+    lib.omcalib_atomic_segments.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_void_p]
+    nseg = nbytes // 64
+    buf = torch.zeros(nseg * 16, device="cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+
+    def launch():
+        rc = lib.omcalib_atomic_segments(buf.data_ptr(), nseg, blocks, iters, st)
+        if rc != 0:
+            raise RuntimeError(f"omcalib_atomic_segments failed ({rc})")
+
+    ms, _ = time_stages([launch], reps, 2, torch)
+    del buf
+    req = blocks * 16 * iters
+    _ATOMIC_PEAK[nbytes] = {"G_requests_per_s": round(req / (ms / reps * 1e-3) / 1e9, 2), "buffer_bytes": nbytes,
+                            "kernel": "omcalib_atomic_segments (16 lanes x 4 B per random 64-byte segment)"}
+    return _ATOMIC_PEAK[nbytes]
+
+
+def measured_atomic_requests(kernel: str, workload: str):
+    """Float-atomic requests per launch (TCC_ATOMIC_sum) from the committed
+    counter summary, only if taken on the current source of the kernel."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        e = json.load(fh).get(kernel, {}).get(workload)
+    if not e or e.get("counter_source_hash") != kernel_source_hash(e.get("family", "fwd")):
+        return None
+    return e.get("counters", {}).get("TCC_ATOMIC_sum")
+
+
 def rows_read(om, scene, og, dg, n_max, n_eval) -> dict:
     """Feature rows the render reads (om_mark_rows), per source."""
     fl = om.mark_rows(scene, og, dg, n_max, n_eval=n_eval)
@@ -334,10 +377,14 @@ def _train_rays(scenegen, torch, name, dev):
     return torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev), rec
 
 
-def _train_rooflines(om, scene, og, dg, out, kw, f_ms, b_ms, fwd_kernel, bwd_kernel, workload, row_bytes):
+def _train_rooflines(om, torch, scene, og, dg, out, kw, f_ms, b_ms, fwd_kernel, bwd_kernel, workload, row_bytes):
     """Forward and backward rooflines of a training step: each must read
     every row its samples touch once; the backward also reads and writes
-    their float32 gradient rows once (64 B per row: read-modify-write)."""
+    their float32 gradient rows once (64 B per row: read-modify-write).
+    The backward also reports its float-atomic requests per second (the
+    march backward's request count from the committed counters, over the
+    time of the backward call) against the calibrated segment-atomic rate:
+    the unit that bounds it."""
     n = og.shape[0]
     rows = rows_read(om, scene, og, dg, kw["n_max"], out["n_eval"])
     nr = sum(rows.values())
@@ -347,8 +394,16 @@ def _train_rooflines(om, scene, og, dg, out, kw, f_ms, b_ms, fwd_kernel, bwd_ker
     fwd_min = nr * row_bytes + n * 64 + live_slots * 28  # rows + rays/outputs + per-batch sums
     bwd_min = nr * (row_bytes + 64) + n * (24 + 52 + 12) + live_slots * 28
     del slots
-    return {"fwd": hbm_roofline(fwd_kernel, workload, f_ms, fwd_min),
-            "bwd": hbm_roofline(bwd_kernel, workload, b_ms, bwd_min), "rows_touched": rows}
+    bwd = hbm_roofline(bwd_kernel, workload, b_ms, bwd_min)
+    march = bwd_kernel[-1] if isinstance(bwd_kernel, tuple) else bwd_kernel
+    req = measured_atomic_requests(march, workload)
+    if req is not None:
+        cal = atomic_segment_peak(torch)
+        got = req / (b_ms * 1e-3) / 1e9
+        bwd["atomics"] = {"achieved": round(got, 2), "peak": cal["G_requests_per_s"], "unit": "G requests/s",
+                          "frac": round(got / cal["G_requests_per_s"], 4), "requests_per_launch": int(req),
+                          "calibration": cal}
+    return {"fwd": hbm_roofline(fwd_kernel, workload, f_ms, fwd_min), "bwd": bwd, "rows_touched": rows}
 
 
 def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, kw, a, occ_eps=0.0):
@@ -382,7 +437,7 @@ def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, kw, a, occ_eps=0.0):
            "samples_per_ray": round(s2 / n2, 1), "targets": "forward colours + N(0, 0.05), seeded",
            "bwd_Msamples_per_s": round(s2 / (b_ms * 1e-3) / 1e6, 1)}
     if occ_eps == 0:
-        res["roofline"] = _train_rooflines(om, scene, o2g, d2g, out2, kw, f_ms, b_ms, "k_march_fwd_f32q<true>",
+        res["roofline"] = _train_rooflines(om, torch, scene, o2g, d2g, out2, kw, f_ms, b_ms, "k_march_fwd_f32q<true>",
                                            ("k_mlp_bwd<10>", "k_march_bwd<F32Store>"), "train-2^18", 32)
     return res
 
@@ -510,7 +565,7 @@ def form_towers(om, scenegen, torch, a):
     return {"workload": "towers: occupancy 512^2, 10% towers, 2^20 rays of 64 cameras, n_max 512", "rays": n,
             "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 3),
             "fwd_ms": round(f_ms, 3), "bwd_ms": round(b_ms, 3), "bwd_Msamples_per_s": round(se / (b_ms * 1e-3) / 1e6, 1),
-            "roofline": _train_rooflines(om, scene_b, og, dg, out, kw, f_ms, b_ms,
+            "roofline": _train_rooflines(om, torch, scene_b, og, dg, out, kw, f_ms, b_ms,
                                          "k_march_fwd_lane<GatherBF16,kBW>", ("k_mlp_bwd<10>", "k_march_bwd<BF16Store>"),
                                          "towers-2^20", 16),
             "samples_per_ray": round(float(npl.mean()), 1), "max_samples": int(npl.max()),

@@ -1,6 +1,7 @@
-// calib.hip -- calibration kernel for the cache-resident gather ceiling
-// (measurement only; built into libomcalib.so, not part of the C ABI of
-// include/omerf.h).
+// calib.hip -- calibration kernels for the bench's ceilings (measurement
+// only; built into libomcalib.so, not part of the C ABI of
+// include/omerf.h): the cache-resident gather rate of the forwards and the
+// float-atomic segment rate of the backward.
 //
 // The forward marches are limited by how fast the vector memory path
 // returns gathered 16-byte lane loads to registers, not by HBM: their
@@ -41,6 +42,28 @@ __global__ __launch_bounds__(kThreads) void k_l1_gather(const uint4* __restrict_
     sink[tid] = acc0 + acc1;
 }
 
+// Request rate of 64-byte float-atomic segments: each 16-lane group adds
+// one float per lane to one 64-byte segment (16 floats) per instruction, the
+// shape of the backward's segment flush, at a segment drawn by a hash of
+// (group, iteration) from `nseg` segments (a power of two).  One request
+// per group and iteration.
+__device__ __forceinline__ uint32_t mix32(uint32_t a) {
+    a ^= a >> 16;
+    a *= 0x7feb352du;
+    a ^= a >> 15;
+    a *= 0x846ca68bu;
+    a ^= a >> 16;
+    return a;
+}
+
+__global__ __launch_bounds__(kThreads) void k_atomic_segments(float* __restrict__ buf, uint32_t seg_mask, int iters) {
+    const uint32_t g = (blockIdx.x * kThreads + threadIdx.x) >> 4, l = threadIdx.x & 15u;
+    for (int it = 0; it < iters; ++it) {
+        const uint32_t seg = mix32(g * 977u + (uint32_t)it) & seg_mask;
+        unsafeAtomicAdd(buf + (size_t)seg * 16 + l, 1.0f);
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -57,6 +80,18 @@ int omcalib_l1_gather(const void* buf, int64_t nvec, int span, int blocks, int i
     if ((1 << shift) != span || shift > 4 || nvec > (int64_t)1 << 24) return -1;
     hipLaunchKernelGGL(k_l1_gather, dim3((unsigned)blocks), dim3(kThreads), 0, (hipStream_t)stream,
                        static_cast<const uint4*>(buf), (uint32_t)(nvec - 1), shift, iters, sink);
+    return (int)hipGetLastError();
+}
+
+// Launches `blocks` blocks of 256 threads; each 16-lane group issues
+// `iters` float-atomic adds of one 64-byte segment of buf (device, nseg
+// segments of 16 floats, nseg a power of two <= 2^26; the values grow by
+// 1.0 per add).  Requests = blocks * 16 * iters.  Returns 0, -1 for bad
+// arguments (nothing launched), or the HIP error code of the launch.
+int omcalib_atomic_segments(float* buf, int64_t nseg, int blocks, int iters, void* stream) {
+    if (!buf || nseg < 1 || (nseg & (nseg - 1)) || nseg > ((int64_t)1 << 26) || blocks < 1 || iters < 1) return -1;
+    hipLaunchKernelGGL(k_atomic_segments, dim3((unsigned)blocks), dim3(kThreads), 0, (hipStream_t)stream, buf,
+                       (uint32_t)(nseg - 1), iters);
     return (int)hipGetLastError();
 }
 

@@ -92,3 +92,23 @@ def test_oracle_pool_equals_serial_oracle():
         assert np.array_equal(par[key], ref[key]), key
     assert par["k_mismatch_rays"].tolist() == [7, 250]
     assert par["workers"] == 2
+
+
+def test_calibration_library_refuses_bad_shapes_before_launching():
+    """The bench's calibration kernels (libomcalib.so) check their arguments
+    on the host and return -1 without launching anything: no GPU is needed
+    to see a refusal."""
+    import ctypes
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lib = ctypes.CDLL(os.path.join(root, "paper_2404_09531_amd", "libomcalib.so"))
+    lib.omcalib_atomic_segments.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_void_p]
+    lib.omcalib_l1_gather.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_void_p, ctypes.c_void_p]
+    fake = 1 << 20
+    for nseg, blocks, iters in ((3, 1, 1), (0, 1, 1), (1 << 27, 1, 1), (1 << 10, 0, 1), (1 << 10, 1, 0)):
+        assert lib.omcalib_atomic_segments(fake, nseg, blocks, iters, None) == -1
+    assert lib.omcalib_atomic_segments(None, 1 << 10, 1, 1, None) == -1
+    for nvec, span in ((1000, 4), (8, 4), (1024, 3), (1024, 32)):
+        assert lib.omcalib_l1_gather(fake, nvec, span, 1, 1, fake, None) == -1
