@@ -19,6 +19,7 @@ import torch
 import oracle
 import paper_2404_09531_amd as om
 import scenegen
+from tests._scenes import micro_scene
 from tests.gpu_util import log, rays_to, upload_scene
 from tests.gradcheck import check, oracle_reference, oracle_upstream
 
@@ -125,6 +126,34 @@ def test_backward_ragged_counts_vs_oracle(tiny_train, n):
     assert (ne[away] == 0).all() and (ne[~away] > 0).any()
     check(grads, ref, scale, f"ragged n={n}")
     check(_backward_plain_direct(scene, t, og, dg, res, up, 64), ref, scale, f"ragged n={n}, om_render_backward")
+
+
+def test_backward_max_samples_vs_oracle():
+    """Rays with up to n_max = 1024 samples (64 batches, every register
+    slot of the batch totals): a box of height 0.5 that the occupancy
+    fills, low density so that every sample keeps a share of the
+    transmittance, near-vertical and oblique rays.  Gradients against the
+    oracle, with the batch totals from a replay and from the forward."""
+    sc = micro_scene(grid=(8, 8, 12), planes=(16, 16, 20), m=4, zmin=0.0, zmax=0.5, seed=31, std=0.5)
+    sc["box_hi"][2] = 0.5
+    g = np.random.Generator(np.random.PCG64(32))
+    n = 37
+    d = np.stack([g.uniform(-0.3, 0.3, n), g.uniform(-0.3, 0.3, n), -np.ones(n)], axis=1)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.stack([g.uniform(-0.5, 0.5, n), g.uniform(-0.5, 0.5, n), np.ones(n)], axis=1)
+    o, d = o.astype(np.float32), d.astype(np.float32)
+    target = g.uniform(0.0, 1.0, (n, 3)).astype(np.float32)
+    prm = oracle.RenderParams(n_max=1024, c_bg=BG)
+    up, _ = oracle_upstream(sc, o, d, prm, target)
+    ref, scale = oracle_reference(sc, o, d, prm, up)
+    scene, t = upload_scene(sc)
+    og, dg = rays_to(o, d)
+    for bw in (False, True):
+        res, grads = _gpu_vjp(scene, t, og, dg, up, 1024, batch_wv=bw)
+        ne = res["n_eval"].cpu().numpy()
+        log(f"test_backward_max_samples_vs_oracle: batch_wv={bw}, samples per ray {ne.min()}..{ne.max()}")
+        assert ne.max() > 768  # the last register slot of the batch totals is used
+        check(grads, ref, scale, f"max samples batch_wv={bw}")
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
