@@ -338,11 +338,12 @@ __global__ __launch_bounds__(mlp_bwd_block<NIN>()) void k_mlp_bwd(const float* _
 #pragma unroll
             for (int c = 0; c < 3; ++c) d3[c] = d_[ray * 3 + c];
         }
-        // The weights are re-read (L1 hits) in every iteration instead of
-        // being hoisted into registers for the whole loop, which would
-        // leave too few registers for the large blocks.
+        // For the 34-input MLP the weights are re-read (L1 hits) in every
+        // iteration instead of being hoisted into registers for the whole
+        // loop, which would leave too few registers for the large blocks;
+        // the 10-input MLP keeps them in registers.
         const float* Wq = W;
-        asm volatile("" : "+s"(Wq));
+        if (NIN != 10) asm volatile("" : "+s"(Wq));
         float x[NIN];
         mlp_input<NIN>(f7, make_float3(d3[0], d3[1], d3[2]), x);
         const MlpAct a = group_mlp_fwd<NIN>(Wq, x, gl);
