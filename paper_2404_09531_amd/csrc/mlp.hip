@@ -13,6 +13,11 @@
 //                  holds rows 4(l/16)..+3 of column l%16) is exactly the B
 //                  operand layout of the next, so no data moves between
 //                  layers.  Biases enter as the accumulator's initial value.
+// k_mlp_bwd      : the backward of G ahead of the backward march: per ray
+//                  dL/dF for the march, and the parameter gradients summed
+//                  over each wave's four rays on MFMA (v_mfma_f32_16x16x4_f32).
+// Also here: the L2 loss, the occupancy pyramid and interval loss, and the
+// view-smoothness loss (Eq. 9-10).
 #include "omerf_launch.h"
 
 namespace omerf {

@@ -539,8 +539,8 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
 }
 
 // ---------------------------------------------------------------------------
-// Deferred MLP input and the group-cooperative MLP (one hidden unit per lane
-// of a 16-lane group), shared by the backward march and the smoothness loss.
+// Deferred MLP input, shared by the MLP forward kernels, the MLP backward
+// and the view-smoothness loss.
 // ---------------------------------------------------------------------------
 // x = [F (7), enc(d)]: enc(d) = d, or [d, sin(2^0 d), cos(2^0 d), ...,
 // sin(2^3 d), cos(2^3 d)] (each term a 3-vector) for NIN = 34.
