@@ -138,15 +138,20 @@ __global__ __launch_bounds__(kBlock) void k_mlp_bf16(const float* __restrict__ W
     const int64_t tiles = (n + 15) / 16;
     const int64_t wave = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    // Every input of a tile (F, d, T, n_eval) is loaded before its MFMAs:
+    // one memory round trip per tile.
     for (int64_t tile = wave; tile < tiles; tile += nwaves) {
         const int64_t r = tile * 16 + col;
         const bool valid = r < n;
-        float f7[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, d3[3] = {0.f, 0.f, 0.f};
+        float f7[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, d3[3] = {0.f, 0.f, 0.f}, t = 0.0f;
+        bool gate = false;
         if (valid) {
 #pragma unroll
             for (int c = 0; c < 7; ++c) f7[c] = F[r * 7 + c];
 #pragma unroll
             for (int c = 0; c < 3; ++c) d3[c] = d_[r * 3 + c];
+            t = T[r];
+            gate = n_eval[r] > 0;
         }
         // Layer 1 over the k-tiles: B operand x[k] of ray `col`, k = 16 kt + 4q .. +3.
         f32x4 h = c1;
@@ -163,8 +168,6 @@ __global__ __launch_bounds__(kBlock) void k_mlp_bf16(const float* __restrict__ W
         h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A3, B3, c3, 0, 0, 0);
         // Rows 0..2 of the output live in lanes with q == 0.
         if (q == 0 && valid) {
-            const bool gate = n_eval[r] > 0;
-            const float t = T[r];
             C[r * 3 + 0] = f7[0] + (gate ? sigmoidf_fast(h[0]) : 0.0f) + t * rp.bg0;
             C[r * 3 + 1] = f7[1] + (gate ? sigmoidf_fast(h[1]) : 0.0f) + t * rp.bg1;
             C[r * 3 + 2] = f7[2] + (gate ? sigmoidf_fast(h[2]) : 0.0f) + t * rp.bg2;
