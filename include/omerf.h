@@ -298,18 +298,21 @@ int om_deferred_mlp(const om_scene* scene, const float* d, int64_t n, const om_p
  * of Eq. 4) turns dL_dC (and dL_dF of om_render_backward_ex) into one total
  * dL/dF per ray and the MLP parameter gradients; the march backward
  * (derivative of Eq. 1-3) then distributes that dL/dF over the samples.
- * The per-ray hand-over between them (8 floats: dL/dF and dL/dC . c_bg)
- * lives in `workspace`: caller-owned device memory of at least
- * om_render_backward_workspace_size(n) bytes, 256-byte aligned, overwritten
- * (OM_ERR_INVALID if it is smaller or misaligned).  The call allocates
- * nothing.
+ * The march backward takes the rays longest first (by their number of
+ * 16-sample batches), handed to its waves on demand.  The per-ray hand-over
+ * between the stages (8 floats: dL/dF and dL/dC . c_bg), that ray order and
+ * its scheduling counters live in `workspace`: caller-owned device memory
+ * of at least om_render_backward_workspace_size(n) bytes, 256-byte aligned,
+ * overwritten (OM_ERR_INVALID if it is smaller or misaligned).  The call
+ * allocates nothing.
  */
 int om_render_backward(const om_scene* scene, const float* o, const float* d, int64_t n,
                        const om_params* p, const om_fwd_out* saved, const float* dL_dC,
                        void* workspace, int64_t workspace_bytes, const om_grads* g, void* stream);
 
-/* Workspace bytes om_render_backward(_ex) needs for n rays (32 n rounded up
- * to a multiple of 256), or -1 (with om_last_error set) if n < 0. */
+/* Workspace bytes om_render_backward(_ex) needs for n rays (0 for n = 0;
+ * else 32 n and 4 n, each rounded up to a multiple of 256, plus 1024), or
+ * -1 (with om_last_error set) if n < 0. */
 int64_t om_render_backward_workspace_size(int64_t n);
 
 /*
@@ -373,8 +376,8 @@ int om_l2_loss_grad(const float* C, const float* target, int64_t n, float* dL_dC
  * so that the backward replays the samples once.  target: device float32
  * [n][3].  workspace: caller-owned device memory of at least
  * om_render_fwd_bwd_l2_workspace_size(n, p) bytes, 256-byte aligned; it
- * holds dL/dC, the backward's per-ray hand-over (om_render_backward)
- * and the per-batch sums (out->batch_wv is ignored).
+ * holds dL/dC, the backward's workspace (om_render_backward) and the
+ * per-batch sums (out->batch_wv is ignored).
  * loss: optional device float[1] receiving the loss as om_l2_loss_grad
  * computes it (overwritten), or NULL.  Equivalent to om_render +
  * om_l2_loss_grad + om_render_backward.  Cites: Eq. 1-4 (forward) and
@@ -393,13 +396,13 @@ int64_t om_render_fwd_bwd_l2_workspace_size(int64_t n, const om_params* p);
  * om_render_fwd_bwd_l2 for callers that cannot allocate device memory: code
  * under HIP graph capture, tight serving or training loops, harnesses that
  * forbid hipMalloc.  Same arguments and results as om_render_fwd_bwd_l2
- * minus the workspace: the workspace (dL/dC, the per-ray hand-over and
+ * minus the workspace: the workspace (dL/dC, the backward's workspace and
  * the per-batch sums) lives
  * in a fixed array of om_render_fwd_bwd_l2_noalloc_max_bytes() bytes
  * (64 MiB) inside the library, one per GPU, held until the process ends.
  * The call allocates nothing (no hipMalloc, hipFree or allocating library
  * routine).  Limit: om_render_fwd_bwd_l2_workspace_size(n, p) must not
- * exceed that size (e.g. 136,000 rays at n_max 256, 430,000 at n_max 64),
+ * exceed that size (e.g. 135,296 rays at n_max 256, 419,421 at n_max 64),
  * else OM_ERR_UNSUPPORTED with om_last_error naming the sizes.  Every
  * call on one GPU shares that GPU's array, which keeps the last call's
  * contents (each call overwrites what it reads before reading it): calls

@@ -368,7 +368,11 @@ int64_t om_render_backward_workspace_size(int64_t n) {
         fail(OM_ERR_INVALID, "n must be >= 0");
         return -1;
     }
-    return (n * 8 * (int64_t)sizeof(float) + 255) / 256 * 256;
+    // G8 (8 floats per ray), the ray order (one int32 per ray), the
+    // scheduling words; each part 256-byte aligned.  No rays, no work.
+    if (n == 0) return 0;
+    return (n * 8 * (int64_t)sizeof(float) + 255) / 256 * 256 + (n * (int64_t)sizeof(int32_t) + 255) / 256 * 256 +
+           kBwdSchedWords * (int64_t)sizeof(int32_t);
 }
 
 namespace {
@@ -392,14 +396,20 @@ int check_backward(const om_scene* scene, const float* o, const float* d, int64_
 }
 
 // MLP backward into G8 (per-ray dL/dF and background term), then the march
-// backward that reads it.
+// backward that reads it.  `ws` is the backward workspace
+// (om_render_backward_workspace_size(n) bytes, 256-byte aligned).
 hipError_t backward_launch(const om_scene* scene, const RayParams& rp, const float* o, const float* d, int64_t n,
                            const float* F, const float* T, const int32_t* n_eval, const float* batch_wv,
-                           const float* dC, const float* dF, float* G8, const om_grads* g, hipStream_t s) {
+                           const float* dC, const float* dF, void* ws, const om_grads* g, hipStream_t s) {
+    char* p = static_cast<char*>(ws);
+    float* G8 = reinterpret_cast<float*>(p);
+    int32_t* order = reinterpret_cast<int32_t*>(p + (n * 8 * (int64_t)sizeof(float) + 255) / 256 * 256);
+    int* sched = reinterpret_cast<int*>(reinterpret_cast<char*>(order) +
+                                        (n * (int64_t)sizeof(int32_t) + 255) / 256 * 256);
     hipError_t e = launch_mlp_bwd(scene->dev.mlp, scene->dev.mlp_in, rp, F, d, n_eval, dC, dF, n, G8, g->mlp, s);
     if (e != hipSuccess) return e;
-    return launch_march_bwd(scene->dev, scene->desc.dtype == OM_BF16, rp, o, d, n, T, n_eval, batch_wv, G8, g->grid,
-                            g->plane_xy, g->plane_xz, g->plane_yz, g->occ, s);
+    return launch_march_bwd(scene->dev, scene->desc.dtype == OM_BF16, rp, o, d, n, T, n_eval, batch_wv, G8, order,
+                            sched, g->grid, g->plane_xy, g->plane_xz, g->plane_yz, g->occ, s);
 }
 
 }  // namespace
@@ -423,7 +433,7 @@ int om_render_backward_ex(const om_scene* scene, const float* o, const float* d,
         return fail(OM_ERR_INVALID, "workspace holds %lld bytes, %lld needed", (long long)workspace_bytes,
                     (long long)need);
     const hipError_t e = backward_launch(scene, rp, o, d, n, saved->F, saved->T, saved->n_eval, saved->batch_wv, dL_dC,
-                                         dL_dF, static_cast<float*>(workspace), g, (hipStream_t)stream);
+                                         dL_dF, workspace, g, (hipStream_t)stream);
     return hip_status(e, "om_render_backward");
 }
 
@@ -464,16 +474,17 @@ int check_fwd_bwd_l2(const om_scene* scene, const float* o, const float* d, int6
 }
 
 // The step itself over a workspace laid out as [dL/dC, 256-byte aligned |
-// per-ray dL/dF and background term (om_render_backward_workspace_size) |
-// per-batch sums of w v]: forward with per-batch sums, loss gradient,
-// MLP backward, march backward.
+// the backward's workspace (om_render_backward_workspace_size: per-ray dL/dF
+// and background term, ray order, scheduling words) | per-batch sums of
+// w v]: forward with per-batch sums, loss gradient, MLP backward, march
+// backward.
 int fwd_bwd_l2_launch(const om_scene* scene, const float* o, const float* d, int64_t n, const om_params* p,
                       const RayParams& rp, const float* target, const om_fwd_out* out, void* workspace, float* loss,
                       const om_grads* g, hipStream_t s, const char* who) {
     char* base = static_cast<char*>(workspace);
     float* dC = reinterpret_cast<float*>(base);
-    float* G8 = reinterpret_cast<float*>(base + (n * 3 * (int64_t)sizeof(float) + 255) / 256 * 256);
-    float* bw = reinterpret_cast<float*>(reinterpret_cast<char*>(G8) + om_render_backward_workspace_size(n));
+    char* bws = base + (n * 3 * (int64_t)sizeof(float) + 255) / 256 * 256;
+    float* bw = reinterpret_cast<float*>(bws + om_render_backward_workspace_size(n));
     hipError_t e = launch_march_fwd(scene->dev, scene->desc.dtype, rp, o, d, n, out->F, out->T, out->n_placed,
                                     out->n_eval, bw, s);
     if (e != hipSuccess) return hip_status(e, who);
@@ -481,7 +492,7 @@ int fwd_bwd_l2_launch(const om_scene* scene, const float* o, const float* d, int
     if (e != hipSuccess) return hip_status(e, who);
     e = launch_l2(out->C, target, n, dC, loss, s);
     if (e != hipSuccess) return hip_status(e, who);
-    e = backward_launch(scene, rp, o, d, n, out->F, out->T, out->n_eval, bw, dC, nullptr, G8, g, s);
+    e = backward_launch(scene, rp, o, d, n, out->F, out->T, out->n_eval, bw, dC, nullptr, bws, g, s);
     return hip_status(e, who);
 }
 
@@ -708,6 +719,6 @@ const char* om_status_str(int status) {
     }
 }
 
-int om_version(void) { return 108; }
+int om_version(void) { return 109; }
 
 }  // extern "C"

@@ -221,12 +221,82 @@ __device__ __forceinline__ void scatter_occ(float* gocc, bool act, const OccValu
     }
 }
 
-// Longest chunk of rays a backward block sorts by length (LDS: 6 KB).
-constexpr int kSortMax = 1024;
+// ---------------------------------------------------------------------------
+// Ray order of the backward: longest first, handed out on demand.
+//
+// A wave's four groups walk their rays in step, so a wave waits for its
+// longest ray, and the kernel waits for its slowest wave.  The rays are
+// therefore counting-sorted by their number of 16-sample batches,
+// descending (k_order_*), and each wave takes the next four rays of that
+// order from a counter whenever it is free: a wave's rays have the same
+// batch count, and the short rays at the end even out the finish.
+//
+// Scheduling words in the workspace (int32): bins [0, 65), cursors
+// [65, 130), the hand-out counter at kOrderCounter.
+// ---------------------------------------------------------------------------
+constexpr int kOrderBins = OM_MAX_SAMPLES / kGroup + 1;  // batch counts 0 .. n_max / 16
+constexpr int kOrderCursor = kOrderBins;
+constexpr int kOrderCounter = 2 * kOrderBins;
+static_assert(kOrderCounter < kBwdSchedWords, "scheduling words");
+
+__device__ __forceinline__ int batch_bin(int ne, int nbins) {
+    return ne <= 0 ? 0 : min((ne + kGroup - 1) / kGroup, nbins - 1);
+}
+
+__global__ __launch_bounds__(64) void k_order_clear(int* __restrict__ hdr) {
+    for (int i = threadIdx.x; i < kBwdSchedWords; i += 64) hdr[i] = 0;
+}
+
+// Rays per batch count: a histogram per block in LDS, added to the bins.
+__global__ __launch_bounds__(256) void k_order_hist(const int32_t* __restrict__ n_eval, int64_t n, int64_t chunk,
+                                                    int nbins, int* __restrict__ hdr) {
+    __shared__ int cnt[kOrderBins];
+    for (int i = threadIdx.x; i < nbins; i += 256) cnt[i] = 0;
+    __syncthreads();
+    const int64_t s = (int64_t)blockIdx.x * chunk, e = min(n, s + chunk);
+    for (int64_t r = s + threadIdx.x; r < e; r += 256) atomicAdd(&cnt[batch_bin(n_eval[r], nbins)], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbins; i += 256)
+        if (cnt[i]) atomicAdd(&hdr[i], cnt[i]);
+}
+
+// Start of each batch count's range in the order, longest first.
+__global__ __launch_bounds__(64) void k_order_scan(int nbins, int* __restrict__ hdr) {
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int b = nbins - 1; b >= 0; --b) {
+            hdr[kOrderCursor + b] = acc;
+            acc += hdr[b];
+        }
+    }
+}
+
+// Each block reserves a range per batch count for its rays (one global
+// atomic per count), then places them there (order within a count is
+// arbitrary).
+__global__ __launch_bounds__(256) void k_order_scatter(const int32_t* __restrict__ n_eval, int64_t n, int64_t chunk,
+                                                       int nbins, int* __restrict__ hdr, int32_t* __restrict__ order) {
+    __shared__ int cnt[kOrderBins], base[kOrderBins];
+    for (int i = threadIdx.x; i < nbins; i += 256) cnt[i] = 0;
+    __syncthreads();
+    const int64_t s = (int64_t)blockIdx.x * chunk, e = min(n, s + chunk);
+    for (int64_t r = s + threadIdx.x; r < e; r += 256) atomicAdd(&cnt[batch_bin(n_eval[r], nbins)], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nbins; i += 256) {
+        base[i] = cnt[i] ? atomicAdd(&hdr[kOrderCursor + i], cnt[i]) : 0;
+        cnt[i] = 0;
+    }
+    __syncthreads();
+    for (int64_t r = s + threadIdx.x; r < e; r += 256) {
+        const int bb = batch_bin(n_eval[r], nbins);
+        order[base[bb] + atomicAdd(&cnt[bb], 1)] = (int32_t)r;
+    }
+}
 
 template <class S, bool kSoft>
 __global__ __launch_bounds__(kBlock, 4) void k_march_bwd(SceneDev sc, RayParams rp, const float* __restrict__ o_,
-                                                       const float* __restrict__ d_, int64_t n, int64_t chunk,
+                                                       const float* __restrict__ d_, int64_t n,
+                                                       const int32_t* __restrict__ order, unsigned int* __restrict__ next_ray,
                                                        const float* __restrict__ Ts,
                                                        const int32_t* __restrict__ n_eval,
                                                        const float* __restrict__ BW, const float* __restrict__ G8,
@@ -235,39 +305,15 @@ __global__ __launch_bounds__(kBlock, 4) void k_march_bwd(SceneDev sc, RayParams 
                                                        float* __restrict__ gocc) {
     __shared__ int qs[kGroupsPerBlock][kQueue];
     __shared__ __attribute__((aligned(16))) Stage stages[kGroupsPerBlock];
-    __shared__ int s_key[kSortMax];
-    __shared__ uint16_t s_ord[kSortMax];
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kGroup - 1);
     const int gid = threadIdx.x / kGroup;
     Stage& stage = stages[gid];
-    const int64_t start = (int64_t)xcd_block(blockIdx.x, gridDim.x) * chunk;
-    const int cnt = (int)(min(n, start + chunk) - start);
-    // A wave's four groups walk their rays in step, so a wave waits for its
-    // longest ray.  The chunk is therefore walked longest-first (a stable
-    // rank sort of n_eval in LDS), which hands each wave rays of similar
-    // length; chunks longer than kSortMax keep their order.
-    const bool by_len = cnt <= kSortMax;
-    if (by_len) {
-        for (int i = threadIdx.x; i < cnt; i += kBlock) s_key[i] = n_eval[start + i];
-        __syncthreads();
-        for (int i = threadIdx.x; i < cnt; i += kBlock) {
-            const int ki = s_key[i];
-            int r = 0;
-            for (int j = 0; j < cnt; ++j) {
-                const int kj = s_key[j];
-                r += (kj > ki) || (kj == ki && j < i);
-            }
-            s_ord[r] = (uint16_t)i;
-        }
-        __syncthreads();
-    }
-    for (int it = gid; it < cnt; it += kGroupsPerBlock) {
-        const int64_t ray = start + (by_len ? (int)s_ord[it] : it);
+    auto ray_body = [&](int64_t ray) {
         const float3 o = load3(o_, ray), d = load3(d_, ray);
         const int ne = n_eval[ray];
         const float Tn = Ts[ray];
-        if (ne <= 0) continue;  // no sample: C = c_bg, no parameter gradient
+        if (ne <= 0) return;  // no sample: C = c_bg, no parameter gradient
         const float4 ga = *reinterpret_cast<const float4*>(G8 + ray * 8);
         const float4 gb = *reinterpret_cast<const float4*>(G8 + ray * 8 + 4);
         const float g7[7] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z};
@@ -371,36 +417,54 @@ __global__ __launch_bounds__(kBlock, 4) void k_march_bwd(SceneDev sc, RayParams 
             ++b;
             return done >= ne;
         });
+    };
+    // Four rays per wave and turn, the next turn's requested ahead.  The
+    // counter is unsigned: it ends below n + 8 x 4 per wave < 2^32.
+    unsigned int first = 0u;
+    if (lane == 0) first = atomicAdd(next_ray, 4u);
+    int64_t base = (int64_t)(unsigned int)__shfl((int)first, 0);
+    while (base < n) {
+        unsigned int ahead = 0u;
+        if (lane == 0) ahead = atomicAdd(next_ray, 4u);
+        const int64_t idx = base + (gid & 3);
+        if (idx < n) ray_body(order[idx]);
+        base = (int64_t)(unsigned int)__shfl((int)ahead, 0);
     }
 }
 
 hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
                             int64_t n, const float* T, const int32_t* n_eval, const float* batch_wv, const float* G8,
-                            float* gV, float* gxy, float* gxz, float* gyz, float* gocc, hipStream_t s) {
-    // Persistent blocks, each owning a contiguous chunk of rays that it walks
-    // longest-first.
-    const int64_t max_blocks = 4096;
-    int64_t nb = (n + kGroupsPerBlock - 1) / kGroupsPerBlock;
-    if (nb > max_blocks) nb = max_blocks;
-    int64_t chunk = (n + nb - 1) / nb;
-    chunk = (chunk + kGroupsPerBlock - 1) / kGroupsPerBlock * kGroupsPerBlock;
-    nb = (n + chunk - 1) / chunk;
-    const dim3 grid((unsigned)nb), block(kBlock);
+                            int32_t* order, int* sched, float* gV, float* gxy, float* gxz, float* gyz, float* gocc,
+                            hipStream_t s) {
+    // Longest-first order (counting sort by batch count), then persistent
+    // blocks whose waves take rays from it on demand.  2048 blocks of 4 waves
+    // cover every wave slot of the device (4 per SIMD); blocks beyond the
+    // slots start when the order is handed out and leave at once.
+    const int nbins = (rp.n_max + kGroup - 1) / kGroup + 1;
+    const int64_t sort_blocks = min((n + 4095) / 4096, (int64_t)1024);
+    const int64_t sort_chunk = (n + sort_blocks - 1) / sort_blocks;
+    hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(64), 0, s, sched);
+    hipLaunchKernelGGL(k_order_hist, dim3((unsigned)sort_blocks), dim3(256), 0, s, n_eval, n, sort_chunk, nbins, sched);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, nbins, sched);
+    hipLaunchKernelGGL(k_order_scatter, dim3((unsigned)sort_blocks), dim3(256), 0, s, n_eval, n, sort_chunk, nbins,
+                       sched, order);
+    unsigned int* next_ray = reinterpret_cast<unsigned int*>(sched + kOrderCounter);
+    const dim3 grid((unsigned)min((n + kGroupsPerBlock - 1) / kGroupsPerBlock, (int64_t)2048)), block(kBlock);
     const bool soft = rp.occ_inv_eps > 0.0f;
     if (bf16) {
         if (soft)
-            hipLaunchKernelGGL((k_march_bwd<BF16Store, true>), grid, block, 0, s, sc, rp, o, d, n, chunk, T, n_eval,
-                               batch_wv, G8, gV, gxy, gxz, gyz, gocc);
+            hipLaunchKernelGGL((k_march_bwd<BF16Store, true>), grid, block, 0, s, sc, rp, o, d, n, order, next_ray, T,
+                               n_eval, batch_wv, G8, gV, gxy, gxz, gyz, gocc);
         else
-            hipLaunchKernelGGL((k_march_bwd<BF16Store, false>), grid, block, 0, s, sc, rp, o, d, n, chunk, T, n_eval,
-                               batch_wv, G8, gV, gxy, gxz, gyz, gocc);
+            hipLaunchKernelGGL((k_march_bwd<BF16Store, false>), grid, block, 0, s, sc, rp, o, d, n, order, next_ray, T,
+                               n_eval, batch_wv, G8, gV, gxy, gxz, gyz, gocc);
     } else {
         if (soft)
-            hipLaunchKernelGGL((k_march_bwd<F32Store, true>), grid, block, 0, s, sc, rp, o, d, n, chunk, T, n_eval,
-                               batch_wv, G8, gV, gxy, gxz, gyz, gocc);
+            hipLaunchKernelGGL((k_march_bwd<F32Store, true>), grid, block, 0, s, sc, rp, o, d, n, order, next_ray, T,
+                               n_eval, batch_wv, G8, gV, gxy, gxz, gyz, gocc);
         else
-            hipLaunchKernelGGL((k_march_bwd<F32Store, false>), grid, block, 0, s, sc, rp, o, d, n, chunk, T, n_eval,
-                               batch_wv, G8, gV, gxy, gxz, gyz, gocc);
+            hipLaunchKernelGGL((k_march_bwd<F32Store, false>), grid, block, 0, s, sc, rp, o, d, n, order, next_ray, T,
+                               n_eval, batch_wv, G8, gV, gxy, gxz, gyz, gocc);
     }
     return hipGetLastError();
 }

@@ -15,9 +15,13 @@ hipError_t launch_mark(const SceneDev& sc, const RayParams& rp, const float* o, 
 hipError_t launch_march_fwd(const SceneDev& sc, int dtype, const RayParams& rp, const float* o, const float* d,
                             int64_t n, float* F, float* T, int32_t* n_placed, int32_t* n_eval, float* batch_wv,
                             hipStream_t s);
+// Scheduling words (int32) of the march backward in its workspace: the
+// ray-order histogram, its cursors and the hand-out counter.
+constexpr int kBwdSchedWords = 256;
 hipError_t launch_march_bwd(const SceneDev& sc, bool bf16, const RayParams& rp, const float* o, const float* d,
                             int64_t n, const float* T, const int32_t* n_eval, const float* batch_wv, const float* G8,
-                            float* gV, float* gxy, float* gxz, float* gyz, float* gocc, hipStream_t s);
+                            int32_t* order, int* sched, float* gV, float* gxy, float* gxz, float* gyz, float* gocc,
+                            hipStream_t s);
 hipError_t launch_mlp_bwd(const float* W, int mlp_in, const RayParams& rp, const float* F, const float* d,
                           const int32_t* n_eval, const float* dC, const float* dF, int64_t n, float* G8, float* gmlp,
                           hipStream_t s);

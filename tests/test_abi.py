@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol(L):
     assert names == set(_lib.EXPORTS)
     for n in names:
         assert hasattr(L, n), n
-    assert L.om_version() == 108
+    assert L.om_version() == 109
     assert L.om_status_str(-2) == b"unsupported shape or dtype"
 
 
@@ -140,8 +140,10 @@ def test_fused_training_step_validation(L):
     p = _params()
     n = 1000
     ws = L.om_render_fwd_bwd_l2_workspace_size(n, ctypes.byref(p))
-    # dL/dC, the backward's per-ray hand-over (8 floats), then 4 batch slots x 7 floats per ray
-    assert ws == (n * 12 + 255) // 256 * 256 + (n * 32 + 255) // 256 * 256 + n * 4 * 7 * 4
+    # dL/dC, the backward's workspace (per-ray hand-over of 8 floats, ray
+    # order, 1 KiB of scheduling words), then 4 batch slots x 7 floats per ray
+    bwd = (n * 32 + 255) // 256 * 256 + (n * 4 + 255) // 256 * 256 + 1024
+    assert ws == (n * 12 + 255) // 256 * 256 + bwd + n * 4 * 7 * 4
     assert L.om_render_fwd_bwd_l2_workspace_size(-1, ctypes.byref(p)) == -1
     assert L.om_render_fwd_bwd_l2_workspace_size(n, ctypes.byref(_params(n_max=0))) == -1
     rc, h = _create(L, _desc())
@@ -159,12 +161,14 @@ def test_fused_training_step_validation(L):
 
 def test_backward_workspace_validation(L):
     """Workspace query and argument checks of the two backward entry points
-    (no device work): 32 bytes per ray rounded up to 256; a workspace that
-    is too small or misaligned is refused before anything is launched."""
+    (no device work): 32 bytes per ray (the hand-over) and 4 bytes per ray
+    (the ray order), each rounded up to 256, plus 1 KiB of scheduling
+    words; a workspace that is too small or misaligned is refused before
+    anything is launched."""
     assert L.om_render_backward_workspace_size(0) == 0
-    assert L.om_render_backward_workspace_size(1) == 256
-    assert L.om_render_backward_workspace_size(1000) == 32000  # 125 x 256
-    assert L.om_render_backward_workspace_size(1001) == 32256
+    assert L.om_render_backward_workspace_size(1) == 256 + 256 + 1024
+    assert L.om_render_backward_workspace_size(1000) == 32000 + 4096 + 1024  # 125 x 256, 16 x 256
+    assert L.om_render_backward_workspace_size(1001) == 32256 + 4096 + 1024
     assert L.om_render_backward_workspace_size(-1) == -1
     n = 1000
     ws = L.om_render_backward_workspace_size(n)

@@ -569,14 +569,14 @@ def test_oblique_finite_differences_2e18(oblique_train):
     assert err.max() <= 1e-3, [(p, f, a) for p, f, a, e in zip(picks, fd, an, err) if e > 1e-3]
 
 
-def test_backward_long_chunks_keep_caller_order():
-    """Above 4096 x 1024 rays a backward block's chunk is longer than the
-    1024 rays it can sort by length and is walked in the caller's order.
-    That path and the length-sorted one must give the same gradients: the
-    whole batch in one call against its two halves in two calls (the
-    backward adds into the gradient buffers), with the same dL/dC."""
-    n = 4096 * 1024 + 4096 * 16 + 5  # 4034 chunks of 1056 rays (> 1024), the last one ragged
-    log(f"test_backward_long_chunks_keep_caller_order: {n} rays")
+def test_backward_large_batch_equals_its_halves():
+    """A batch of 4.26 M rays (the ray-order sort then runs as 1,024 blocks
+    of ~4,160 rays, each reserving its own ranges of the order; the waves
+    take rays from a counter that passes 2^22) against its two halves in
+    two calls (the backward adds into the gradient buffers), with the same
+    dL/dC: the same gradients."""
+    n = 4096 * 1024 + 4096 * 16 + 5  # ragged against every block size involved
+    log(f"test_backward_large_batch_equals_its_halves: {n} rays")
     sc = scenegen.make_scene(scenegen.TINY)
     scene, t = upload_scene(sc)
     o, d = scenegen.oblique_rays(n, seed=23)
