@@ -161,11 +161,14 @@ def l1_gather_peak(torch, span: int, blocks: int = 8192, iters: int = 64, reps: 
 _ATOMIC_PEAK = {}
 
 
-def atomic_segment_peak(torch, nbytes: int = 1 << 30, blocks: int = 8192, iters: int = 64, reps: int = 5) -> dict:
+def atomic_segment_peak(torch, nbytes: int = 256 << 20, blocks: int = 32768, iters: int = 16, reps: int = 5) -> dict:
     """Rate (G requests/s) at which the device performs float atomics of one
     64-byte segment per 16-lane group, at random segments of a zeroed
     `nbytes` buffer (calibration kernel in libomcalib.so; the backward's
-    segment flush has this shape).  Measured once per process."""
+    segment flush has this shape).  The default, 256 MiB of targets, is the
+    best case: the rate is flat from 4 to 256 MiB and falls beyond (the
+    targets then miss the memory-side cache), so it is the ceiling of the
+    unit.  Measured once per process and size."""
     if nbytes in _ATOMIC_PEAK:
         return _ATOMIC_PEAK[nbytes]
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_2404_09531_amd", "libomcalib.so"))
@@ -398,7 +401,10 @@ def _train_rooflines(om, torch, scene, og, dg, out, kw, f_ms, b_ms, fwd_kernel, 
     march = bwd_kernel[-1] if isinstance(bwd_kernel, tuple) else bwd_kernel
     req = measured_atomic_requests(march, workload)
     if req is not None:
-        cal = atomic_segment_peak(torch)
+        cal = dict(atomic_segment_peak(torch))
+        # context: the same pattern over 1 GiB of targets, about the span a
+        # training step's gradient rows cover
+        cal["G_requests_per_s_1GiB_targets"] = atomic_segment_peak(torch, nbytes=1 << 30)["G_requests_per_s"]
         got = req / (b_ms * 1e-3) / 1e9
         bwd["atomics"] = {"achieved": round(got, 2), "peak": cal["G_requests_per_s"], "unit": "G requests/s",
                           "frac": round(got / cal["G_requests_per_s"], 4), "requests_per_launch": int(req),
