@@ -471,10 +471,11 @@ __device__ __forceinline__ void wave_order() {
 }
 
 // Eq. 2 for 8-bit storage, one lane per sample: the 4 grid corner pairs
-// (16 bytes each), then the 6 plane corner pairs, each group loaded before
-// its weighted code sums are decoded with the source's per-channel (lo,
-// step).  Two load groups instead of one keep the kernel at 86 VGPRs,
-// 5 waves per SIMD (one group of 10 needs 97: 4 waves).
+// (16 bytes each), then the 2 XY pairs, then the 4 XZ and YZ pairs, each
+// group loaded before its weighted code sums are decoded with the source's
+// per-channel (lo, step).  Three load groups keep the kernel at 78 VGPRs,
+// 6 waves per SIMD (two groups, grid and planes: 86, 5 waves; one group of
+// 10: 97, 4 waves).
 __device__ __forceinline__ void decode_add(const SceneDev& sc, int src, const float* a, float* t) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) t[c] += fmaf(sc.qstep[8 * src + c], a[c], sc.qlo[8 * src + c]);
@@ -505,28 +506,32 @@ __device__ __forceinline__ void gather_u8(const SceneDev& sc, const Corners& c, 
         }
         decode_add(sc, 0, a, t);
     }
-    uint4 r[6];
     const uint8_t* P[3] = {static_cast<const uint8_t*>(sc.pxy), static_cast<const uint8_t*>(sc.pxz),
                            static_cast<const uint8_t*>(sc.pyz)};
     const uint32_t pb[3] = {c.xy, c.xz, c.yz}, ps[3] = {nx, nx, ny};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        __builtin_memcpy(&r[2 * q], P[q] + (size_t)pb[q] * 8, 16);
-        __builtin_memcpy(&r[1 + 2 * q], P[q] + (size_t)(pb[q] + ps[q]) * 8, 16);
-    }
     const float u0 = 1.0f - c.ux, u1 = c.ux, v0 = 1.0f - c.uy, v1 = c.uy, e0 = 1.0f - c.uz, e1 = c.uz;
     const float wa[3][2] = {{u0, u1}, {u0, u1}, {v0, v1}};  // first axis: x, x, y
     const float wb[3][2] = {{v0, v1}, {e0, e1}, {e0, e1}};  // second axis: y, z, z
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int g = 0; g < 2; ++g) {  // planes [q0, q1): XY, then XZ and YZ
+        const int q0 = g == 0 ? 0 : 1, q1 = g == 0 ? 1 : 3;
+        uint4 r[4];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) a[i] = 0.0f;
-        const uint4 lo = r[2 * q], hi = r[1 + 2 * q];
-        U8Store::acc(make_uint2(lo.x, lo.y), wa[q][0] * wb[q][0], a);
-        U8Store::acc(make_uint2(lo.z, lo.w), wa[q][1] * wb[q][0], a);
-        U8Store::acc(make_uint2(hi.x, hi.y), wa[q][0] * wb[q][1], a);
-        U8Store::acc(make_uint2(hi.z, hi.w), wa[q][1] * wb[q][1], a);
-        decode_add(sc, 1 + q, a, t);
+        for (int q = q0; q < q1; ++q) {
+            __builtin_memcpy(&r[2 * (q - q0)], P[q] + (size_t)pb[q] * 8, 16);
+            __builtin_memcpy(&r[1 + 2 * (q - q0)], P[q] + (size_t)(pb[q] + ps[q]) * 8, 16);
+        }
+#pragma unroll
+        for (int q = q0; q < q1; ++q) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a[i] = 0.0f;
+            const uint4 lo = r[2 * (q - q0)], hi = r[1 + 2 * (q - q0)];
+            U8Store::acc(make_uint2(lo.x, lo.y), wa[q][0] * wb[q][0], a);
+            U8Store::acc(make_uint2(lo.z, lo.w), wa[q][1] * wb[q][0], a);
+            U8Store::acc(make_uint2(hi.x, hi.y), wa[q][0] * wb[q][1], a);
+            U8Store::acc(make_uint2(hi.z, hi.w), wa[q][1] * wb[q][1], a);
+            decode_add(sc, 1 + q, a, t);
+        }
     }
 }
 
