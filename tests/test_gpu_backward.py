@@ -604,3 +604,41 @@ def test_backward_large_batch_equals_its_halves():
         log(f"  {k}: max |g| {scale:.3e}, max |whole - halves| / max |g| {float(diff.max()) / scale:.2e}")
         assert scale > 0
         assert float((diff - (1e-3 * halves[k].abs() + 5e-5 * scale)).max()) <= 0, k
+
+
+def test_backward_does_not_depend_on_ray_order():
+    """The march backward walks the rays longest first (by batch count) and
+    hands them to its waves on demand, whatever order the caller gives.
+    The same rays, saved outputs and dL/dC in a shuffled order must give the
+    same gradients (lengths from 0 to ~450 samples, so the batch-count
+    bins from 0 up are populated)."""
+    sc = scenegen.make_scene(scenegen.TINY)
+    scene, t = upload_scene(sc)
+    n = 50_000
+    o, d = scenegen.oblique_rays(n, seed=31)
+    d = d.copy()
+    d[::7, 2] = -d[::7, 2]  # every 7th ray points up, away from the box: no sample
+    log(f"test_backward_does_not_depend_on_ray_order: {n} rays, n_max 512")
+    og, dg = rays_to(o, d)
+    kw = dict(n_max=512, c_bg=BG)
+    res = om.render(scene, og, dg, batch_wv=True, **kw)
+    gen = torch.Generator(device=og.device)
+    gen.manual_seed(5)
+    dC = (torch.randn(res["C"].shape, device=og.device, generator=gen) * 1e-5).contiguous()
+    perm = torch.randperm(n, generator=torch.Generator().manual_seed(7)).to(og.device)
+    zero = lambda: {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp")}  # noqa: E731
+    a = zero()
+    om.render_backward(scene, og, dg, res, dC, a, **kw)
+    b = zero()
+    shuffled = {k: v[perm].contiguous() for k, v in res.items()}
+    om.render_backward(scene, og[perm].contiguous(), dg[perm].contiguous(), shuffled, dC[perm].contiguous(), b, **kw)
+    torch.cuda.synchronize()
+    ne = res["n_eval"].cpu().numpy()
+    log(f"  n_eval from {ne.min()} to {ne.max()}, {len(np.unique((ne + 15) // 16))} batch counts")
+    assert ne.max() > 256 and (ne == 0).any()
+    for k in (*SOURCES, "mlp"):
+        scale = float(a[k].abs().max())
+        diff = (a[k] - b[k]).abs()
+        log(f"  {k}: max |g| {scale:.3e}, max |a - b| / max |g| {float(diff.max()) / scale:.2e}")
+        assert scale > 0
+        assert float((diff - (1e-3 * b[k].abs() + 5e-5 * scale)).max()) <= 0, k
