@@ -249,8 +249,14 @@ __device__ __forceinline__ void quad_gather(const SceneDev& sc, const Corners& c
     }
 }
 
+// Waves per SIMD the float32 forward is compiled for: the soft-occupancy
+// forms at 4 (<= 128 VGPRs, no spill); the others keep the compiler's
+// choice, which is 4 already.
+template <bool kSoft>
+constexpr int f32q_min_waves() { return kSoft ? 4 : 1; }
+
 template <bool kBW, bool kSoft, bool kSparse>
-__global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParams rp, const float* __restrict__ o_,
+__global__ __launch_bounds__(kBlock, (f32q_min_waves<kSoft>())) void k_march_fwd_f32q(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                            const float* __restrict__ d_, int64_t n,
                                                            float* __restrict__ F, float* __restrict__ T,
                                                            int32_t* __restrict__ n_placed,
@@ -283,7 +289,6 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParam
             if (i < nb) {
                 const float3 p = lattice_point(ks, o, d, rp.delta);
                 quad_gather(sc, corners_of<kSparse>(sc, p), h, ch, t);
-                if (kSoft) msoft[j] = occ_value(sc, p, rp.occ_inv_eps).m;
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) t[c] += pair_swap(t[c]);
@@ -301,6 +306,17 @@ __global__ __launch_bounds__(kBlock) void k_march_fwd_f32q(SceneDev sc, RayParam
                 }
             }
             a[j] = quad_bcast0(a[j]);
+        }
+        if (kSoft) {
+            // The soft mask (Eq. 6, 8) once the quarters are gathered: its
+            // occupancy loads and arithmetic then do not add to the
+            // gather's registers, which keeps the kernel at 4 waves.
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = 4 * j + s;
+                const int ks = __shfl(kq, i, kGroup);
+                if (i < nb) msoft[j] = occ_value(sc, lattice_point(ks, o, d, rp.delta), rp.occ_inv_eps).m;
+            }
         }
         // Optical depth in front of sample 4j + s: carry + all samples of
         // quarters < j + samples of quads < s in quarter j.
