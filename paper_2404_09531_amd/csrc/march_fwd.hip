@@ -249,14 +249,27 @@ __device__ __forceinline__ void quad_gather(const SceneDev& sc, const Corners& c
     }
 }
 
+// Sparse voxel blocks, in two steps (corners_of<true> does both): the
+// atlas block of a sample's grid cell, clamped as there, and the flat
+// index of the cell's base vertex inside that block.
+__device__ __forceinline__ uint32_t sparse_block(const SceneDev& sc, const Corners& c) {
+    const int32_t id = sc.blk_idx[((c.iz >> sc.blk_shift) * sc.bny + (c.iy >> sc.blk_shift)) * sc.bnx +
+                                  (c.ix >> sc.blk_shift)];
+    return min((uint32_t)id, sc.n_blocks);
+}
+__device__ __forceinline__ uint32_t sparse_vertex(const SceneDev& sc, const Corners& c, uint32_t b) {
+    const int m = (1 << sc.blk_shift) - 1;
+    return b * sc.blk_verts + ((uint32_t)(c.iz & m) * sc.gsy + (uint32_t)(c.iy & m)) * sc.gsy + (uint32_t)(c.ix & m);
+}
+
 // Waves per SIMD the float32 forward is compiled for: the soft-occupancy
-// forms at 4 (<= 128 VGPRs, no spill); the others keep the compiler's
-// choice, which is 4 already.
-template <bool kSoft>
-constexpr int f32q_min_waves() { return kSoft ? 4 : 1; }
+// and sparse forms at 4 (<= 128 VGPRs, no spill); the others keep the
+// compiler's choice, which is 4 already.
+template <bool kSoft, bool kSparse>
+constexpr int f32q_min_waves() { return kSoft || kSparse ? 4 : 1; }
 
 template <bool kBW, bool kSoft, bool kSparse>
-__global__ __launch_bounds__(kBlock, (f32q_min_waves<kSoft>())) void k_march_fwd_f32q(SceneDev sc, RayParams rp, const float* __restrict__ o_,
+__global__ __launch_bounds__(kBlock, (f32q_min_waves<kSoft, kSparse>())) void k_march_fwd_f32q(SceneDev sc, RayParams rp, const float* __restrict__ o_,
                                                            const float* __restrict__ d_, int64_t n,
                                                            float* __restrict__ F, float* __restrict__ T,
                                                            int32_t* __restrict__ n_placed,
@@ -280,15 +293,23 @@ __global__ __launch_bounds__(kBlock, (f32q_min_waves<kSoft>())) void k_march_fwd
     const int slots = (rp.n_max + kGroup - 1) / kGroup;
     const int placed = march_candidates(sc, rp, o, d, qs[gid], gl, lane, [&](int kq, int nb) {
         float a[4], v[4][4], msoft[4];
+        // Sparse blocks: lane gl looks up the block of sample gl, so the
+        // batch's 16 index loads are in flight together, not one per
+        // quarter ahead of that quarter's corner loads.
+        uint32_t blk = 0u;
+        if (kSparse && gl < nb) blk = sparse_block(sc, corners_of<false>(sc, lattice_point(kq, o, d, rp.delta)));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int i = 4 * j + s;
             const int ks = __shfl(kq, i, kGroup);
+            const uint32_t bj = kSparse ? (uint32_t)__shfl((int)blk, i, kGroup) : 0u;
             float t[4] = {0.0f, 0.0f, 0.0f, 0.0f};
             msoft[j] = 0.0f;
             if (i < nb) {
                 const float3 p = lattice_point(ks, o, d, rp.delta);
-                quad_gather(sc, corners_of<kSparse>(sc, p), h, ch, t);
+                Corners c = corners_of<false>(sc, p);
+                if (kSparse) c.g = sparse_vertex(sc, c, bj);
+                quad_gather(sc, c, h, ch, t);
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) t[c] += pair_swap(t[c]);
