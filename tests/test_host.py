@@ -112,3 +112,56 @@ def test_calibration_library_refuses_bad_shapes_before_launching():
     assert lib.omcalib_atomic_segments(None, 1 << 10, 1, 1, None) == -1
     for nvec, span in ((1000, 4), (8, 4), (1024, 3), (1024, 32)):
         assert lib.omcalib_l1_gather(fake, nvec, span, 1, 1, fake, None) == -1
+
+
+def _counter_csv(path, rows):
+    """A rocprofv3-style counter CSV: (dispatch id, kernel name, counter, value)."""
+    path.parent.mkdir(parents=True, exist_ok=True)
+    lines = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+    lines += [f'{i},"{k}",{c},{v}' for i, k, c, v in rows]
+    path.write_text("\n".join(lines) + "\n")
+
+
+def test_traffic_summary_scales_by_the_copy_calibration(tmp_path, monkeypatch):
+    """bench_counters.py traffic: the per-launch DRAM bytes are the median
+    FETCH_SIZE and WRITE_SIZE of the kernel's dispatches (KiB), each scaled
+    by what the counter reads for the 1 GiB copy of the same run; --slice
+    selects dispatches; a pattern must name exactly one kernel."""
+    import argparse
+
+    import pytest
+
+    sys.path.insert(0, ROOT)
+    import bench_counters as bc
+
+    copy = "__amd_rocclr_copyBuffer"
+    kern = "void omerf::k_march_fwd_f32q<false, false, false>(omerf::SceneDev)"
+    other = "void omerf::k_march_fwd_f32q<true, false, false>(omerf::SceneDev)"
+    # the copy reads 2^30 B and writes 2^30 B: FETCH_SIZE counts half of it
+    _counter_csv(tmp_path / "f" / "x_counter_collection.csv",
+                 [(0, copy, "FETCH_SIZE", 524288.0), (9, other, "FETCH_SIZE", 7.0)] +
+                 [(i + 1, kern, "FETCH_SIZE", v) for i, v in enumerate((100.0, 300.0, 500.0))])
+    _counter_csv(tmp_path / "w" / "x_counter_collection.csv",
+                 [(0, copy, "WRITE_SIZE", 1048576.0), (9, other, "WRITE_SIZE", 7.0)] +
+                 [(i + 1, kern, "WRITE_SIZE", v) for i, v in enumerate((10.0, 30.0, 50.0))])
+    rec_path = tmp_path / "traffic.json"
+    monkeypatch.setattr(bc, "TRAFFIC", str(rec_path))
+    monkeypatch.setattr(bc, "source_hash", lambda fam: "h-" + fam)
+
+    def run(workload, slc, spec):
+        bc.cmd_traffic(argparse.Namespace(fetch=str(tmp_path / "f"), write=str(tmp_path / "w"), workload=workload,
+                                          slice=slc, kernels=[spec]))
+        return json.loads(rec_path.read_text())
+
+    rec = run("all", None, "k=k_march_fwd_f32q<false")
+    e = rec["k"]["all"]
+    assert e["fetch_scale"] == 2.0 and e["write_scale"] == 1.0
+    assert e["hbm_bytes_per_launch"] == 300 * 1024 * 2 + 30 * 1024  # medians of the three dispatches
+    assert e["dispatches"] == 3 and e["source_hash"] == "h-fwd"
+    rec = run("first-two", "0:2", "k=k_march_fwd_f32q<false")
+    assert rec["k"]["first-two"]["hbm_bytes_per_launch"] == 200 * 1024 * 2 + 20 * 1024
+    assert rec["k"]["all"]["hbm_bytes_per_launch"] == 300 * 1024 * 2 + 30 * 1024  # kept
+    with pytest.raises(SystemExit):
+        run("none", None, "k=k_mlp_bwd")        # no such kernel
+    with pytest.raises(SystemExit):
+        run("many", None, "k=k_march_fwd_f32q")  # two kernels match
