@@ -165,3 +165,26 @@ def test_traffic_summary_scales_by_the_copy_calibration(tmp_path, monkeypatch):
         run("none", None, "k=k_mlp_bwd")        # no such kernel
     with pytest.raises(SystemExit):
         run("many", None, "k=k_march_fwd_f32q")  # two kernels match
+
+
+def test_counter_summary_takes_medians_and_mfma_fraction(tmp_path, monkeypatch):
+    """bench_counters.py counters: per counter the median over the kernel's
+    dispatches, recorded with the hash of its source family; rocprofv3's
+    MfmaUtil (percent) also becomes the fraction the bench reports."""
+    import argparse
+
+    sys.path.insert(0, ROOT)
+    import bench_counters as bc
+
+    kern = "void omerf::k_mlp_bf16<10>(float const*)"
+    rows = [(i, kern, "MfmaUtil", v) for i, v in enumerate((6.0, 7.0, 9.0))]
+    rows += [(i + 3, kern, "TCC_ATOMIC_sum", v) for i, v in enumerate((5.0, 1.0, 3.0))]
+    _counter_csv(tmp_path / "c" / "y_counter_collection.csv", rows)
+    rec_path = tmp_path / "traffic.json"
+    monkeypatch.setattr(bc, "TRAFFIC", str(rec_path))
+    monkeypatch.setattr(bc, "source_hash", lambda fam: "h-" + fam)
+    bc.cmd_counters(argparse.Namespace(dir=str(tmp_path / "c"), workload="w", kernels=["k_mlp_bf16<10>=k_mlp_bf16<10>"]))
+    e = json.loads(rec_path.read_text())["k_mlp_bf16<10>"]["w"]
+    assert e["counters"] == {"MfmaUtil": 7.0, "TCC_ATOMIC_sum": 3.0}
+    assert e["mfma_busy_frac"] == 0.07
+    assert e["family"] == "mlp" and e["counter_source_hash"] == "h-mlp" and e["source_hash"] == "h-mlp"
