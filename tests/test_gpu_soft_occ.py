@@ -53,17 +53,21 @@ def test_soft_forward_matches_oracle(tiny_soft, dtype):
     assert np.abs(hard["C"] - ref["C"]).max() > 1e-3
 
 
-@pytest.mark.parametrize("batch_wv", [False, True])
-def test_soft_backward_matches_oracle(tiny_soft, batch_wv):
+@pytest.mark.parametrize("dtype,batch_wv", [(torch.float32, False), (torch.float32, True), (torch.bfloat16, True)])
+def test_soft_backward_matches_oracle(tiny_soft, dtype, batch_wv):
+    """float32 storage with and without the per-batch sums, and bfloat16
+    storage (float32 master gradients) against the oracle of the rounded
+    scene."""
     sc, o, d, target = tiny_soft
-    log(f"test_soft_backward_matches_oracle: batch sums {batch_wv}")
-    scene, t = upload_scene(sc)
+    log(f"test_soft_backward_matches_oracle: {dtype}, batch sums {batch_wv}")
+    ref_sc = sc if dtype == torch.float32 else {**sc, **{k: bf16_round(sc[k]) for k in SOURCES}}
+    scene, t = upload_scene(sc, dtype=dtype)
     og, dg = rays_to(o, d)
     tg = torch.from_numpy(target).to(og.device)
     prm = oracle.RenderParams(n_max=64, c_bg=BG, occ_eps=EPS)
-    up, ref_loss = oracle_upstream(sc, o, d, prm, target)
-    ref, scale = oracle_reference(sc, o, d, prm, up)
-    res = om.render(scene, og, dg, n_max=64, c_bg=BG, occ_eps=EPS, batch_wv=batch_wv)
+    up, ref_loss = oracle_upstream(ref_sc, o, d, prm, target)
+    ref, scale = oracle_reference(ref_sc, o, d, prm, up)
+    res = om.render(scene, og, dg, n_max=64, c_bg=BG, occ_eps=EPS, batch_wv=batch_wv, mlp_bf16=0)
     loss = om.l2_loss_fp64(res["C"], tg).item()
     assert abs(loss - ref_loss) <= 1e-4 * ref_loss
     grads = {k: torch.zeros(t[k].shape, dtype=torch.float32, device=og.device) for k in (*SOURCES, "mlp", "occ")}
@@ -71,7 +75,7 @@ def test_soft_backward_matches_oracle(tiny_soft, batch_wv):
                        occ_eps=EPS)
     g = {k: v.double().cpu().numpy() for k, v in grads.items()}
     assert np.abs(ref["occ"][1]).max() > 0
-    check(g, ref, scale, f"tiny soft occupancy batch_wv={batch_wv}")
+    check(g, ref, scale, f"tiny soft occupancy {dtype} batch_wv={batch_wv}")
 
 
 def test_soft_render_fn_returns_occupancy_gradient(tiny_soft):
