@@ -36,9 +36,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BG = (0.25, 0.5, 0.75)
-ALL_FORMS = ("tiny_fp32_render,fp32_render_row_order,fp32_render_ert,bf16_render,u8_render,sparse_render,"
-             "fp32_fwd_bwd,fp32_fwd_bwd_soft_occ,fp32_fwd_bwd_enc_smooth,bf16_render_4k_x8,high_altitude_mips,"
-             "towers_bf16_fwd_bwd")
+ALL_FORMS = ("tiny_fp32_render,fp32_render_row_order,fp32_render_row_order_ordered,fp32_render_ert,bf16_render,"
+             "u8_render,sparse_render,fp32_fwd_bwd,fp32_fwd_bwd_ordered,fp32_fwd_bwd_soft_occ,fp32_fwd_bwd_enc_smooth,"
+             "bf16_render_4k_x8,high_altitude_mips,towers_bf16_fwd_bwd")
 
 
 def parse():
@@ -288,6 +288,35 @@ def form_row_order(om, scenegen, torch, scene, kw, a, l1_peak):
             "l1_frac": round((s * 640 + n * 64) / (m_ms * 1e-3) / 1e9 / l1_peak["GBps"], 4)}
 
 
+def form_row_order_ordered(om, scenegen, torch, scene, kw, a):
+    """The row-major headline frame ordered by the library first
+    (om_order_rays: rays by where they cross the scene), rendered in that
+    order, and its colours scattered back into pixel order (om_scatter_rows);
+    all three inside the timed step."""
+    dev = torch.device("cuda:0")
+    _, rec = scenegen.workload("oblique-1080p")
+    o, d = scenegen.make_rays(dict(rec, order="row"))
+    og, dg = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
+    n = o.shape[0]
+    out = _outputs(torch, n, dev)
+    bufs = (torch.empty((n,), dtype=torch.int32, device=dev), torch.empty_like(og), torch.empty_like(dg))
+    ws = torch.empty((om.order_rays_workspace_size(n),), dtype=torch.uint8, device=dev)
+    image = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    order = lambda: om.order_rays(scene, og, dg, out=bufs, workspace=ws)  # noqa: E731
+    m = lambda: om.render_into(scene, bufs[1], bufs[2], out, stage="march", **kw)  # noqa: E731
+    ml = lambda: om.render_into(scene, bufs[1], bufs[2], out, stage="mlp", **kw)  # noqa: E731
+    back = lambda: om.scatter_rows(out["C"], bufs[0], image)  # noqa: E731
+    tot, (o_ms, m_ms, l_ms, b_ms) = time_stages([order, m, ml, back], a.steps, a.warmup, torch)
+    ms = tot / a.steps
+    plain = _outputs(torch, n, dev)
+    om.render_into(scene, og, dg, plain, **kw)
+    same = bool(torch.equal(image, plain["C"]))
+    return {"workload": "oblique-1080p, row-major ray order, ordered by om_order_rays", "rays": n,
+            "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
+            "order_ms": round(o_ms, 4), "march_ms": round(m_ms, 4), "mlp_ms": round(l_ms, 4),
+            "scatter_ms": round(b_ms, 4), "image_bit_identical_to_row_order_render": same}
+
+
 def form_bf16_render(om, torch, t, og, dg, out, kw, n, a, rows, l1_peak, crop_idx, crops):
     """bfloat16 grid/planes + bfloat16 MFMA MLP on the same 1080p image."""
     scene_b, tb = _bf16_scene(om, t)
@@ -446,6 +475,42 @@ def form_fp32_fwd_bwd(om, scenegen, torch, scene, t, kw, a, occ_eps=0.0):
         res["roofline"] = _train_rooflines(om, torch, scene, o2g, d2g, out2, kw, f_ms, b_ms, "k_march_fwd_f32q<true>",
                                            ("k_mlp_bwd<10>", "k_march_bwd<F32Store>"), "train-2^18", 32)
     return res
+
+
+def form_fp32_fwd_bwd_ordered(om, scenegen, torch, scene, t, kw, a):
+    """The float32 training step of form_fp32_fwd_bwd with the batch ordered
+    by the library first (om_order_rays, and the targets brought along with
+    om_gather_rows), inside the timed step.  The loss and gradients are those
+    of the same ray set: only the order of the float atomics differs."""
+    dev = t["grid"].device
+    o2g, d2g, _ = _train_rays(scenegen, torch, "train-2^18", dev)
+    n2 = o2g.shape[0]
+    out2 = _outputs(torch, n2, dev, om.batch_slots(kw["n_max"]))
+    om.render_into(scene, o2g, d2g, out2, **kw)
+    g = torch.Generator(device=dev)
+    g.manual_seed(2)
+    target = (out2["C"] + 0.05 * torch.randn(out2["C"].shape, device=dev, generator=g)).contiguous()
+    bufs = (torch.empty((n2,), dtype=torch.int32, device=dev), torch.empty_like(o2g), torch.empty_like(d2g))
+    ows = torch.empty((om.order_rays_workspace_size(n2),), dtype=torch.uint8, device=dev)
+    tgt = torch.empty_like(target)
+    grads = {k: torch.zeros(t[k].shape, device=dev) for k in ("grid", "plane_xy", "plane_xz", "plane_yz", "mlp")}
+    dC = torch.empty_like(out2["C"])
+    ws = torch.empty((om.backward_workspace_size(n2),), dtype=torch.uint8, device=dev)
+
+    def order():
+        om.order_rays(scene, o2g, d2g, out=bufs, workspace=ows)
+        om.gather_rows(target, bufs[0], out=tgt)
+
+    fwd = lambda: om.render_into(scene, bufs[1], bufs[2], out2, **kw)  # noqa: E731
+    lossg = lambda: om.l2_loss_grad(out2["C"], tgt, dL_dC=dC, with_loss=False)  # noqa: E731
+    bwd = lambda: om.render_backward(scene, bufs[1], bufs[2], out2, dC, grads, workspace=ws, **kw)  # noqa: E731
+    steps = max(3, a.steps // 2)
+    tot, (o_ms, f_ms, l_ms, b_ms) = time_stages([order, fwd, lossg, bwd], steps, a.warmup, torch)
+    ms = tot / steps
+    return {"workload": "2^18 rays, 16 cameras 1920x1080, oblique scene, ordered by om_order_rays", "rays": n2,
+            "Mrays_per_s": round(n2 / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4),
+            "order_ms": round(o_ms, 4), "fwd_ms": round(f_ms, 4), "loss_ms": round(l_ms, 4),
+            "bwd_ms": round(b_ms, 4)}
 
 
 SMOOTH_RAYS = 1 << 10  # directions per step in the view-smoothness loss
@@ -746,6 +811,8 @@ def main():
         forms["tiny_fp32_render"] = form_tiny(om, scenegen, torch, a)
     if "fp32_render_row_order" in want:
         forms["fp32_render_row_order"] = form_row_order(om, scenegen, torch, scene, kw, a, l1_quad)
+    if "fp32_render_row_order_ordered" in want:
+        forms["fp32_render_row_order_ordered"] = form_row_order_ordered(om, scenegen, torch, scene, kw, a)
     if "bf16_render" in want:
         forms["bf16_render"] = form_bf16_render(om, torch, t, og, dg, out, kw, n, a, rows, l1_lane, crop_idx, crops)
     if "fp32_render_ert" in want:
@@ -756,6 +823,8 @@ def main():
         forms["u8_render"] = form_u8_render(om, torch, t, og, dg, out, kw, n, a, rows, l1_lane, crop_idx, crops)
     if "fp32_fwd_bwd" in want:
         forms["fp32_fwd_bwd"] = form_fp32_fwd_bwd(om, scenegen, torch, scene, t, kw, a)
+    if "fp32_fwd_bwd_ordered" in want:
+        forms["fp32_fwd_bwd_ordered"] = form_fp32_fwd_bwd_ordered(om, scenegen, torch, scene, t, kw, a)
     if "fp32_fwd_bwd_soft_occ" in want:
         forms["fp32_fwd_bwd_soft_occ"] = form_fp32_fwd_bwd(om, scenegen, torch, scene, t, kw, a, occ_eps=0.01)
     if "fp32_fwd_bwd_enc_smooth" in want:

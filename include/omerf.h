@@ -480,6 +480,55 @@ int om_sparse_grid_fill(const om_scene* scene, int block_shift, const int32_t* g
  */
 int om_cast_bf16(const float* src, int64_t n, uint16_t* dst, void* stream);
 
+/*
+ * Locality order of a batch of rays (scheduling only; not part of the
+ * method: each ray is rendered on its own, Eq. 1-3, so every result is the
+ * same in any order).  Rays that cross the scene near one another read the
+ * same grid and plane rows; rendered next to each other they share those
+ * rows in the caches.  Callers whose rays come in no such order (row-major
+ * pixels, random training rays) order them here, render the reordered
+ * copies, and take results back with om_scatter_rows (or bring per-ray
+ * inputs along, such as training targets, with om_gather_rows).
+ *  - Key of a ray: the point where it meets the horizontal plane halfway up
+ *    the scene box, on a 256 x 256 lattice over the box footprint (clamped
+ *    to its edge), as a 16-bit Morton code; a ray parallel to that plane
+ *    takes the cell of its origin, a non-finite point cell 0.
+ *  - order: device int32 [n], written with a permutation of 0..n-1 that
+ *    lists the rays by key; rays with equal keys keep their input order
+ *    within runs of consecutive rays of one 64-ray wave, and such runs of
+ *    one key follow one another in an unspecified order (it may differ
+ *    between calls).
+ *  - o_sorted, d_sorted: device float32 [n][3], written with o[order[i]]
+ *    and d[order[i]]; they must not overlap o or d.
+ *  - workspace: caller-owned device memory of at least
+ *    om_order_rays_workspace_size(n) bytes, 256-byte aligned (the key
+ *    histogram and one 16-bit key per ray).  n = 0 is a no-op and needs
+ *    none.  n must not exceed 2^31 - 1.
+ * Asynchronous on `stream`; calls that share a workspace must not overlap.
+ * om_order_rays_workspace_size returns -1 (and sets the error) for n
+ * outside [0, 2^31 - 1].
+ */
+int om_order_rays(const om_scene* scene, const float* o, const float* d, int64_t n, int32_t* order, float* o_sorted,
+                  float* d_sorted, void* workspace, int64_t workspace_bytes, void* stream);
+int64_t om_order_rays_workspace_size(int64_t n);
+
+/*
+ * Row gathers and scatters that apply a ray order to per-ray data (rows of
+ * `cols` float32 values, 1 <= cols <= 64, row-major, device memory):
+ *  - om_gather_rows: dst[i] = src[idx[i]] for i < n; src has src_rows rows,
+ *    dst n rows.
+ *  - om_scatter_rows: dst[idx[i]] = src[i] for i < n; src has n rows, dst
+ *    dst_rows rows.  Rows of dst that no index names are left as they are;
+ *    with repeated indices the surviving row is unspecified.
+ * Index entries outside [0, src_rows) (gather) or [0, dst_rows) (scatter)
+ * are skipped: the gather leaves that row of dst unwritten.  dst must not
+ * overlap src.  n = 0 is a no-op.  Asynchronous on `stream`.
+ */
+int om_gather_rows(const float* src, int64_t src_rows, int cols, const int32_t* idx, int64_t n, float* dst,
+                   void* stream);
+int om_scatter_rows(const float* src, int cols, const int32_t* idx, int64_t n, float* dst, int64_t dst_rows,
+                    void* stream);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* om_last_error(void);
 

@@ -69,6 +69,70 @@ def to_bf16(t: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor
     return out
 
 
+def order_rays_workspace_size(n: int) -> int:
+    """Bytes of workspace order_rays needs (om_order_rays_workspace_size)."""
+    nb = _lib.lib().om_order_rays_workspace_size(n)
+    if nb < 0:
+        raise _lib.OmerfError("om_order_rays_workspace_size", _lib.OM_ERR_INVALID, _lib.lib().om_last_error().decode())
+    return int(nb)
+
+
+def order_rays(scene, o, d, out=None, workspace=None):
+    """Locality order of a batch of rays (om_order_rays): returns (order
+    int32 [n], o[order], d[order]).  `out` may hold preallocated
+    (order, o_sorted, d_sorted) tensors; `workspace` a uint8 device tensor
+    of order_rays_workspace_size(n) bytes (allocated if None)."""
+    n = o.shape[0]
+    _need(o, "o", torch.float32, (n, 3))
+    _need(d, "d", torch.float32, (n, 3))
+    if out is None:
+        out = (torch.empty((n,), dtype=torch.int32, device=o.device), torch.empty_like(o), torch.empty_like(d))
+    order, os_, ds_ = out
+    _need(order, "order", torch.int32, (n,))
+    _need(os_, "o_sorted", torch.float32, (n, 3))
+    _need(ds_, "d_sorted", torch.float32, (n, 3))
+    nb = order_rays_workspace_size(n)
+    if workspace is None:
+        workspace = torch.empty((max(nb, 1),), dtype=torch.uint8, device=o.device)
+    _lib.check("om_order_rays", _lib.lib().om_order_rays(scene.handle, o.data_ptr(), d.data_ptr(), n,
+                                                         order.data_ptr(), os_.data_ptr(), ds_.data_ptr(),
+                                                         workspace.data_ptr(), workspace.numel(), _lib.stream_of(o)))
+    return order, os_, ds_
+
+
+def _rows(t, name):
+    if t.dim() not in (1, 2):
+        raise ValueError(f"{name}: rows of floats expected, got shape {tuple(t.shape)}")
+    return t.shape[0], (t.shape[1] if t.dim() == 2 else 1)
+
+
+def gather_rows(src, idx, out=None):
+    """out[i] = src[idx[i]] on float32 rows (om_gather_rows)."""
+    rows, cols = _rows(src, "src")
+    _need(src, "src", torch.float32)
+    _need(idx, "idx", torch.int32, (idx.shape[0],))
+    shape = (idx.shape[0],) + tuple(src.shape[1:])
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=src.device)
+    _need(out, "out", torch.float32, shape)
+    _lib.check("om_gather_rows", _lib.lib().om_gather_rows(src.data_ptr(), rows, cols, idx.data_ptr(), idx.shape[0],
+                                                           out.data_ptr(), _lib.stream_of(src)))
+    return out
+
+
+def scatter_rows(src, idx, out):
+    """out[idx[i]] = src[i] on float32 rows (om_scatter_rows)."""
+    n, cols = _rows(src, "src")
+    _need(src, "src", torch.float32)
+    _need(idx, "idx", torch.int32, (n,))
+    _need(out, "out", torch.float32)
+    if tuple(out.shape[1:]) != tuple(src.shape[1:]):
+        raise ValueError(f"out: rows of shape {tuple(src.shape[1:])} expected, got {tuple(out.shape[1:])}")
+    _lib.check("om_scatter_rows", _lib.lib().om_scatter_rows(src.data_ptr(), cols, idx.data_ptr(), n, out.data_ptr(),
+                                                             out.shape[0], _lib.stream_of(src)))
+    return out
+
+
 class Scene:
     """Library handle over borrowed device tensors.
 

@@ -25,7 +25,8 @@ EXPORTS = ("om_scene_create", "om_scene_update", "om_scene_destroy", "om_occupan
            "om_render_fwd_bwd_l2_noalloc", "om_render_fwd_bwd_l2_noalloc_max_bytes",
            "om_occ_interval_loss", "om_feature_range", "om_quant_params", "om_quantize_u8",
            "om_sparse_grid_index", "om_sparse_grid_fill",
-           "om_cast_bf16", "om_mark_rows", "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str",
+           "om_cast_bf16", "om_order_rays", "om_order_rays_workspace_size", "om_gather_rows", "om_scatter_rows",
+           "om_mark_rows", "om_l2_loss_fp64", "om_l2_loss_grad", "om_last_error", "om_status_str",
            "om_version")
 
 
@@ -92,6 +93,12 @@ def lib() -> ctypes.CDLL:
         L.om_sparse_grid_index.argtypes = [c_void_p, c_int, c_void_p, c_int64, c_void_p]
         L.om_sparse_grid_fill.argtypes = [c_void_p, c_int, c_void_p, c_int64, c_void_p, c_void_p]
         L.om_cast_bf16.argtypes = [c_void_p, c_int64, c_void_p, c_void_p]
+        L.om_order_rays.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_int64, c_void_p]
+        L.om_order_rays_workspace_size.argtypes = [c_int64]
+        L.om_order_rays_workspace_size.restype = c_int64
+        L.om_gather_rows.argtypes = [c_void_p, c_int64, c_int, c_void_p, c_int64, c_void_p, c_void_p]
+        L.om_scatter_rows.argtypes = [c_void_p, c_int, c_void_p, c_int64, c_void_p, c_int64, c_void_p]
         L.om_mark_rows.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(OmParams), c_void_p, c_void_p,
                                    c_void_p, c_void_p, c_void_p, c_void_p]
         L.om_l2_loss_fp64.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]

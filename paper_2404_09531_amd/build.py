@@ -13,7 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "march_fwd.hip", "march_bwd.hip", "mlp.hip", "bake.hip"]
+SOURCES = ["api.hip", "march_fwd.hip", "march_bwd.hip", "mlp.hip", "bake.hip", "order.hip"]
 LIB = os.path.join(HERE, "libomerf.so")
 # measurement-only calibration kernels (not part of the C ABI)
 CALIB_SOURCES = ["calib.hip"]

@@ -694,6 +694,74 @@ int om_cast_bf16(const float* src, int64_t n, uint16_t* dst, void* stream) {
     return hip_status(launch_cast_bf16(src, n, dst, (hipStream_t)stream), "om_cast_bf16");
 }
 
+namespace {
+static int64_t order_keys_offset() { return (order_hist_bytes() + 255) / 256 * 256; }
+}  // namespace
+
+int64_t om_order_rays_workspace_size(int64_t n) {
+    if (n < 0 || n > INT32_MAX) {
+        fail(OM_ERR_INVALID, "n must lie in [0, 2^31 - 1]");
+        return -1;
+    }
+    // The key histogram, then one 16-bit key per ray.  No rays, no work.
+    if (n == 0) return 0;
+    return order_keys_offset() + (n * (int64_t)sizeof(uint16_t) + 255) / 256 * 256;
+}
+
+int om_order_rays(const om_scene* scene, const float* o, const float* d, int64_t n, int32_t* order, float* o_sorted,
+                  float* d_sorted, void* workspace, int64_t workspace_bytes, void* stream) {
+    if (!scene) return fail(OM_ERR_INVALID, "NULL scene");
+    if (n < 0 || n > INT32_MAX) return fail(OM_ERR_INVALID, "n must lie in [0, 2^31 - 1]");
+    if (n == 0) return ok();
+    if (!o || !d || !order || !o_sorted || !d_sorted || !workspace) return fail(OM_ERR_INVALID, "NULL pointer");
+    if ((uintptr_t)workspace & 255u) return fail(OM_ERR_INVALID, "workspace must be 256-byte aligned");
+    const int64_t need = om_order_rays_workspace_size(n);
+    if (workspace_bytes < need)
+        return fail(OM_ERR_INVALID, "workspace of %lld bytes, %lld needed", (long long)workspace_bytes, (long long)need);
+    const char* ob = reinterpret_cast<const char*>(o);
+    const char* db = reinterpret_cast<const char*>(d);
+    const int64_t rb = n * 3 * (int64_t)sizeof(float);
+    for (const float* w : {(const float*)o_sorted, (const float*)d_sorted}) {
+        const char* wb = reinterpret_cast<const char*>(w);
+        if ((wb < ob + rb && ob < wb + rb) || (wb < db + rb && db < wb + rb))
+            return fail(OM_ERR_INVALID, "o_sorted and d_sorted must not overlap o or d");
+    }
+    int* hist = static_cast<int*>(workspace);
+    uint16_t* keys = reinterpret_cast<uint16_t*>(static_cast<char*>(workspace) + order_keys_offset());
+    return hip_status(launch_order_rays(scene->desc.box_lo, scene->desc.box_hi, o, d, n, order, o_sorted, d_sorted,
+                                        hist, keys, (hipStream_t)stream),
+                      "om_order_rays");
+}
+
+namespace {
+static int rows_args(const float* src, int cols, const int32_t* idx, int64_t n, const float* dst, int64_t src_rows,
+              int64_t dst_rows) {
+    if (n < 0 || n > INT32_MAX) return fail(OM_ERR_INVALID, "n must lie in [0, 2^31 - 1]");
+    if (cols < 1 || cols > 64) return fail(OM_ERR_INVALID, "cols must lie in [1, 64]");
+    if (src_rows < 0 || dst_rows < 0) return fail(OM_ERR_INVALID, "row counts must be >= 0");
+    if (n > 0 && (!src || !idx || !dst)) return fail(OM_ERR_INVALID, "NULL pointer");
+    const char* sb = reinterpret_cast<const char*>(src);
+    const char* db = reinterpret_cast<const char*>(dst);
+    const int64_t s_bytes = src_rows * cols * (int64_t)sizeof(float), d_bytes = dst_rows * cols * (int64_t)sizeof(float);
+    if (n > 0 && db < sb + s_bytes && sb < db + d_bytes) return fail(OM_ERR_INVALID, "dst must not overlap src");
+    return OM_OK;
+}
+}  // namespace
+
+int om_gather_rows(const float* src, int64_t src_rows, int cols, const int32_t* idx, int64_t n, float* dst,
+                   void* stream) {
+    const int st = rows_args(src, cols, idx, n, dst, src_rows, n);
+    if (st != OM_OK || n == 0) return st == OM_OK ? ok() : st;
+    return hip_status(launch_rows_gather(src, src_rows, cols, idx, n, dst, (hipStream_t)stream), "om_gather_rows");
+}
+
+int om_scatter_rows(const float* src, int cols, const int32_t* idx, int64_t n, float* dst, int64_t dst_rows,
+                    void* stream) {
+    const int st = rows_args(src, cols, idx, n, dst, n, dst_rows);
+    if (st != OM_OK || n == 0) return st == OM_OK ? ok() : st;
+    return hip_status(launch_rows_scatter(src, cols, idx, n, dst, dst_rows, (hipStream_t)stream), "om_scatter_rows");
+}
+
 int om_l2_loss_fp64(const float* C, const float* target, int64_t n, double* out, void* stream) {
     if (n <= 0) return fail(OM_ERR_INVALID, "n must be > 0");
     if (!C || !target || !out) return fail(OM_ERR_INVALID, "NULL pointer");
@@ -719,6 +787,6 @@ const char* om_status_str(int status) {
     }
 }
 
-int om_version(void) { return 109; }
+int om_version(void) { return 110; }
 
 }  // extern "C"

@@ -38,6 +38,16 @@ hipError_t launch_blocks_fill(const SceneDev& sc, int shift, int bnx, int bny, i
                               int64_t n_blocks, int units, void* atlas, hipStream_t s);
 hipError_t launch_cast_bf16(const float* src, int64_t n, uint16_t* dst, hipStream_t s);
 hipError_t launch_l2(const float* C, const float* tgt, int64_t n, float* dC, float* loss, hipStream_t s);
+// Ray locality order (order.hip): histogram bytes of its workspace, the
+// order with the reordered rays, and row gathers / scatters.
+int64_t order_hist_bytes();
+hipError_t launch_order_rays(const float* box_lo, const float* box_hi, const float* o, const float* d, int64_t n,
+                             int32_t* order, float* o_out, float* d_out, int* hist, uint16_t* keys,
+                             hipStream_t s);
+hipError_t launch_rows_gather(const float* src, int64_t src_rows, int cols, const int32_t* idx, int64_t n,
+                              float* dst, hipStream_t s);
+hipError_t launch_rows_scatter(const float* src, int cols, const int32_t* idx, int64_t n, float* dst,
+                               int64_t dst_rows, hipStream_t s);
 hipError_t launch_l2_fp64(const float* C, const float* tgt, int64_t n, double* loss, hipStream_t s);
 
 }  // namespace omerf

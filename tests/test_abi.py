@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol(L):
     assert names == set(_lib.EXPORTS)
     for n in names:
         assert hasattr(L, n), n
-    assert L.om_version() == 109
+    assert L.om_version() == 110
     assert L.om_status_str(-2) == b"unsupported shape or dtype"
 
 
@@ -189,6 +189,44 @@ def test_backward_workspace_validation(L):
     # n = 0 is a no-op that needs no workspace
     assert L.om_render_backward_ex(h, None, None, 0, ctypes.byref(p), ctypes.byref(out), None, None, None, 0,
                                    ctypes.byref(g), None) == 0
+    L.om_scene_destroy(h)
+
+
+def test_order_rays_validation(L):
+    """Workspace query and argument checks of the ray order and the row
+    gathers (no device work): a 256 KiB key histogram plus 2 bytes per ray
+    rounded up to 256; n beyond 2^31 - 1, a short or misaligned workspace,
+    outputs overlapping the rays, and cols outside [1, 64] are refused
+    before anything is launched; n = 0 is a no-op."""
+    assert L.om_order_rays_workspace_size(0) == 0
+    assert L.om_order_rays_workspace_size(1) == 262144 + 256
+    assert L.om_order_rays_workspace_size(128) == 262144 + 256
+    assert L.om_order_rays_workspace_size(129) == 262144 + 512
+    assert L.om_order_rays_workspace_size(-1) == -1
+    assert L.om_order_rays_workspace_size(1 << 31) == -1
+    rc, h = _create(L, _desc())
+    n = 1000
+    ws = L.om_order_rays_workspace_size(n)
+    o, d, order, os_, ds_ = (FAKE + k * (1 << 20) for k in range(5))
+    call = lambda w, nb, a=os_, b=ds_: L.om_order_rays(h, o, d, n, order, a, b, w, nb, None)  # noqa: E731
+    assert call(FAKE + (8 << 20), ws - 1) == _lib.OM_ERR_INVALID
+    assert "workspace" in L.om_last_error().decode()
+    assert call(FAKE + (8 << 20) + 16, ws) == _lib.OM_ERR_INVALID
+    assert call(None, ws) == _lib.OM_ERR_INVALID
+    assert call(FAKE + (8 << 20), ws, a=o + 4) == _lib.OM_ERR_INVALID
+    assert "overlap" in L.om_last_error().decode()
+    assert call(FAKE + (8 << 20), ws, b=d) == _lib.OM_ERR_INVALID
+    assert L.om_order_rays(None, o, d, n, order, os_, ds_, FAKE, ws, None) == _lib.OM_ERR_INVALID
+    assert L.om_order_rays(h, o, d, 1 << 31, order, os_, ds_, FAKE, 1 << 40, None) == _lib.OM_ERR_INVALID
+    assert L.om_order_rays(h, None, None, 0, None, None, None, None, 0, None) == 0
+    for cols in (0, 65):
+        assert L.om_gather_rows(o, n, cols, order, n, os_, None) == _lib.OM_ERR_INVALID
+        assert L.om_scatter_rows(o, cols, order, n, os_, n, None) == _lib.OM_ERR_INVALID
+    assert L.om_gather_rows(o, n, 3, order, n, o + 12, None) == _lib.OM_ERR_INVALID
+    assert "overlap" in L.om_last_error().decode()
+    assert L.om_scatter_rows(o, 3, None, n, os_, n, None) == _lib.OM_ERR_INVALID
+    assert L.om_gather_rows(None, 0, 3, None, 0, None, None) == 0
+    assert L.om_scatter_rows(None, 3, None, 0, None, 0, None) == 0
     L.om_scene_destroy(h)
 
 
