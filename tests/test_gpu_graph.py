@@ -123,3 +123,42 @@ def test_training_step_graph_replays_match_eager(tiny):
             err = float((grads[k] - grads_e[k]).abs().max())
             assert err <= 1e-5 * scale[k], (rep, k, err / scale[k])
     log(f"  loss {loss.item():.9e}, 3 replays equal to the eager step")
+
+
+def test_ordered_render_graph_replays_equal_eager(tiny):
+    """The ray order (its histogram cleared by a fill kernel), the render of
+    the reordered rays and the scatter back, captured together; between
+    replays the same order workspace is used eagerly for other rays, so a
+    replay that did not clear it would place rays outside their bins."""
+    log("test_ordered_render_graph_replays_equal_eager")
+    sc, scene, t = tiny
+    o, d = scenegen.oblique_rays(3000, seed=43)
+    og, dg = rays_to(o, d)
+    o2, d2 = scenegen.oblique_rays(2500, seed=44)
+    og2, dg2 = rays_to(o2, d2)
+    kw = dict(n_max=64, c_bg=BG)
+    eager = om.render(scene, og, dg, **kw)
+    n = og.shape[0]
+    ws = torch.empty((om.order_rays_workspace_size(n),), dtype=torch.uint8, device=og.device)
+    bufs = (torch.empty((n,), dtype=torch.int32, device=og.device), torch.empty_like(og), torch.empty_like(dg))
+    out = {k: torch.empty_like(v) for k, v in eager.items()}
+    image = torch.full_like(eager["C"], -7)
+
+    def fn():
+        om.order_rays(scene, og, dg, out=bufs, workspace=ws)
+        om.render_into(scene, bufs[1], bufs[2], out, **kw)
+        om.scatter_rows(out["C"], bufs[0], image)
+
+    _warm(fn)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    for rep in range(3):
+        image.fill_(-7)
+        om.order_rays(scene, og2, dg2, workspace=ws)  # eager use of the same workspace
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        idx = bufs[0].cpu().numpy()
+        assert np.array_equal(np.sort(idx), np.arange(n, dtype=np.int32)), rep
+        assert torch.equal(image, eager["C"]), rep
