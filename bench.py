@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 BG = (0.25, 0.5, 0.75)
 ALL_FORMS = ("tiny_fp32_render,fp32_render_row_order,fp32_render_row_order_ordered,fp32_render_ert,bf16_render,"
              "u8_render,sparse_render,fp32_fwd_bwd,fp32_fwd_bwd_ordered,fp32_fwd_bwd_soft_occ,fp32_fwd_bwd_enc_smooth,"
-             "bf16_render_4k_x8,high_altitude_mips,towers_bf16_fwd_bwd")
+             "bf16_render_4k_x8,high_altitude_mips,towers_bf16_fwd_bwd,towers_bf16_fwd_bwd_ordered")
 
 
 def parse():
@@ -601,9 +601,11 @@ def form_bf16_4k(om, scenegen, torch, t, kw, a, l1_peak, crops):
                          "hbm_frac": round(n * 52 / (lb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
-def form_towers(om, scenegen, torch, a):
+def form_towers(om, scenegen, torch, a, ordered=False):
     """Uneven rays: 512^2 occupancy with 10% towers, 2^20 rays of 64 cameras,
-    n_max 512; bfloat16 storage, float32 master gradients."""
+    n_max 512; bfloat16 storage, float32 master gradients.  ordered=True:
+    the batch is ordered by om_order_rays (targets gathered along) inside
+    the timed step."""
     dev = torch.device("cuda:0")
     cfg, rec = scenegen.workload("towers-2^20")
     sc = scenegen.make_scene(cfg)
@@ -626,6 +628,24 @@ def form_towers(om, scenegen, torch, a):
     ws = torch.empty((om.backward_workspace_size(n),), dtype=torch.uint8, device=dev)
     bwd = lambda: om.render_backward(scene_b, og, dg, out, dC, grads, workspace=ws, **kw)  # noqa: E731
     steps = max(3, a.steps // 4)
+    if ordered:
+        bufs = (torch.empty((n,), dtype=torch.int32, device=dev), torch.empty_like(og), torch.empty_like(dg))
+        ows = torch.empty((om.order_rays_workspace_size(n),), dtype=torch.uint8, device=dev)
+        tgt = torch.empty_like(target)
+
+        def order():
+            om.order_rays(scene_b, og, dg, out=bufs, workspace=ows)
+            om.gather_rows(target, bufs[0], out=tgt)
+
+        fwd = lambda: om.render_into(scene_b, bufs[1], bufs[2], out, **kw)  # noqa: E731
+        lossg = lambda: om.l2_loss_grad(out["C"], tgt, dL_dC=dC, with_loss=False)  # noqa: E731
+        bwd = lambda: om.render_backward(scene_b, bufs[1], bufs[2], out, dC, grads, workspace=ws, **kw)  # noqa: E731
+        tot, (o_ms, f_ms, l_ms, b_ms) = time_stages([order, fwd, lossg, bwd], steps, 1, torch)
+        ms = tot / steps
+        return {"workload": "towers: occupancy 512^2, 10% towers, 2^20 rays of 64 cameras, n_max 512, "
+                            "ordered by om_order_rays", "rays": n,
+                "Mrays_per_s": round(n / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 3),
+                "order_ms": round(o_ms, 3), "fwd_ms": round(f_ms, 3), "bwd_ms": round(b_ms, 3)}
     tot, (f_ms, l_ms, b_ms) = time_stages([fwd, lossg, bwd], steps, 1, torch)
     ms = tot / steps
     npl = out["n_placed"].cpu().numpy()
@@ -837,6 +857,11 @@ def main():
         del t, scene, out, og, dg
         torch.cuda.empty_cache()
         forms["towers_bf16_fwd_bwd"] = form_towers(om, scenegen, torch, a)
+    if "towers_bf16_fwd_bwd_ordered" in want:
+        if "towers_bf16_fwd_bwd" not in want:
+            del t, scene, out, og, dg
+            torch.cuda.empty_cache()
+        forms["towers_bf16_fwd_bwd_ordered"] = form_towers(om, scenegen, torch, a, ordered=True)
 
     cpu = None
     if not a.no_cpu_baseline:
